@@ -1,0 +1,271 @@
+"""CPU oracle for the AMG-preconditioned flexible CG -- TEST INFRASTRUCTURE ONLY.
+
+A plain sequential FP64 implementation (``amg_oracle.c``) of what the GPU
+library computes, written from the paper's algorithms (arXiv 2303.02352:
+Sec. 3 Alg. 1, Sec. 3.1 Alg. 2 / Alg. 3, Sec. 4.1 matching).  Only the tests,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package.  It shares no code with ``paper_2303_02352_amd``.
+
+Functions pinned by tests in ``tests/test_oracle_*.py``; the pins are listed
+in each test module's docstring.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "amg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, INVALID, NOT_SPD, NONFINITE, NOMEM = 0, 1, -1, -2, -3, -4
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile ``liboracle.so`` with gcc (plain C, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [(name, C.c_int32) for name in (
+        "aggr_steps", "max_levels", "coarse_max", "coarse_solver", "coarse_sweeps",
+        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond")]
+
+
+@dataclass
+class AMGParams:
+    """Method parameters (defaults: s = 2 pairwise steps -> aggregates <= 4,
+    coarsest <= 100 rows by dense Cholesky, 4 + 4 l1-Jacobi sweeps, constant
+    smooth vector)."""
+    aggr_steps: int = 2
+    max_levels: int = 40
+    coarse_max: int = 100
+    coarse_solver: int = 0
+    coarse_sweeps: int = 20
+    pre_sweeps: int = 4
+    post_sweeps: int = 4
+    smooth_vec: int = 0
+    smooth_sweeps: int = 20
+    precond: int = 1
+
+    def c(self) -> Params:
+        return Params(*[int(getattr(self, f.name)) for f in fields(self)])
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        L.orc_validate.argtypes = [C.c_int32, _i32p, _i32p, _f64p]
+        L.orc_spmv.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]
+        L.orc_l1_dinv.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p]
+        L.orc_edge_weights.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]
+        L.orc_match_greedy.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p]
+        L.orc_match_suitor.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p]
+        L.orc_cholesky.argtypes = [C.c_int32, _f64p, _f64p]
+        L.orc_chol_solve.argtypes = [C.c_int32, _f64p, _f64p, _f64p]
+        L.orc_setup.restype = C.c_void_p
+        L.orc_setup.argtypes = [C.c_int32, _i32p, _i32p, _f64p, C.POINTER(Params), C.c_void_p,
+                                C.POINTER(C.c_int)]
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_nlevels.argtypes = [C.c_void_p]
+        L.orc_coarse_dense.argtypes = [C.c_void_p]
+        L.orc_level_size.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64)]
+        L.orc_opc.restype = C.c_double
+        L.orc_opc.argtypes = [C.c_void_p]
+        L.orc_export_level.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        L.orc_export_coarse_factor.argtypes = [C.c_void_p, _f64p]
+        L.orc_vcycle.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_pcg.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32,
+                              C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.orc_pairwise_step.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p,
+                                        _f64p, C.POINTER(C.c_int32),
+                                        C.POINTER(C.POINTER(C.c_double)),
+                                        C.POINTER(C.POINTER(C.c_int32)),
+                                        C.POINTER(C.POINTER(C.c_int32)),
+                                        C.POINTER(C.POINTER(C.c_double)),
+                                        C.POINTER(C.c_int64)]
+        L.orc_free_ptr.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _csr_args(A):
+    return (int(A.n), np.ascontiguousarray(A.row_ptr, np.int32),
+            np.ascontiguousarray(A.col, np.int32), np.ascontiguousarray(A.val, np.float64))
+
+
+def validate(A) -> int:
+    return lib().orc_validate(*_csr_args(A))
+
+
+def spmv(A, x):
+    y = np.empty(A.n)
+    lib().orc_spmv(*_csr_args(A), np.ascontiguousarray(x, np.float64), y)
+    return y
+
+
+def l1_dinv(A):
+    d = np.empty(A.n)
+    lib().orc_l1_dinv(*_csr_args(A), d)
+    return d
+
+
+def edge_weights(A, w):
+    out = np.empty(A.nnz)
+    st = lib().orc_edge_weights(*_csr_args(A), np.ascontiguousarray(w, np.float64), out)
+    assert st == OK
+    return out
+
+
+def match_greedy(A, w):
+    mate = np.empty(A.n, np.int32)
+    st = lib().orc_match_greedy(*_csr_args(A), np.ascontiguousarray(w, np.float64), mate)
+    assert st == OK
+    return mate
+
+
+def match_suitor(A, w, order):
+    mate = np.empty(A.n, np.int32)
+    st = lib().orc_match_suitor(*_csr_args(A), np.ascontiguousarray(w, np.float64),
+                                np.ascontiguousarray(order, np.int32), mate)
+    assert st == OK
+    return mate
+
+
+def cholesky(D):
+    D = np.ascontiguousarray(D, np.float64)
+    L = np.empty_like(D)
+    st = lib().orc_cholesky(D.shape[0], D, L)
+    return st, L
+
+
+def chol_solve(L, r):
+    x = np.empty(L.shape[0])
+    lib().orc_chol_solve(L.shape[0], np.ascontiguousarray(L), np.ascontiguousarray(r, np.float64), x)
+    return x
+
+
+def pairwise_step(A, w):
+    """One pairwise coarsening step: dict with mate, agg, pval, nc, wc and the coarse CSR."""
+    L = lib()
+    n = A.n
+    mate = np.empty(n, np.int32)
+    agg = np.empty(n, np.int32)
+    pval = np.empty(n)
+    nc = C.c_int32()
+    wc = C.POINTER(C.c_double)()
+    crp = C.POINTER(C.c_int32)()
+    cci = C.POINTER(C.c_int32)()
+    cv = C.POINTER(C.c_double)()
+    cnnz = C.c_int64()
+    st = L.orc_pairwise_step(*_csr_args(A), np.ascontiguousarray(w, np.float64), mate, agg, pval,
+                             C.byref(nc), C.byref(wc), C.byref(crp), C.byref(cci), C.byref(cv),
+                             C.byref(cnnz))
+    assert st == OK, st
+    m, z = nc.value, cnnz.value
+    out = dict(mate=mate, agg=agg, pval=pval, nc=m,
+               wc=np.ctypeslib.as_array(wc, (m,)).copy(),
+               row_ptr=np.ctypeslib.as_array(crp, (m + 1,)).copy(),
+               col=np.ctypeslib.as_array(cci, (max(z, 1),))[:z].copy(),
+               val=np.ctypeslib.as_array(cv, (max(z, 1),))[:z].copy())
+    for p in (wc, crp, cci, cv):
+        L.orc_free_ptr(C.cast(p, C.c_void_p))
+    return out
+
+
+class Hierarchy:
+    """Oracle AMG hierarchy: ``Hierarchy(A, AMGParams(...), w=None)``."""
+
+    def __init__(self, A, params: AMGParams | None = None, w=None):
+        self.params = params or AMGParams()
+        L = lib()
+        st = C.c_int()
+        self._w = None if w is None else np.ascontiguousarray(w, np.float64)
+        wp = None if self._w is None else self._w.ctypes.data_as(C.c_void_p)
+        cp = self.params.c()
+        self.h = L.orc_setup(*_csr_args(A), C.byref(cp), wp, C.byref(st))
+        self.status = st.value
+        self.n = A.n
+        if not self.h:
+            raise OracleError(self.status)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_free(self.h)
+            self.h = None
+
+    @property
+    def nlevels(self) -> int:
+        return lib().orc_nlevels(self.h)
+
+    @property
+    def coarse_dense(self) -> bool:
+        return bool(lib().orc_coarse_dense(self.h))
+
+    def level_size(self, k):
+        n, z = C.c_int32(), C.c_int64()
+        assert lib().orc_level_size(self.h, k, C.byref(n), C.byref(z)) == OK
+        return n.value, z.value
+
+    def sizes(self):
+        return [self.level_size(k) for k in range(self.nlevels)]
+
+    def opc(self) -> float:
+        return lib().orc_opc(self.h)
+
+    def level(self, k):
+        n, z = self.level_size(k)
+        rp = np.empty(n + 1, np.int32)
+        ci = np.empty(max(z, 1), np.int32)
+        v = np.empty(max(z, 1))
+        w = np.empty(n)
+        dinv = np.empty(n)
+        agg = np.full(n, -1, np.int32)
+        pval = np.zeros(n)
+        args = [a.ctypes.data_as(C.c_void_p) for a in (rp, ci, v, w, agg, pval, dinv)]
+        assert lib().orc_export_level(self.h, k, *args) == OK
+        return dict(n=n, nnz=z, row_ptr=rp, col=ci[:z], val=v[:z], w=w, dinv=dinv,
+                    agg=agg if k < self.nlevels - 1 else None,
+                    pval=pval if k < self.nlevels - 1 else None)
+
+    def coarse_factor(self):
+        n, _ = self.level_size(self.nlevels - 1)
+        Lf = np.empty((n, n))
+        assert lib().orc_export_coarse_factor(self.h, Lf) == OK
+        return Lf
+
+    def vcycle(self, r):
+        z = np.empty(self.n)
+        assert lib().orc_vcycle(self.h, np.ascontiguousarray(r, np.float64), z) == OK
+        return z
+
+    def pcg(self, b, x0=None, rtol=1e-6, maxit=1000):
+        """Returns (x, iterations, recurrence relative residual, status)."""
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+        it, rel = C.c_int32(), C.c_double()
+        st = lib().orc_pcg(self.h, np.ascontiguousarray(b, np.float64), x, float(rtol), int(maxit),
+                           C.byref(it), C.byref(rel))
+        return x, it.value, rel.value, st
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__("oracle status %d" % status)
+        self.status = status
