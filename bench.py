@@ -1,0 +1,203 @@
+"""Benchmark: AMG-PCG on 3D Poisson 160^3 (7-point, FP64) on one MI355X.
+
+One step = one pass of the whole path on the resident input: amg_setup
+(smooth vector, matching, aggregation, Galerkin products, coarsest factor)
+followed by amg_pcg_solve from x0 = 0 to a relative residual of 1e-6.
+`value` is the PCG solve time in seconds (HIP events on the hierarchy's
+stream around amg_pcg_solve, mean over the timed steps).
+
+Printed JSON line (rank 0): the contract fields plus
+  roofline      dominant kernel (fine-level l1-Jacobi sweep): algorithmic
+                bytes per launch / mean launch time (HIP events on the
+                library stream), against 8 TB/s HBM;
+  cpu_baseline  the CPU oracle (single thread) on the same 160^3 system;
+  detail        setup/solve split, iterations, per-kernel GB/s, and the
+                mixed-precision form on the same system.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+N_EDGE = 160
+SEED = 2
+RTOL = 1e-6
+MAXIT = 1000
+METRIC = "AMG-PCG solve s & SpMV GB/s, 3D Poisson 160³ FP64 vs mixed/learned"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("solve.hip", "amg_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2303_02352_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name, algorithmic_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_name)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, b):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    H = oracle.Hierarchy(A)
+    t1 = time.perf_counter()
+    x, it, rel, st = H.pcg(b, rtol=RTOL, maxit=MAXIT)
+    t2 = time.perf_counter()
+    return dict(value=t2 - t1, unit="s", cores=1, kind="oracle",
+                sample="full 160^3 FP64 solve to rtol 1e-6 (%d iterations, single thread); "
+                       "oracle setup %.2f s not included" % (it, t1 - t0),
+                iterations=it, relres=rel, setup_s=t1 - t0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU's share of the problem; runs on %d GPUs are not "
+              "supported by this build (use --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2303_02352_amd as amd
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log("generating 160^3 Poisson")
+    A = W.poisson7(N_EDGE)
+    xs, b = W.manufactured_rhs(A, SEED)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rp, ci, va, bd = d(A.row_ptr), d(A.col), d(A.val), d(b)
+    stream = torch.cuda.Stream()          # default priority
+    torch.cuda.synchronize()
+
+    def one_step(precision=amd.AMG_PREC_DOUBLE):
+        with torch.cuda.stream(stream):
+            t0 = time.perf_counter()
+            H = amd.Hierarchy(rp, ci, va, precision=precision)
+            t1 = time.perf_counter()
+            x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st, it, rel = H.solve(bd, x, rtol=RTOL, maxit=MAXIT)
+            e1.record(stream)
+            e1.synchronize()
+            t2 = time.perf_counter()
+        return H, x, dict(status=st, iters=it, relres=rel, setup_s=t1 - t0,
+                          solve_s=e0.elapsed_time(e1) / 1e3, wall_solve_s=t2 - t1)
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        H, x, rec = one_step()
+        H.close()
+    torch.cuda.synchronize()
+    log("timed steps", args.steps)
+    recs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        H, x, rec = one_step()
+        recs.append(rec)
+        if _ < args.steps - 1:
+            H.close()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    last = recs[-1]
+    info = H.info()
+    xg = x.cpu().numpy()
+    true_rel = float(np.linalg.norm(b - A.scipy() @ xg) / np.linalg.norm(b))
+    solve_s = float(np.mean([r["solve_s"] for r in recs]))
+    setup_s = float(np.mean([r["setup_s"] for r in recs]))
+
+    # per-kernel timings on the fine level (library stream, HIP events)
+    kt = {}
+    for name, kid in (("spmv_dots", amd.KERNEL_SPMV), ("sweep", amd.KERNEL_SWEEP),
+                      ("restrict", amd.KERNEL_RESTRICT), ("prolong", amd.KERNEL_PROLONG),
+                      ("pcg_update", amd.KERNEL_UPDATE)):
+        ms, by = H.time_kernel(kid, 0, args.kernel_reps)
+        kt[name] = dict(avg_ms=ms, bytes=by, gbps=by / (ms * 1e-3) / 1e9)
+    log("kernels", json.dumps(kt))
+    sw = kt["sweep"]
+    traffic = measured_traffic("sweep_poisson160", sw["bytes"])
+    roofline = dict(bound="hbm", achieved=sw["gbps"], peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=sw["gbps"] / HBM_PEAK_GBPS, traffic=traffic,
+                    kernel="k_sweep<double> (fine-level l1-Jacobi sweep, 160^3)",
+                    bytes_per_launch=sw["bytes"], avg_launch_ms=sw["avg_ms"])
+    H.close()
+
+    forms = {}
+    if not args.no_forms:
+        log("mixed-precision form")
+        Hm, xm, rm = one_step(amd.AMG_PREC_MIXED)
+        Hm.close()
+        Hm, xm, rm = one_step(amd.AMG_PREC_MIXED)
+        xmh = xm.cpu().numpy()
+        forms["mixed"] = dict(solve_s=rm["solve_s"], setup_s=rm["setup_s"], iters=rm["iters"],
+                              relres=rm["relres"],
+                              true_relres=float(np.linalg.norm(b - A.scipy() @ xmh) / np.linalg.norm(b)),
+                              speedup_vs_fp64_solve=solve_s / rm["solve_s"],
+                              max_rel_diff_vs_fp64_solution=float(np.max(np.abs(xmh - xg)) / np.max(np.abs(xg))))
+        Hm.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(A, b)
+        log("cpu", json.dumps(cpu))
+
+    out = {
+        "metric": METRIC, "value": solve_s, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_total / args.steps * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D Poisson 7-point 160^3 (4,096,000 rows, 28,518,400 nnz, CSR "
+                               "FP64, int32 indices), b = A x*, x* ~ U[-1,1) seed 2",
+                   "rtol": RTOL, "aggr_steps": 2, "coarse_max": 100, "pre_post_sweeps": [4, 4],
+                   "coarsest": "dense FP64 Cholesky", "step": "amg_setup + amg_pcg_solve"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "detail": {"iterations": last["iters"], "relres": last["relres"], "true_relres": true_rel,
+                   "solve_s_each": [r["solve_s"] for r in recs],
+                   "setup_s": setup_s, "titer_ms": solve_s / max(1, last["iters"]) * 1e3,
+                   "levels": info["n"], "opc": info["opc"],
+                   "matching_rounds": info["matching_rounds"],
+                   "kernels_fine_level": kt, "forms": forms,
+                   "spmv_gbps": kt["spmv_dots"]["gbps"],
+                   "spmv_frac": kt["spmv_dots"]["gbps"] / HBM_PEAK_GBPS,
+                   "smoother_gbps": kt["sweep"]["gbps"],
+                   "smoother_frac": kt["sweep"]["gbps"] / HBM_PEAK_GBPS},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

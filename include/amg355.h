@@ -1,0 +1,187 @@
+/*
+ * amg355.h -- C ABI of the MI355X (gfx950) AMG-preconditioned flexible CG.
+ *
+ * Method: Bernaschi, Celestini, D'Ambra, Vella, "Multi-GPU aggregation-based
+ * AMG preconditioner for iterative linear solvers", arXiv 2303.02352.
+ *   - Sec. 3, Alg. 1: flexible (Notay) preconditioned conjugate gradient for
+ *     A x = b with A symmetric positive definite.
+ *   - Sec. 3.1, Alg. 2: V-cycle with l1-Jacobi smoothing, piecewise-constant
+ *     restriction / prolongation, direct solve at the coarsest level.
+ *   - Sec. 3.1, Alg. 3 and Sec. 4.1: coarsening by 1/2-approximate maximum
+ *     weight matching (Suitor), pairwise prolongators composed s times,
+ *     Galerkin products P^T A P.
+ *   - Sec. 5: stopping rule (relative l2 residual, iteration limit) and the
+ *     operator complexity reported by amg_info.
+ *
+ * All compute runs on the GPU in this library's HIP kernels.  Indices are
+ * int32, values IEEE binary64 (float copies for AMG_PREC_MIXED).
+ *
+ * Errors: every entry point returns an int status (AMG_OK = 0; AMG_NOT_CONVERGED
+ * = 1 is a warning; negative values are errors).  No exception, abort or
+ * longjmp crosses this boundary.  amg_last_error() returns a thread-local
+ * message for the last failure on the calling thread.
+ *
+ * Threading: a hierarchy may be used by one host thread at a time.  All work
+ * is ordered on the hierarchy's stream (amg_params.stream, NULL = the null
+ * stream); calls that return host-visible results synchronise that stream.
+ */
+#ifndef AMG355_H
+#define AMG355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- statuses */
+#define AMG_OK 0
+#define AMG_NOT_CONVERGED 1       /* maxit reached with relres > rtol (warning) */
+#define AMG_ERR_INVALID (-1)      /* bad argument or malformed / unsymmetric CSR */
+#define AMG_ERR_NOT_SPD (-2)      /* a_ii <= 0, Cholesky pivot <= 0, or rho <= 0 in PCG */
+#define AMG_ERR_NONFINITE (-3)    /* NaN or Inf in the input or produced by the iteration */
+#define AMG_ERR_NOMEM (-4)        /* device allocation failed */
+#define AMG_ERR_DEVICE (-5)       /* any other HIP runtime error */
+#define AMG_ERR_UNSUPPORTED (-6)  /* a parameter combination this build does not provide */
+
+/* coarse_solver */
+#define AMG_COARSE_CHOLESKY 0     /* dense FP64 Cholesky (coarsest n <= 1024, else Jacobi sweeps) */
+#define AMG_COARSE_JACOBI 1       /* coarse_sweeps l1-Jacobi sweeps (Sec. 5 setting) */
+/* smooth_vec */
+#define AMG_SMOOTH_ONES 0         /* w = 1 */
+#define AMG_SMOOTH_RELAX 1        /* smooth_sweeps l1-Jacobi sweeps on A w = 0 from w = 1, w /= max|w| */
+#define AMG_SMOOTH_GIVEN 2        /* w supplied in amg_params.smooth_vector (e.g. a learned surrogate) */
+/* precision */
+#define AMG_PREC_DOUBLE 0         /* everything in binary64 */
+#define AMG_PREC_MIXED 1          /* V-cycle below the coarsest level in binary32; PCG,
+                                     residuals, dots and the coarsest solve in binary64 */
+
+/* Square sparse matrix in CSR form.
+ *   row_ptr: n+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx: nnz entries, strictly ascending within each row, in [0, n),
+ *            the diagonal present in every row
+ *   val:     nnz entries; A must be bitwise symmetric (a_ij == a_ji) with
+ *            a_ii > 0 (s.p.d. is assumed, Sec. 1 and 3; violations found
+ *            later surface as AMG_ERR_NOT_SPD)
+ *   on_device: 1 if the three arrays are device pointers, 0 if host pointers.
+ * The arrays are only read, during amg_setup; the caller keeps ownership. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+  int32_t on_device;
+} amg_csr;
+
+/* Method parameters.  amg_params_default() fills:
+ *   aggr_steps 2 (aggregates of at most 4), max_levels 40, coarse_max 100,
+ *   coarse_solver CHOLESKY, coarse_sweeps 20, pre/post sweeps 4/4,
+ *   smooth_vec ONES, smooth_sweeps 20, precond 1, precision DOUBLE,
+ *   smooth_vector NULL, stream NULL.
+ * The paper's own runs (Sec. 5, Appendix A) use aggr_steps 3, coarse_max
+ * 40*nd, coarse_solver JACOBI with 20 sweeps. */
+typedef struct {
+  int32_t aggr_steps;      /* s >= 1: pairwise matching steps composed per level (Sec. 3.1) */
+  int32_t max_levels;      /* >= 1, fine level included */
+  int32_t coarse_max;      /* >= 1: stop coarsening when n <= coarse_max (Alg. 3) */
+  int32_t coarse_solver;   /* AMG_COARSE_* */
+  int32_t coarse_sweeps;   /* >= 1 */
+  int32_t pre_sweeps;      /* >= 0 */
+  int32_t post_sweeps;     /* >= 0 */
+  int32_t smooth_vec;      /* AMG_SMOOTH_* */
+  int32_t smooth_sweeps;   /* >= 0 */
+  int32_t precond;         /* 1: AMG V-cycle; 0: B = I, plain CG (Appendix A) */
+  int32_t precision;       /* AMG_PREC_* */
+  const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
+  void *stream;            /* hipStream_t on which all work is ordered; NULL = null stream */
+} amg_params;
+
+typedef struct amg_hierarchy amg_hierarchy;   /* opaque, owned by the library */
+
+#define AMG_MAX_LEVELS 64
+typedef struct {
+  int32_t levels;
+  int32_t n[AMG_MAX_LEVELS];
+  int64_t nnz[AMG_MAX_LEVELS];
+  double opc;                   /* sum_k nnz(A_k) / nnz(A_0)  (Sec. 5) */
+  int32_t coarse_dense;         /* 1 if the coarsest level is solved by Cholesky */
+  int32_t matching_rounds;      /* total GPU matching rounds over all pairwise steps */
+  double setup_ms;              /* wall time of amg_setup (stream-synchronised) */
+  double setup_match_ms;        /* part spent in weights + matching + aggregation */
+  double setup_rap_ms;          /* part spent in Galerkin products */
+  int64_t device_bytes;         /* device memory held by the hierarchy */
+} amg_info_t;
+
+/* Fill *p with the defaults above.  Returns AMG_OK or AMG_ERR_INVALID (p NULL). */
+int amg_params_default(amg_params *p);
+
+/* Build the hierarchy (Alg. 3 with s-step composition, Sec. 3.1/4.1) on the
+ * GPU: validate A, copy it to library-owned device memory, compute the smooth
+ * vector, then per level match / aggregate / form P / Galerkin product, and
+ * factor the coarsest matrix.  The result is deterministic: aggregate maps,
+ * coarse patterns and coarse values do not depend on thread scheduling.
+ * On success *h_out owns all device memory; release it with amg_destroy.
+ * Errors: INVALID (NULL args, bad parameters, malformed or unsymmetric CSR),
+ * NOT_SPD (a_ii <= 0 or a non-positive Cholesky pivot), NONFINITE, NOMEM,
+ * DEVICE.  On error *h_out is NULL. */
+int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out);
+
+/* Solve A x = b with flexible PCG (Alg. 1) preconditioned by one V-cycle
+ * (Alg. 2) per iteration.  b, x: device pointers to n doubles; x holds the
+ * initial guess on entry and the solution on exit; b is not modified.
+ * Stops when ||r_i||_2 <= rtol ||r_0||_2 (recurrence residual, tested after
+ * every update of r) or after maxit iterations (Sec. 5).  *iters_out = number
+ * of preconditioner applications (0 when r_0 = 0); *relres_out = ||r||/||r_0||.
+ * Returns OK, NOT_CONVERGED, NOT_SPD (rho <= 0), NONFINITE, INVALID (rtol <= 0,
+ * maxit < 1, NULL), DEVICE.  Synchronises the hierarchy's stream. */
+int amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                  int32_t *iters_out, double *relres_out);
+
+/* Release everything held by h.  NULL-safe.  Synchronises the stream first. */
+void amg_destroy(amg_hierarchy *h);
+
+/* Static description of a status code. */
+const char *amg_strerror(int code);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *amg_last_error(void);
+
+/* Sizes, operator complexity and setup timings. */
+int amg_info(const amg_hierarchy *h, amg_info_t *out);
+
+/* Introspection for parity tests: copy level k to HOST buffers (any may be
+ * NULL).  row_ptr n_k+1, col_idx/val nnz_k (canonical CSR, columns
+ * ascending), dinv n_k (1 / l1 row sum), w n_k (smooth vector), and for
+ * k < levels-1 agg n_k (row of level k+1 holding fine row i) and pval n_k
+ * (the one nonzero of row i of the composite prolongator).  Synchronises. */
+int amg_export_level(const amg_hierarchy *h, int32_t k, int32_t *row_ptr, int32_t *col_idx,
+                     double *val, double *dinv, double *w, int32_t *agg, double *pval);
+
+/* z = B r: one V-cycle of Alg. 2 (B = I when precond = 0).  r, z: device
+ * pointers to n_0 doubles, may not alias.  Enqueued on the stream; returns
+ * without synchronising. */
+int amg_vcycle(amg_hierarchy *h, const double *r, double *z);
+
+/* y = A_k x on level k with the solve-phase SpMV kernel.  Device pointers to
+ * n_k doubles, may not alias.  Enqueued on the stream, not synchronised. */
+int amg_spmv(amg_hierarchy *h, int32_t k, const double *x, double *y);
+
+/* One l1-Jacobi sweep on level k with the solve-phase kernel:
+ * xn = x + (r - A_k x) / M_k.  Device pointers, xn must not alias x or r. */
+int amg_sweep(amg_hierarchy *h, int32_t k, const double *r, const double *x, double *xn);
+
+/* Timing of one solve-phase kernel in its solve launch configuration:
+ * kernel 0 = SpMV (+3 dots) on level k, 1 = l1-Jacobi sweep on level k,
+ * 2 = residual + restriction from level k, 3 = prolongation into level k,
+ * 4 = the fused PCG vector update (level 0 only).  It is launched `reps`
+ * times on the hierarchy's stream between two HIP events on that stream,
+ * operating on the hierarchy's own work vectors; *avg_ms is the mean
+ * duration and *bytes the algorithmic bytes one launch moves.  Synchronises. */
+int amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t k, int32_t reps, double *avg_ms,
+                    double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMG355_H */

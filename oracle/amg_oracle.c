@@ -36,7 +36,7 @@
 #define ORC_NOMEM (-4)
 
 #define ORC_MAXLEV 64
-#define ORC_DENSE_MAX 4096   /* largest coarsest level solved by dense Cholesky */
+#define ORC_DENSE_MAX 1024   /* largest coarsest level solved by dense Cholesky */
 #define ORC_STAGNATION 0.95  /* stop coarsening when n_{k+1} > 0.95 n_k */
 
 typedef struct {
@@ -512,9 +512,14 @@ static int smooth_vector(const orc_params *p, const csr_t *A, const double *dinv
     sweep(A, dinv, z, w, t);
     memcpy(w, t, sizeof(double) * (size_t)n);
   }
+  /* a non-finite or all-zero result falls back to the constant vector */
   double mx = 0.0;
-  for (int32_t i = 0; i < n; i++) if (fabs(w[i]) > mx) mx = fabs(w[i]);
-  if (mx > 0.0 && isfinite(mx)) {
+  int finite = 1;
+  for (int32_t i = 0; i < n; i++) {
+    if (!isfinite(w[i])) finite = 0;
+    else if (fabs(w[i]) > mx) mx = fabs(w[i]);
+  }
+  if (finite && mx > 0.0) {
     for (int32_t i = 0; i < n; i++) w[i] = w[i] / mx;
   } else {
     for (int32_t i = 0; i < n; i++) w[i] = 1.0;

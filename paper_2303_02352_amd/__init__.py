@@ -1,0 +1,213 @@
+"""Python binding of libamg355 (MI355X AMG-preconditioned flexible CG).
+
+Argument marshalling only: every step of setup and solve runs in the HIP
+kernels of ``libamg355.so`` behind the C ABI of ``include/amg355.h``.  The
+functions keep the C names (``amg_setup``, ``amg_pcg_solve``, ...); the
+``Hierarchy`` class is a convenience wrapper over them.  torch tensors supply
+device memory and the stream; there is no CPU fallback, and importing the
+package raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamg355.so")
+
+AMG_OK, AMG_NOT_CONVERGED = 0, 1
+AMG_ERR_INVALID, AMG_ERR_NOT_SPD, AMG_ERR_NONFINITE = -1, -2, -3
+AMG_ERR_NOMEM, AMG_ERR_DEVICE, AMG_ERR_UNSUPPORTED = -4, -5, -6
+AMG_COARSE_CHOLESKY, AMG_COARSE_JACOBI = 0, 1
+AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN = 0, 1, 2
+AMG_PREC_DOUBLE, AMG_PREC_MIXED = 0, 1
+AMG_MAX_LEVELS = 64
+KERNEL_SPMV, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_UPDATE = 0, 1, 2, 3, 4
+
+
+class amg_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("on_device", C.c_int32)]
+
+
+class amg_params(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in (
+        "aggr_steps", "max_levels", "coarse_max", "coarse_solver", "coarse_sweeps",
+        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond", "precision")] + [
+        ("smooth_vector", C.c_void_p), ("stream", C.c_void_p)]
+
+
+class amg_info_t(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("n", C.c_int32 * AMG_MAX_LEVELS),
+                ("nnz", C.c_int64 * AMG_MAX_LEVELS), ("opc", C.c_double),
+                ("coarse_dense", C.c_int32), ("matching_rounds", C.c_int32),
+                ("setup_ms", C.c_double), ("setup_match_ms", C.c_double),
+                ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64)]
+
+
+EXPORTS = {
+    "amg_params_default": (C.c_int, [C.POINTER(amg_params)]),
+    "amg_setup": (C.c_int, [C.POINTER(amg_csr), C.POINTER(amg_params), C.POINTER(C.c_void_p)]),
+    "amg_pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "amg_destroy": (None, [C.c_void_p]),
+    "amg_strerror": (C.c_char_p, [C.c_int]),
+    "amg_last_error": (C.c_char_p, []),
+    "amg_info": (C.c_int, [C.c_void_p, C.POINTER(amg_info_t)]),
+    "amg_export_level": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7),
+    "amg_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amg_spmv": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "amg_sweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amg_time_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libamg355.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libamg355.so is not built: run `python -m paper_2303_02352_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class AMGError(RuntimeError):
+    def __init__(self, code, where):
+        L = load()
+        msg = L.amg_last_error().decode() or L.amg_strerror(code).decode()
+        super().__init__("%s: status %d (%s)" % (where, code, msg))
+        self.code = code
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor / numpy array (contiguous)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        assert a.is_contiguous()
+        return C.c_void_p(a.data_ptr())
+    assert a.flags["C_CONTIGUOUS"]
+    return C.c_void_p(a.ctypes.data)
+
+
+def _on_device(a):
+    return 1 if (hasattr(a, "is_cuda") and a.is_cuda) else 0
+
+
+def default_params(**overrides) -> amg_params:
+    p = amg_params()
+    load().amg_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Hierarchy:
+    """AMG hierarchy built by ``amg_setup``.
+
+    ``row_ptr`` (int32), ``col`` (int32), ``val`` (float64): torch CUDA
+    tensors or host numpy arrays.  Keyword arguments override fields of
+    ``amg_params`` (e.g. ``aggr_steps=3``, ``precision=AMG_PREC_MIXED``);
+    ``smooth_vector`` is an array of n doubles in the CSR's memory space.
+    """
+
+    def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, **params):
+        L = load()
+        self.n = int(row_ptr.shape[0]) - 1
+        self.nnz = int(col.shape[0])
+        A = amg_csr(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _on_device(val))
+        p = default_params(**params)
+        if smooth_vector is not None:
+            p.smooth_vec = AMG_SMOOTH_GIVEN
+            p.smooth_vector = _ptr(smooth_vector)
+        p.stream = stream if stream is not None else (current_stream() if A.on_device else None)
+        self.params = p
+        h = C.c_void_p()
+        st = L.amg_setup(C.byref(A), C.byref(p), C.byref(h))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_setup")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().amg_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x, rtol=1e-6, maxit=1000, check=True):
+        """Flexible PCG; x (device) holds x0 on entry.  Returns (status, iters, relres)."""
+        it, rel = C.c_int32(), C.c_double()
+        st = load().amg_pcg_solve(self.h, _ptr(b), _ptr(x), float(rtol), int(maxit),
+                                  C.byref(it), C.byref(rel))
+        if check and st < 0:
+            raise AMGError(st, "amg_pcg_solve")
+        return st, it.value, rel.value
+
+    def info(self) -> dict:
+        inf = amg_info_t()
+        st = load().amg_info(self.h, C.byref(inf))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_info")
+        L = inf.levels
+        return dict(levels=L, n=list(inf.n[:L]), nnz=list(inf.nnz[:L]), opc=inf.opc,
+                    coarse_dense=bool(inf.coarse_dense), matching_rounds=inf.matching_rounds,
+                    setup_ms=inf.setup_ms, setup_match_ms=inf.setup_match_ms,
+                    setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes)
+
+    def export_level(self, k) -> dict:
+        inf = self.info()
+        n, nnz = inf["n"][k], inf["nnz"][k]
+        out = dict(row_ptr=np.empty(n + 1, np.int32), col=np.empty(nnz, np.int32),
+                   val=np.empty(nnz), dinv=np.empty(n), w=np.empty(n),
+                   agg=np.full(n, -1, np.int32), pval=np.zeros(n))
+        st = load().amg_export_level(self.h, k, *[_ptr(out[f]) for f in
+                                                  ("row_ptr", "col", "val", "dinv", "w", "agg", "pval")])
+        if st != AMG_OK:
+            raise AMGError(st, "amg_export_level")
+        if k == inf["levels"] - 1:
+            out["agg"] = out["pval"] = None
+        out["n"], out["nnz"] = n, nnz
+        return out
+
+    def vcycle(self, r, z):
+        st = load().amg_vcycle(self.h, _ptr(r), _ptr(z))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_vcycle")
+
+    def spmv(self, k, x, y):
+        st = load().amg_spmv(self.h, int(k), _ptr(x), _ptr(y))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_spmv")
+
+    def sweep(self, k, r, x, xn):
+        st = load().amg_sweep(self.h, int(k), _ptr(r), _ptr(x), _ptr(xn))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_sweep")
+
+    def time_kernel(self, kernel, k=0, reps=20):
+        ms, by = C.c_double(), C.c_double()
+        st = load().amg_time_kernel(self.h, int(kernel), int(k), int(reps), C.byref(ms), C.byref(by))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_time_kernel")
+        return ms.value, by.value

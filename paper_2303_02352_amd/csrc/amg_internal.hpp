@@ -1,0 +1,192 @@
+// Internal definitions shared by the HIP translation units of libamg355.
+// Not part of the public ABI (include/amg355.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "amg355.h"
+
+namespace amg {
+
+// ------------------------------------------------------------------ errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+
+#define AMG_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      ::amg::fail(e_ == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE,             \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                     \
+  } while (0)
+
+#define AMG_LAUNCH_CHECK() AMG_HIP(hipGetLastError())
+
+// --------------------------------------------------------- device buffers
+
+// Owning device array.  Moves only.
+template <class T>
+struct dvec {
+  T *p = nullptr;
+  size_t n = 0;
+  dvec() = default;
+  explicit dvec(size_t count) { alloc(count); }
+  dvec(const dvec &) = delete;
+  dvec &operator=(const dvec &) = delete;
+  dvec(dvec &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  dvec &operator=(dvec &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~dvec() { release(); }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) AMG_HIP(hipMalloc(reinterpret_cast<void **>(&p), sizeof(T) * count));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return sizeof(T) * n; }
+  T *get() const { return p; }
+};
+
+// ---------------------------------------------------------------- layouts
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kSlice = 64;         // SELL slice height = one wavefront of rows
+constexpr int kBlock = 256;        // rows per workgroup in row-parallel kernels
+constexpr int kXcd = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kMaxDotBlocks = 2048;
+constexpr int kDenseMax = 1024;    // largest coarsest level factored densely
+constexpr double kStagnation = 0.95;
+
+// Canonical CSR (setup, export, next-level construction).
+struct DevCSR {
+  int n = 0;
+  int64_t nnz = 0;
+  dvec<int> rp, ci;
+  dvec<double> v;
+};
+
+// Sliced ELLPACK with slice height 64 (one wavefront): row r of slice s keeps
+// its k-th stored entry at slot sptr[s] + k*64 + (r % 64); slots past the end
+// of a row hold col = r, val = 0.  Entry order within a row = CSR order.
+struct Sell {
+  int n = 0;
+  int nslices = 0;
+  int64_t nslots = 0;
+  dvec<int> sptr;     // nslices + 1 slot offsets (multiples of 64)
+  dvec<int> col;
+  dvec<double> val;
+  dvec<float> valf;   // binary32 copy for the mixed-precision V-cycle
+};
+
+struct Level {
+  DevCSR A;
+  Sell S;
+  dvec<double> dinv, w;
+  dvec<float> dinvf;
+  // transfer to level k+1 (empty on the coarsest level)
+  int nc = 0;
+  dvec<int> agg;          // n: coarse row of fine row i
+  dvec<double> pval;      // n: value of P(i, agg[i])
+  dvec<float> pvalf;
+  dvec<int> mptr, mem;    // CSR of P^T: members of each aggregate, ascending
+  // V-cycle work vectors
+  dvec<double> r, x, t;
+  dvec<float> rf, xf, tf;
+};
+
+struct Scalars {        // PCG state living in device memory
+  double rho, c, a, rr, nr0, thr, alpha, beta, gamma;
+  int it, done, status, pad;
+};
+
+struct Timing {
+  double setup_ms = 0, match_ms = 0, rap_ms = 0;
+  int rounds = 0;
+};
+
+}  // namespace amg
+
+struct amg_hierarchy {
+  amg_params p{};
+  hipStream_t stream = nullptr;
+  int own_stream = 0;
+  std::vector<amg::Level> L;
+  int coarse_dense = 0;
+  amg::dvec<double> Lc, LcT;   // coarsest Cholesky factor, column-major and row-major
+  // PCG vectors
+  amg::dvec<double> u, r, w, v, d, q;
+  amg::dvec<double> partials;  // kMaxDotBlocks * 3
+  amg::dvec<unsigned> counter; // last-block detection
+  amg::dvec<amg::Scalars> sc;
+  amg::Scalars *sc_host = nullptr;   // pinned mirror
+  amg::Timing tm;
+  // hipGraph of one PCG iteration (V-cycle + SpMV/dots + update)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int use_graph = 1;
+};
+
+namespace amg {
+
+// ------------------------------------------------------- setup interface
+void build_hierarchy(amg_hierarchy *h, const amg_csr *A);
+void coarse_factor(amg_hierarchy *h);
+
+// -------------------------------------------------------- solve interface
+void alloc_solve_buffers(amg_hierarchy *h);
+void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z);
+void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y);
+void enqueue_sweep(amg_hierarchy *h, int k, const double *r, const double *x, double *xn);
+int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,
+              double *relres);
+void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, double *bytes);
+void destroy_graph(amg_hierarchy *h);
+
+// ----------------------------------------------------------- small helpers
+inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+int64_t device_bytes(const amg_hierarchy *h);
+
+}  // namespace amg
+
+// ------------------------------------------------------ device-side helpers
+#ifdef __HIPCC__
+namespace amg {
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b -> XCD
+// b % 8).  Remap so that each XCD walks one contiguous range of logical
+// blocks: neighbouring rows then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  int per = nb / kXcd, rem = nb % kXcd;
+  int x = b % kXcd, j = b / kXcd;
+  return x * per + (x < rem ? x : rem) + j;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Deterministic sum over a 64-lane wavefront (fixed xor-butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+  return v;
+}
+}  // namespace amg
+#endif

@@ -1,0 +1,251 @@
+// C ABI entry points (include/amg355.h).  Every function catches the
+// library's internal errors and returns a status code; nothing is thrown
+// across the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "amg_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const amg::Error &e) {
+    return set_error(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    return set_error(AMG_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(AMG_ERR_DEVICE, "unexpected internal error");
+  }
+}
+
+int check_params(const amg_params *p) {
+  if (p->aggr_steps < 1 || p->max_levels < 1 || p->coarse_max < 1 || p->coarse_sweeps < 1 ||
+      p->pre_sweeps < 0 || p->post_sweeps < 0 || p->smooth_sweeps < 0)
+    return set_error(AMG_ERR_INVALID, "parameter out of range");
+  if (p->coarse_solver != AMG_COARSE_CHOLESKY && p->coarse_solver != AMG_COARSE_JACOBI)
+    return set_error(AMG_ERR_INVALID, "unknown coarse_solver");
+  if (p->smooth_vec < AMG_SMOOTH_ONES || p->smooth_vec > AMG_SMOOTH_GIVEN)
+    return set_error(AMG_ERR_INVALID, "unknown smooth_vec");
+  if (p->smooth_vec == AMG_SMOOTH_GIVEN && !p->smooth_vector)
+    return set_error(AMG_ERR_INVALID, "smooth_vec = GIVEN needs smooth_vector");
+  if (p->precision != AMG_PREC_DOUBLE && p->precision != AMG_PREC_MIXED)
+    return set_error(AMG_ERR_INVALID, "unknown precision");
+  if (p->precond != 0 && p->precond != 1) return set_error(AMG_ERR_INVALID, "precond must be 0 or 1");
+  return AMG_OK;
+}
+}  // namespace
+
+namespace amg {
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+int64_t device_bytes(const amg_hierarchy *h) {
+  int64_t b = 0;
+  for (const Level &L : h->L) {
+    b += L.A.rp.bytes() + L.A.ci.bytes() + L.A.v.bytes();
+    b += L.S.sptr.bytes() + L.S.col.bytes() + L.S.val.bytes() + L.S.valf.bytes();
+    b += L.dinv.bytes() + L.w.bytes() + L.dinvf.bytes() + L.agg.bytes() + L.pval.bytes();
+    b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
+    b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();
+  }
+  b += h->Lc.bytes() + h->LcT.bytes();
+  b += h->u.bytes() + h->r.bytes() + h->w.bytes() + h->v.bytes() + h->d.bytes() + h->q.bytes();
+  b += h->partials.bytes() + h->counter.bytes() + h->sc.bytes();
+  return b;
+}
+}  // namespace amg
+
+extern "C" {
+
+int amg_params_default(amg_params *p) {
+  if (!p) return set_error(AMG_ERR_INVALID, "NULL params");
+  std::memset(p, 0, sizeof(*p));
+  p->aggr_steps = 2;
+  p->max_levels = 40;
+  p->coarse_max = 100;
+  p->coarse_solver = AMG_COARSE_CHOLESKY;
+  p->coarse_sweeps = 20;
+  p->pre_sweeps = 4;
+  p->post_sweeps = 4;
+  p->smooth_vec = AMG_SMOOTH_ONES;
+  p->smooth_sweeps = 20;
+  p->precond = 1;
+  p->precision = AMG_PREC_DOUBLE;
+  p->smooth_vector = nullptr;
+  p->stream = nullptr;
+  return AMG_OK;
+}
+
+int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
+  if (h_out) *h_out = nullptr;
+  if (!A || !p || !h_out) return set_error(AMG_ERR_INVALID, "NULL argument");
+  if (A->n <= 0 || A->nnz < A->n || A->nnz >= (int64_t(1) << 31) || !A->row_ptr || !A->col_idx ||
+      !A->val)
+    return set_error(AMG_ERR_INVALID, "bad CSR header (n, nnz or NULL array)");
+  int st = check_params(p);
+  if (st != AMG_OK) return st;
+  amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
+  if (!h) return set_error(AMG_ERR_NOMEM, "host allocation failed");
+  h->p = *p;
+  if (p->stream) {
+    h->stream = static_cast<hipStream_t>(p->stream);
+  } else {
+    // The null stream cannot be captured into a graph: work goes to a
+    // library-owned blocking stream, which stays ordered with null-stream work.
+    if (hipStreamCreate(&h->stream) != hipSuccess) {
+      delete h;
+      return set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    h->own_stream = 1;
+  }
+  st = guarded([&] {
+    amg::build_hierarchy(h, A);
+    return AMG_OK;
+  });
+  h->p.smooth_vector = nullptr;
+  if (st != AMG_OK) {
+    std::string msg = g_last_error;
+    amg_destroy(h);
+    g_last_error = msg;
+    return st;
+  }
+  *h_out = h;
+  return AMG_OK;
+}
+
+int amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                  int32_t *iters_out, double *relres_out) {
+  if (!h || !b || !x || !iters_out || !relres_out) return set_error(AMG_ERR_INVALID, "NULL argument");
+  if (!(rtol > 0.0) || !std::isfinite(rtol) || maxit < 1)
+    return set_error(AMG_ERR_INVALID, "rtol must be > 0 and maxit >= 1");
+  return guarded([&] {
+    int it = 0;
+    double rel = 0.0;
+    int st = amg::pcg_solve(h, b, x, rtol, maxit, &it, &rel);
+    *iters_out = it;
+    *relres_out = rel;
+    if (st == AMG_ERR_NOT_SPD) g_last_error = "PCG breakdown: rho <= 0 (A or B not s.p.d.)";
+    if (st == AMG_ERR_NONFINITE) g_last_error = "non-finite value in the iteration";
+    return st;
+  });
+}
+
+void amg_destroy(amg_hierarchy *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  amg::destroy_graph(h);
+  if (h->sc_host) (void)hipHostFree(h->sc_host);
+  h->sc_host = nullptr;
+  hipStream_t s = h->stream;
+  const int own = h->own_stream;
+  delete h;   // frees all device buffers
+  if (own) (void)hipStreamDestroy(s);
+}
+
+const char *amg_strerror(int code) {
+  switch (code) {
+    case AMG_OK: return "ok";
+    case AMG_NOT_CONVERGED: return "not converged within maxit";
+    case AMG_ERR_INVALID: return "invalid argument";
+    case AMG_ERR_NOT_SPD: return "matrix or preconditioner not symmetric positive definite";
+    case AMG_ERR_NONFINITE: return "non-finite value";
+    case AMG_ERR_NOMEM: return "out of memory";
+    case AMG_ERR_DEVICE: return "HIP device error";
+    case AMG_ERR_UNSUPPORTED: return "unsupported parameter combination";
+    default: return "unknown status";
+  }
+}
+
+const char *amg_last_error(void) { return g_last_error.c_str(); }
+
+int amg_info(const amg_hierarchy *h, amg_info_t *out) {
+  if (!h || !out) return set_error(AMG_ERR_INVALID, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->levels = static_cast<int32_t>(h->L.size());
+  double tot = 0.0;
+  for (size_t k = 0; k < h->L.size(); ++k) {
+    out->n[k] = h->L[k].A.n;
+    out->nnz[k] = h->L[k].A.nnz;
+    tot += static_cast<double>(h->L[k].A.nnz);
+  }
+  out->opc = tot / static_cast<double>(h->L[0].A.nnz);
+  out->coarse_dense = h->coarse_dense;
+  out->matching_rounds = h->tm.rounds;
+  out->setup_ms = h->tm.setup_ms;
+  out->setup_match_ms = h->tm.match_ms;
+  out->setup_rap_ms = h->tm.rap_ms;
+  out->device_bytes = amg::device_bytes(h);
+  return AMG_OK;
+}
+
+int amg_export_level(const amg_hierarchy *h, int32_t k, int32_t *row_ptr, int32_t *col_idx,
+                     double *val, double *dinv, double *w, int32_t *agg, double *pval) {
+  if (!h) return set_error(AMG_ERR_INVALID, "NULL hierarchy");
+  if (k < 0 || k >= static_cast<int32_t>(h->L.size())) return set_error(AMG_ERR_INVALID, "level out of range");
+  return guarded([&] {
+    const amg::Level &L = h->L[k];
+    const auto d2h = hipMemcpyDeviceToHost;
+    hipStream_t s = h->stream;
+    if (row_ptr) AMG_HIP(hipMemcpyAsync(row_ptr, L.A.rp.p, sizeof(int) * (L.A.n + 1), d2h, s));
+    if (col_idx) AMG_HIP(hipMemcpyAsync(col_idx, L.A.ci.p, sizeof(int) * L.A.nnz, d2h, s));
+    if (val) AMG_HIP(hipMemcpyAsync(val, L.A.v.p, sizeof(double) * L.A.nnz, d2h, s));
+    if (dinv) AMG_HIP(hipMemcpyAsync(dinv, L.dinv.p, sizeof(double) * L.A.n, d2h, s));
+    if (w && L.w.p) AMG_HIP(hipMemcpyAsync(w, L.w.p, sizeof(double) * L.A.n, d2h, s));
+    if (k + 1 < static_cast<int32_t>(h->L.size())) {
+      if (agg) AMG_HIP(hipMemcpyAsync(agg, L.agg.p, sizeof(int) * L.A.n, d2h, s));
+      if (pval) AMG_HIP(hipMemcpyAsync(pval, L.pval.p, sizeof(double) * L.A.n, d2h, s));
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    return AMG_OK;
+  });
+}
+
+int amg_vcycle(amg_hierarchy *h, const double *r, double *z) {
+  if (!h || !r || !z || r == z) return set_error(AMG_ERR_INVALID, "bad argument");
+  return guarded([&] {
+    amg::enqueue_vcycle(h, r, z);
+    return AMG_OK;
+  });
+}
+
+int amg_spmv(amg_hierarchy *h, int32_t k, const double *x, double *y) {
+  if (!h || !x || !y || x == y) return set_error(AMG_ERR_INVALID, "bad argument");
+  if (k < 0 || k >= static_cast<int32_t>(h->L.size())) return set_error(AMG_ERR_INVALID, "level out of range");
+  return guarded([&] {
+    amg::enqueue_spmv(h, k, x, y);
+    return AMG_OK;
+  });
+}
+
+int amg_sweep(amg_hierarchy *h, int32_t k, const double *r, const double *x, double *xn) {
+  if (!h || !r || !x || !xn || xn == x || xn == r) return set_error(AMG_ERR_INVALID, "bad argument");
+  if (k < 0 || k >= static_cast<int32_t>(h->L.size())) return set_error(AMG_ERR_INVALID, "level out of range");
+  return guarded([&] {
+    amg::enqueue_sweep(h, k, r, x, xn);
+    return AMG_OK;
+  });
+}
+
+int amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t k, int32_t reps, double *avg_ms,
+                    double *bytes) {
+  if (!h || !avg_ms || !bytes || reps < 1) return set_error(AMG_ERR_INVALID, "bad argument");
+  return guarded([&] {
+    amg::time_kernel(h, kernel, k, reps, avg_ms, bytes);
+    return AMG_OK;
+  });
+}
+
+}  // extern "C"

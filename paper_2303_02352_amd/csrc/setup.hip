@@ -1,0 +1,799 @@
+// Hierarchy construction on the GPU (Alg. 3 with the s-step composition of
+// Sec. 3.1; matching of Sec. 4.1).  Every kernel is deterministic: results do
+// not depend on workgroup scheduling, so aggregate maps, coarse patterns and
+// coarse values are reproducible bit for bit.  Floating-point contraction is
+// disabled for this library (-ffp-contract=off): each multiply and add rounds
+// on its own, in the orders stated at each kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+
+namespace {
+
+constexpr int kFree = -2;    // matching state: not yet decided
+constexpr int kSingle = -1;  // no partner (also the exported value)
+
+inline dim3 grid_for(int64_t n, int block = kBlock) {
+  return dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + block - 1) / block)));
+}
+
+// ------------------------------------------------------------------- scan
+// Exclusive prefix sum of int32 counts; out has n+1 entries, out[n] = total.
+__global__ void k_scan_tiles(const int *in, int *out, int *tile_sum, int n) {
+  constexpr int kItems = 4, kTile = kBlock * kItems;
+  __shared__ int wsum[kBlock / kWave];
+  const int base = blockIdx.x * kTile + threadIdx.x * kItems;
+  int v[kItems], local = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    local += v[j];
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  int incl = local;
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += t;
+  }
+  if (lane == kWave - 1) wsum[wid] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int q = 0; q < wid; ++q) woff += wsum[q];
+  int run = woff + incl - local;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == kBlock - 1) tile_sum[blockIdx.x] = woff + incl;
+}
+
+__global__ void k_scan_add(int *out, const int *tile_off, int n) {
+  constexpr int kTile = kBlock * 4;
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] += tile_off[i / kTile];
+}
+
+__global__ void k_set_total(int *out, int n, const int *tile_off, const int *tile_sum, int ntiles) {
+  out[n] = tile_off[ntiles - 1] + tile_sum[ntiles - 1];
+}
+
+void exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
+  constexpr int kTile = kBlock * 4;
+  const int ntiles = std::max(1, ceil_div(n, kTile));
+  dvec<int> tsum(ntiles), toff(ntiles + 1);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, in, out, tsum.p, n);
+  AMG_LAUNCH_CHECK();
+  if (ntiles > 1) {
+    exclusive_scan(tsum.p, toff.p, ntiles, s);
+    hipLaunchKernelGGL(k_scan_add, grid_for(n), dim3(kBlock), 0, s, out, toff.p, n);
+    AMG_LAUNCH_CHECK();
+  } else {
+    AMG_HIP(hipMemsetAsync(toff.p, 0, sizeof(int), s));
+  }
+  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, toff.p, tsum.p, ntiles);
+  AMG_LAUNCH_CHECK();
+  AMG_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
+}
+
+int read_int(const int *dptr, hipStream_t s) {
+  int v = 0;
+  AMG_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// ------------------------------------------------------------- validation
+// flags[0]: malformed structure, flags[1]: a_ii <= 0 or missing diagonal,
+// flags[2]: non-finite value, flags[3]: not bitwise symmetric.
+__global__ void k_validate_rows(int n, int64_t nnz, const int *rp, const int *ci, const double *v,
+                                int *flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i == 0 && rp[0] != 0) atomicOr(&flags[0], 1);
+  if (i == n - 1 && static_cast<int64_t>(rp[n]) != nnz) atomicOr(&flags[0], 1);
+  const int lo = rp[i], hi = rp[i + 1];
+  if (lo < 0 || hi < lo || static_cast<int64_t>(hi) > nnz) { atomicOr(&flags[0], 1); return; }
+  bool diag = false;
+  for (int k = lo; k < hi; ++k) {
+    const int j = ci[k];
+    if (j < 0 || j >= n || (k > lo && j <= ci[k - 1])) { atomicOr(&flags[0], 1); return; }
+    const double a = v[k];
+    if (!isfinite(a)) atomicOr(&flags[2], 1);
+    if (j == i) {
+      diag = true;
+      if (!(a > 0.0)) atomicOr(&flags[1], 1);
+    }
+  }
+  if (!diag) atomicOr(&flags[1], 1);
+}
+
+// Run only after k_validate_rows found a well-formed structure.
+__global__ void k_validate_sym(int n, const int *rp, const int *ci, const double *v, int *flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    int lo = rp[j], hi = rp[j + 1] - 1, pos = -1;
+    while (lo <= hi) {
+      int mid = (lo + hi) >> 1;
+      int c = ci[mid];
+      if (c == i) { pos = mid; break; }
+      if (c < i) lo = mid + 1; else hi = mid - 1;
+    }
+    if (pos < 0 || __double_as_longlong(v[pos]) != __double_as_longlong(v[k])) {
+      atomicOr(&flags[3], 1);
+      return;
+    }
+  }
+}
+
+// ------------------------------------------------- diagonals and smoothing
+__global__ void k_diag(int n, const int *rp, const int *ci, const double *v, double *d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == i) a = v[k];
+  d[i] = a;
+}
+
+// l1-Jacobi (Sec. 3.1): M_ii = sum_j |a_ij| folded in CSR order; dinv = 1/M_ii.
+__global__ void k_l1_dinv(int n, const int *rp, const double *v, double *dinv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) m = m + fabs(v[k]);
+  dinv[i] = 1.0 / m;
+}
+
+// One sweep on CSR (setup only): xn = x + dinv * (r - A x), r = 0 here.
+__global__ void k_csr_relax0(int n, const int *rp, const int *ci, const double *v,
+                             const double *dinv, const double *x, double *xn) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + v[k] * x[ci[k]];
+  xn[i] = x[i] + dinv[i] * (0.0 - s);
+}
+
+__global__ void k_fill(int n, double *x, double val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = val;
+}
+
+// max |x| by atomicMax on the IEEE bit pattern (order independent for x >= 0).
+__global__ void k_absmax(int n, const double *x, unsigned long long *out, int *nonfinite) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = fabs(x[i]);
+  if (!isfinite(a)) { atomicOr(nonfinite, 1); return; }
+  atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(a)));
+}
+
+__global__ void k_scale_by_max(int n, double *x, const unsigned long long *mx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m = __longlong_as_double(static_cast<long long>(*mx));
+  x[i] = (m > 0.0) ? x[i] / m : 1.0;
+}
+
+__global__ void k_check_finite(int n, const double *x, int *flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------- matching weights
+// w_hat = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2), evaluated with
+// i = min(row, col) so both stored copies of an edge get the same bits:
+// num = ((2 a) w_lo) w_hi, den = (a_lolo w_lo) w_lo + (a_hihi w_hi) w_hi.
+// Eligible edges (a_ij != 0, w_hat > 0) keep their weight, others get -1.
+__global__ void k_weights(int n, const int *rp, const int *ci, const double *v, const double *d,
+                          const double *w, double *wgt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    const double a = v[k];
+    double out = -1.0;
+    if (j != i && a != 0.0) {
+      const int lo = j < i ? j : i, hi = j < i ? i : j;
+      const double wl = w[lo], wh = w[hi];
+      const double num = ((2.0 * a) * wl) * wh;
+      const double den = (d[lo] * wl) * wl + (d[hi] * wh) * wh;
+      const double x = 1.0 - num / den;
+      if (x > 0.0) out = x;
+    }
+    wgt[k] = out;
+  }
+}
+
+// Strict total order on edges: weight, then max endpoint, then min endpoint.
+__device__ __forceinline__ bool key_gt(double wa, int ha, int la, double wb, int hb, int lb) {
+  if (wa != wb) return wa > wb;
+  if (ha != hb) return ha > hb;
+  return la > lb;
+}
+
+// Matching by locally dominant edges: every undecided vertex names its
+// heaviest eligible edge to an undecided neighbour; mutual choices are
+// matched.  Under the strict total order this reproduces the sequential
+// greedy matching (and Suitor's result) whatever the round structure.
+__global__ void k_match_cand(int n, const int *rp, const int *ci, const double *wgt,
+                             const int *mate, int *cand) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || mate[i] != kFree) return;
+  int best = -1, bh = 0, bl = 0;
+  double bw = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const double x = wgt[k];
+    if (!(x > 0.0)) continue;
+    const int j = ci[k];
+    if (mate[j] != kFree) continue;
+    const int hi = j > i ? j : i, lo = j > i ? i : j;
+    if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
+  }
+  cand[i] = best;
+}
+
+__global__ void k_match_commit(int n, int *mate, const int *cand, int *nfree) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || mate[i] != kFree) return;
+  const int c = cand[i];
+  if (c < 0) mate[i] = kSingle;
+  else if (cand[c] == i) mate[i] = c;
+  else atomicAdd(nfree, 1);
+}
+
+// ------------------------------------------------------------ aggregation
+// Aggregates are numbered by their smallest fine index, ascending.
+__global__ void k_agg_flags(int n, const int *mate, int *flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = mate[i];
+  flag[i] = (m < 0 || m > i) ? 1 : 0;
+}
+
+__global__ void k_agg_ids(int n, const int *mate, const int *pos, int *agg, int *rep) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = mate[i];
+  const int root = (m >= 0 && m < i) ? m : i;
+  agg[i] = pos[root];
+  if (root == i) rep[pos[i]] = i;
+}
+
+// p_i = w_i / sqrt(w_lo^2 + w_hi^2) on a pair, w_i / |w_i| (1 if w_i = 0) on a singleton.
+__global__ void k_pair_pvals(int n, const int *mate, const double *w, double *p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = mate[i];
+  const double wi = w[i];
+  if (j < 0) { p[i] = (wi == 0.0) ? 1.0 : wi / fabs(wi); return; }
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  const double wl = w[lo], wh = w[hi];
+  const double nrm = sqrt(wl * wl + wh * wh);
+  p[i] = wi / nrm;
+}
+
+// w_c = P^T w, members ascending: rep first, then its mate.
+__global__ void k_pair_restrict_w(int nc, const int *rep, const int *mate, const double *p,
+                                  const double *w, double *wc) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int lo = rep[I], hi = mate[lo];
+  double s = 0.0;
+  s = s + p[lo] * w[lo];
+  if (hi >= 0) s = s + p[hi] * w[hi];
+  wc[I] = s;
+}
+
+// ------------------------------------------------------ Galerkin product
+// A_c(I,J) = sum of (p_i p_j) a_ij over stored a_ij with agg(i) = I,
+// agg(j) = J.  Terms of one coarse entry are folded in ascending (u, v),
+// u = the fine index on the side of min(I,J), v = the other, so entries
+// (I,J) and (J,I) fold identical term sequences (bitwise-symmetric A_c).
+__global__ void k_rap_count_terms(int nc, const int *rep, const int *mate, const int *rp,
+                                  int *cnt) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int lo = rep[I], hi = mate[lo];
+  int c = rp[lo + 1] - rp[lo];
+  if (hi >= 0) c += rp[hi + 1] - rp[hi];
+  cnt[I] = c;
+}
+
+__device__ __forceinline__ bool term_lt(int Ja, unsigned long long ka, int Jb,
+                                        unsigned long long kb) {
+  return Ja < Jb || (Ja == Jb && ka < kb);
+}
+
+__global__ void k_rap_terms(int nc, const int *rep, const int *mate, const int *rp, const int *ci,
+                            const double *v, const int *agg, const double *p, const int *toff,
+                            int *tJ, unsigned long long *tK, double *tT, int *ucnt) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int lo = rep[I], hi = mate[lo];
+  const int base = toff[I];
+  int c = 0;
+  for (int m = 0; m < 2; ++m) {
+    const int i = (m == 0) ? lo : hi;
+    if (i < 0) break;
+    const double pi = p[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int j = ci[k];
+      const int J = agg[j];
+      const unsigned u = static_cast<unsigned>(I <= J ? i : j);
+      const unsigned w2 = static_cast<unsigned>(I <= J ? j : i);
+      const unsigned long long key = (static_cast<unsigned long long>(u) << 32) | w2;
+      const double t = (pi * p[j]) * v[k];
+      // insertion into the sorted prefix [base, base + c)
+      int q = c;
+      while (q > 0 && term_lt(J, key, tJ[base + q - 1], tK[base + q - 1])) {
+        tJ[base + q] = tJ[base + q - 1];
+        tK[base + q] = tK[base + q - 1];
+        tT[base + q] = tT[base + q - 1];
+        --q;
+      }
+      tJ[base + q] = J;
+      tK[base + q] = key;
+      tT[base + q] = t;
+      ++c;
+    }
+  }
+  int u = 0;
+  for (int q = 0; q < c; ++q)
+    if (q == 0 || tJ[base + q] != tJ[base + q - 1]) ++u;
+  ucnt[I] = u;
+}
+
+__global__ void k_rap_fold(int nc, const int *toff, const int *tJ, const double *tT,
+                           const int *crp, int *cci, double *cv) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int b = toff[I], e = toff[I + 1];
+  int out = crp[I];
+  for (int q = b; q < e;) {
+    const int J = tJ[q];
+    double s = tT[q];
+    int r = q + 1;
+    while (r < e && tJ[r] == J) { s = s + tT[r]; ++r; }
+    cci[out] = J;
+    cv[out] = s;
+    ++out;
+    q = r;
+  }
+}
+
+// Composite prolongator: agg <- agg_t(agg), p <- p * p_t(agg)  (left to right).
+__global__ void k_compose(int n, int *agg, double *p, const int *agg_t, const double *p_t) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = agg[i];
+  p[i] = p[i] * p_t[a];
+  agg[i] = agg_t[a];
+}
+
+__global__ void k_iota(int n, int *a, double *p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  a[i] = i;
+  p[i] = 1.0;
+}
+
+// Members of each aggregate (CSR of P^T), ascending.
+__global__ void k_count_members(int n, const int *agg, int *cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_place_members(int n, const int *agg, const int *mptr, int *fill, int *mem) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = agg[i];
+  const int pos = mptr[a] + atomicAdd(&fill[a], 1);
+  mem[pos] = i;
+}
+
+__global__ void k_sort_members(int nc, const int *mptr, int *mem) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int b = mptr[I], e = mptr[I + 1];
+  for (int q = b + 1; q < e; ++q) {
+    const int x = mem[q];
+    int r = q;
+    while (r > b && mem[r - 1] > x) { mem[r] = mem[r - 1]; --r; }
+    mem[r] = x;
+  }
+}
+
+// ------------------------------------------------------------------ SELL
+__global__ void k_sell_width(int n, int nslices, const int *rp, int *slots) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  int w = 0;
+  const int r0 = s * kSlice, r1 = min(n, r0 + kSlice);
+  for (int r = r0; r < r1; ++r) w = max(w, rp[r + 1] - rp[r]);
+  slots[s] = w * kSlice;
+}
+
+__global__ void k_sell_fill(int n, int nslices, const int *rp, const int *ci, const double *v,
+                            const int *sptr, int *scol, double *sval) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nslices * kSlice) return;
+  const int s = r / kSlice, lane = r % kSlice;
+  const int width = (sptr[s + 1] - sptr[s]) / kSlice;
+  const int base = sptr[s] + lane;
+  const int len = (r < n) ? rp[r + 1] - rp[r] : 0;
+  const int start = (r < n) ? rp[r] : 0;
+  const int pad_col = (r < n) ? r : n - 1;
+  for (int k = 0; k < width; ++k) {
+    if (k < len) {
+      scol[base + k * kSlice] = ci[start + k];
+      sval[base + k * kSlice] = v[start + k];
+    } else {
+      scol[base + k * kSlice] = pad_col;
+      sval[base + k * kSlice] = 0.0;
+    }
+  }
+}
+
+__global__ void k_d2f(int64_t n, const double *a, float *b) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<float>(a[i]);
+}
+
+// ------------------------------------------------------- coarsest factor
+__global__ void k_densify(int n, const int *rp, const int *ci, const double *v, double *D) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) D[static_cast<int64_t>(i) * n + ci[k]] = v[k];
+}
+
+// Right-looking Cholesky in one workgroup, in place on the row-major lower
+// triangle.  Entry (i,l) receives the updates -L_ij L_lj for j = 0, 1, ...
+// in ascending order, the same fold as the left-looking definition
+// L_il = (a_il - sum_{j<l} L_ij L_lj) / L_ll.
+__global__ void k_cholesky(int n, double *D, int *flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const double piv = D[static_cast<int64_t>(j) * n + j];
+      if (!(piv > 0.0)) bad = 1;
+      else D[static_cast<int64_t>(j) * n + j] = sqrt(piv);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double ljj = D[static_cast<int64_t>(j) * n + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x)
+      D[static_cast<int64_t>(i) * n + j] = D[static_cast<int64_t>(i) * n + j] / ljj;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int64_t t = threadIdx.x; t < static_cast<int64_t>(m) * m; t += blockDim.x) {
+      const int ii = static_cast<int>(t / m), ll = static_cast<int>(t % m);
+      if (ll > ii) continue;
+      const int i = j + 1 + ii, l = j + 1 + ll;
+      D[static_cast<int64_t>(i) * n + l] =
+          D[static_cast<int64_t>(i) * n + l] - D[static_cast<int64_t>(i) * n + j] * D[static_cast<int64_t>(l) * n + j];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && bad) *flag = 1;
+}
+
+// Lcm: column-major L (Lcm[j*n + i] = L_ij), Lrm: row-major (Lrm[i*n + j] = L_ij).
+__global__ void k_split_factor(int n, const double *D, double *Lcm, double *Lrm) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(t / n), j = static_cast<int>(t % n);
+  const double x = (j <= i) ? D[t] : 0.0;
+  Lrm[t] = x;
+  Lcm[static_cast<int64_t>(j) * n + i] = x;
+}
+
+// --------------------------------------------------------- host helpers
+
+double now_ms() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double, std::milli>(clk::now().time_since_epoch()).count();
+}
+
+void check_flags(const dvec<int> &flags, hipStream_t s) {
+  int f[4] = {0, 0, 0, 0};
+  AMG_HIP(hipMemcpyAsync(f, flags.p, sizeof(f), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  if (f[0]) fail(AMG_ERR_INVALID, "malformed CSR (row_ptr, column range or ordering)");
+  if (f[2]) fail(AMG_ERR_NONFINITE, "non-finite matrix value");
+  if (f[1]) fail(AMG_ERR_NOT_SPD, "missing or non-positive diagonal entry");
+  if (f[3]) fail(AMG_ERR_INVALID, "matrix is not bitwise symmetric");
+}
+
+void build_sell(Level &Lv, hipStream_t s, bool want_float) {
+  Sell &S = Lv.S;
+  const int n = Lv.A.n;
+  S.n = n;
+  S.nslices = ceil_div(n, kSlice);
+  dvec<int> slots(S.nslices);
+  S.sptr.alloc(S.nslices + 1);
+  hipLaunchKernelGGL(k_sell_width, grid_for(S.nslices), dim3(kBlock), 0, s, n, S.nslices,
+                     Lv.A.rp.p, slots.p);
+  AMG_LAUNCH_CHECK();
+  exclusive_scan(slots.p, S.sptr.p, S.nslices, s);
+  S.nslots = read_int(S.sptr.p + S.nslices, s);
+  S.col.alloc(S.nslots);
+  S.val.alloc(S.nslots);
+  hipLaunchKernelGGL(k_sell_fill, grid_for(static_cast<int64_t>(S.nslices) * kSlice), dim3(kBlock),
+                     0, s, n, S.nslices, Lv.A.rp.p, Lv.A.ci.p, Lv.A.v.p, S.sptr.p, S.col.p, S.val.p);
+  AMG_LAUNCH_CHECK();
+  if (want_float) {
+    S.valf.alloc(S.nslots);
+    hipLaunchKernelGGL(k_d2f, grid_for(S.nslots), dim3(kBlock), 0, s, S.nslots, S.val.p, S.valf.p);
+    AMG_LAUNCH_CHECK();
+  }
+}
+
+// One pairwise step on (A, w): matching, aggregates, P values, w_c, A_c.
+struct PairStep {
+  int nc = 0;
+  dvec<int> agg, rep, mate;
+  dvec<double> p, wc;
+  DevCSR Ac;
+};
+
+void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &out, Timing &tm) {
+  const int n = A.n;
+  const dim3 g = grid_for(n), b(kBlock);
+  double t0 = now_ms();
+  dvec<double> d(n), wgt(A.nnz);
+  hipLaunchKernelGGL(k_diag, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p);
+  AMG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
+  AMG_LAUNCH_CHECK();
+  out.mate.alloc(n);
+  dvec<int> cand(n), nfree(64);
+  {
+    std::vector<int> init(n, kFree);
+    AMG_HIP(hipMemcpyAsync(out.mate.p, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
+  // Rounds are issued in batches; each round counts the vertices left undecided.
+  int rounds = 0;
+  const int kBatch = 16;
+  for (;;) {
+    AMG_HIP(hipMemsetAsync(nfree.p, 0, sizeof(int) * kBatch, s));
+    for (int q = 0; q < kBatch; ++q) {
+      hipLaunchKernelGGL(k_match_cand, g, b, 0, s, n, A.rp.p, A.ci.p, wgt.p, out.mate.p, cand.p);
+      hipLaunchKernelGGL(k_match_commit, g, b, 0, s, n, out.mate.p, cand.p, nfree.p + q);
+    }
+    AMG_LAUNCH_CHECK();
+    rounds += kBatch;
+    const int left = read_int(nfree.p + kBatch - 1, s);
+    if (left == 0) break;
+    if (rounds > n + 2 * kBatch) fail(AMG_ERR_DEVICE, "matching did not terminate");
+  }
+  tm.rounds += rounds;
+  dvec<int> flag(n), pos(n + 1);
+  hipLaunchKernelGGL(k_agg_flags, g, b, 0, s, n, out.mate.p, flag.p);
+  AMG_LAUNCH_CHECK();
+  exclusive_scan(flag.p, pos.p, n, s);
+  const int nc = read_int(pos.p + n, s);
+  out.nc = nc;
+  out.agg.alloc(n);
+  out.rep.alloc(nc);
+  out.p.alloc(n);
+  out.wc.alloc(nc);
+  hipLaunchKernelGGL(k_agg_ids, g, b, 0, s, n, out.mate.p, pos.p, out.agg.p, out.rep.p);
+  hipLaunchKernelGGL(k_pair_pvals, g, b, 0, s, n, out.mate.p, w, out.p.p);
+  hipLaunchKernelGGL(k_pair_restrict_w, grid_for(nc), b, 0, s, nc, out.rep.p, out.mate.p, out.p.p,
+                     w, out.wc.p);
+  AMG_LAUNCH_CHECK();
+  AMG_HIP(hipStreamSynchronize(s));
+  double t1 = now_ms();
+  tm.match_ms += t1 - t0;
+
+  // Galerkin product
+  const dim3 gc = grid_for(nc);
+  dvec<int> tcnt(nc), toff(nc + 1), ucnt(nc);
+  hipLaunchKernelGGL(k_rap_count_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, tcnt.p);
+  AMG_LAUNCH_CHECK();
+  exclusive_scan(tcnt.p, toff.p, nc, s);
+  const int nterms = read_int(toff.p + nc, s);
+  dvec<int> tJ(nterms);
+  dvec<unsigned long long> tK(nterms);
+  dvec<double> tT(nterms);
+  hipLaunchKernelGGL(k_rap_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
+                     out.agg.p, out.p.p, toff.p, tJ.p, tK.p, tT.p, ucnt.p);
+  AMG_LAUNCH_CHECK();
+  out.Ac.n = nc;
+  out.Ac.rp.alloc(nc + 1);
+  exclusive_scan(ucnt.p, out.Ac.rp.p, nc, s);
+  out.Ac.nnz = read_int(out.Ac.rp.p + nc, s);
+  out.Ac.ci.alloc(out.Ac.nnz);
+  out.Ac.v.alloc(out.Ac.nnz);
+  hipLaunchKernelGGL(k_rap_fold, gc, b, 0, s, nc, toff.p, tJ.p, tT.p, out.Ac.rp.p, out.Ac.ci.p,
+                     out.Ac.v.p);
+  AMG_LAUNCH_CHECK();
+  AMG_HIP(hipStreamSynchronize(s));
+  tm.rap_ms += now_ms() - t1;
+}
+
+void finish_level(Level &Lv, hipStream_t s, bool want_float) {
+  const int n = Lv.A.n;
+  Lv.dinv.alloc(n);
+  hipLaunchKernelGGL(k_l1_dinv, grid_for(n), dim3(kBlock), 0, s, n, Lv.A.rp.p, Lv.A.v.p, Lv.dinv.p);
+  AMG_LAUNCH_CHECK();
+  build_sell(Lv, s, want_float);
+  if (want_float) {
+    Lv.dinvf.alloc(n);
+    hipLaunchKernelGGL(k_d2f, grid_for(n), dim3(kBlock), 0, s, static_cast<int64_t>(n), Lv.dinv.p,
+                       Lv.dinvf.p);
+    AMG_LAUNCH_CHECK();
+  }
+}
+
+void build_members(Level &Lv, hipStream_t s) {
+  const int n = Lv.A.n, nc = Lv.nc;
+  dvec<int> cnt(nc), fill(nc);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * nc, s));
+  AMG_HIP(hipMemsetAsync(fill.p, 0, sizeof(int) * nc, s));
+  hipLaunchKernelGGL(k_count_members, grid_for(n), dim3(kBlock), 0, s, n, Lv.agg.p, cnt.p);
+  AMG_LAUNCH_CHECK();
+  Lv.mptr.alloc(nc + 1);
+  exclusive_scan(cnt.p, Lv.mptr.p, nc, s);
+  Lv.mem.alloc(n);
+  hipLaunchKernelGGL(k_place_members, grid_for(n), dim3(kBlock), 0, s, n, Lv.agg.p, Lv.mptr.p, fill.p,
+                     Lv.mem.p);
+  hipLaunchKernelGGL(k_sort_members, grid_for(nc), dim3(kBlock), 0, s, nc, Lv.mptr.p, Lv.mem.p);
+  AMG_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+// ===================================================== hierarchy builder
+void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
+  hipStream_t s = h->stream;
+  const amg_params &P = h->p;
+  const double t_start = now_ms();
+  const bool want_float = (P.precision == AMG_PREC_MIXED);
+  h->L.clear();
+  h->L.emplace_back();
+  Level &L0 = h->L[0];
+  const int n = Ain->n;
+  L0.A.n = n;
+  L0.A.nnz = Ain->nnz;
+  L0.A.rp.alloc(n + 1);
+  L0.A.ci.alloc(Ain->nnz);
+  L0.A.v.alloc(Ain->nnz);
+  const hipMemcpyKind kind = Ain->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  AMG_HIP(hipMemcpyAsync(L0.A.rp.p, Ain->row_ptr, sizeof(int) * (n + 1), kind, s));
+  AMG_HIP(hipMemcpyAsync(L0.A.ci.p, Ain->col_idx, sizeof(int) * Ain->nnz, kind, s));
+  AMG_HIP(hipMemcpyAsync(L0.A.v.p, Ain->val, sizeof(double) * Ain->nnz, kind, s));
+  {
+    dvec<int> flags(4);
+    AMG_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * 4, s));
+    hipLaunchKernelGGL(k_validate_rows, grid_for(n), dim3(kBlock), 0, s, n, Ain->nnz, L0.A.rp.p,
+                       L0.A.ci.p, L0.A.v.p, flags.p);
+    AMG_LAUNCH_CHECK();
+    check_flags(flags, s);
+    hipLaunchKernelGGL(k_validate_sym, grid_for(n), dim3(kBlock), 0, s, n, L0.A.rp.p, L0.A.ci.p,
+                       L0.A.v.p, flags.p);
+    AMG_LAUNCH_CHECK();
+    check_flags(flags, s);
+  }
+  finish_level(L0, s, want_float);
+
+  // smooth vector of the fine level
+  L0.w.alloc(n);
+  if (P.smooth_vec == AMG_SMOOTH_GIVEN) {
+    AMG_HIP(hipMemcpyAsync(L0.w.p, P.smooth_vector, sizeof(double) * n, kind, s));
+    dvec<int> flag(1);
+    AMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_check_finite, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, flag.p);
+    AMG_LAUNCH_CHECK();
+    if (read_int(flag.p, s)) fail(AMG_ERR_NONFINITE, "non-finite smooth vector");
+  } else {
+    hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, 1.0);
+    AMG_LAUNCH_CHECK();
+    if (P.smooth_vec == AMG_SMOOTH_RELAX) {
+      dvec<double> t(n);
+      for (int it = 0; it < P.smooth_sweeps; ++it) {
+        hipLaunchKernelGGL(k_csr_relax0, grid_for(n), dim3(kBlock), 0, s, n, L0.A.rp.p, L0.A.ci.p,
+                           L0.A.v.p, L0.dinv.p, L0.w.p, t.p);
+        AMG_LAUNCH_CHECK();
+        std::swap(L0.w, t);
+      }
+      dvec<unsigned long long> mx(1);
+      dvec<int> nf(1);
+      AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
+      AMG_HIP(hipMemsetAsync(nf.p, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_absmax, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, mx.p, nf.p);
+      AMG_LAUNCH_CHECK();
+      if (read_int(nf.p, s)) {
+        hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, 1.0);
+      } else {
+        hipLaunchKernelGGL(k_scale_by_max, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, mx.p);
+      }
+      AMG_LAUNCH_CHECK();
+    }
+  }
+
+  const int maxlev = std::min(P.max_levels, AMG_MAX_LEVELS);
+  while (P.precond && static_cast<int>(h->L.size()) < maxlev && h->L.back().A.n > P.coarse_max) {
+    const int k = static_cast<int>(h->L.size()) - 1;
+    const int nk = h->L[k].A.n;
+    dvec<int> agg(nk);
+    dvec<double> pv(nk);
+    hipLaunchKernelGGL(k_iota, grid_for(nk), dim3(kBlock), 0, s, nk, agg.p, pv.p);
+    AMG_LAUNCH_CHECK();
+    PairStep cur;          // owns the intermediate matrix after step 0
+    bool owned = false;
+    for (int step = 0; step < P.aggr_steps; ++step) {
+      const DevCSR &Acur = owned ? cur.Ac : h->L[k].A;
+      const double *wcur = owned ? cur.wc.p : h->L[k].w.p;
+      if (step > 0 && Acur.n <= P.coarse_max) break;
+      PairStep nxt;
+      pairwise_step(Acur, wcur, s, nxt, h->tm);
+      hipLaunchKernelGGL(k_compose, grid_for(nk), dim3(kBlock), 0, s, nk, agg.p, pv.p, nxt.agg.p,
+                         nxt.p.p);
+      AMG_LAUNCH_CHECK();
+      AMG_HIP(hipStreamSynchronize(s));
+      cur = std::move(nxt);
+      owned = true;
+    }
+    if (!owned || static_cast<double>(cur.Ac.n) > kStagnation * static_cast<double>(nk)) break;
+    Level &Lk = h->L[k];
+    Lk.nc = cur.Ac.n;
+    Lk.agg = std::move(agg);
+    Lk.pval = std::move(pv);
+    build_members(Lk, s);
+    if (want_float) {
+      Lk.pvalf.alloc(nk);
+      hipLaunchKernelGGL(k_d2f, grid_for(nk), dim3(kBlock), 0, s, static_cast<int64_t>(nk),
+                         Lk.pval.p, Lk.pvalf.p);
+      AMG_LAUNCH_CHECK();
+    }
+    Level next;
+    next.A = std::move(cur.Ac);
+    next.w = std::move(cur.wc);
+    h->L.push_back(std::move(next));
+    finish_level(h->L.back(), s, want_float);
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  coarse_factor(h);
+  alloc_solve_buffers(h);
+  AMG_HIP(hipStreamSynchronize(s));
+  h->tm.setup_ms = now_ms() - t_start;
+}
+
+void coarse_factor(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  Level &C = h->L.back();
+  const int n = C.A.n;
+  h->coarse_dense = h->p.precond && h->p.coarse_solver == AMG_COARSE_CHOLESKY && n <= kDenseMax;
+  if (!h->coarse_dense) return;
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  dvec<double> D(nn);
+  dvec<int> flag(1);
+  AMG_HIP(hipMemsetAsync(D.p, 0, sizeof(double) * nn, s));
+  AMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_densify, grid_for(n), dim3(kBlock), 0, s, n, C.A.rp.p, C.A.ci.p, C.A.v.p, D.p);
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, n, D.p, flag.p);
+  AMG_LAUNCH_CHECK();
+  if (read_int(flag.p, s)) fail(AMG_ERR_NOT_SPD, "coarsest matrix has a non-positive Cholesky pivot");
+  h->Lc.alloc(nn);
+  h->LcT.alloc(nn);
+  hipLaunchKernelGGL(k_split_factor, grid_for(nn), dim3(kBlock), 0, s, n, D.p, h->Lc.p, h->LcT.p);
+  AMG_LAUNCH_CHECK();
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace amg
