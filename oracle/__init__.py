@@ -91,7 +91,11 @@ def lib():
         L.orc_opc.argtypes = [C.c_void_p]
         L.orc_export_level.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
         L.orc_export_coarse_factor.argtypes = [C.c_void_p, _f64p]
+        L.orc_export_coarse_inverse.argtypes = [C.c_void_p, _f64p]
         L.orc_vcycle.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_vcycle_f32.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_pcg_mixed.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.orc_pcg.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32,
                               C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.orc_pairwise_step.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p,
@@ -251,17 +255,30 @@ class Hierarchy:
         assert lib().orc_export_coarse_factor(self.h, Lf) == OK
         return Lf
 
+    def coarse_inverse(self):
+        n, _ = self.level_size(self.nlevels - 1)
+        Ai = np.empty((n, n))
+        assert lib().orc_export_coarse_inverse(self.h, Ai) == OK
+        return Ai
+
     def vcycle(self, r):
         z = np.empty(self.n)
         assert lib().orc_vcycle(self.h, np.ascontiguousarray(r, np.float64), z) == OK
         return z
 
-    def pcg(self, b, x0=None, rtol=1e-6, maxit=1000):
+    def vcycle_f32(self, r):
+        """Mixed-precision form of the V-cycle (binary32 inside, binary64 in/out)."""
+        z = np.empty(self.n)
+        assert lib().orc_vcycle_f32(self.h, np.ascontiguousarray(r, np.float64), z) == OK
+        return z
+
+    def pcg(self, b, x0=None, rtol=1e-6, maxit=1000, mixed=False):
         """Returns (x, iterations, recurrence relative residual, status)."""
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         it, rel = C.c_int32(), C.c_double()
-        st = lib().orc_pcg(self.h, np.ascontiguousarray(b, np.float64), x, float(rtol), int(maxit),
-                           C.byref(it), C.byref(rel))
+        f = lib().orc_pcg_mixed if mixed else lib().orc_pcg
+        st = f(self.h, np.ascontiguousarray(b, np.float64), x, float(rtol), int(maxit),
+               C.byref(it), C.byref(rel))
         return x, it.value, rel.value, st
 
 

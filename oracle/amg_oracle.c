@@ -68,10 +68,15 @@ typedef struct {
   double *w[ORC_MAXLEV];     /* smooth vector of each level */
   int32_t *agg[ORC_MAXLEV];  /* level k row -> level k+1 row */
   double *pval[ORC_MAXLEV];  /* the one nonzero of row i of P_k */
-  int coarse_dense;          /* 1 if the coarsest level is solved by Cholesky */
+  int coarse_dense;          /* 1 if the coarsest level is solved directly */
   double *L;                 /* dense lower Cholesky factor, row-major */
+  double *Ainv;              /* inverse of the coarsest matrix, row-major */
   /* V-cycle work vectors per level */
   double *vx[ORC_MAXLEV], *vt[ORC_MAXLEV], *vr[ORC_MAXLEV], *vres[ORC_MAXLEV], *ve[ORC_MAXLEV];
+  /* binary32 copies for the mixed-precision V-cycle (built on first use) */
+  float *fv[ORC_MAXLEV], *fdinv[ORC_MAXLEV], *fpval[ORC_MAXLEV];
+  float *fx[ORC_MAXLEV], *ft[ORC_MAXLEV], *fr[ORC_MAXLEV], *fres[ORC_MAXLEV], *fe[ORC_MAXLEV];
+  int have_f32;
 } orc_h;
 
 /* ------------------------------------------------------------------ utils */
@@ -628,6 +633,18 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
     *status = cholesky(m, D, h->L);
     free(D);
     if (*status != ORC_OK) { orc_free(h); return NULL; }
+    /* the direct solve z = A^-1 r uses the inverse, column j = chol_solve(e_j) */
+    h->Ainv = (double *)malloc(sizeof(double) * (size_t)m * m);
+    double *e = (double *)calloc((size_t)m, sizeof(double));
+    double *col = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!h->Ainv || !e || !col) { free(e); free(col); orc_free(h); *status = ORC_NOMEM; return NULL; }
+    for (int32_t j = 0; j < m; j++) {
+      e[j] = 1.0;
+      chol_solve(m, h->L, e, col);
+      e[j] = 0.0;
+      for (int32_t i = 0; i < m; i++) h->Ainv[(int64_t)i * m + j] = col[i];
+    }
+    free(e); free(col);
   }
   for (int k = 0; k < h->nlev; k++) {
     size_t nb = sizeof(double) * (size_t)h->A[k].n;
@@ -648,8 +665,11 @@ void orc_free(orc_h *h) {
     csr_free(&h->A[k]);
     free(h->dinv[k]); free(h->w[k]); free(h->agg[k]); free(h->pval[k]);
     free(h->vx[k]); free(h->vt[k]); free(h->vr[k]); free(h->vres[k]); free(h->ve[k]);
+    free(h->fv[k]); free(h->fdinv[k]); free(h->fpval[k]);
+    free(h->fx[k]); free(h->ft[k]); free(h->fr[k]); free(h->fres[k]); free(h->fe[k]);
   }
   free(h->L);
+  free(h->Ainv);
   free(h);
 }
 
@@ -672,12 +692,23 @@ static void smooth_from_zero(const csr_t *A, const double *dinv, const double *r
   }
 }
 
+/* Coarsest direct solve z = (A^nl)^-1 r (Alg. 2): row i of the inverse
+ * times r, folded over j ascending. */
+static void coarse_direct(const orc_h *h, const double *r, double *z) {
+  int32_t n = h->A[h->nlev - 1].n;
+  for (int32_t i = 0; i < n; i++) {
+    double s = 0.0;
+    for (int32_t j = 0; j < n; j++) s = s + h->Ainv[(int64_t)i * n + j] * r[j];
+    z[i] = s;
+  }
+}
+
 static void vcycle(orc_h *h, int k, const double *r, double *z) {
   const csr_t *A = &h->A[k];
   int32_t n = A->n;
   double *x = h->vx[k], *t = h->vt[k];
   if (k == h->nlev - 1) {
-    if (h->coarse_dense) chol_solve(n, h->L, r, z);
+    if (h->coarse_dense) coarse_direct(h, r, z);
     else {
       smooth_from_zero(A, h->dinv[k], r, h->p.coarse_sweeps, x, t);
       memcpy(z, x, sizeof(double) * (size_t)n);
@@ -709,14 +740,127 @@ int orc_vcycle(orc_h *h, const double *r, double *z) {
   return ORC_OK;
 }
 
+/* ------------------------------------------------- binary32 V-cycle
+ * Mixed-precision form: the same V-cycle evaluated in binary32.  Matrix
+ * values and prolongator values are rounded to binary32; the l1 diagonal is
+ * folded in binary32 from the rounded values; the coarsest solve converts
+ * its right-hand side to binary64, uses the binary64 factor, and rounds the
+ * result back.  Input and output stay binary64. */
+static void spmv_f(const csr_t *A, const float *v, const float *x, float *y) {
+  for (int32_t i = 0; i < A->n; i++) {
+    float s = 0.0f;
+    for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) s = s + v[k] * x[A->ci[k]];
+    y[i] = s;
+  }
+}
+
+static void sweep_f(const csr_t *A, const float *v, const float *dinv, const float *r,
+                    const float *x, float *xn) {
+  for (int32_t i = 0; i < A->n; i++) {
+    float s = 0.0f;
+    for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) s = s + v[k] * x[A->ci[k]];
+    xn[i] = x[i] + dinv[i] * (r[i] - s);
+  }
+}
+
+static int build_f32(orc_h *h) {
+  for (int k = 0; k < h->nlev; k++) {
+    const csr_t *A = &h->A[k];
+    size_t n = (size_t)A->n, z = (size_t)(A->nnz > 0 ? A->nnz : 1);
+    h->fv[k] = (float *)malloc(sizeof(float) * z);
+    h->fdinv[k] = (float *)malloc(sizeof(float) * n);
+    h->fx[k] = (float *)malloc(sizeof(float) * n); h->ft[k] = (float *)malloc(sizeof(float) * n);
+    h->fr[k] = (float *)malloc(sizeof(float) * n); h->fres[k] = (float *)malloc(sizeof(float) * n);
+    h->fe[k] = (float *)malloc(sizeof(float) * n);
+    if (!h->fv[k] || !h->fdinv[k] || !h->fx[k] || !h->ft[k] || !h->fr[k] || !h->fres[k] || !h->fe[k])
+      return ORC_NOMEM;
+    for (int64_t t = 0; t < A->nnz; t++) h->fv[k][t] = (float)A->v[t];
+    for (int32_t i = 0; i < A->n; i++) {
+      float m = 0.0f;
+      for (int32_t t = A->rp[i]; t < A->rp[i + 1]; t++) m = m + fabsf(h->fv[k][t]);
+      h->fdinv[k][i] = 1.0f / m;
+    }
+    if (k < h->nlev - 1) {
+      h->fpval[k] = (float *)malloc(sizeof(float) * n);
+      if (!h->fpval[k]) return ORC_NOMEM;
+      for (int32_t i = 0; i < A->n; i++) h->fpval[k][i] = (float)h->pval[k][i];
+    }
+  }
+  h->have_f32 = 1;
+  return ORC_OK;
+}
+
+static void smooth_from_zero_f(const orc_h *h, int k, const float *r, int nsw, float *x, float *t) {
+  const csr_t *A = &h->A[k];
+  int32_t n = A->n;
+  if (nsw <= 0) { for (int32_t i = 0; i < n; i++) x[i] = 0.0f; return; }
+  for (int32_t i = 0; i < n; i++) x[i] = h->fdinv[k][i] * r[i];
+  for (int s = 1; s < nsw; s++) {
+    sweep_f(A, h->fv[k], h->fdinv[k], r, x, t);
+    memcpy(x, t, sizeof(float) * (size_t)n);
+  }
+}
+
+static void vcycle_f(orc_h *h, int k, const float *r, float *z) {
+  const csr_t *A = &h->A[k];
+  int32_t n = A->n;
+  float *x = h->fx[k], *t = h->ft[k];
+  if (k == h->nlev - 1) {
+    if (h->coarse_dense) {
+      double *rd = (double *)malloc(sizeof(double) * (size_t)n);
+      double *zd = (double *)malloc(sizeof(double) * (size_t)n);
+      for (int32_t i = 0; i < n; i++) rd[i] = (double)r[i];
+      coarse_direct(h, rd, zd);
+      for (int32_t i = 0; i < n; i++) z[i] = (float)zd[i];
+      free(rd); free(zd);
+    } else {
+      smooth_from_zero_f(h, k, r, h->p.coarse_sweeps, x, t);
+      memcpy(z, x, sizeof(float) * (size_t)n);
+    }
+    return;
+  }
+  smooth_from_zero_f(h, k, r, h->p.pre_sweeps, x, t);
+  float *res = h->fres[k];
+  spmv_f(A, h->fv[k], x, res);
+  for (int32_t i = 0; i < n; i++) res[i] = r[i] - res[i];
+  int32_t nc = h->A[k + 1].n;
+  float *rc = h->fr[k + 1];
+  for (int32_t I = 0; I < nc; I++) rc[I] = 0.0f;
+  for (int32_t i = 0; i < n; i++) rc[h->agg[k][i]] = rc[h->agg[k][i]] + h->fpval[k][i] * res[i];
+  float *ec = h->fe[k + 1];
+  vcycle_f(h, k + 1, rc, ec);
+  for (int32_t i = 0; i < n; i++) x[i] = x[i] + h->fpval[k][i] * ec[h->agg[k][i]];
+  for (int s = 0; s < h->p.post_sweeps; s++) {
+    sweep_f(A, h->fv[k], h->fdinv[k], r, x, t);
+    memcpy(x, t, sizeof(float) * (size_t)n);
+  }
+  memcpy(z, x, sizeof(float) * (size_t)n);
+}
+
+/* z = B_32 r with r, z binary64 (single-level hierarchies use the binary64 solve). */
+int orc_vcycle_f32(orc_h *h, const double *r, double *z) {
+  if (!h) return ORC_INVALID;
+  int32_t n = h->A[0].n;
+  if (!h->p.precond || h->nlev == 1) return orc_vcycle(h, r, z);
+  if (!h->have_f32 && build_f32(h) != ORC_OK) return ORC_NOMEM;
+  float *rf = (float *)malloc(sizeof(float) * (size_t)n);
+  float *zf = (float *)malloc(sizeof(float) * (size_t)n);
+  if (!rf || !zf) { free(rf); free(zf); return ORC_NOMEM; }
+  for (int32_t i = 0; i < n; i++) rf[i] = (float)r[i];
+  vcycle_f(h, 0, rf, zf);
+  for (int32_t i = 0; i < n; i++) z[i] = (double)zf[i];
+  free(rf); free(zf);
+  return ORC_OK;
+}
+
 /* ------------------------------------------------------------- flexible CG
  * Alg. 1 (Notay's flexible PCG, Sec. 3).  u holds u_0 on entry, the solution on exit.
  * Stop when ||r_i||_2 <= rtol ||r_0||_2 (recurrence residual, tested after
  * every update of r) or after maxit preconditioner applications (Sec. 5); the
  * iteration count is the number of applications of B.  rho <= 0 (or not
  * finite) means A or B is not s.p.d. */
-int orc_pcg(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
-            int32_t *iters, double *relres) {
+static int pcg_impl(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
+                    int32_t *iters, double *relres, int mixed) {
   if (!h || !b || !u || !(rtol > 0.0) || maxit < 1) return ORC_INVALID;
   const csr_t *A = &h->A[0];
   int32_t n = A->n;
@@ -736,7 +880,8 @@ int orc_pcg(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
   if (nr0 == 0.0) goto done;
 
   /* initial step */
-  orc_vcycle(h, r, w); it = 1;
+  if (mixed) orc_vcycle_f32(h, r, w); else orc_vcycle(h, r, w);
+  it = 1;
   spmv(A, w, v);
   double alpha = dot(n, w, r);
   double beta = dot(n, w, v);
@@ -753,7 +898,8 @@ int orc_pcg(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
   while (!(nr <= rtol * nr0)) {
     if (!isfinite(nr)) { status = ORC_NONFINITE; goto done; }
     if (it >= maxit) { status = ORC_NOT_CONVERGED; goto done; }
-    orc_vcycle(h, r, w); it++;
+    if (mixed) orc_vcycle_f32(h, r, w); else orc_vcycle(h, r, w);
+    it++;
     spmv(A, w, v);
     alpha = dot(n, w, r);
     beta = dot(n, w, v);
@@ -776,6 +922,17 @@ done:
   *relres = rel;
   free(r); free(w); free(v); free(d); free(q);
   return status;
+}
+
+int orc_pcg(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
+            int32_t *iters, double *relres) {
+  return pcg_impl(h, b, u, rtol, maxit, iters, relres, 0);
+}
+
+/* Flexible CG with the binary32 V-cycle (mixed-precision form). */
+int orc_pcg_mixed(orc_h *h, const double *b, double *u, double rtol, int32_t maxit,
+                  int32_t *iters, double *relres) {
+  return pcg_impl(h, b, u, rtol, maxit, iters, relres, 1);
 }
 
 /* ------------------------------------------------------------ introspection */
@@ -811,6 +968,14 @@ int orc_export_level(const orc_h *h, int k, int32_t *rp, int32_t *ci, double *v,
     if (agg) memcpy(agg, h->agg[k], sizeof(int32_t) * (size_t)A->n);
     if (pval) memcpy(pval, h->pval[k], sizeof(double) * (size_t)A->n);
   }
+  return ORC_OK;
+}
+
+/* Inverse of the coarsest matrix (n_c x n_c, row-major). */
+int orc_export_coarse_inverse(const orc_h *h, double *Ainv) {
+  if (!h || !h->coarse_dense) return ORC_INVALID;
+  int32_t m = h->A[h->nlev - 1].n;
+  memcpy(Ainv, h->Ainv, sizeof(double) * (size_t)m * m);
   return ORC_OK;
 }
 

@@ -70,9 +70,10 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kSlice = 64;         // SELL slice height = one wavefront of rows
 constexpr int kBlock = 256;        // rows per workgroup in row-parallel kernels
 constexpr int kXcd = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
-constexpr int kMaxDotBlocks = 2048;
 constexpr int kDenseMax = 1024;    // largest coarsest level factored densely
 constexpr double kStagnation = 0.95;
+constexpr int kTailRows = 1024;    // levels up to this size run in the coarse-tail kernel
+constexpr int kTailThreads = 1024;
 
 // Canonical CSR (setup, export, next-level construction).
 struct DevCSR {
@@ -113,7 +114,22 @@ struct Level {
 
 struct Scalars {        // PCG state living in device memory
   double rho, c, a, rr, nr0, thr, alpha, beta, gamma;
-  int it, done, status, pad;
+  int it;       // preconditioner applications so far
+  int done;     // 1 once converged, broken down or at maxit
+  int status;   // 0 or an AMG_ERR_* code
+  int conv;     // 1 if ||r|| <= rtol ||r_0|| was reached
+  int maxit;
+  int pad;
+};
+
+// Device-side description of one level for the coarse-tail kernel.
+template <class T>
+struct TailDesc {
+  int n, nc;
+  const int *sptr, *col;
+  const T *val, *dinv, *pval;
+  const int *agg, *mptr, *mem;
+  T *r, *x, *t;
 };
 
 struct Timing {
@@ -129,13 +145,16 @@ struct amg_hierarchy {
   int own_stream = 0;
   std::vector<amg::Level> L;
   int coarse_dense = 0;
-  amg::dvec<double> Lc, LcT;   // coarsest Cholesky factor, column-major and row-major
+  amg::dvec<double> Ainv;      // inverse of the coarsest matrix, column-major
+  // levels [tail_start, levels) run inside one workgroup (coarse-tail kernel)
+  int tail_start = 0;
+  amg::dvec<unsigned char> tail_desc_d, tail_desc_f;   // TailDesc<double> / <float> arrays
   // PCG vectors
   amg::dvec<double> u, r, w, v, d, q;
-  amg::dvec<double> partials;  // kMaxDotBlocks * 3
-  amg::dvec<unsigned> counter; // last-block detection
+  amg::dvec<double> partials;  // 3 per workgroup of the fine-level reductions
   amg::dvec<amg::Scalars> sc;
-  amg::Scalars *sc_host = nullptr;   // pinned mirror
+  amg::Scalars *sc_host = nullptr;   // pinned, host-coherent mirror written by the GPU
+  amg::Scalars *sc_host_dev = nullptr;   // device address of sc_host
   amg::Timing tm;
   // hipGraph of one PCG iteration (V-cycle + SpMV/dots + update)
   hipGraph_t graph = nullptr;

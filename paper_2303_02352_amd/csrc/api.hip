@@ -61,9 +61,9 @@ int64_t device_bytes(const amg_hierarchy *h) {
     b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
     b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();
   }
-  b += h->Lc.bytes() + h->LcT.bytes();
+  b += h->Ainv.bytes() + h->tail_desc_d.bytes() + h->tail_desc_f.bytes();
   b += h->u.bytes() + h->r.bytes() + h->w.bytes() + h->v.bytes() + h->d.bytes() + h->q.bytes();
-  b += h->partials.bytes() + h->counter.bytes() + h->sc.bytes();
+  b += h->partials.bytes() + h->sc.bytes();
   return b;
 }
 }  // namespace amg

@@ -154,6 +154,16 @@ __global__ void k_l1_dinv(int n, const int *rp, const double *v, double *dinv) {
   dinv[i] = 1.0 / m;
 }
 
+// binary32 diagonal of the mixed-precision V-cycle: the same fold over the
+// values rounded to binary32, carried out in binary32.
+__global__ void k_l1_dinv_f(int n, const int *rp, const double *v, float *dinv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float m = 0.0f;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) m = m + fabsf(static_cast<float>(v[k]));
+  dinv[i] = 1.0f / m;
+}
+
 // One sweep on CSR (setup only): xn = x + dinv * (r - A x), r = 0 here.
 __global__ void k_csr_relax0(int n, const int *rp, const int *ci, const double *v,
                              const double *dinv, const double *x, double *xn) {
@@ -490,14 +500,23 @@ __global__ void k_cholesky(int n, double *D, int *flag) {
   if (threadIdx.x == 0 && bad) *flag = 1;
 }
 
-// Lcm: column-major L (Lcm[j*n + i] = L_ij), Lrm: row-major (Lrm[i*n + j] = L_ij).
-__global__ void k_split_factor(int n, const double *D, double *Lcm, double *Lrm) {
-  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= static_cast<int64_t>(n) * n) return;
-  const int i = static_cast<int>(t / n), j = static_cast<int>(t % n);
-  const double x = (j <= i) ? D[t] : 0.0;
-  Lrm[t] = x;
-  Lcm[static_cast<int64_t>(j) * n + i] = x;
+// Inverse of the coarsest matrix from its Cholesky factor L (row-major lower
+// triangle of D): thread j solves L y = e_j (k ascending), then L^T x = y
+// (k descending) and stores x as column j of the column-major inverse.
+__global__ void k_chol_inverse(int n, const double *D, double *Ainv) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double *x = Ainv + static_cast<int64_t>(j) * n;
+  for (int i = 0; i < n; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = 0; k < i; ++k) s = s - D[static_cast<int64_t>(i) * n + k] * x[k];
+    x[i] = s / D[static_cast<int64_t>(i) * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = x[i];
+    for (int k = n - 1; k > i; --k) s = s - D[static_cast<int64_t>(k) * n + i] * x[k];
+    x[i] = s / D[static_cast<int64_t>(i) * n + i];
+  }
 }
 
 // --------------------------------------------------------- host helpers
@@ -634,8 +653,7 @@ void finish_level(Level &Lv, hipStream_t s, bool want_float) {
   build_sell(Lv, s, want_float);
   if (want_float) {
     Lv.dinvf.alloc(n);
-    hipLaunchKernelGGL(k_d2f, grid_for(n), dim3(kBlock), 0, s, static_cast<int64_t>(n), Lv.dinv.p,
-                       Lv.dinvf.p);
+    hipLaunchKernelGGL(k_l1_dinv_f, grid_for(n), dim3(kBlock), 0, s, n, Lv.A.rp.p, Lv.A.v.p, Lv.dinvf.p);
     AMG_LAUNCH_CHECK();
   }
 }
@@ -789,9 +807,8 @@ void coarse_factor(amg_hierarchy *h) {
   hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, n, D.p, flag.p);
   AMG_LAUNCH_CHECK();
   if (read_int(flag.p, s)) fail(AMG_ERR_NOT_SPD, "coarsest matrix has a non-positive Cholesky pivot");
-  h->Lc.alloc(nn);
-  h->LcT.alloc(nn);
-  hipLaunchKernelGGL(k_split_factor, grid_for(nn), dim3(kBlock), 0, s, n, D.p, h->Lc.p, h->LcT.p);
+  h->Ainv.alloc(nn);
+  hipLaunchKernelGGL(k_chol_inverse, grid_for(n), dim3(kBlock), 0, s, n, D.p, h->Ainv.p);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipStreamSynchronize(s));
 }

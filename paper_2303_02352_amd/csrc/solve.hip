@@ -4,11 +4,18 @@
 // one row per lane, entries in CSR order), so every row sum is a left fold
 // in CSR order: SpMV, sweeps, residuals, restriction and prolongation give
 // the same bits as a sequential evaluation.  Only the three PCG dot products
-// and the residual norm are tree reductions (fixed order, so repeatable).
+// and the residual norm are tree reductions; they run in two phases (one
+// partial per workgroup, then one workgroup folds the partials in index
+// order), so they are repeatable and need no grid-wide fences.
+//
+// Kernels that belong to a PCG iteration take `skip` (the device-side
+// `done` flag): once the iteration has converged or broken down they return
+// at once, which lets the host keep the next iteration queued.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "amg_internal.hpp"
 
@@ -20,9 +27,14 @@ inline dim3 grid_for(int64_t n, int block = kBlock) {
   return dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + block - 1) / block)));
 }
 
+#define AMG_SKIP_IF_DONE() \
+  if (skip && *skip) return
+
 // ------------------------------------------------------ SELL row kernels
-// Row r of slice s: slots sptr[s] + k*64 + lane, k < width(s).
-template <class T>
+// Row r of slice s: slots sptr[s] + k*64 + lane, k < width(s).  Streamed
+// (non-temporal) loads for matrices read once per pass; plain loads in the
+// coarse-tail kernel, whose working set stays in cache.
+template <class T, bool kStream = true>
 __device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
                                          const T *__restrict__ val, const T *__restrict__ x, int r,
                                          T &sum, T &l1) {
@@ -30,13 +42,15 @@ __device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int
   const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
   const int *cp = col + b + lane;
   const T *vp = val + b + lane;
+  auto ldc = [](const int *p) { return kStream ? ld_stream(p) : *p; };
+  auto ldv = [](const T *p) { return kStream ? ld_stream(p) : *p; };
   T acc = T(0), m = T(0);
   int k = 0;
   for (; k + 4 <= width; k += 4) {
-    const int c0 = ld_stream(cp + (k + 0) * 64), c1 = ld_stream(cp + (k + 1) * 64);
-    const int c2 = ld_stream(cp + (k + 2) * 64), c3 = ld_stream(cp + (k + 3) * 64);
-    const T a0 = ld_stream(vp + (k + 0) * 64), a1 = ld_stream(vp + (k + 1) * 64);
-    const T a2 = ld_stream(vp + (k + 2) * 64), a3 = ld_stream(vp + (k + 3) * 64);
+    const int c0 = ldc(cp + (k + 0) * 64), c1 = ldc(cp + (k + 1) * 64);
+    const int c2 = ldc(cp + (k + 2) * 64), c3 = ldc(cp + (k + 3) * 64);
+    const T a0 = ldv(vp + (k + 0) * 64), a1 = ldv(vp + (k + 1) * 64);
+    const T a2 = ldv(vp + (k + 2) * 64), a3 = ldv(vp + (k + 3) * 64);
     const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
     acc = acc + a0 * x0; m = m + fabs(a0);
     acc = acc + a1 * x1; m = m + fabs(a1);
@@ -44,8 +58,8 @@ __device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int
     acc = acc + a3 * x3; m = m + fabs(a3);
   }
   for (; k < width; ++k) {
-    const int c = ld_stream(cp + k * 64);
-    const T a = ld_stream(vp + k * 64);
+    const int c = ldc(cp + k * 64);
+    const T a = ldv(vp + k * 64);
     acc = acc + a * x[c];
     m = m + fabs(a);
   }
@@ -66,13 +80,15 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ 
 }
 
 // l1-Jacobi sweep: xn = x + dinv * (r - A x), dinv = 1 / sum_j |a_ij| taken
-// from the streamed row (same fold as the stored diagonal would use).
+// from the streamed row (the same fold that defines the stored diagonal).
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_sweep(int n, const int *__restrict__ sptr,
+__global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n,
+                                                  const int *__restrict__ sptr,
                                                   const int *__restrict__ col,
                                                   const T *__restrict__ val,
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ x, T *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -83,144 +99,305 @@ __global__ void __launch_bounds__(kBlock) k_sweep(int n, const int *__restrict__
 
 // First sweep from x = 0: x = dinv * r.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_sweep_first(int n, const T *__restrict__ dinv,
+__global__ void __launch_bounds__(kBlock) k_sweep_first(const int *skip, int n,
+                                                        const T *__restrict__ dinv,
                                                         const T *__restrict__ rhs,
                                                         T *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r < n) x[r] = dinv[r] * rhs[r];
 }
 
-// Residual + restriction fused per aggregate:
-// rc[I] = sum over members i of I (ascending) of p_i (r_i - (A x)_i).
+// Restriction, pass 1 (row parallel): t_i = p_i (r_i - (A x)_i).
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int *__restrict__ mptr,
-                                                     const int *__restrict__ mem,
-                                                     const T *__restrict__ pval,
-                                                     const int *__restrict__ sptr,
-                                                     const int *__restrict__ col,
-                                                     const T *__restrict__ val,
-                                                     const T *__restrict__ rhs,
-                                                     const T *__restrict__ x, T *__restrict__ rc) {
+__global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n,
+                                                         const int *__restrict__ sptr,
+                                                         const int *__restrict__ col,
+                                                         const T *__restrict__ val,
+                                                         const T *__restrict__ pval,
+                                                         const T *__restrict__ rhs,
+                                                         const T *__restrict__ x,
+                                                         T *__restrict__ t) {
+  AMG_SKIP_IF_DONE();
+  const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (r >= n) return;
+  T s, m;
+  sell_row(sptr, col, val, x, r, s, m);
+  t[r] = pval[r] * (rhs[r] - s);
+}
+
+// Restriction, pass 2 (aggregate parallel): r_c[I] = sum of t over the
+// members of I in ascending order.  When the coarse level starts with a
+// smoothing sweep its first iterate x_c = dinv_c r_c is written as well.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_agg_sum(const int *skip, int nc,
+                                                    const int *__restrict__ mptr,
+                                                    const int *__restrict__ mem,
+                                                    const T *__restrict__ t, T *__restrict__ rc,
+                                                    const T *__restrict__ dinvc,
+                                                    T *__restrict__ xc) {
+  AMG_SKIP_IF_DONE();
   const int I = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (I >= nc) return;
   T acc = T(0);
-  for (int q = mptr[I]; q < mptr[I + 1]; ++q) {
-    const int i = mem[q];
-    T s, m;
-    sell_row(sptr, col, val, x, i, s, m);
-    acc = acc + pval[i] * (rhs[i] - s);
-  }
+  for (int q = mptr[I]; q < mptr[I + 1]; ++q) acc = acc + t[mem[q]];
   rc[I] = acc;
+  if (xc) xc[I] = dinvc[I] * acc;
 }
 
 // x_i += p_i * e[agg_i]
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_prolong(int n, const int *__restrict__ agg,
+__global__ void __launch_bounds__(kBlock) k_prolong(const int *skip, int n,
+                                                    const int *__restrict__ agg,
                                                     const T *__restrict__ pval,
                                                     const T *__restrict__ e, T *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r < n) x[r] = x[r] + pval[r] * e[agg[r]];
 }
 
 template <class T>
-__global__ void k_zero(int n, T *x) {
+__global__ void k_zero(const int *skip, int n, T *x) {
+  AMG_SKIP_IF_DONE();
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) x[r] = T(0);
 }
 
-__global__ void k_f2d(int n, const float *a, double *b) {
+// Mixed precision entry: rf = (float) r and, if the fine level starts with a
+// sweep, its first iterate x = dinv * rf.
+__global__ void __launch_bounds__(kBlock) k_d2f_first(const int *skip, int n,
+                                                      const double *__restrict__ r,
+                                                      const float *__restrict__ dinv,
+                                                      float *__restrict__ rf,
+                                                      float *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float b = static_cast<float>(r[i]);
+  rf[i] = b;
+  if (x) x[i] = dinv[i] * b;
+}
+
+__global__ void k_f2d(const int *skip, int n, const float *__restrict__ a, double *__restrict__ b) {
+  AMG_SKIP_IF_DONE();
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) b[r] = static_cast<double>(a[r]);
 }
 
-// ---------------------------------------------------- coarsest direct solve
-// One wavefront: L y = r by columns (k ascending per row), then L^T x = y by
-// columns (k descending per row): the same folds as row-oriented substitution.
-template <class TI, class TO>
-__global__ void __launch_bounds__(kWave) k_chol_solve(int n, const double *__restrict__ Lcm,
-                                                      const double *__restrict__ Lrm,
-                                                      const TI *__restrict__ rin,
-                                                      TO *__restrict__ xout) {
-  extern __shared__ double sh[];
-  double *s = sh;        // running right-hand side
-  double *y = sh + n;    // solution of the current triangle
-  for (int i = threadIdx.x; i < n; i += kWave) s[i] = static_cast<double>(rin[i]);
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double yj = s[j] / Lcm[static_cast<int64_t>(j) * n + j];
-    if (threadIdx.x == 0) y[j] = yj;
-    for (int i = j + 1 + threadIdx.x; i < n; i += kWave)
-      s[i] = s[i] - Lcm[static_cast<int64_t>(j) * n + i] * yj;
+// ------------------------------------------------------ coarse-tail kernel
+// Levels [kt, nl) of the V-cycle in ONE workgroup: every phase (sweep,
+// scaled residual, aggregate sum, prolongation, coarsest solve) loops over
+// the level's rows and ends with a workgroup barrier, so the small levels
+// cost no kernel launches and their data stays in this CU's caches.  The
+// per-row folds are the ones of the multi-workgroup kernels.
+// Coarsest level: z = A^-1 r with the column-major inverse, row i folded
+// over j ascending, in binary64 (also for the binary32 cycle).
+template <class T>
+__device__ __forceinline__ T *tail_first(const TailDesc<T> &L, bool coarsest, int dense, int pre,
+                                         int post, int csw, T *out) {
+  if (coarsest) {
+    if (dense) return nullptr;
+    return ((csw - 1) % 2 == 0) ? out : L.t;
+  }
+  if (pre == 0) return nullptr;
+  return (((pre - 1) + post) % 2 == 0) ? out : L.t;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(
+    const int *skip, int m, const TailDesc<T> *__restrict__ D, const double *__restrict__ Ainv,
+    int dense, int pre, int post, int csw, const T *__restrict__ top_rhs, T *__restrict__ top_out,
+    int first_done) {
+  AMG_SKIP_IF_DONE();
+  __shared__ T *Abuf[AMG_MAX_LEVELS], *Bbuf[AMG_MAX_LEVELS];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // ---- descent
+  for (int j = 0; j < m; ++j) {
+    const TailDesc<T> L = D[j];
+    const T *rhs = (j == 0) ? top_rhs : L.r;
+    T *out = (j == 0) ? top_out : L.x;
+    const bool coarsest = (j == m - 1);
+    const bool have_first = (j == 0) ? (first_done != 0) : true;
+    if (coarsest) {
+      if (dense) {
+        for (int i = tid; i < L.n; i += nt) {
+          double acc = 0.0;
+          for (int c = 0; c < L.n; ++c)
+            acc = acc + Ainv[static_cast<int64_t>(c) * L.n + i] * static_cast<double>(rhs[c]);
+          out[i] = static_cast<T>(acc);
+        }
+      } else {
+        T *A = tail_first<T>(L, true, dense, pre, post, csw, out);
+        T *B = (A == out) ? L.t : out;
+        if (!have_first)
+          for (int i = tid; i < L.n; i += nt) A[i] = L.dinv[i] * rhs[i];
+        __syncthreads();
+        for (int q = 1; q < csw; ++q) {
+          for (int i = tid; i < L.n; i += nt) {
+            T sm, l1;
+            sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
+            B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
+          }
+          __syncthreads();
+          T *tmp = A; A = B; B = tmp;
+        }
+      }
+      __syncthreads();
+      break;
+    }
+    const int swaps = (pre > 0 ? pre - 1 : 0) + post;
+    T *A = (swaps % 2 == 0) ? out : L.t;
+    T *B = (A == out) ? L.t : out;
+    if (pre == 0) {
+      for (int i = tid; i < L.n; i += nt) A[i] = T(0);
+    } else if (!have_first) {
+      for (int i = tid; i < L.n; i += nt) A[i] = L.dinv[i] * rhs[i];
+    }
+    __syncthreads();
+    for (int q = 1; q < pre; ++q) {
+      for (int i = tid; i < L.n; i += nt) {
+        T sm, l1;
+        sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
+        B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
+      }
+      __syncthreads();
+      T *tmp = A; A = B; B = tmp;
+    }
+    for (int i = tid; i < L.n; i += nt) {
+      T sm, l1;
+      sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
+      B[i] = L.pval[i] * (rhs[i] - sm);
+    }
+    __syncthreads();
+    const TailDesc<T> C = D[j + 1];
+    T *xc = tail_first<T>(C, j + 1 == m - 1, dense, pre, post, csw, C.x);
+    for (int I = tid; I < L.nc; I += nt) {
+      T acc = T(0);
+      for (int q = L.mptr[I]; q < L.mptr[I + 1]; ++q) acc = acc + B[L.mem[q]];
+      C.r[I] = acc;
+      if (xc) xc[I] = C.dinv[I] * acc;
+    }
+    if (tid == 0) { Abuf[j] = A; Bbuf[j] = B; }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += kWave) s[i] = y[i];
-  __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
-    const double xj = s[j] / Lrm[static_cast<int64_t>(j) * n + j];
-    if (threadIdx.x == 0) y[j] = xj;
-    for (int i = threadIdx.x; i < j; i += kWave)
-      s[i] = s[i] - Lrm[static_cast<int64_t>(j) * n + i] * xj;
+  // ---- ascent
+  for (int j = m - 2; j >= 0; --j) {
+    const TailDesc<T> L = D[j];
+    const T *rhs = (j == 0) ? top_rhs : L.r;
+    const T *e = D[j + 1].x;
+    T *A = Abuf[j], *B = Bbuf[j];
+    for (int i = tid; i < L.n; i += nt) A[i] = A[i] + L.pval[i] * e[L.agg[i]];
     __syncthreads();
+    for (int q = 0; q < post; ++q) {
+      for (int i = tid; i < L.n; i += nt) {
+        T sm, l1;
+        sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
+        B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
+      }
+      __syncthreads();
+      T *tmp = A; A = B; B = tmp;
+    }
   }
-  for (int i = threadIdx.x; i < n; i += kWave) xout[i] = static_cast<TO>(y[i]);
 }
 
 // ----------------------------------------------------------- PCG kernels
-// Row chunking shared by the reduction kernels: G <= 2048 workgroups, each
-// owns a contiguous run of rows (multiple of 256) and writes one partial per
-// quantity; the last workgroup to finish folds the partials in index order.
-__device__ __forceinline__ double block_sum(double v, double *red) {
+constexpr int kFinish = 1024;   // threads of the one-workgroup finishing kernels
+constexpr int kRowsDot = 2;     // rows per thread in the SpMV + dots kernels
+constexpr int kRowsUpd = 4;     // elements per thread in the vector update
+
+// Deterministic workgroup sum (fixed butterfly in each wave, waves in order).
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double *red) {
   v = wave_sum(v);
   const int wid = threadIdx.x / kWave;
-  __syncthreads();
   if ((threadIdx.x & (kWave - 1)) == 0) red[wid] = v;
   __syncthreads();
   double t = red[0];
-  for (int q = 1; q < kBlock / kWave; ++q) t = t + red[q];
+  for (int q = 1; q < NT / kWave; ++q) t = t + red[q];
+  __syncthreads();
   return t;
 }
 
-// Returns true in every thread of the last workgroup to arrive.
-__device__ __forceinline__ bool arrive_last(unsigned *counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
+// Fold part[q*3 + o], q = 0..np-1, for o < NQ: each thread folds its
+// indices q = tid, tid + 1024, ... in order (loads issued four at a time),
+// then the workgroup sum combines the threads in a fixed order.
+template <int NQ>
+__device__ __forceinline__ void fold_parts(const double *__restrict__ part, int np, double *red,
+                                           double *out) {
+  double acc[NQ];
+#pragma unroll
+  for (int o = 0; o < NQ; ++o) acc[o] = 0.0;
+  int q = threadIdx.x;
+  for (; q + 3 * kFinish < np; q += 4 * kFinish) {
+    double v[4][NQ];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int o = 0; o < NQ; ++o) v[u][o] = part[(q + u * kFinish) * 3 + o];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + v[u][o];
+  }
+  for (; q < np; q += kFinish)
+#pragma unroll
+    for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + part[q * 3 + o];
+#pragma unroll
+  for (int o = 0; o < NQ; ++o) out[o] = group_sum<kFinish>(acc[o], red);
 }
 
-__device__ __forceinline__ double fold_partials(const double *part, int np, int stride_off,
-                                                double *red) {
-  double t = 0.0;
-  for (int q = threadIdx.x; q < np; q += kBlock) t = t + part[q * 3 + stride_off];
-  return block_sum(t, red);
+// Optional outputs of the kernels that produce the PCG residual r: the first
+// smoothing iterate of the next V-cycle (x = dinv * r), or for the binary32
+// cycle rf = (float) r and x = dinv_f * rf.  Null pointers disable them.
+struct FirstOut {
+  const double *dinv;
+  double *x;
+  const float *dinvf;
+  float *rf;
+  float *xf;
+};
+
+__device__ __forceinline__ void first_out(const FirstOut &fo, int i, double ri) {
+  if (fo.x) fo.x[i] = fo.dinv[i] * ri;
+  if (fo.rf) {
+    const float b = static_cast<float>(ri);
+    fo.rf[i] = b;
+    if (fo.xf) fo.xf[i] = fo.dinvf[i] * b;
+  }
 }
 
-// r = b - A u; ||r||^2.  Last block: nr0, threshold rtol * nr0, reset state.
-__global__ void __launch_bounds__(kBlock) k_pcg_init(int n, int rpb, const int *__restrict__ sptr,
+// r = b - A u, partial ||r||^2 per workgroup (kRowsDot rows per thread).
+__global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const int *__restrict__ sptr,
                                                      const int *__restrict__ col,
                                                      const double *__restrict__ val,
                                                      const double *__restrict__ b,
                                                      const double *__restrict__ u,
-                                                     double *__restrict__ r, double *part,
-                                                     unsigned *counter, Scalars *sc, double rtol) {
+                                                     double *__restrict__ r,
+                                                     double *__restrict__ part, FirstOut fo) {
   __shared__ double red[kBlock / kWave];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
   double rr = 0.0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    double s, m;
-    sell_row(sptr, col, val, u, row, s, m);
-    const double ri = b[row] - s;
-    r[row] = ri;
-    rr = rr + ri * ri;
+#pragma unroll
+  for (int h = 0; h < kRowsDot; ++h) {
+    const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
+    if (row < n) {
+      double s, m;
+      sell_row(sptr, col, val, u, row, s, m);
+      const double ri = b[row] - s;
+      r[row] = ri;
+      first_out(fo, row, ri);
+      rr = rr + ri * ri;
+    }
   }
-  rr = block_sum(rr, red);
+  rr = group_sum<kBlock>(rr, red);
   if (threadIdx.x == 0) part[lb * 3] = rr;
-  if (!arrive_last(counter)) return;
-  const double tot = fold_partials(part, gridDim.x, 0, red);
+}
+
+__global__ void __launch_bounds__(kFinish) k_pcg_init_finish(int nb, const double *part,
+                                                             Scalars *sc, double rtol, int maxit) {
+  __shared__ double red[kFinish / kWave];
+  double tot;
+  fold_parts<1>(part, nb, red, &tot);
   if (threadIdx.x == 0) {
     const double nr0 = sqrt(tot);
     sc->nr0 = nr0;
@@ -230,49 +407,60 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, int rpb, const int *
     sc->c = 0.0;
     sc->a = 0.0;
     sc->it = 0;
+    sc->maxit = maxit;
+    sc->conv = (nr0 == 0.0) ? 1 : 0;
     sc->status = isfinite(nr0) ? 0 : AMG_ERR_NONFINITE;
     sc->done = (nr0 == 0.0 || !isfinite(nr0)) ? 1 : 0;
-    *counter = 0u;
   }
 }
 
-// v = A w; alpha = w.r, beta = w.v, gamma = w.q.  Last block: rho, c, a (Alg. 1).
+// v = A w and partial dots alpha = w.r, beta = w.v, gamma = w.q.
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
-    int n, int rpb, const int *__restrict__ sptr, const int *__restrict__ col,
+    const int *skip, int n, const int *__restrict__ sptr, const int *__restrict__ col,
     const double *__restrict__ val, const double *__restrict__ w, const double *__restrict__ r,
-    const double *__restrict__ q, double *__restrict__ v, double *part, unsigned *counter,
-    Scalars *sc) {
+    const double *__restrict__ q, double *__restrict__ v, double *__restrict__ part) {
+  AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock / kWave];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
   double al = 0.0, be = 0.0, ga = 0.0;
-  for (int row = r0 + threadIdx.x; row < r1; row += kBlock) {
-    double s, m;
-    sell_row(sptr, col, val, w, row, s, m);
-    v[row] = s;
-    const double wi = w[row];
-    al = al + wi * r[row];
-    be = be + wi * s;
-    ga = ga + wi * q[row];
+#pragma unroll
+  for (int h = 0; h < kRowsDot; ++h) {
+    const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
+    if (row < n) {
+      double s, m;
+      sell_row(sptr, col, val, w, row, s, m);
+      v[row] = s;
+      const double wi = w[row];
+      al = al + wi * r[row];
+      be = be + wi * s;
+      ga = ga + wi * q[row];
+    }
   }
-  al = block_sum(al, red);
-  be = block_sum(be, red);
-  ga = block_sum(ga, red);
+  al = group_sum<kBlock>(al, red);
+  be = group_sum<kBlock>(be, red);
+  ga = group_sum<kBlock>(ga, red);
   if (threadIdx.x == 0) {
     part[lb * 3 + 0] = al;
     part[lb * 3 + 1] = be;
     part[lb * 3 + 2] = ga;
   }
-  if (!arrive_last(counter)) return;
-  const double A = fold_partials(part, gridDim.x, 0, red);
-  const double B = fold_partials(part, gridDim.x, 1, red);
-  const double G = fold_partials(part, gridDim.x, 2, red);
+}
+
+// rho_i = beta - gamma^2 / rho_{i-1}; c = gamma / rho_{i-1}; a = alpha / rho_i (Alg. 1).
+__global__ void __launch_bounds__(kFinish) k_pcg_dots_finish(const int *skip, int nb,
+                                                             const double *part, Scalars *sc) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double red[kFinish / kWave];
+  double t[3];
+  fold_parts<3>(part, nb, red, t);
   if (threadIdx.x == 0) {
+    const double A = t[0], B = t[1], G = t[2];
     const double rho_prev = sc->rho;
     const double rho = B - (G * G) / rho_prev;
     sc->alpha = A;
     sc->beta = B;
     sc->gamma = G;
+    sc->it = sc->it + 1;
     if (!isfinite(rho) || !isfinite(A)) {
       sc->status = AMG_ERR_NONFINITE;
       sc->done = 1;
@@ -283,45 +471,68 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
     sc->c = G / rho_prev;
     sc->a = A / rho;
     sc->rho = rho;
-    *counter = 0u;
   }
 }
 
-// d = w - c d; u = u + a d; q = v - c q; r = r - a q; ||r||^2.
-// Last block: convergence test ||r|| <= rtol ||r_0|| (Sec. 5).
-__global__ void __launch_bounds__(kBlock) k_pcg_update(int n, int rpb, const double *__restrict__ w,
+// d = w - c d; u = u + a d; q = v - c q; r = r - a q; partial ||r||^2.
+__global__ void __launch_bounds__(kBlock) k_pcg_update(const int *skip, int n,
+                                                       const double *__restrict__ w,
                                                        const double *__restrict__ v,
                                                        double *__restrict__ d,
                                                        double *__restrict__ u,
                                                        double *__restrict__ q,
-                                                       double *__restrict__ r, double *part,
-                                                       unsigned *counter, Scalars *sc) {
+                                                       double *__restrict__ r,
+                                                       const Scalars *__restrict__ sc,
+                                                       double *__restrict__ part, FirstOut fo) {
+  AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock / kWave];
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int r0 = lb * rpb, r1 = min(n, r0 + rpb);
   const double c = sc->c, a = sc->a;
   double rr = 0.0;
-  for (int i = r0 + threadIdx.x; i < r1; i += kBlock) {
-    const double di = w[i] - c * d[i];
-    d[i] = di;
-    u[i] = u[i] + a * di;
-    const double qi = v[i] - c * q[i];
-    q[i] = qi;
-    const double ri = r[i] - a * qi;
-    r[i] = ri;
-    rr = rr + ri * ri;
+#pragma unroll
+  for (int h = 0; h < kRowsUpd; ++h) {
+    const int i = (lb * kRowsUpd + h) * kBlock + threadIdx.x;
+    if (i < n) {
+      const double di = w[i] - c * d[i];
+      d[i] = di;
+      u[i] = u[i] + a * di;
+      const double qi = v[i] - c * q[i];
+      q[i] = qi;
+      const double ri = r[i] - a * qi;
+      r[i] = ri;
+      first_out(fo, i, ri);
+      rr = rr + ri * ri;
+    }
   }
-  rr = block_sum(rr, red);
+  rr = group_sum<kBlock>(rr, red);
   if (threadIdx.x == 0) part[lb * 3] = rr;
-  if (!arrive_last(counter)) return;
-  const double tot = fold_partials(part, gridDim.x, 0, red);
+}
+
+// ||r|| <= rtol ||r_0|| ends the iteration (Sec. 5); so do a non-finite norm
+// and the iteration limit.  The state is then copied to host-coherent pinned
+// memory (also when the iteration was skipped), which the host polls.
+__global__ void __launch_bounds__(kFinish) k_pcg_norm_finish(const int *skip, int nb,
+                                                             const double *part, Scalars *sc,
+                                                             Scalars *host) {
+  __shared__ double red[kFinish / kWave];
+  const bool live = !(*skip);
+  double tot = 0.0;
+  if (live) fold_parts<1>(part, nb, red, &tot);
   if (threadIdx.x == 0) {
-    const double nr = sqrt(tot);
-    sc->rr = tot;
-    sc->it = sc->it + 1;
-    if (nr <= sc->thr) sc->done = 1;
-    else if (!isfinite(nr)) { sc->status = AMG_ERR_NONFINITE; sc->done = 1; }
-    *counter = 0u;
+    if (live) {
+      const double nr = sqrt(tot);
+      sc->rr = tot;
+      if (nr <= sc->thr) {
+        sc->conv = 1;
+        sc->done = 1;
+      } else if (!isfinite(nr)) {
+        sc->status = AMG_ERR_NONFINITE;
+        sc->done = 1;
+      } else if (sc->it >= sc->maxit) {
+        sc->done = 1;
+      }
+    }
+    *host = *sc;
   }
 }
 
@@ -345,32 +556,60 @@ template <class T> T *tbuf(Level &L);
 template <> double *tbuf<double>(Level &L) { return L.t.p; }
 template <> float *tbuf<float>(Level &L) { return L.tf.p; }
 
+template <class T> const TailDesc<T> *tail_desc(amg_hierarchy *h);
+template <> const TailDesc<double> *tail_desc<double>(amg_hierarchy *h) {
+  return reinterpret_cast<const TailDesc<double> *>(h->tail_desc_d.p);
+}
+template <> const TailDesc<float> *tail_desc<float>(amg_hierarchy *h) {
+  return reinterpret_cast<const TailDesc<float> *>(h->tail_desc_f.p);
+}
+
 template <class T>
-void launch_sweep(const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s) {
+void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s) {
   const int n = L.A.n;
-  hipLaunchKernelGGL(k_sweep<T>, grid_for(n), dim3(kBlock), 0, s, n, L.S.sptr.p, L.S.col.p,
+  hipLaunchKernelGGL(k_sweep<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.S.sptr.p, L.S.col.p,
                      vals<T>(L.S), rhs, x, xn);
 }
 
-// Level k of the V-cycle in precision T; result lands in `out`.
+// Where level k puts the first smoothing iterate so that, after all its
+// ping-pong sweeps, the level's result lands in `out`.  nullptr when the
+// level has no first sweep (direct coarsest solve, or no pre-smoothing).
 template <class T>
-void vcycle_level(amg_hierarchy *h, int k, const T *rhs, T *out) {
+T *first_buffer(amg_hierarchy *h, int k, T *out) {
+  Level &L = h->L[k];
+  const amg_params &P = h->p;
+  if (k == static_cast<int>(h->L.size()) - 1) {
+    if (h->coarse_dense) return nullptr;
+    return ((P.coarse_sweeps - 1) % 2 == 0) ? out : tbuf<T>(L);
+  }
+  if (P.pre_sweeps == 0) return nullptr;
+  const int swaps = (P.pre_sweeps - 1) + P.post_sweeps;
+  return (swaps % 2 == 0) ? out : tbuf<T>(L);
+}
+
+// Level k of the V-cycle in precision T; the result lands in `out`.
+// first_done: the first smoothing iterate is already in first_buffer(k).
+template <class T>
+void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out, bool first_done) {
   hipStream_t s = h->stream;
   Level &L = h->L[k];
   const int n = L.A.n;
   const int nl = static_cast<int>(h->L.size());
   const amg_params &P = h->p;
+  if (k >= h->tail_start) {
+    hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k,
+                       tail_desc<T>(h) + (k - h->tail_start), h->Ainv.p, h->coarse_dense,
+                       P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out, first_done ? 1 : 0);
+    return;
+  }
   if (k == nl - 1) {
-    if (h->coarse_dense) {
-      const size_t shm = sizeof(double) * 2 * n;
-      hipLaunchKernelGGL((k_chol_solve<T, T>), dim3(1), dim3(kWave), shm, s, n, h->Lc.p, h->LcT.p,
-                         rhs, out);
-    } else {
-      const int sw = P.coarse_sweeps;
-      T *A = (sw - 1) % 2 == 0 ? out : tbuf<T>(L);
+    {
+      T *A = first_buffer<T>(h, k, out);
       T *B = (A == out) ? tbuf<T>(L) : out;
-      hipLaunchKernelGGL(k_sweep_first<T>, grid_for(n), dim3(kBlock), 0, s, n, dinv_of<T>(L), rhs, A);
-      for (int q = 1; q < sw; ++q) { launch_sweep<T>(L, rhs, A, B, s); std::swap(A, B); }
+      if (!first_done)
+        hipLaunchKernelGGL(k_sweep_first<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, dinv_of<T>(L),
+                           rhs, A);
+      for (int q = 1; q < P.coarse_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
     }
     return;
   }
@@ -378,40 +617,122 @@ void vcycle_level(amg_hierarchy *h, int k, const T *rhs, T *out) {
   T *A = (swaps % 2 == 0) ? out : tbuf<T>(L);
   T *B = (A == out) ? tbuf<T>(L) : out;
   if (P.pre_sweeps == 0) {
-    hipLaunchKernelGGL(k_zero<T>, grid_for(n), dim3(kBlock), 0, s, n, A);
+    hipLaunchKernelGGL(k_zero<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, A);
   } else {
-    hipLaunchKernelGGL(k_sweep_first<T>, grid_for(n), dim3(kBlock), 0, s, n, dinv_of<T>(L), rhs, A);
-    for (int q = 1; q < P.pre_sweeps; ++q) { launch_sweep<T>(L, rhs, A, B, s); std::swap(A, B); }
+    if (!first_done)
+      hipLaunchKernelGGL(k_sweep_first<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, dinv_of<T>(L),
+                         rhs, A);
+    for (int q = 1; q < P.pre_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
   }
+  // restriction of the residual; B is free until the first post-sweep
+  hipLaunchKernelGGL(k_resid_scaled<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.S.sptr.p,
+                     L.S.col.p, vals<T>(L.S), pval_of<T>(L), rhs, A, B);
   Level &C = h->L[k + 1];
-  hipLaunchKernelGGL(k_restrict<T>, grid_for(L.nc), dim3(kBlock), 0, s, L.nc, L.mptr.p, L.mem.p,
-                     pval_of<T>(L), L.S.sptr.p, L.S.col.p, vals<T>(L.S), rhs, A, rbuf<T>(C));
-  vcycle_level<T>(h, k + 1, rbuf<T>(C), xbuf<T>(C));
-  hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, n, L.agg.p, pval_of<T>(L),
+  T *xc = first_buffer<T>(h, k + 1, xbuf<T>(C));
+  hipLaunchKernelGGL(k_agg_sum<T>, grid_for(L.nc), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p, L.mem.p,
+                     B, rbuf<T>(C), dinv_of<T>(C), xc);
+  vcycle_level<T>(h, skip, k + 1, rbuf<T>(C), xbuf<T>(C), xc != nullptr);
+  hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
                      xbuf<T>(C), A);
-  for (int q = 0; q < P.post_sweeps; ++q) { launch_sweep<T>(L, rhs, A, B, s); std::swap(A, B); }
+  for (int q = 0; q < P.post_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
 }
 
-// Mixed precision (R: binary32 V-cycle, binary64 outer iteration): r is
-// rounded to binary32 on entry, the whole cycle (coarsest solve excepted,
-// which converts to binary64 inside its kernel) runs in binary32, and the
-// result is widened back to binary64.
-__global__ void k_d2f_vec(int n, const double *a, float *b) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < n) b[r] = static_cast<float>(a[r]);
-}
-
-void vcycle_mixed(amg_hierarchy *h, const double *r, double *z) {
+// Mixed precision: the residual is rounded to binary32 on entry (fused with
+// the first sweep), the cycle runs in binary32 except for the coarsest solve
+// (binary64 inside its kernel), and the result is widened to binary64.
+void vcycle_mixed(amg_hierarchy *h, const int *skip, const double *r, double *z, bool first_done) {
   hipStream_t s = h->stream;
   Level &L = h->L[0];
   const int n = L.A.n;
   if (h->L.size() == 1) {   // single level: the direct solve in binary64
-    vcycle_level<double>(h, 0, r, z);
+    vcycle_level<double>(h, skip, 0, r, z, false);
     return;
   }
-  hipLaunchKernelGGL(k_d2f_vec, grid_for(n), dim3(kBlock), 0, s, n, r, L.rf.p);
-  vcycle_level<float>(h, 0, L.rf.p, L.xf.p);
-  hipLaunchKernelGGL(k_f2d, grid_for(n), dim3(kBlock), 0, s, n, L.xf.p, z);
+  float *x1 = first_buffer<float>(h, 0, L.xf.p);
+  if (!first_done)
+    hipLaunchKernelGGL(k_d2f_first, grid_for(n), dim3(kBlock), 0, s, skip, n, r, L.dinvf.p, L.rf.p, x1);
+  vcycle_level<float>(h, skip, 0, L.rf.p, L.xf.p, x1 != nullptr);
+  hipLaunchKernelGGL(k_f2d, grid_for(n), dim3(kBlock), 0, s, skip, n, L.xf.p, z);
+}
+
+// first_done: the residual kernel already wrote the first smoothing iterate
+// (the outputs described by first_out_for).
+void vcycle_any(amg_hierarchy *h, const int *skip, const double *r, double *z,
+                bool first_done = false) {
+  const int n = h->L[0].A.n;
+  if (!h->p.precond) {
+    AMG_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    return;
+  }
+  if (h->p.precision == AMG_PREC_MIXED) vcycle_mixed(h, skip, r, z, first_done);
+  else vcycle_level<double>(h, skip, 0, r, z, first_done);
+  AMG_LAUNCH_CHECK();
+}
+
+// What the PCG residual kernels write for the next V-cycle whose output is z.
+FirstOut first_out_for(amg_hierarchy *h, double *z) {
+  FirstOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (!h->p.precond) return fo;
+  Level &L = h->L[0];
+  if (h->p.precision == AMG_PREC_MIXED && h->L.size() > 1) {
+    fo.rf = L.rf.p;
+    fo.dinvf = L.dinvf.p;
+    fo.xf = first_buffer<float>(h, 0, L.xf.p);
+  } else {
+    fo.dinv = L.dinv.p;
+    fo.x = first_buffer<double>(h, 0, z);
+  }
+  return fo;
+}
+
+int nb_dot(int n) { return std::max(1, ceil_div(n, kBlock * kRowsDot)); }
+int nb_upd(int n) { return std::max(1, ceil_div(n, kBlock * kRowsUpd)); }
+
+void enqueue_iteration(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  const Level &L0 = h->L[0];
+  const int n = L0.A.n, nbd = nb_dot(n), nbu = nb_upd(n);
+  const int *skip = &h->sc.p->done;
+  const FirstOut fo = first_out_for(h, h->w.p);
+  vcycle_any(h, skip, h->r.p, h->w.p, /*first_done=*/true);
+  hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(nbd), dim3(kBlock), 0, s, skip, n, L0.S.sptr.p,
+                     L0.S.col.p, L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+  hipLaunchKernelGGL(k_pcg_dots_finish, dim3(1), dim3(kFinish), 0, s, skip, nbd, h->partials.p,
+                     h->sc.p);
+  hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, skip, n, h->w.p, h->v.p, h->d.p,
+                     h->u.p, h->q.p, h->r.p, h->sc.p, h->partials.p, fo);
+  hipLaunchKernelGGL(k_pcg_norm_finish, dim3(1), dim3(kFinish), 0, s, skip, nbu, h->partials.p,
+                     h->sc.p, h->sc_host_dev);
+  AMG_LAUNCH_CHECK();
+}
+
+template <class T>
+void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32) {
+  std::vector<TailDesc<T>> D;
+  for (size_t k = h->tail_start; k < h->L.size(); ++k) {
+    Level &L = h->L[k];
+    TailDesc<T> t{};
+    t.n = L.A.n;
+    t.nc = L.nc;
+    t.sptr = L.S.sptr.p;
+    t.col = L.S.col.p;
+    t.val = vals<T>(L.S);
+    t.dinv = dinv_of<T>(L);
+    t.pval = pval_of<T>(L);
+    t.agg = L.agg.p;
+    t.mptr = L.mptr.p;
+    t.mem = L.mem.p;
+    t.r = rbuf<T>(L);
+    t.x = xbuf<T>(L);
+    t.t = tbuf<T>(L);
+    D.push_back(t);
+  }
+  (void)fp32;
+  dst.alloc(sizeof(TailDesc<T>) * std::max<size_t>(1, D.size()));
+  if (!D.empty())
+    AMG_HIP(hipMemcpyAsync(dst.p, D.data(), sizeof(TailDesc<T>) * D.size(), hipMemcpyHostToDevice,
+                           h->stream));
+  AMG_HIP(hipStreamSynchronize(h->stream));
 }
 
 }  // namespace
@@ -433,23 +754,26 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   }
   const int n = h->L[0].A.n;
   h->u.alloc(n); h->r.alloc(n); h->w.alloc(n); h->v.alloc(n); h->d.alloc(n); h->q.alloc(n);
-  h->partials.alloc(kMaxDotBlocks * 3);
-  h->counter.alloc(1);
+  h->partials.alloc(static_cast<size_t>(nb_dot(n)) * 3);
+  // levels small enough for the single-workgroup coarse tail (sizes decrease
+  // down the hierarchy, so the tail is a suffix)
+  const int nl = static_cast<int>(h->L.size());
+  h->tail_start = nl;
+  for (int k = 0; k < nl; ++k)
+    if (h->L[k].A.n <= kTailRows) { h->tail_start = k; break; }
+  if (h->coarse_dense && h->tail_start > nl - 1) fail(AMG_ERR_DEVICE, "dense coarsest level outside the tail");
+  upload_tail<double>(h, h->tail_desc_d, false);
+  if (mixed) upload_tail<float>(h, h->tail_desc_f, true);
   h->sc.alloc(1);
-  AMG_HIP(hipMemsetAsync(h->counter.p, 0, sizeof(unsigned), h->stream));
-  if (!h->sc_host) AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->sc_host), sizeof(Scalars)));
+  AMG_HIP(hipMemsetAsync(h->sc.p, 0, sizeof(Scalars), h->stream));
+  if (!h->sc_host) {
+    AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->sc_host), sizeof(Scalars),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    AMG_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&h->sc_host_dev), h->sc_host, 0));
+  }
 }
 
-void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z) {
-  const int n = h->L[0].A.n;
-  if (!h->p.precond) {
-    AMG_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    return;
-  }
-  if (h->p.precision == AMG_PREC_MIXED) vcycle_mixed(h, r, z);
-  else vcycle_level<double>(h, 0, r, z);
-  AMG_LAUNCH_CHECK();
-}
+void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z) { vcycle_any(h, nullptr, r, z); }
 
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y) {
   const Level &L = h->L[k];
@@ -459,27 +783,9 @@ void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y) {
 }
 
 void enqueue_sweep(amg_hierarchy *h, int k, const double *r, const double *x, double *xn) {
-  launch_sweep<double>(h->L[k], r, x, xn, h->stream);
+  launch_sweep<double>(nullptr, h->L[k], r, x, xn, h->stream);
   AMG_LAUNCH_CHECK();
 }
-
-namespace {
-int dot_blocks(int n) { return std::min(kMaxDotBlocks, std::max(1, ceil_div(n, kBlock))); }
-int rows_per_block(int n, int G) { return ceil_div(ceil_div(n, G), kBlock) * kBlock; }
-
-void enqueue_iteration(amg_hierarchy *h) {
-  hipStream_t s = h->stream;
-  const Level &L0 = h->L[0];
-  const int n = L0.A.n, G = dot_blocks(n), rpb = rows_per_block(n, G);
-  enqueue_vcycle(h, h->r.p, h->w.p);
-  hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(G), dim3(kBlock), 0, s, n, rpb, L0.S.sptr.p, L0.S.col.p,
-                     L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p, h->counter.p,
-                     h->sc.p);
-  hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kBlock), 0, s, n, rpb, h->w.p, h->v.p, h->d.p,
-                     h->u.p, h->q.p, h->r.p, h->partials.p, h->counter.p, h->sc.p);
-  AMG_LAUNCH_CHECK();
-}
-}  // namespace
 
 void destroy_graph(amg_hierarchy *h) {
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
@@ -488,51 +794,64 @@ void destroy_graph(amg_hierarchy *h) {
   h->graph = nullptr;
 }
 
+// Alg. 1.  One iteration = one graph launch [V-cycle, v = A w + dots,
+// scalars, vector updates + ||r||^2, convergence test, copy of the scalars
+// to pinned host memory].  The host keeps one further iteration queued and
+// waits on the older one; a queued iteration after convergence does nothing.
 int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,
               double *relres) {
   hipStream_t s = h->stream;
   const Level &L0 = h->L[0];
-  const int n = L0.A.n, G = dot_blocks(n), rpb = rows_per_block(n, G);
+  const int n = L0.A.n, nb = nb_dot(n);
   AMG_HIP(hipMemcpyAsync(h->u.p, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, n, h->d.p);
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, n, h->q.p);
-  hipLaunchKernelGGL(k_pcg_init, dim3(G), dim3(kBlock), 0, s, n, rpb, L0.S.sptr.p, L0.S.col.p,
-                     L0.S.val.p, b, h->u.p, h->r.p, h->partials.p, h->counter.p, h->sc.p, rtol);
+  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->d.p);
+  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->q.p);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(kBlock), 0, s, n, L0.S.sptr.p, L0.S.col.p, L0.S.val.p,
+                     b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
+  hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, h->partials.p, h->sc.p, rtol,
+                     maxit);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipMemcpyAsync(h->sc_host, h->sc.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   Scalars st = *h->sc_host;
-  if (st.status != 0) { *iters = 0; *relres = NAN; return st.status; }
-  if (st.nr0 == 0.0) {
-    AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (!st.done) {
+    if (h->use_graph && !h->graph_exec) {
+      AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      enqueue_iteration(h);
+      AMG_HIP(hipStreamEndCapture(s, &h->graph));
+      AMG_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    }
+    auto launch = [&]() {
+      if (h->graph_exec) AMG_HIP(hipGraphLaunch(h->graph_exec, s));
+      else enqueue_iteration(h);
+    };
+    hipEvent_t ev[2];
+    AMG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    AMG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    launch();
+    AMG_HIP(hipEventRecord(ev[1], s));
+    for (int j = 1;; ++j) {
+      const bool more = j + 1 <= maxit;
+      if (more) {
+        launch();
+        AMG_HIP(hipEventRecord(ev[(j + 1) % 2], s));
+      }
+      AMG_HIP(hipEventSynchronize(ev[j % 2]));
+      const volatile int *done = &h->sc_host->done;
+      if (*done || !more) break;
+    }
     AMG_HIP(hipStreamSynchronize(s));
-    *iters = 0;
-    *relres = 0.0;
-    return AMG_OK;
-  }
-  if (h->use_graph && !h->graph_exec) {
-    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration(h);
-    AMG_HIP(hipStreamEndCapture(s, &h->graph));
-    AMG_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
-  }
-  int it = 0, status = AMG_OK;
-  for (;;) {
-    if (h->graph_exec) AMG_HIP(hipGraphLaunch(h->graph_exec, s));
-    else enqueue_iteration(h);
-    ++it;
-    AMG_HIP(hipMemcpyAsync(h->sc_host, h->sc.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    AMG_HIP(hipStreamSynchronize(s));
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     st = *h->sc_host;
-    if (st.status != 0) { status = st.status; break; }
-    if (st.done) break;
-    if (it >= maxit) { status = AMG_NOT_CONVERGED; break; }
   }
   AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   AMG_HIP(hipStreamSynchronize(s));
-  *iters = it;
-  *relres = sqrt(st.rr) / st.nr0;
-  return status;
+  *iters = st.it;
+  *relres = (st.nr0 == 0.0) ? 0.0 : sqrt(st.rr) / st.nr0;
+  if (st.status != 0) return st.status;
+  if (st.nr0 == 0.0) return AMG_OK;
+  return st.conv ? AMG_OK : AMG_NOT_CONVERGED;
 }
 
 // ------------------------------------------------------- kernel timing
@@ -542,46 +861,54 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   Level &L = h->L[k];
   const int n = L.A.n;
   const double nnz = static_cast<double>(L.A.nnz);
-  const int G = dot_blocks(n), rpb = rows_per_block(n, G);
+  const int nbd = nb_dot(n), nbu = nb_upd(n);
+  const bool has_coarse = k + 1 < static_cast<int>(h->L.size());
+  if ((kernel == 2 || kernel == 3) && !has_coarse) fail(AMG_ERR_INVALID, "no coarser level");
+  if (kernel == 4 && k != 0) fail(AMG_ERR_INVALID, "the PCG update exists on level 0 only");
+  if (kernel < 0 || kernel > 4) fail(AMG_ERR_INVALID, "unknown kernel id");
   auto launch = [&]() {
     switch (kernel) {
       case 0:
         if (k == 0) {
-          hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(G), dim3(kBlock), 0, s, n, rpb, L.S.sptr.p,
-                             L.S.col.p, L.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p,
-                             h->counter.p, h->sc.p);
+          hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(nbd), dim3(kBlock), 0, s, nullptr, n, L.S.sptr.p,
+                             L.S.col.p, L.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
         } else {
           hipLaunchKernelGGL(k_spmv<double>, grid_for(n), dim3(kBlock), 0, s, n, L.S.sptr.p,
                              L.S.col.p, L.S.val.p, L.x.p, L.t.p);
         }
         break;
       case 1:
-        launch_sweep<double>(L, L.r.p, L.x.p, L.t.p, s);
+        launch_sweep<double>(nullptr, L, L.r.p, L.x.p, L.t.p, s);
         break;
       case 2:
-        if (k + 1 >= static_cast<int>(h->L.size())) fail(AMG_ERR_INVALID, "no coarser level");
-        hipLaunchKernelGGL(k_restrict<double>, grid_for(L.nc), dim3(kBlock), 0, s, L.nc, L.mptr.p,
-                           L.mem.p, L.pval.p, L.S.sptr.p, L.S.col.p, L.S.val.p, L.r.p, L.x.p,
-                           h->L[k + 1].r.p);
+        hipLaunchKernelGGL(k_resid_scaled<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n,
+                           L.S.sptr.p, L.S.col.p, L.S.val.p, L.pval.p, L.r.p, L.x.p, L.t.p);
+        hipLaunchKernelGGL(k_agg_sum<double>, grid_for(L.nc), dim3(kBlock), 0, s, nullptr, L.nc,
+                           L.mptr.p, L.mem.p, L.t.p, h->L[k + 1].r.p, h->L[k + 1].dinv.p,
+                           h->L[k + 1].x.p);
         break;
       case 3:
-        if (k + 1 >= static_cast<int>(h->L.size())) fail(AMG_ERR_INVALID, "no coarser level");
-        hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, n, L.agg.p, L.pval.p,
-                           h->L[k + 1].x.p, L.t.p);
-        break;
-      case 4:
-        if (k != 0) fail(AMG_ERR_INVALID, "the PCG update exists on level 0 only");
-        hipLaunchKernelGGL(k_pcg_update, dim3(G), dim3(kBlock), 0, s, n, rpb, h->w.p, h->v.p, h->d.p,
-                           h->u.p, h->q.p, h->r.p, h->partials.p, h->counter.p, h->sc.p);
+        hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, L.agg.p,
+                           L.pval.p, h->L[k + 1].x.p, L.t.p);
         break;
       default:
-        fail(AMG_ERR_INVALID, "unknown kernel id");
+        hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, nullptr, n, h->w.p, h->v.p,
+                           h->d.p, h->u.p, h->q.p, h->r.p, h->sc.p, h->partials.p,
+                           first_out_for(h, h->w.p));
+        break;
     }
     AMG_LAUNCH_CHECK();
   };
-  // defined, finite inputs for the timed launches
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, n, L.x.p);
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, n, L.r.p);
+  // defined, finite inputs for the timed launches (the PCG scalars are left
+  // as the last solve set them, or zero)
+  for (double *p : {L.x.p, L.r.p, L.t.p})
+    hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, p);
+  if (k == 0)
+    for (double *p : {h->w.p, h->r.p, h->q.p, h->v.p, h->d.p, h->u.p})
+      hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, p);
+  if (has_coarse)
+    hipLaunchKernelGGL(k_zero<double>, grid_for(L.nc), dim3(kBlock), 0, s, nullptr, L.nc,
+                       h->L[k + 1].x.p);
   launch();
   hipEvent_t e0, e1;
   AMG_HIP(hipEventCreate(&e0));
@@ -595,13 +922,18 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = static_cast<double>(ms) / std::max(1, reps);
+  // algorithmic bytes: matrix values + column indices streamed once, vectors once
   const double bv = 8.0, nd = static_cast<double>(n), ncd = static_cast<double>(L.nc);
   switch (kernel) {
     case 0: *bytes = (bv + 4) * nnz + 2 * bv * nd + (k == 0 ? 2 * bv * nd : 0.0); break;
     case 1: *bytes = (bv + 4) * nnz + 3 * bv * nd; break;
-    case 2: *bytes = (bv + 4) * nnz + 2 * bv * nd + (bv + 4) * nd + 4 * (ncd + 1) + bv * ncd; break;
+    case 2: *bytes = (bv + 4) * nnz + 5 * bv * nd + 4 * nd + 4 * (ncd + 1) + 3 * bv * ncd; break;
     case 3: *bytes = 3 * bv * nd + 4 * nd + bv * ncd; break;
-    default: *bytes = 10 * bv * nd; break;
+    default: {
+      const FirstOut fo = first_out_for(h, h->w.p);
+      *bytes = 10 * bv * nd + (fo.x ? 16 * nd : 0.0) + (fo.rf ? 4 * nd : 0.0) + (fo.xf ? 8 * nd : 0.0);
+      break;
+    }
   }
 }
 

@@ -207,3 +207,42 @@ def test_host_csr_input_equals_device_input():
     for k in range(Hd.info()["levels"]):
         a, b = Hd.export_level(k), Hh.export_level(k)
         assert np.array_equal(bits(a["val"]), bits(b["val"]))
+
+
+MIXED_CASES = ["poisson32", "poisson33_ragged", "diffusion27_14_relax", "lognormal7_20_relax",
+               "poisson17_s3_jacobi"]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES)
+def test_mixed_precision_vcycle_and_pcg(case):
+    """Mixed form: binary32 V-cycle, binary64 PCG.  The GPU cycle is compared
+    with the oracle's binary32 cycle (relative 1e-6, bit-exact expected) and
+    its distance to the binary64 cycle is reported; PCG reaches the same rtol
+    with the oracle's mixed iteration count +-1."""
+    import paper_2303_02352_amd as amd
+    make, params = CASES[case]
+    A = make()
+    say("mixed parity", case)
+    Ho = oracle.Hierarchy(A, oracle_params(**params))
+    Hg = gpu_hierarchy(A, precision=amd.AMG_PREC_MIXED, **params)
+    assert_same_hierarchy(Hg, Ho)        # setup stays binary64
+    r = W.uniform_pm1(78, A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    Hg.vcycle(dev(r), z)
+    zg = host(z)
+    z32 = Ho.vcycle_f32(r)
+    z64 = Ho.vcycle(r)
+    err32 = np.max(np.abs(zg - z32)) / np.max(np.abs(z32))
+    err64 = np.max(np.abs(zg - z64)) / np.max(np.abs(z64))
+    say("  vs oracle binary32 %.2e (bitwise %s), vs binary64 %.2e" %
+        (err32, np.array_equal(bits(zg), bits(z32)), err64))
+    assert err32 <= 1e-6
+    assert err64 <= 1e-5
+    xs, b = W.manufactured_rhs(A, 1)
+    xo, ito, relo, sto = Ho.pcg(b, mixed=True)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st, it, rel = Hg.solve(dev(b), x)
+    say("  pcg oracle-mixed its %d | gpu-mixed its %d rel %.2e" % (ito, it, rel))
+    assert st == 0 and sto == 0 and abs(it - ito) <= 1 and rel <= 1e-6
+    xg = host(x)
+    assert np.linalg.norm(b - A.scipy() @ xg) / np.linalg.norm(b) <= 1e-6 * 1.01

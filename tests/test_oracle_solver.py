@@ -245,3 +245,17 @@ def test_paper_hierarchy_300():
     H = oracle.Hierarchy(A, _paper_params(nd))
     assert H.nlevels == g["strong_scaling_300"]["levels"]
     assert abs(H.opc() - g["operator_complexity"]["value"]) <= g["operator_complexity"]["tolerance"]
+
+
+def test_coarse_inverse_against_numpy():
+    """The coarsest direct solve multiplies by A_c^-1, whose columns come from
+    the Cholesky factor; it must agree with numpy's inverse."""
+    A = W.diffusion27(6, 3)
+    H = oracle.Hierarchy(A, oracle.AMGParams(coarse_max=60))
+    assert H.coarse_dense
+    lv = H.level(H.nlevels - 1)
+    Ac = W.CSR(lv["n"], lv["row_ptr"], lv["col"], lv["val"]).scipy().toarray()
+    Ai = H.coarse_inverse()
+    ref = np.linalg.inv(Ac)
+    assert np.max(np.abs(Ai - ref)) <= 1e-13 * np.linalg.cond(Ac) * np.max(np.abs(ref))
+    assert np.max(np.abs(Ai @ Ac - np.eye(lv["n"]))) <= 1e-12
