@@ -71,6 +71,40 @@ def cpu_baseline(A, b):
                 iterations=it, relres=rel, setup_s=t1 - t0)
 
 
+def batched_leg(amd, torch, W, np, dev):
+    """64 Poisson systems, edges log-uniform in [16, 96] (seed 5), 16 RHS each,
+    FP64 outer / FP32 V-cycle, solved by amg_batch_solve (graph launches)."""
+    edges = W.batched_edges(64, 5)
+    nrhs = 16
+    systems = [W.poisson7(N) for N in edges]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    bt = amd.Batch([(d(A.row_ptr), d(A.col), d(A.val)) for A in systems],
+                   precision=amd.AMG_PREC_MIXED)
+    bs = []
+    for s, A in enumerate(systems):
+        xs = W.batched_rhs(s, A.n, nrhs).T
+        bs.append(np.ascontiguousarray(A.scipy() @ xs).reshape(-1))
+    B = d(np.concatenate(bs))
+    ntot = sum(A.n for A in systems)
+    times = []
+    for rep in range(3):
+        X = torch.zeros(ntot * nrhs, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, its, rel, pst = bt.solve(B, X, nrhs, rtol=RTOL, maxit=MAXIT)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    inf = bt.info()
+    bt.close()
+    t = min(times[1:])
+    return dict(systems=len(systems), nrhs=nrhs, rows=ntot, nnz=int(sum(A.nnz for A in systems)),
+                edges_min=min(edges), edges_max=max(edges), solve_s=t, solve_s_first=times[0],
+                status=st, iters_max=int(its.max()), iters_mean=float(its.mean()),
+                relres_max=float(rel.max()), pair_solves_per_s=len(systems) * nrhs / t,
+                levels=inf["levels"], cols_per_lane=inf["cols_per_lane"], setup_ms=inf["setup_ms"],
+                tune_ms=inf["tune_ms"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -167,6 +202,11 @@ def main():
                               speedup_vs_fp64_solve=solve_s / rm["solve_s"],
                               max_rel_diff_vs_fp64_solution=float(np.max(np.abs(xmh - xg)) / np.max(np.abs(xg))))
         Hm.close()
+
+    if not args.no_forms and not args.no_batched:
+        log("batched form")
+        forms["batched"] = batched_leg(amd, torch, W, np, dev)
+        log("batched", json.dumps(forms["batched"]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -181,6 +181,54 @@ int amg_sweep(amg_hierarchy *h, int32_t k, const double *r, const double *x, dou
 int amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t k, int32_t reps, double *avg_ms,
                     double *bytes);
 
+
+/* ------------------------------------------------------------------ batched
+ * Many independent systems, each with nrhs right-hand sides, solved together
+ * (every (system, right-hand side) pair is its own flexible CG, Alg. 1, with
+ * its own stopping test).  The hierarchies are built per system with the
+ * single-system setup and stacked level by level; vectors are RHS-
+ * interleaved.  The iterations run as one hipGraph launch per 32 iterations
+ * (a whole solve of up to 32 iterations is one launch); converged pairs stay
+ * frozen, so per-pair iteration counts are exact.  Every system must end in a
+ * direct coarsest solve (coarse_solver CHOLESKY, coarsest n <= 1024). */
+typedef struct amg_batch amg_batch;   /* opaque, owned by the library */
+
+typedef struct {
+  int32_t nsys;
+  int32_t levels;                     /* depth of the deepest system */
+  int32_t n[AMG_MAX_LEVELS];          /* stacked rows per level */
+  int32_t n_smoothed[AMG_MAX_LEVELS]; /* rows of systems that continue below the level */
+  int64_t nnz[AMG_MAX_LEVELS];
+  int32_t cols_per_lane[AMG_MAX_LEVELS];  /* tuned: lanes per row = nrhs / cols_per_lane */
+  double setup_ms, tune_ms;
+} amg_batch_info_t;
+
+/* Build the hierarchies of nsys systems A[0..nsys-1] (same parameters for
+ * all; smooth_vec GIVEN is not accepted).  Errors as amg_setup, plus
+ * UNSUPPORTED when a system does not end in a direct coarsest solve. */
+int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_batch **out);
+
+/* Solve A_s X_s = B_s for every system s.  B, X: device pointers; systems are
+ * stored one after another in the order given to amg_batch_setup, each as an
+ * n_s x nrhs row-major block (entry (i, c) of system s at (off_s + i) * nrhs + c,
+ * off_s = n_0 + ... + n_{s-1}).  X holds initial guesses on entry.  nrhs in
+ * {1, 2, 4, 8, 16}.  Outputs (host arrays of nsys * nrhs, index s * nrhs + c):
+ * iterations, recurrence relative residual, status of the pair.  Returns the
+ * most severe pair status (OK, NOT_CONVERGED or an error).  The first call
+ * with a given nrhs allocates vectors, times the smoothing-kernel variants
+ * and captures the iteration graph.  Synchronises. */
+int amg_batch_solve(amg_batch *bt, int32_t nrhs, const double *B, double *X, double rtol,
+                    int32_t maxit, int32_t *iters, double *relres, int32_t *status);
+
+/* Z = B_s R for every system and right-hand side (one batched V-cycle), same
+ * layout as amg_batch_solve.  Synchronises. */
+int amg_batch_vcycle(amg_batch *bt, int32_t nrhs, const double *R, double *Z);
+
+int amg_batch_info(const amg_batch *bt, amg_batch_info_t *out);
+
+/* NULL-safe. */
+void amg_batch_destroy(amg_batch *bt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,13 @@ class amg_info_t(C.Structure):
                 ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64)]
 
 
+class amg_batch_info_t(C.Structure):
+    _fields_ = [("nsys", C.c_int32), ("levels", C.c_int32), ("n", C.c_int32 * AMG_MAX_LEVELS),
+                ("n_smoothed", C.c_int32 * AMG_MAX_LEVELS), ("nnz", C.c_int64 * AMG_MAX_LEVELS),
+                ("cols_per_lane", C.c_int32 * AMG_MAX_LEVELS), ("setup_ms", C.c_double),
+                ("tune_ms", C.c_double)]
+
+
 EXPORTS = {
     "amg_params_default": (C.c_int, [C.POINTER(amg_params)]),
     "amg_setup": (C.c_int, [C.POINTER(amg_csr), C.POINTER(amg_params), C.POINTER(C.c_void_p)]),
@@ -62,6 +69,13 @@ EXPORTS = {
     "amg_sweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amg_time_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "amg_batch_setup": (C.c_int, [C.c_int32, C.POINTER(amg_csr), C.POINTER(amg_params),
+                                  C.POINTER(C.c_void_p)]),
+    "amg_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amg_batch_vcycle": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "amg_batch_info": (C.c_int, [C.c_void_p, C.POINTER(amg_batch_info_t)]),
+    "amg_batch_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -211,3 +225,67 @@ class Hierarchy:
         if st != AMG_OK:
             raise AMGError(st, "amg_time_kernel")
         return ms.value, by.value
+
+
+class Batch:
+    """Batched hierarchy (``amg_batch_setup``) over several systems.
+
+    ``systems``: list of (row_ptr, col, val) torch CUDA tensors or host numpy
+    arrays.  Vectors passed to ``solve``/``vcycle`` are device tensors holding
+    the systems one after another, each an n_s x nrhs row-major block.
+    """
+
+    def __init__(self, systems, stream=None, **params):
+        L = load()
+        self._keep = systems
+        arr = (amg_csr * len(systems))()
+        for i, (rp, ci, va) in enumerate(systems):
+            arr[i] = amg_csr(int(rp.shape[0]) - 1, int(ci.shape[0]), _ptr(rp), _ptr(ci), _ptr(va),
+                             _on_device(va))
+        self.sizes = [int(s[0].shape[0]) - 1 for s in systems]
+        p = default_params(**params)
+        p.stream = stream if stream is not None else (current_stream() if arr[0].on_device else None)
+        self.params = p
+        h = C.c_void_p()
+        st = L.amg_batch_setup(len(systems), arr, C.byref(p), C.byref(h))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_batch_setup")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().amg_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, B, X, nrhs, rtol=1e-6, maxit=1000, check=True):
+        """Returns (status, iters[nsys, nrhs], relres[nsys, nrhs], pair_status[nsys, nrhs])."""
+        ns = len(self.sizes)
+        it = np.zeros(ns * nrhs, np.int32)
+        rel = np.zeros(ns * nrhs)
+        pst = np.zeros(ns * nrhs, np.int32)
+        st = load().amg_batch_solve(self.h, int(nrhs), _ptr(B), _ptr(X), float(rtol), int(maxit),
+                                    _ptr(it), _ptr(rel), _ptr(pst))
+        if check and st < 0:
+            raise AMGError(st, "amg_batch_solve")
+        return st, it.reshape(ns, nrhs), rel.reshape(ns, nrhs), pst.reshape(ns, nrhs)
+
+    def vcycle(self, R, Z, nrhs):
+        st = load().amg_batch_vcycle(self.h, int(nrhs), _ptr(R), _ptr(Z))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_batch_vcycle")
+
+    def info(self) -> dict:
+        inf = amg_batch_info_t()
+        st = load().amg_batch_info(self.h, C.byref(inf))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_batch_info")
+        L = inf.levels
+        return dict(nsys=inf.nsys, levels=L, n=list(inf.n[:L]), n_smoothed=list(inf.n_smoothed[:L]),
+                    nnz=list(inf.nnz[:L]), cols_per_lane=list(inf.cols_per_lane[:L]),
+                    setup_ms=inf.setup_ms, tune_ms=inf.tune_ms)

@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <utility>
 #include <vector>
@@ -167,6 +168,10 @@ namespace amg {
 // ------------------------------------------------------- setup interface
 void build_hierarchy(amg_hierarchy *h, const amg_csr *A);
 void coarse_factor(amg_hierarchy *h);
+void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s);  // out: n+1 entries
+int device_read_int(const int *p, hipStream_t s);
+void finalize_level(Level &Lv, hipStream_t s, bool want_float);  // l1 diagonal + SELL from Lv.A
+double wall_ms();
 
 // -------------------------------------------------------- solve interface
 void alloc_solve_buffers(amg_hierarchy *h);
@@ -177,6 +182,11 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
               double *relres);
 void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, double *bytes);
 void destroy_graph(amg_hierarchy *h);
+
+// --------------------------------------------------- C ABI error plumbing
+int api_set_error(int code, const std::string &msg);
+int api_guarded(const std::function<int()> &f);   // maps amg::Error to a status
+const std::string &api_last_error();
 
 // ----------------------------------------------------------- small helpers
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 
@@ -51,6 +52,9 @@ int check_params(const amg_params *p) {
 
 namespace amg {
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+int api_set_error(int code, const std::string &msg) { return set_error(code, msg); }
+int api_guarded(const std::function<int()> &f) { return guarded(f); }
+const std::string &api_last_error() { return g_last_error; }
 
 int64_t device_bytes(const amg_hierarchy *h) {
   int64_t b = 0;

@@ -1,0 +1,1019 @@
+// Batched AMG-PCG: many independent s.p.d. systems of uneven size, each with
+// several right-hand sides, solved together.
+//
+// Layout.  Every system gets its own hierarchy (the single-system setup,
+// unchanged), then level k of all systems that reach level k is stacked into
+// one block-diagonal matrix.  Systems are ordered by depth (deepest first),
+// so at every level the active systems form a prefix, and the systems whose
+// coarsest level is k come last ("terminal" rows).  Vectors are RHS-
+// interleaved: entry (row i, right-hand side c) lives at i * NR + c, so one
+// pass over a SELL matrix serves all NR right-hand sides.
+//
+// Each (system, right-hand side) pair is its own flexible CG (Alg. 1) with
+// its own scalars and stopping test; a pair that has converged keeps its
+// vectors frozen, so iteration counts are exact per pair.  The whole solve
+// is captured as one hipGraph (iterations unrolled, masked) and launched
+// once.  Rows-per-wave of the smoothing and residual kernels (lanes per row
+// = NR / columns-per-lane) are chosen per level by timing the candidates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "amg_internal.hpp"
+
+namespace amg {
+namespace {
+
+constexpr int kBTile = 256;   // rows per reduction tile of the level-0 PCG kernels
+
+struct BScalars {
+  double rho, c, a, rr, nr0, thr;
+  int it, done, conv, status;
+};
+
+struct BLevel {
+  int n = 0;        // rows of all systems active on this level
+  int n_cont = 0;   // rows of the systems that continue below (a prefix)
+  Level L;          // stacked matrix, l1 diagonals, transfer to the next level
+  // systems whose coarsest level is this one (rows [n_cont, n))
+  int nterm = 0;
+  dvec<int> term_off, term_n;
+  dvec<long long> term_inv;     // offset of each inverse in inv_pool
+  dvec<double> inv_pool;        // column-major inverses of the coarsest matrices
+  int cpl = 1;                  // tuned columns per lane (sweeps / residual)
+  int tune_best = 1;
+  // RHS-interleaved work vectors
+  dvec<double> r, x, t;
+  dvec<float> rf, xf, tf;
+};
+
+inline dim3 grid_for(int64_t n, int block = kBlock) {
+  return dim3(static_cast<unsigned>(std::max<int64_t>(1, (n + block - 1) / block)));
+}
+
+#define AMG_SKIP_IF_DONE() \
+  if (skip && *skip) return
+
+// ------------------------------------------------------------ stacking
+__global__ void k_add_copy(int n, const int *__restrict__ src, int *__restrict__ dst, int add) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] + add;
+}
+
+__global__ void k_set_one(int *p, int v) { *p = v; }
+
+// --------------------------------------------------------- SELL, NR columns
+// Row `row`, columns cb .. cb+CPL-1: acc[j] = sum_k a_k x[col_k * NR + cb + j]
+// folded in CSR order; l1 = sum_k |a_k|.
+template <class T, int NR, int CPL>
+__device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__restrict__ col,
+                                     const T *__restrict__ val, const T *__restrict__ x, int row,
+                                     int cb, T (&acc)[CPL], T &l1) {
+  const int s = row >> 6, lane = row & 63;
+  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) acc[j] = T(0);
+  T m = T(0);
+  for (int k = 0; k < width; ++k) {
+    const int c = col[b + k * 64 + lane];
+    const T a = val[b + k * 64 + lane];
+    m = m + fabs(a);
+    const T *xp = x + static_cast<int64_t>(c) * NR + cb;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a * xp[j];
+  }
+  l1 = m;
+}
+
+// xn = x + dinv (rhs - A x) on rows [0, n)
+template <class T, int NR, int CPL>
+__global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
+                                                   const int *__restrict__ sptr,
+                                                   const int *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const T *__restrict__ rhs,
+                                                   const T *__restrict__ x, T *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
+  constexpr int LPR = NR / CPL;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int row = gid / LPR, cb = (gid % LPR) * CPL;
+  if (row >= n) return;
+  T acc[CPL], l1;
+  brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
+  const T di = T(1) / l1;
+  const int64_t o = static_cast<int64_t>(row) * NR + cb;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) xn[o + j] = x[o + j] + di * (rhs[o + j] - acc[j]);
+}
+
+// t = p (rhs - A x) on rows [0, n)
+template <class T, int NR, int CPL>
+__global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
+                                                   const int *__restrict__ sptr,
+                                                   const int *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const T *__restrict__ pval,
+                                                   const T *__restrict__ rhs,
+                                                   const T *__restrict__ x, T *__restrict__ t) {
+  AMG_SKIP_IF_DONE();
+  constexpr int LPR = NR / CPL;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int row = gid / LPR, cb = (gid % LPR) * CPL;
+  if (row >= n) return;
+  T acc[CPL], l1;
+  brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
+  const T p = pval[row];
+  const int64_t o = static_cast<int64_t>(row) * NR + cb;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) t[o + j] = p * (rhs[o + j] - acc[j]);
+}
+
+// x = dinv * rhs on rows [0, n)
+template <class T, int NR>
+__global__ void __launch_bounds__(kBlock) k_bsweep_first(const int *skip, int n,
+                                                         const T *__restrict__ dinv,
+                                                         const T *__restrict__ rhs,
+                                                         T *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < static_cast<int64_t>(n) * NR) x[e] = dinv[e / NR] * rhs[e];
+}
+
+// rc[I] = sum over members (ascending) of t; xc[I] = dinv_c[I] rc[I] when asked
+template <class T, int NR>
+__global__ void __launch_bounds__(kBlock) k_bagg(const int *skip, int nc,
+                                                 const int *__restrict__ mptr,
+                                                 const int *__restrict__ mem,
+                                                 const T *__restrict__ t, T *__restrict__ rc,
+                                                 const T *__restrict__ dinvc, T *__restrict__ xc) {
+  AMG_SKIP_IF_DONE();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= static_cast<int64_t>(nc) * NR) return;
+  const int I = static_cast<int>(e / NR), c = static_cast<int>(e % NR);
+  T acc = T(0);
+  for (int q = mptr[I]; q < mptr[I + 1]; ++q) acc = acc + t[static_cast<int64_t>(mem[q]) * NR + c];
+  rc[e] = acc;
+  if (xc) xc[e] = dinvc[I] * acc;
+}
+
+// x += p e[agg] on rows [0, n)
+template <class T, int NR>
+__global__ void __launch_bounds__(kBlock) k_bprolong(const int *skip, int n,
+                                                     const int *__restrict__ agg,
+                                                     const T *__restrict__ pval,
+                                                     const T *__restrict__ e, T *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= static_cast<int64_t>(n) * NR) return;
+  const int i = static_cast<int>(q / NR), c = static_cast<int>(q % NR);
+  x[q] = x[q] + pval[i] * e[static_cast<int64_t>(agg[i]) * NR + c];
+}
+
+// Terminal systems: z = A_c^-1 r, one workgroup per system, binary64 fold
+// over j ascending (column-major inverse), NR columns at once.
+template <class T, int NR>
+__global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *__restrict__ toff,
+                                                    const int *__restrict__ tn,
+                                                    const long long *__restrict__ tinv,
+                                                    const double *__restrict__ pool,
+                                                    const T *__restrict__ rhs, T *__restrict__ out) {
+  AMG_SKIP_IF_DONE();
+  const int sys = blockIdx.x;
+  const int off = toff[sys], n = tn[sys];
+  const double *Ai = pool + tinv[sys];
+  for (int e = threadIdx.x; e < n * NR; e += blockDim.x) {
+    const int i = e / NR, c = e % NR;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j)
+      acc = acc + Ai[static_cast<int64_t>(j) * n + i] *
+                      static_cast<double>(rhs[static_cast<int64_t>(off + j) * NR + c]);
+    out[static_cast<int64_t>(off + i) * NR + c] = static_cast<T>(acc);
+  }
+}
+
+__global__ void k_bd2f(int64_t m, const double *__restrict__ a, float *__restrict__ b,
+                       const int *skip) {
+  AMG_SKIP_IF_DONE();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < m) b[e] = static_cast<float>(a[e]);
+}
+
+__global__ void k_bf2d(int64_t m, const float *__restrict__ a, double *__restrict__ b,
+                       const int *skip) {
+  AMG_SKIP_IF_DONE();
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < m) b[e] = static_cast<double>(a[e]);
+}
+
+template <class T>
+__global__ void k_bzero(int64_t m, T *x) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e < m) x[e] = T(0);
+}
+
+// ------------------------------------------------------- level-0 PCG kernels
+// A tile is <= kBTile rows of one system.  Thread (rsub, c): rows r0 + rsub,
+// r0 + rsub + 256/NR, ...; the partial of column c folds the threads with
+// that column in increasing rsub.
+template <int NR>
+__device__ __forceinline__ double tile_column_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < NR)
+    for (int g = 0; g < kBlock / NR; ++g) s = s + red[g * NR + threadIdx.x];
+  __syncthreads();
+  return s;
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ trow0,
+                                                      const int *__restrict__ trow1,
+                                                      const int *__restrict__ sptr,
+                                                      const int *__restrict__ col,
+                                                      const double *__restrict__ val,
+                                                      const double *__restrict__ b,
+                                                      const double *__restrict__ u,
+                                                      double *__restrict__ r,
+                                                      double *__restrict__ part) {
+  __shared__ double red[kBlock];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int c = threadIdx.x % NR;
+  double rr = 0.0;
+  for (int row = trow0[tile] + threadIdx.x / NR; row < trow1[tile]; row += kBlock / NR) {
+    double acc[1], l1;
+    brow<double, NR, 1>(sptr, col, val, u, row, c, acc, l1);
+    const int64_t o = static_cast<int64_t>(row) * NR + c;
+    const double ri = b[o] - acc[0];
+    r[o] = ri;
+    rr = rr + ri * ri;
+  }
+  rr = tile_column_sum<NR>(rr, red);
+  if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + c) * 3] = rr;
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
+    const int *skip, const int *__restrict__ trow0, const int *__restrict__ trow1,
+    const int *__restrict__ sptr, const int *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ v, double *__restrict__ part) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double red[kBlock];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int c = threadIdx.x % NR;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int row = trow0[tile] + threadIdx.x / NR; row < trow1[tile]; row += kBlock / NR) {
+    double acc[1], l1;
+    brow<double, NR, 1>(sptr, col, val, w, row, c, acc, l1);
+    const int64_t o = static_cast<int64_t>(row) * NR + c;
+    v[o] = acc[0];
+    const double wi = w[o];
+    al = al + wi * r[o];
+    be = be + wi * acc[0];
+    ga = ga + wi * q[o];
+  }
+  al = tile_column_sum<NR>(al, red);
+  be = tile_column_sum<NR>(be, red);
+  ga = tile_column_sum<NR>(ga, red);
+  if (threadIdx.x < NR) {
+    const int64_t o = (static_cast<int64_t>(tile) * NR + c) * 3;
+    part[o] = al;
+    part[o + 1] = be;
+    part[o + 2] = ga;
+  }
+}
+
+// Fold the tiles of system `blockIdx.x` per column: thread (g, c) folds tiles
+// g, g + G, ... in order; then the G group sums are folded in order.
+template <int NR, int NQ>
+__device__ __forceinline__ void system_fold(const int *tile_ptr, const double *part, double *red,
+                                            double (&out)[NQ]) {
+  constexpr int G = kBlock / NR;
+  const int sys = blockIdx.x, c = threadIdx.x % NR, g = threadIdx.x / NR;
+  double acc[NQ];
+#pragma unroll
+  for (int o = 0; o < NQ; ++o) acc[o] = 0.0;
+  for (int t = tile_ptr[sys] + g; t < tile_ptr[sys + 1]; t += G)
+#pragma unroll
+    for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + part[(static_cast<int64_t>(t) * NR + c) * 3 + o];
+#pragma unroll
+  for (int o = 0; o < NQ; ++o) {
+    red[threadIdx.x] = acc[o];
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x < NR)
+      for (int q = 0; q < G; ++q) s = s + red[q * NR + threadIdx.x];
+    out[o] = s;
+    __syncthreads();
+  }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_init_finish(const int *tile_ptr,
+                                                             const double *part, BScalars *sc,
+                                                             double rtol, int *active) {
+  __shared__ double red[kBlock];
+  double t[1];
+  system_fold<NR, 1>(tile_ptr, part, red, t);
+  if (threadIdx.x < NR) {
+    BScalars &S = sc[blockIdx.x * NR + threadIdx.x];
+    const double nr0 = sqrt(t[0]);
+    S.nr0 = nr0;
+    S.rr = t[0];
+    S.thr = rtol * nr0;
+    S.rho = 1.0;
+    S.c = 0.0;
+    S.a = 0.0;
+    S.it = 0;
+    S.conv = (nr0 == 0.0) ? 1 : 0;
+    S.status = isfinite(nr0) ? 0 : AMG_ERR_NONFINITE;
+    S.done = (nr0 == 0.0 || !isfinite(nr0)) ? 1 : 0;
+    if (!S.done) atomicAdd(active, 1);
+  }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_dots_finish(const int *skip, const int *tile_ptr,
+                                                             const double *part, BScalars *sc) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double red[kBlock];
+  double t[3];
+  system_fold<NR, 3>(tile_ptr, part, red, t);
+  if (threadIdx.x < NR) {
+    BScalars &S = sc[blockIdx.x * NR + threadIdx.x];
+    if (S.done) return;
+    const double A = t[0], B = t[1], G = t[2];
+    const double rho_prev = S.rho;
+    const double rho = B - (G * G) / rho_prev;
+    S.it = S.it + 1;
+    if (!isfinite(rho) || !isfinite(A)) {
+      S.status = AMG_ERR_NONFINITE;
+      S.done = 1;
+      return;
+    }
+    if (!(rho > 0.0)) {
+      S.status = AMG_ERR_NOT_SPD;
+      S.done = 1;
+      return;
+    }
+    S.c = G / rho_prev;
+    S.a = A / rho;
+    S.rho = rho;
+  }
+}
+
+// d = w - c d; u += a d; q = v - c q; r -= a q for live pairs; partial ||r||^2.
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_update(
+    const int *skip, const int *__restrict__ trow0, const int *__restrict__ trow1,
+    const int *__restrict__ tsys, const double *__restrict__ w, const double *__restrict__ v,
+    double *__restrict__ d, double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
+    const BScalars *__restrict__ sc, double *__restrict__ part) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double red[kBlock];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int c = threadIdx.x % NR;
+  const BScalars &S = sc[tsys[tile] * NR + c];
+  const bool live = !S.done;
+  const double cc = S.c, a = S.a;
+  double rr = 0.0;
+  if (live) {
+    for (int row = trow0[tile] + threadIdx.x / NR; row < trow1[tile]; row += kBlock / NR) {
+      const int64_t o = static_cast<int64_t>(row) * NR + c;
+      const double di = w[o] - cc * d[o];
+      d[o] = di;
+      u[o] = u[o] + a * di;
+      const double qi = v[o] - cc * q[o];
+      q[o] = qi;
+      const double ri = r[o] - a * qi;
+      r[o] = ri;
+      rr = rr + ri * ri;
+    }
+  }
+  rr = tile_column_sum<NR>(rr, red);
+  if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + c) * 3] = rr;
+}
+
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_bpcg_norm_finish(const int *skip, const int *tile_ptr,
+                                                             const double *part, BScalars *sc,
+                                                             int maxit, int *active) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double red[kBlock];
+  double t[1];
+  system_fold<NR, 1>(tile_ptr, part, red, t);
+  if (threadIdx.x < NR) {
+    BScalars &S = sc[blockIdx.x * NR + threadIdx.x];
+    if (S.done) return;
+    const double nr = sqrt(t[0]);
+    S.rr = t[0];
+    if (nr <= S.thr) {
+      S.conv = 1;
+      S.done = 1;
+    } else if (!isfinite(nr)) {
+      S.status = AMG_ERR_NONFINITE;
+      S.done = 1;
+    } else if (S.it >= maxit) {
+      S.done = 1;
+    }
+    if (!S.done) atomicAdd(active, 1);
+  }
+}
+
+// all_done = (no live pair); the counter restarts; snapshot for the host.
+__global__ void k_ball_done(int *active, int *all_done, int *host_flag) {
+  const int live = *active;
+  *all_done = (live == 0) ? 1 : 0;
+  *active = 0;
+  *host_flag = (live == 0) ? 1 : 0;
+}
+
+}  // namespace
+}  // namespace amg
+
+// ===================================================================
+struct amg_batch {
+  amg_params p{};
+  hipStream_t stream = nullptr;
+  int own_stream = 0;
+  int nsys = 0;
+  std::vector<int> order;              // internal position -> user system id
+  std::vector<int> pos_of;             // user system id -> internal position
+  std::vector<int> nl;                 // levels per internal position
+  std::vector<int64_t> n0;             // level-0 rows per user system
+  std::vector<int64_t> user_off, int_off;   // level-0 row offsets (user order / internal order)
+  std::vector<amg::BLevel> B;
+  int ntiles = 0;
+  amg::dvec<int> trow0, trow1, tsys, tile_ptr;
+  // per-nrhs state
+  int nr = 0;
+  amg::dvec<double> bint, u, r, w, v, d, q, partials;
+  amg::dvec<amg::BScalars> sc;
+  amg::dvec<int> active, all_done;
+  int *host_flag = nullptr, *host_flag_dev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_reps = 0, graph_maxit = 0;
+  double setup_ms = 0.0, tune_ms = 0.0;
+  int64_t nnz0 = 0;
+};
+
+namespace amg {
+namespace {
+
+template <class T> T *bv_r(BLevel &L);
+template <> double *bv_r<double>(BLevel &L) { return L.r.p; }
+template <> float *bv_r<float>(BLevel &L) { return L.rf.p; }
+template <class T> T *bv_x(BLevel &L);
+template <> double *bv_x<double>(BLevel &L) { return L.x.p; }
+template <> float *bv_x<float>(BLevel &L) { return L.xf.p; }
+template <class T> T *bv_t(BLevel &L);
+template <> double *bv_t<double>(BLevel &L) { return L.t.p; }
+template <> float *bv_t<float>(BLevel &L) { return L.tf.p; }
+template <class T> const T *bvals(const Level &L);
+template <> const double *bvals<double>(const Level &L) { return L.S.val.p; }
+template <> const float *bvals<float>(const Level &L) { return L.S.valf.p; }
+template <class T> const T *bdinv(const Level &L);
+template <> const double *bdinv<double>(const Level &L) { return L.dinv.p; }
+template <> const float *bdinv<float>(const Level &L) { return L.dinvf.p; }
+template <class T> const T *bpval(const Level &L);
+template <> const double *bpval<double>(const Level &L) { return L.pval.p; }
+template <> const float *bpval<float>(const Level &L) { return L.pvalf.p; }
+
+template <class T, int NR, int CPL>
+void launch_bsweep(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
+  constexpr int LPR = NR / CPL;
+  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn);
+}
+
+template <class T, int NR, int CPL>
+void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
+  constexpr int LPR = NR / CPL;
+  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t);
+}
+
+template <class T, int NR>
+void sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
+  if (NR % 4 == 0 && L.cpl == 4) launch_bsweep<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, x, xn, s);
+  else if (NR % 2 == 0 && L.cpl == 2) launch_bsweep<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, x, xn, s);
+  else launch_bsweep<T, NR, 1>(skip, L, n, rhs, x, xn, s);
+}
+
+template <class T, int NR>
+void resid_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
+  if (NR % 4 == 0 && L.cpl == 4) launch_bresid<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, x, t, s);
+  else if (NR % 2 == 0 && L.cpl == 2) launch_bresid<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, x, t, s);
+  else launch_bresid<T, NR, 1>(skip, L, n, rhs, x, t, s);
+}
+
+// first iterate location of level k (nullptr: no smoothing on this level)
+template <class T>
+T *bfirst(amg_batch *bt, int k, T *out) {
+  BLevel &L = bt->B[k];
+  const amg_params &P = bt->p;
+  if (L.n_cont == 0 || P.pre_sweeps == 0) return nullptr;
+  const int swaps = (P.pre_sweeps - 1) + P.post_sweeps;
+  return (swaps % 2 == 0) ? out : bv_t<T>(L);
+}
+
+template <class T, int NR>
+void bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, bool first_done) {
+  hipStream_t s = bt->stream;
+  BLevel &L = bt->B[k];
+  const amg_params &P = bt->p;
+  const int nc0 = L.n_cont;
+  if (L.nterm > 0)
+    hipLaunchKernelGGL((k_bcoarse<T, NR>), dim3(L.nterm), dim3(kBlock), 0, s, skip, L.term_off.p,
+                       L.term_n.p, L.term_inv.p, L.inv_pool.p, rhs, out);
+  if (nc0 == 0) return;
+  const int swaps = (P.pre_sweeps > 0 ? P.pre_sweeps - 1 : 0) + P.post_sweeps;
+  T *A = (swaps % 2 == 0) ? out : bv_t<T>(L);
+  T *Bf = (A == out) ? bv_t<T>(L) : out;
+  if (P.pre_sweeps == 0) {
+    hipLaunchKernelGGL(k_bzero<T>, grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+                       static_cast<int64_t>(nc0) * NR, A);
+  } else {
+    if (!first_done)
+      hipLaunchKernelGGL((k_bsweep_first<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock),
+                         0, s, skip, nc0, bdinv<T>(L.L), rhs, A);
+    for (int qq = 1; qq < P.pre_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
+  }
+  resid_any<T, NR>(skip, L, nc0, rhs, A, Bf, s);
+  BLevel &C = bt->B[k + 1];
+  T *xc = bfirst<T>(bt, k + 1, bv_x<T>(C));
+  hipLaunchKernelGGL((k_bagg<T, NR>), grid_for(static_cast<int64_t>(C.n) * NR), dim3(kBlock), 0, s, skip,
+                     C.n, L.L.mptr.p, L.L.mem.p, Bf, bv_r<T>(C), bdinv<T>(C.L), xc);
+  bvcycle_level<T, NR>(bt, skip, k + 1, bv_r<T>(C), bv_x<T>(C), xc != nullptr);
+  hipLaunchKernelGGL((k_bprolong<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+                     skip, nc0, L.L.agg.p, bpval<T>(L.L), bv_x<T>(C), A);
+  for (int qq = 0; qq < P.post_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
+}
+
+template <int NR>
+void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
+  hipStream_t s = bt->stream;
+  const int64_t m = static_cast<int64_t>(bt->B[0].n) * NR;
+  if (!bt->p.precond) {
+    AMG_HIP(hipMemcpyAsync(z, r, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  if (bt->p.precision == AMG_PREC_MIXED) {
+    BLevel &L = bt->B[0];
+    hipLaunchKernelGGL(k_bd2f, grid_for(m), dim3(kBlock), 0, s, m, r, L.rf.p, skip);
+    bvcycle_level<float, NR>(bt, skip, 0, L.rf.p, L.xf.p, false);
+    hipLaunchKernelGGL(k_bf2d, grid_for(m), dim3(kBlock), 0, s, m, L.xf.p, z, skip);
+    // single-level systems: their whole cycle is the binary64 direct solve
+    if (L.nterm > 0)
+      hipLaunchKernelGGL((k_bcoarse<double, NR>), dim3(L.nterm), dim3(kBlock), 0, s, skip,
+                         L.term_off.p, L.term_n.p, L.term_inv.p, L.inv_pool.p, r, z);
+  } else {
+    bvcycle_level<double, NR>(bt, skip, 0, r, z, false);
+  }
+  AMG_LAUNCH_CHECK();
+}
+
+template <int NR>
+void benqueue_iteration(amg_batch *bt, int maxit) {
+  hipStream_t s = bt->stream;
+  const BLevel &L0 = bt->B[0];
+  const int *skip = bt->all_done.p;
+  bvcycle<NR>(bt, skip, bt->r.p, bt->w.p);
+  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, skip, bt->trow0.p,
+                     bt->trow1.p, L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p,
+                     bt->v.p, bt->partials.p);
+  hipLaunchKernelGGL((k_bpcg_dots_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, skip,
+                     bt->tile_ptr.p, bt->partials.p, bt->sc.p);
+  hipLaunchKernelGGL((k_bpcg_update<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, skip, bt->trow0.p,
+                     bt->trow1.p, bt->tsys.p, bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p,
+                     bt->sc.p, bt->partials.p);
+  hipLaunchKernelGGL((k_bpcg_norm_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, skip,
+                     bt->tile_ptr.p, bt->partials.p, bt->sc.p, maxit, bt->active.p);
+  hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p,
+                     bt->host_flag_dev);
+  AMG_LAUNCH_CHECK();
+}
+
+// Time the sweep variants on every level with active smoothing rows and keep
+// the fastest columns-per-lane (rows per wave = 64 / (NR / cpl)).
+template <class T, int NR>
+void autotune(amg_batch *bt) {
+  hipStream_t s = bt->stream;
+  hipEvent_t e0, e1;
+  AMG_HIP(hipEventCreate(&e0));
+  AMG_HIP(hipEventCreate(&e1));
+  for (auto &L : bt->B) {
+    L.cpl = 1;
+    if (L.n_cont == 0 || NR == 1) continue;
+    const int64_t m = static_cast<int64_t>(L.n) * NR;
+    T *x = bv_x<T>(L), *t = bv_t<T>(L), *r = bv_r<T>(L);
+    for (T *p : {x, t, r}) hipLaunchKernelGGL(k_bzero<T>, grid_for(m), dim3(kBlock), 0, s, m, p);
+    float best = 1e30f;
+    for (int cpl : {1, 2, 4}) {
+      if (NR % cpl != 0) continue;
+      L.cpl = cpl;
+      sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s);   // warm
+      AMG_HIP(hipEventRecord(e0, s));
+      for (int q = 0; q < 5; ++q) sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s);
+      AMG_HIP(hipEventRecord(e1, s));
+      AMG_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; L.tune_best = cpl; }
+    }
+    L.cpl = L.tune_best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+}  // namespace amg
+
+namespace amg {
+namespace {
+
+// ------------------------------------------------------------ batched setup
+void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
+  hipStream_t s = bt->stream;
+  const bool mixed = bt->p.precision == AMG_PREC_MIXED;
+  const double t0 = wall_ms();
+  std::vector<amg_hierarchy *> H(nsys, nullptr);
+  struct Cleanup {
+    std::vector<amg_hierarchy *> &H;
+    ~Cleanup() {
+      for (auto *h : H)
+        if (h) { destroy_graph(h); if (h->sc_host) (void)hipHostFree(h->sc_host); delete h; }
+    }
+  } cleanup{H};
+  bt->nsys = nsys;
+  bt->nl.assign(nsys, 0);
+  bt->n0.assign(nsys, 0);
+  for (int sid = 0; sid < nsys; ++sid) {
+    H[sid] = new amg_hierarchy();
+    H[sid]->p = bt->p;
+    H[sid]->p.smooth_vector = nullptr;
+    if (bt->p.smooth_vec == AMG_SMOOTH_GIVEN) fail(AMG_ERR_UNSUPPORTED, "batched setup takes no given smooth vector");
+    H[sid]->stream = s;
+    build_hierarchy(H[sid], &A[sid]);
+    if (bt->p.precond && !H[sid]->coarse_dense)
+      fail(AMG_ERR_UNSUPPORTED, "batched solve needs a direct coarsest solve on every system");
+  }
+  // deepest systems first (stable): active systems on any level form a prefix
+  std::vector<int> order(nsys);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return H[a]->L.size() > H[b]->L.size(); });
+  bt->order = order;
+  bt->pos_of.assign(nsys, 0);
+  std::vector<int> nlp(nsys);
+  for (int p = 0; p < nsys; ++p) { bt->pos_of[order[p]] = p; nlp[p] = static_cast<int>(H[order[p]]->L.size()); }
+  for (int sid = 0; sid < nsys; ++sid) { bt->nl[sid] = static_cast<int>(H[sid]->L.size()); bt->n0[sid] = H[sid]->L[0].A.n; }
+  const int max_nl = nlp[0];
+  bt->B.clear();
+  bt->B.resize(max_nl);
+  std::vector<int64_t> roff0;
+  for (int k = 0; k < max_nl; ++k) {
+    BLevel &BL = bt->B[k];
+    int na = 0, ncnt = 0;
+    while (na < nsys && nlp[na] > k) ++na;
+    while (ncnt < na && nlp[ncnt] > k + 1) ++ncnt;
+    std::vector<int64_t> roff(na + 1, 0), zoff(na + 1, 0);
+    for (int p = 0; p < na; ++p) {
+      const Level &Ls = H[order[p]]->L[k];
+      roff[p + 1] = roff[p] + Ls.A.n;
+      zoff[p + 1] = zoff[p] + Ls.A.nnz;
+    }
+    if (roff[na] >= (int64_t(1) << 31) / 16 || zoff[na] >= (int64_t(1) << 31))
+      fail(AMG_ERR_UNSUPPORTED, "batched problem too large for int32 indexing");
+    if (k == 0) roff0 = roff;
+    BL.n = static_cast<int>(roff[na]);
+    BL.n_cont = static_cast<int>(roff[ncnt]);
+    DevCSR &C = BL.L.A;
+    C.n = BL.n;
+    C.nnz = zoff[na];
+    C.rp.alloc(C.n + 1);
+    C.ci.alloc(C.nnz);
+    C.v.alloc(C.nnz);
+    for (int p = 0; p < na; ++p) {
+      const Level &Ls = H[order[p]]->L[k];
+      hipLaunchKernelGGL(k_add_copy, grid_for(Ls.A.n), dim3(kBlock), 0, s, Ls.A.n, Ls.A.rp.p,
+                         C.rp.p + roff[p], static_cast<int>(zoff[p]));
+      hipLaunchKernelGGL(k_add_copy, grid_for(Ls.A.nnz), dim3(kBlock), 0, s, static_cast<int>(Ls.A.nnz),
+                         Ls.A.ci.p, C.ci.p + zoff[p], static_cast<int>(roff[p]));
+      AMG_HIP(hipMemcpyAsync(C.v.p + zoff[p], Ls.A.v.p, sizeof(double) * Ls.A.nnz,
+                             hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, C.rp.p + C.n, static_cast<int>(C.nnz));
+    AMG_LAUNCH_CHECK();
+    finalize_level(BL.L, s, mixed);
+    if (ncnt > 0 && k + 1 < max_nl) {
+      std::vector<int64_t> coff(ncnt + 1, 0);
+      for (int p = 0; p < ncnt; ++p) coff[p + 1] = coff[p] + H[order[p]]->L[k + 1].A.n;
+      Level &L = BL.L;
+      L.nc = static_cast<int>(coff[ncnt]);
+      L.agg.alloc(BL.n_cont);
+      L.pval.alloc(BL.n_cont);
+      if (mixed) L.pvalf.alloc(BL.n_cont);
+      L.mptr.alloc(L.nc + 1);
+      L.mem.alloc(BL.n_cont);
+      for (int p = 0; p < ncnt; ++p) {
+        const Level &Ls = H[order[p]]->L[k];
+        const int nk = Ls.A.n, nck = Ls.nc;
+        hipLaunchKernelGGL(k_add_copy, grid_for(nk), dim3(kBlock), 0, s, nk, Ls.agg.p, L.agg.p + roff[p],
+                           static_cast<int>(coff[p]));
+        AMG_HIP(hipMemcpyAsync(L.pval.p + roff[p], Ls.pval.p, sizeof(double) * nk, hipMemcpyDeviceToDevice, s));
+        if (mixed)
+          AMG_HIP(hipMemcpyAsync(L.pvalf.p + roff[p], Ls.pvalf.p, sizeof(float) * nk,
+                                 hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_add_copy, grid_for(nck), dim3(kBlock), 0, s, nck, Ls.mptr.p, L.mptr.p + coff[p],
+                           static_cast<int>(roff[p]));
+        hipLaunchKernelGGL(k_add_copy, grid_for(nk), dim3(kBlock), 0, s, nk, Ls.mem.p, L.mem.p + roff[p],
+                           static_cast<int>(roff[p]));
+      }
+      hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, L.mptr.p + L.nc, BL.n_cont);
+      AMG_LAUNCH_CHECK();
+    }
+    // systems whose coarsest level is k
+    BL.nterm = na - ncnt;
+    if (BL.nterm > 0) {
+      std::vector<int> toff, tn;
+      std::vector<long long> tinv;
+      long long pool = 0;
+      for (int p = ncnt; p < na; ++p) {
+        const int m = H[order[p]]->L[k].A.n;
+        toff.push_back(static_cast<int>(roff[p]));
+        tn.push_back(m);
+        tinv.push_back(pool);
+        pool += static_cast<long long>(m) * m;
+      }
+      BL.term_off.alloc(BL.nterm);
+      BL.term_n.alloc(BL.nterm);
+      BL.term_inv.alloc(BL.nterm);
+      BL.inv_pool.alloc(std::max<long long>(1, pool));
+      AMG_HIP(hipMemcpyAsync(BL.term_off.p, toff.data(), sizeof(int) * BL.nterm, hipMemcpyHostToDevice, s));
+      AMG_HIP(hipMemcpyAsync(BL.term_n.p, tn.data(), sizeof(int) * BL.nterm, hipMemcpyHostToDevice, s));
+      AMG_HIP(hipMemcpyAsync(BL.term_inv.p, tinv.data(), sizeof(long long) * BL.nterm, hipMemcpyHostToDevice, s));
+      for (int p = ncnt, q = 0; p < na; ++p, ++q) {
+        const amg_hierarchy *hs = H[order[p]];
+        const int m = tn[q];
+        if (bt->p.precond)
+          AMG_HIP(hipMemcpyAsync(BL.inv_pool.p + tinv[q], hs->Ainv.p, sizeof(double) * m * m,
+                                 hipMemcpyDeviceToDevice, s));
+      }
+      AMG_HIP(hipStreamSynchronize(s));
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+  }
+  // level-0 tiles (never crossing a system) and row offsets
+  std::vector<int> r0, r1, ts, tp(nsys + 1, 0);
+  for (int p = 0; p < nsys; ++p) {
+    tp[p] = static_cast<int>(r0.size());
+    for (int64_t a = roff0[p]; a < roff0[p + 1]; a += kBTile) {
+      r0.push_back(static_cast<int>(a));
+      r1.push_back(static_cast<int>(std::min<int64_t>(a + kBTile, roff0[p + 1])));
+      ts.push_back(p);
+    }
+  }
+  tp[nsys] = static_cast<int>(r0.size());
+  bt->ntiles = static_cast<int>(r0.size());
+  bt->trow0.alloc(bt->ntiles);
+  bt->trow1.alloc(bt->ntiles);
+  bt->tsys.alloc(bt->ntiles);
+  bt->tile_ptr.alloc(nsys + 1);
+  AMG_HIP(hipMemcpyAsync(bt->trow0.p, r0.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(bt->trow1.p, r1.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(bt->tsys.p, ts.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+  AMG_HIP(hipMemcpyAsync(bt->tile_ptr.p, tp.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+  bt->user_off.assign(nsys + 1, 0);
+  bt->int_off.assign(nsys, 0);
+  for (int sid = 0; sid < nsys; ++sid) {
+    bt->user_off[sid + 1] = bt->user_off[sid] + bt->n0[sid];
+    bt->int_off[sid] = roff0[bt->pos_of[sid]];
+  }
+  bt->nnz0 = bt->B[0].L.A.nnz;
+  AMG_HIP(hipStreamSynchronize(s));
+  bt->setup_ms = wall_ms() - t0;
+}
+
+void batch_release_graph(amg_batch *bt) {
+  if (bt->graph_exec) (void)hipGraphExecDestroy(bt->graph_exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->graph_exec = nullptr;
+  bt->graph = nullptr;
+}
+
+template <int NR>
+void batch_buffers(amg_batch *bt) {
+  if (bt->nr == NR) return;
+  batch_release_graph(bt);
+  const bool mixed = bt->p.precision == AMG_PREC_MIXED;
+  for (auto &L : bt->B) {
+    const size_t m = static_cast<size_t>(L.n) * NR;
+    if (mixed) { L.rf.alloc(m); L.xf.alloc(m); L.tf.alloc(m); L.r.release(); L.x.release(); L.t.release(); }
+    else { L.r.alloc(m); L.x.alloc(m); L.t.alloc(m); L.rf.release(); L.xf.release(); L.tf.release(); }
+  }
+  const size_t m0 = static_cast<size_t>(bt->B[0].n) * NR;
+  for (auto *v : {&bt->bint, &bt->u, &bt->r, &bt->w, &bt->v, &bt->d, &bt->q}) v->alloc(m0);
+  bt->partials.alloc(static_cast<size_t>(bt->ntiles) * NR * 3);
+  bt->sc.alloc(static_cast<size_t>(bt->nsys) * NR);
+  bt->active.alloc(1);
+  bt->all_done.alloc(1);
+  if (!bt->host_flag) {
+    AMG_HIP(hipHostMalloc(reinterpret_cast<void **>(&bt->host_flag), sizeof(int),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    AMG_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&bt->host_flag_dev), bt->host_flag, 0));
+  }
+  const double t0 = wall_ms();
+  if (bt->p.precond) {
+    if (mixed) autotune<float, NR>(bt);
+    else autotune<double, NR>(bt);
+  }
+  AMG_HIP(hipStreamSynchronize(bt->stream));
+  bt->tune_ms = wall_ms() - t0;
+  bt->nr = NR;
+}
+
+// user layout (systems in user order) <-> internal layout (depth order)
+template <int NR>
+void batch_permute(amg_batch *bt, const double *src, double *dst, bool to_internal) {
+  for (int sid = 0; sid < bt->nsys; ++sid) {
+    const int64_t ui = bt->user_off[sid] * NR, ii = bt->int_off[sid] * NR, m = bt->n0[sid] * NR;
+    if (to_internal)
+      AMG_HIP(hipMemcpyAsync(dst + ii, src + ui, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
+    else
+      AMG_HIP(hipMemcpyAsync(dst + ui, src + ii, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
+  }
+}
+
+constexpr int kGraphIters = 32;   // iterations per graph launch
+
+template <int NR>
+int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int maxit,
+                   int32_t *iters, double *relres, int32_t *status) {
+  hipStream_t s = bt->stream;
+  batch_buffers<NR>(bt);
+  const int64_t m0 = static_cast<int64_t>(bt->B[0].n) * NR;
+  const BLevel &L0 = bt->B[0];
+  batch_permute<NR>(bt, Bu, bt->bint.p, true);
+  batch_permute<NR>(bt, Xu, bt->u.p, true);
+  hipLaunchKernelGGL(k_bzero<double>, grid_for(m0), dim3(kBlock), 0, s, m0, bt->d.p);
+  hipLaunchKernelGGL(k_bzero<double>, grid_for(m0), dim3(kBlock), 0, s, m0, bt->q.p);
+  AMG_HIP(hipMemsetAsync(bt->active.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL((k_bpcg_init<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, bt->trow0.p, bt->trow1.p,
+                     L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->bint.p, bt->u.p, bt->r.p,
+                     bt->partials.p);
+  hipLaunchKernelGGL((k_bpcg_init_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, bt->tile_ptr.p,
+                     bt->partials.p, bt->sc.p, rtol, bt->active.p);
+  hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p, bt->host_flag_dev);
+  AMG_LAUNCH_CHECK();
+  const int reps = std::min(maxit, kGraphIters);
+  if (!bt->graph_exec || bt->graph_reps != reps || bt->graph_maxit != maxit) {
+    batch_release_graph(bt);
+    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < reps; ++i) benqueue_iteration<NR>(bt, maxit);
+    AMG_HIP(hipStreamEndCapture(s, &bt->graph));
+    AMG_HIP(hipGraphInstantiate(&bt->graph_exec, bt->graph, nullptr, nullptr, 0));
+    bt->graph_reps = reps;
+    bt->graph_maxit = maxit;
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  for (int done_it = 0; !*static_cast<volatile int *>(bt->host_flag) && done_it < maxit; done_it += reps) {
+    AMG_HIP(hipGraphLaunch(bt->graph_exec, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
+  batch_permute<NR>(bt, bt->u.p, Xu, false);
+  std::vector<BScalars> S(static_cast<size_t>(bt->nsys) * NR);
+  AMG_HIP(hipMemcpyAsync(S.data(), bt->sc.p, sizeof(BScalars) * S.size(), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  int worst = AMG_OK;
+  for (int sid = 0; sid < bt->nsys; ++sid) {
+    const int p = bt->pos_of[sid];
+    for (int c = 0; c < NR; ++c) {
+      const BScalars &x = S[static_cast<size_t>(p) * NR + c];
+      const size_t o = static_cast<size_t>(sid) * NR + c;
+      iters[o] = x.it;
+      relres[o] = (x.nr0 == 0.0) ? 0.0 : sqrt(x.rr) / x.nr0;
+      int st = x.status != 0 ? x.status : ((x.conv || x.nr0 == 0.0) ? AMG_OK : AMG_NOT_CONVERGED);
+      status[o] = st;
+      if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+      else if (st == AMG_NOT_CONVERGED && worst == AMG_OK) worst = st;
+    }
+  }
+  return worst;
+}
+
+template <int NR>
+void batch_vcycle_nr(amg_batch *bt, const double *Ru, double *Zu) {
+  batch_buffers<NR>(bt);
+  batch_permute<NR>(bt, Ru, bt->r.p, true);
+  bvcycle<NR>(bt, nullptr, bt->r.p, bt->w.p);
+  batch_permute<NR>(bt, bt->w.p, Zu, false);
+  AMG_HIP(hipStreamSynchronize(bt->stream));
+}
+
+}  // namespace
+}  // namespace amg
+
+// ============================================================== C ABI
+extern "C" {
+
+int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_batch **out) {
+  if (out) *out = nullptr;
+  if (nsys < 1 || !A || !p || !out) return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
+  for (int s = 0; s < nsys; ++s)
+    if (A[s].n <= 0 || A[s].nnz < A[s].n || !A[s].row_ptr || !A[s].col_idx || !A[s].val)
+      return amg::api_set_error(AMG_ERR_INVALID, "bad CSR header in the batch");
+  amg_params dflt;
+  amg_params_default(&dflt);
+  amg_batch *bt = new (std::nothrow) amg_batch();
+  if (!bt) return amg::api_set_error(AMG_ERR_NOMEM, "host allocation failed");
+  bt->p = *p;
+  bt->p.smooth_vector = nullptr;
+  if (p->stream) {
+    bt->stream = static_cast<hipStream_t>(p->stream);
+  } else {
+    if (hipStreamCreate(&bt->stream) != hipSuccess) {
+      delete bt;
+      return amg::api_set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
+    }
+    bt->own_stream = 1;
+  }
+  int st = amg::api_guarded([&] {
+    amg::batch_build(bt, nsys, A);
+    return AMG_OK;
+  });
+  if (st != AMG_OK) {
+    std::string msg = amg::api_last_error();
+    amg_batch_destroy(bt);
+    amg::api_set_error(st, msg);
+    return st;
+  }
+  *out = bt;
+  return AMG_OK;
+}
+
+int amg_batch_solve(amg_batch *bt, int32_t nrhs, const double *B, double *X, double rtol,
+                    int32_t maxit, int32_t *iters, double *relres, int32_t *status) {
+  if (!bt || !B || !X || !iters || !relres || !status || !(rtol > 0.0) || maxit < 1)
+    return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
+  return amg::api_guarded([&] {
+    switch (nrhs) {
+      case 1: return amg::batch_solve_nr<1>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 2: return amg::batch_solve_nr<2>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 4: return amg::batch_solve_nr<4>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 8: return amg::batch_solve_nr<8>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 16: return amg::batch_solve_nr<16>(bt, B, X, rtol, maxit, iters, relres, status);
+      default: return amg::api_set_error(AMG_ERR_UNSUPPORTED, "nrhs must be 1, 2, 4, 8 or 16");
+    }
+  });
+}
+
+int amg_batch_vcycle(amg_batch *bt, int32_t nrhs, const double *R, double *Z) {
+  if (!bt || !R || !Z || R == Z) return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
+  return amg::api_guarded([&] {
+    switch (nrhs) {
+      case 1: amg::batch_vcycle_nr<1>(bt, R, Z); break;
+      case 2: amg::batch_vcycle_nr<2>(bt, R, Z); break;
+      case 4: amg::batch_vcycle_nr<4>(bt, R, Z); break;
+      case 8: amg::batch_vcycle_nr<8>(bt, R, Z); break;
+      case 16: amg::batch_vcycle_nr<16>(bt, R, Z); break;
+      default: return amg::api_set_error(AMG_ERR_UNSUPPORTED, "nrhs must be 1, 2, 4, 8 or 16");
+    }
+    return AMG_OK;
+  });
+}
+
+int amg_batch_info(const amg_batch *bt, amg_batch_info_t *out) {
+  if (!bt || !out) return amg::api_set_error(AMG_ERR_INVALID, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->nsys = bt->nsys;
+  out->levels = static_cast<int32_t>(bt->B.size());
+  for (size_t k = 0; k < bt->B.size() && k < AMG_MAX_LEVELS; ++k) {
+    out->n[k] = bt->B[k].n;
+    out->n_smoothed[k] = bt->B[k].n_cont;
+    out->nnz[k] = bt->B[k].L.A.nnz;
+    out->cols_per_lane[k] = bt->B[k].cpl;
+  }
+  out->setup_ms = bt->setup_ms;
+  out->tune_ms = bt->tune_ms;
+  return AMG_OK;
+}
+
+void amg_batch_destroy(amg_batch *bt) {
+  if (!bt) return;
+  (void)hipStreamSynchronize(bt->stream);
+  amg::batch_release_graph(bt);
+  if (bt->host_flag) (void)hipHostFree(bt->host_flag);
+  hipStream_t s = bt->stream;
+  const int own = bt->own_stream;
+  delete bt;
+  if (own) (void)hipStreamDestroy(s);
+}
+
+}  // extern "C"

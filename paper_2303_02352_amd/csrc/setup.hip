@@ -676,6 +676,12 @@ void build_members(Level &Lv, hipStream_t s) {
 
 }  // namespace
 
+// Entry points for the other translation units (batched hierarchy).
+void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s) { exclusive_scan(in, out, n, s); }
+int device_read_int(const int *p, hipStream_t s) { return read_int(p, s); }
+void finalize_level(Level &Lv, hipStream_t s, bool want_float) { finish_level(Lv, s, want_float); }
+double wall_ms() { return now_ms(); }
+
 // ===================================================== hierarchy builder
 void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   hipStream_t s = h->stream;
