@@ -48,7 +48,7 @@ def kernel_source_hash():
 def measured_traffic(kernel_name, algorithmic_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_name)
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % kernel_name)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-profile", action="store_true",
+                    help="only: build the 160^3 hierarchy, launch the fine-level sweep "
+                         "--kernel-reps times, then copy 1 GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU's share of the problem; runs on %d GPUs are not "
@@ -135,6 +138,19 @@ def main():
     rp, ci, va, bd = d(A.row_ptr), d(A.col), d(A.val), d(b)
     stream = torch.cuda.Stream()          # default priority
     torch.cuda.synchronize()
+
+    if args.kernel_profile:
+        with torch.cuda.stream(stream):
+            H = amd.Hierarchy(rp, ci, va)
+            ms, by = H.time_kernel(amd.KERNEL_SWEEP, 0, args.kernel_reps)
+            src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        print(json.dumps({"kernel": "k_sweep<double> level 0", "avg_ms": ms, "algorithmic_bytes": by,
+                          "launches": args.kernel_reps + 1, "calibration_copy_bytes": src.numel() * 8,
+                          "source_hash": kernel_source_hash()}), flush=True)
+        return
 
     def one_step(precision=amd.AMG_PREC_DOUBLE):
         with torch.cuda.stream(stream):

@@ -253,13 +253,18 @@ __global__ void k_match_cand(int n, const int *rp, const int *ci, const double *
   cand[i] = best;
 }
 
+// nfree counts the wavefronts that still hold an undecided vertex (only
+// zero / non-zero matters), one atomic per wavefront.
 __global__ void k_match_commit(int n, int *mate, const int *cand, int *nfree) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || mate[i] != kFree) return;
-  const int c = cand[i];
-  if (c < 0) mate[i] = kSingle;
-  else if (cand[c] == i) mate[i] = c;
-  else atomicAdd(nfree, 1);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool open = false;
+  if (i < n && mate[i] == kFree) {
+    const int c = cand[i];
+    if (c < 0) mate[i] = kSingle;
+    else if (cand[c] == i) mate[i] = c;
+    else open = true;
+  }
+  if (__ballot(open) != 0ull && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(nfree, 1);
 }
 
 // ------------------------------------------------------------ aggregation
