@@ -105,6 +105,96 @@ def batched_leg(amd, torch, W, np, dev):
                 tune_ms=inf["tune_ms"])
 
 
+def learned_leg(amd, torch, W, np, dev):
+    """7-point log-normal diffusion 128^3 (sigma^2 = 2, ell = 8, seed 7; not a
+    training field): smooth vector from 20 relaxation sweeps (plain) versus the
+    network's prediction (learned), both through the same setup and FP64 solve."""
+    from paper_2303_02352_amd import surrogate
+    A = W.lognormal7(128, 7)
+    xs, b = W.manufactured_rhs(A, 8)
+    csr = surrogate.device_csr(A, torch)
+    bd = torch.from_numpy(b).to(dev)
+    params, meta = surrogate.load_params()
+    net = amd.SmoothVectorNet(params)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def solve(H):
+        x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+        (st, it, rel), t = timed(lambda: H.solve(bd, x, rtol=RTOL, maxit=MAXIT))
+        return dict(status=st, iters=it, relres=rel, solve_s=t,
+                    conv_factor=float(rel ** (1.0 / max(1, it))))
+
+    res = {}
+    for rep in range(2):          # second pass is reported (warm)
+        # smooth-vector generation alone: one-level setups with and without relaxation
+        H1, t_relax = timed(lambda: amd.Hierarchy(*csr, smooth_vec=amd.AMG_SMOOTH_RELAX,
+                                                  smooth_sweeps=20, max_levels=1))
+        H1.close()
+        H1, t_ones = timed(lambda: amd.Hierarchy(*csr, max_levels=1))
+        H1.close()
+        Hp, tsp = timed(lambda: amd.Hierarchy(*csr, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20))
+        plain = dict(setup_s=tsp, wgen_s=max(0.0, t_relax - t_ones), **solve(Hp),
+                     levels=Hp.info()["n"], opc=Hp.info()["opc"])
+        Hp.close()
+        w, t_inf = timed(lambda: surrogate.learned_smooth_vector(net, csr, torch))
+        fallback = w is None
+        if fallback:
+            Hl, tsl = timed(lambda: amd.Hierarchy(*csr, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20))
+        else:
+            Hl, tsl = timed(lambda: amd.Hierarchy(*csr, smooth_vector=w))
+        learned = dict(setup_s=tsl, wgen_s=t_inf, fallback_to_relax=fallback, **solve(Hl),
+                       levels=Hl.info()["n"], opc=Hl.info()["opc"])
+        Hl.close()
+        res = dict(workload="lognormal7 128^3 seed 7 (sigma^2 = 2, ell = 8)", plain=plain, learned=learned)
+    p, l = res["plain"], res["learned"]
+    res["speedup_solve"] = p["solve_s"] / l["solve_s"]
+    res["speedup_wgen"] = p["wgen_s"] / max(1e-9, l["wgen_s"])
+    res["speedup_setup_plus_solve"] = (p["setup_s"] + p["solve_s"]) / (l["setup_s"] + l["wgen_s"] + l["solve_s"])
+    res["model"] = dict(final_loss=meta.get("final_loss"), steps=meta.get("steps"),
+                        training_fields=len(meta.get("fields", [])))
+    net.close()
+    return res
+
+
+def mixed27_leg(amd, torch, W, np, dev):
+    """27-point diffusion 128^3, kappa log-uniform in [1e-3, 1e3] (seed 3),
+    x* seed 4, relaxation smooth vector: FP64 V-cycle versus binary32 V-cycle
+    (FP64 outer CG, dots and coarsest solve)."""
+    A = W.diffusion27(128, 3)
+    xs, b = W.manufactured_rhs(A, 4)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rp, ci, va, bd = d(A.row_ptr), d(A.col), d(A.val), d(b)
+    out = {}
+    for name, prec in (("fp64", amd.AMG_PREC_DOUBLE), ("mixed", amd.AMG_PREC_MIXED)):
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = amd.Hierarchy(rp, ci, va, smooth_vec=amd.AMG_SMOOTH_RELAX, precision=prec)
+            t1 = time.perf_counter()
+            x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            st, it, rel = H.solve(bd, x, rtol=RTOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out[name] = dict(status=st, iters=it, relres=rel, setup_s=t1 - t0, solve_s=t2 - t1,
+                             levels=H.info()["n"], x=x.cpu().numpy())
+            H.close()
+    x64, x32 = out["fp64"].pop("x"), out["mixed"].pop("x")
+    S = A.scipy()
+    for name, xv in (("fp64", x64), ("mixed", x32)):
+        out[name]["true_relres"] = float(np.linalg.norm(b - S @ xv) / np.linalg.norm(b))
+        out[name]["rel_error_vs_exact"] = float(np.linalg.norm(xv - xs) / np.linalg.norm(xs))
+    out["mixed"]["max_rel_diff_vs_fp64_solution"] = float(np.max(np.abs(x32 - x64)) / np.max(np.abs(x64)))
+    out["speedup_solve"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    out["workload"] = "diffusion27 128^3 (2,097,152 rows, 55,742,968 nnz)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +308,14 @@ def main():
                               speedup_vs_fp64_solve=solve_s / rm["solve_s"],
                               max_rel_diff_vs_fp64_solution=float(np.max(np.abs(xmh - xg)) / np.max(np.abs(xg))))
         Hm.close()
+
+    if not args.no_forms:
+        log("mixed precision, 27-point 128^3")
+        forms["mixed_27pt"] = mixed27_leg(amd, torch, W, np, dev)
+        log("mixed27", json.dumps(forms["mixed_27pt"]))
+        log("learned form")
+        forms["learned"] = learned_leg(amd, torch, W, np, dev)
+        log("learned", json.dumps(forms["learned"]))
 
     if not args.no_forms and not args.no_batched:
         log("batched form")

@@ -229,6 +229,41 @@ int amg_batch_info(const amg_batch *bt, amg_batch_info_t *out);
 /* NULL-safe. */
 void amg_batch_destroy(amg_batch *bt);
 
+/* ------------------------------------------------- learned smooth vector
+ * A two-layer message-passing network over the graph of A that predicts
+ * log w, w being the smooth vector that drives the matching weights (Sec. 3.1
+ * leaves its source open; the targets are the method's own relaxation
+ * vectors, AMG_SMOOTH_RELAX).  Node features (8): 1, log(a_ii)/4,
+ * s_i/a_ii with s_i = sum_{j!=i}|a_ij|, two l1-Jacobi sweeps on A w = 0 from
+ * ones, log(max/min off-diagonal |a_ij|)/4, (#off-diagonals)/6, 0.
+ * Aggregation (Ahat X)_i = sum_{j!=i}|a_ij| X_j / s_i.
+ *   h1 = ReLU([X | Ahat X] W1 + b1), h2 = ReLU([h1 | Ahat h1] W2 + b2),
+ *   y = h2 wh + bh,  w = exp(y).
+ * Parameters (binary32, flat): W1 16x32 row-major, b1[32], W2 64x32, b2[32],
+ * wh[32], bh[1].  Dense products read bfloat16 activations and weights and
+ * accumulate in binary32 (MFMA).  The CSR must be in device memory. */
+#define AMG_MPNN_NPARAMS 2657
+typedef struct amg_mpnn amg_mpnn;
+
+/* params: host array of AMG_MPNN_NPARAMS floats (NULL = all zero).
+ * stream: hipStream_t (NULL = a library-owned stream). */
+int amg_mpnn_create(const float *params, void *stream, amg_mpnn **out);
+/* Copy the current parameters to a host array of AMG_MPNN_NPARAMS floats. */
+int amg_mpnn_get_params(const amg_mpnn *m, float *params);
+/* Node features as the network stores them (bfloat16 values widened to
+ * binary32), host array of 8 n floats, row-major.  Synchronises. */
+int amg_mpnn_features(amg_mpnn *m, const amg_csr *A, float *X_host);
+/* Predict: w_out (device, n doubles) = exp(y) and/or y_host (host, n floats). */
+int amg_mpnn_predict(amg_mpnn *m, const amg_csr *A, double *w_out, float *y_host);
+/* One training step on one graph: loss = mean (y - log w_target)^2 with
+ * w_target a device array of n positive doubles; the gradient is copied to
+ * grad_host (host, AMG_MPNN_NPARAMS floats) when given; then one Adam step
+ * (beta 0.9 / 0.999) with learning rate lr (lr = 0: no update).  Synchronises. */
+int amg_mpnn_train_step(amg_mpnn *m, const amg_csr *A, const double *w_target, float lr,
+                        float *loss_out, float *grad_host);
+/* NULL-safe. */
+void amg_mpnn_destroy(amg_mpnn *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,15 @@ EXPORTS = {
     "amg_batch_vcycle": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "amg_batch_info": (C.c_int, [C.c_void_p, C.POINTER(amg_batch_info_t)]),
     "amg_batch_destroy": (None, [C.c_void_p]),
+    "amg_mpnn_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amg_mpnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "amg_mpnn_features": (C.c_int, [C.c_void_p, C.POINTER(amg_csr), C.c_void_p]),
+    "amg_mpnn_predict": (C.c_int, [C.c_void_p, C.POINTER(amg_csr), C.c_void_p, C.c_void_p]),
+    "amg_mpnn_train_step": (C.c_int, [C.c_void_p, C.POINTER(amg_csr), C.c_void_p, C.c_float,
+                                      C.POINTER(C.c_float), C.c_void_p]),
+    "amg_mpnn_destroy": (None, [C.c_void_p]),
 }
+AMG_MPNN_NPARAMS = 2657
 
 _lib = None
 
@@ -289,3 +297,67 @@ class Batch:
         return dict(nsys=inf.nsys, levels=L, n=list(inf.n[:L]), n_smoothed=list(inf.n_smoothed[:L]),
                     nnz=list(inf.nnz[:L]), cols_per_lane=list(inf.cols_per_lane[:L]),
                     setup_ms=inf.setup_ms, tune_ms=inf.tune_ms)
+
+
+class SmoothVectorNet:
+    """Learned smooth-vector network (``amg_mpnn_*``): features, predict, train."""
+
+    def __init__(self, params=None, stream=None):
+        L = load()
+        theta = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if theta is not None:
+            assert theta.shape == (AMG_MPNN_NPARAMS,)
+        h = C.c_void_p()
+        st = L.amg_mpnn_create(_ptr(theta), stream, C.byref(h))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_mpnn_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().amg_mpnn_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _csr(row_ptr, col, val):
+        return amg_csr(int(row_ptr.shape[0]) - 1, int(col.shape[0]), _ptr(row_ptr), _ptr(col), _ptr(val),
+                       _on_device(val))
+
+    def params(self):
+        out = np.empty(AMG_MPNN_NPARAMS, np.float32)
+        st = load().amg_mpnn_get_params(self.h, _ptr(out))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_mpnn_get_params")
+        return out
+
+    def features(self, row_ptr, col, val):
+        A = self._csr(row_ptr, col, val)
+        X = np.empty((A.n, 8), np.float32)
+        st = load().amg_mpnn_features(self.h, C.byref(A), _ptr(X))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_mpnn_features")
+        return X
+
+    def predict(self, row_ptr, col, val, w_out=None, want_y=False):
+        """w_out: device float64 tensor of n (exp of the prediction); returns y (host) if asked."""
+        A = self._csr(row_ptr, col, val)
+        y = np.empty(A.n, np.float32) if want_y else None
+        st = load().amg_mpnn_predict(self.h, C.byref(A), _ptr(w_out), _ptr(y))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_mpnn_predict")
+        return y
+
+    def train_step(self, row_ptr, col, val, w_target, lr, want_grad=False):
+        A = self._csr(row_ptr, col, val)
+        loss = C.c_float()
+        g = np.empty(AMG_MPNN_NPARAMS, np.float32) if want_grad else None
+        st = load().amg_mpnn_train_step(self.h, C.byref(A), _ptr(w_target), float(lr), C.byref(loss), _ptr(g))
+        if st != AMG_OK:
+            raise AMGError(st, "amg_mpnn_train_step")
+        return (loss.value, g) if want_grad else loss.value

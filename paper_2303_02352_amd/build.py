@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamg355.so")
-SOURCES = ["setup.hip", "solve.hip", "batch.hip", "api.hip"]
+SOURCES = ["setup.hip", "solve.hip", "batch.hip", "mpnn.hip", "api.hip"]
 HEADERS = [os.path.join(CSRC, "amg_internal.hpp"), os.path.join(ROOT, "include", "amg355.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

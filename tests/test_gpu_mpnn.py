@@ -1,0 +1,104 @@
+"""GPU parity of the learned smooth-vector network (amg_mpnn_*).
+
+Against the numpy oracle (oracle/mpnn.py, its backward pass pinned by finite
+differences on the CPU), with the oracle emulating the bfloat16 storage:
+  * features: equal up to one bfloat16 unit in the last place;
+  * forward prediction y: relative L2 error <= 2e-2;
+  * gradient of the loss: relative L2 error <= 5e-2 per parameter block,
+    loss within 2e-2 relative;
+and the properties the method needs: training lowers the loss, and the
+predicted vector is positive, finite and drives a working hierarchy.
+The prediction itself is "parity unpinned" beyond this (trained weights have
+no closed form); PCG iterations judge it in bench.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.mpnn as M
+import workloads as W
+
+from gpu_helpers import dev, host, require_gpu, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _net(theta=None):
+    import paper_2303_02352_amd as amd
+    return amd.SmoothVectorNet(theta)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, float) - np.asarray(b, float)) / max(1e-30, np.linalg.norm(b)))
+
+
+@pytest.mark.parametrize("N,seed", [(12, 3), (17, 5)])
+def test_features_match_oracle(N, seed):
+    A = W.lognormal7(N, seed, ell=4.0)
+    say("mpnn features", N, seed)
+    Xg = _net().features(dev(A.row_ptr), dev(A.col), dev(A.val))
+    Xo = M.round_bf16(M.features(A)[0])
+    ulp = np.maximum(np.abs(Xo), 1e-30) * 2.0 ** -7
+    assert np.all(np.abs(Xg - Xo) <= ulp + 1e-12), np.max(np.abs(Xg - Xo) / ulp)
+
+
+@pytest.mark.parametrize("N,seed", [(12, 3), (21, 8)])
+def test_forward_matches_oracle(N, seed):
+    A = W.lognormal7(N, seed, ell=4.0)
+    theta = M.init_params(seed).astype(np.float32)
+    say("mpnn forward", N, seed)
+    yg = _net(theta).predict(dev(A.row_ptr), dev(A.col), dev(A.val), want_y=True)
+    yo, _ = M.forward(theta.astype(np.float64), A, bf16=True)
+    err = _rel(yg, yo)
+    say("  rel L2 %.2e" % err)
+    assert err <= 2e-2
+
+
+def test_gradient_matches_oracle():
+    A = W.lognormal7(14, 4, ell=4.0)
+    theta = M.init_params(7).astype(np.float32)
+    target = 0.2 + W.uniform(60, A.n)
+    say("mpnn gradient")
+    loss_g, g = _net(theta).train_step(dev(A.row_ptr), dev(A.col), dev(A.val), dev(target), 0.0,
+                                       want_grad=True)
+    loss_o, go = M.loss_and_grad(theta.astype(np.float64), A, np.log(target), bf16=True)
+    say("  loss gpu %.6e oracle %.6e" % (loss_g, loss_o))
+    assert abs(loss_g - loss_o) <= 2e-2 * loss_o
+    o = 0
+    for name, shp in M.SHAPES:
+        m = int(np.prod(shp))
+        err = _rel(g[o:o + m], go[o:o + m])
+        say("  %s rel L2 %.2e" % (name, err))
+        assert err <= 5e-2, name
+        o += m
+
+
+def test_training_lowers_loss_and_vector_drives_hierarchy():
+    import paper_2303_02352_amd as amd
+    from paper_2303_02352_amd import surrogate
+    fields = [W.lognormal7(16, s, ell=4.0) for s in (30, 31)]
+    data = []
+    for A in fields:
+        csr = surrogate.device_csr(A, torch)
+        data.append(csr + (surrogate.relax_target(csr, torch),))
+    net = _net(surrogate.init_params(1))
+    hist = surrogate.train(net, data, 120, 3e-3, log_every=0)
+    say("  loss %.3e -> %.3e" % (hist[0], hist[-1]))
+    assert np.mean(hist[-10:]) < 0.5 * np.mean(hist[:10])
+    A = W.lognormal7(16, 32, ell=4.0)
+    csr = surrogate.device_csr(A, torch)
+    w = surrogate.learned_smooth_vector(net, csr, torch)
+    assert w is not None
+    H = amd.Hierarchy(*csr, smooth_vector=w)
+    xs, b = W.manufactured_rhs(A, 1)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st, it, rel = H.solve(dev(b), x)
+    assert st == 0 and rel <= 1e-6
+    # the learned vector goes through the same setup as any other: oracle parity
+    Ho = oracle.Hierarchy(A, oracle.AMGParams(smooth_vec=2), w=host(w))
+    assert H.info()["n"] == [s[0] for s in Ho.sizes()]
