@@ -164,16 +164,6 @@ __global__ void k_l1_dinv_f(int n, const int *rp, const double *v, float *dinv) 
   dinv[i] = 1.0f / m;
 }
 
-// One sweep on CSR (setup only): xn = x + dinv * (r - A x), r = 0 here.
-__global__ void k_csr_relax0(int n, const int *rp, const int *ci, const double *v,
-                             const double *dinv, const double *x, double *xn) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + v[k] * x[ci[k]];
-  xn[i] = x[i] + dinv[i] * (0.0 - s);
-}
-
 __global__ void k_fill(int n, double *x, double val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = val;
@@ -733,11 +723,10 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, 1.0);
     AMG_LAUNCH_CHECK();
     if (P.smooth_vec == AMG_SMOOTH_RELAX) {
-      dvec<double> t(n);
+      dvec<double> t(n), zero(n);
+      AMG_HIP(hipMemsetAsync(zero.p, 0, sizeof(double) * n, s));
       for (int it = 0; it < P.smooth_sweeps; ++it) {
-        hipLaunchKernelGGL(k_csr_relax0, grid_for(n), dim3(kBlock), 0, s, n, L0.A.rp.p, L0.A.ci.p,
-                           L0.A.v.p, L0.dinv.p, L0.w.p, t.p);
-        AMG_LAUNCH_CHECK();
+        enqueue_sweep(h, 0, zero.p, L0.w.p, t.p);   // w <- w + dinv (0 - A w)
         std::swap(L0.w, t);
       }
       dvec<unsigned long long> mx(1);

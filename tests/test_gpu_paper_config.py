@@ -1,0 +1,51 @@
+"""The paper's own configuration (Sec. 5 and Appendix A) on the GPU path:
+three composed pairwise steps (aggregates of at most 8), coarsest size at most
+40 * nd solved by 20 l1-Jacobi sweeps, 4 + 4 sweeps, unit right-hand side.
+Pins from the paper's text (tests/golden/paper_hierarchy.json): 4 levels at
+130^3 on one node, operator complexity about 1.14; the whole hierarchy is
+also bit-exact with the oracle's at 130^3."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+from gpu_helpers import assert_same_hierarchy, dev, gpu_hierarchy, require_gpu, say, torch
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_hierarchy.json")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def paper_params(nd):
+    g = json.load(open(GOLDEN))["params"]
+    return dict(aggr_steps=g["aggr_steps"], coarse_max=g["coarse_max_per_nd"] * nd,
+                max_levels=g["max_levels"], coarse_solver=1, coarse_sweeps=g["coarse_sweeps"],
+                pre_sweeps=g["pre_sweeps"], post_sweeps=g["post_sweeps"])
+
+
+def test_paper_hierarchy_130_on_gpu():
+    g = json.load(open(GOLDEN))
+    nd = g["weak_scaling_130"]["nd"]
+    A = W.poisson7(nd)
+    p = paper_params(nd)
+    say("paper config 130^3")
+    Hg = gpu_hierarchy(A, **p)
+    inf = Hg.info()
+    assert inf["levels"] == g["weak_scaling_130"]["levels_on_one_node"]
+    assert abs(inf["opc"] - g["operator_complexity"]["value"]) <= g["operator_complexity"]["tolerance"]
+    Ho = oracle.Hierarchy(A, oracle.AMGParams(**p))
+    assert_same_hierarchy(Hg, Ho)
+    b = np.ones(A.n)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st, it, rel = Hg.solve(dev(b), x)
+    xo, ito, relo, sto = Ho.pcg(b)
+    say("  iterations gpu %d oracle %d" % (it, ito))
+    assert st == 0 and abs(it - ito) <= 1 and rel <= 1e-6
