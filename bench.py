@@ -314,7 +314,7 @@ def main():
     kt = {}
     for name, kid in (("spmv_dots", amd.KERNEL_SPMV), ("sweep", amd.KERNEL_SWEEP),
                       ("restrict", amd.KERNEL_RESTRICT), ("prolong", amd.KERNEL_PROLONG),
-                      ("pcg_update", amd.KERNEL_UPDATE)):
+                      ("corr_sweep", amd.KERNEL_CORR_SWEEP), ("pcg_update", amd.KERNEL_UPDATE)):
         ms, by = H.time_kernel(kid, 0, args.kernel_reps)
         kt[name] = dict(avg_ms=ms, bytes=by, gbps=by / (ms * 1e-3) / 1e9)
     log("kernels", json.dumps(kt))

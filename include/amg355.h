@@ -174,7 +174,8 @@ int amg_sweep(amg_hierarchy *h, int32_t k, const double *r, const double *x, dou
 /* Timing of one solve-phase kernel in its solve launch configuration:
  * kernel 0 = SpMV (+3 dots) on level k, 1 = l1-Jacobi sweep on level k,
  * 2 = residual + restriction from level k, 3 = prolongation into level k,
- * 4 = the fused PCG vector update (level 0 only).  It is launched `reps`
+ * 4 = the fused PCG vector update (level 0 only), 5 = prolongation into
+ * level k fused with the first post-smoothing sweep.  It is launched `reps`
  * times on the hierarchy's stream between two HIP events on that stream,
  * operating on the hierarchy's own work vectors; *avg_ms is the mean
  * duration and *bytes the algorithmic bytes one launch moves.  Synchronises. */

@@ -24,7 +24,7 @@ AMG_COARSE_CHOLESKY, AMG_COARSE_JACOBI = 0, 1
 AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN = 0, 1, 2
 AMG_PREC_DOUBLE, AMG_PREC_MIXED = 0, 1
 AMG_MAX_LEVELS = 64
-KERNEL_SPMV, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_UPDATE = 0, 1, 2, 3, 4
+KERNEL_SPMV, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_UPDATE, KERNEL_CORR_SWEEP = 0, 1, 2, 3, 4, 5
 
 
 class amg_csr(C.Structure):

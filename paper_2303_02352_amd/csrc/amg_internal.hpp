@@ -74,7 +74,9 @@ constexpr int kXcd = 8;            // MI355X: 8 XCDs, workgroups dispatched roun
 constexpr int kDenseMax = 1024;    // largest coarsest level factored densely
 constexpr double kStagnation = 0.95;
 constexpr int kTailRows = 1024;    // levels up to this size run in the coarse-tail kernel
-constexpr int kTailThreads = 1024;
+constexpr int kTailThreads = 1024; // one row (and one aggregate) per thread
+constexpr int kTailLds = 8192;     // LDS elements for the tail's vectors: 4 per row and level
+static_assert(kTailRows <= kTailThreads, "the coarse tail maps one row to one thread");
 
 // Canonical CSR (setup, export, next-level construction).
 struct DevCSR {
@@ -95,7 +97,23 @@ struct Sell {
   dvec<int> col;
   dvec<double> val;
   dvec<float> valf;   // binary32 copy for the mixed-precision V-cycle
+  // Compact column form read by the streaming kernels: the 64 slots k of a
+  // slice (one "group", index sptr[s]/64 + k) share cbase[group] = smallest
+  // column among them and keep col - cbase as 16 bits in cdel.  A slice whose
+  // group spans more than 65535 columns keeps cbase = -1 on all its groups and
+  // is read from `col`.
+  dvec<int> cbase;               // nslots / 64
+  dvec<unsigned short> cdel;     // nslots
+  int64_t nnz_compact = 0;       // matrix entries in compact slices
+  int64_t groups_compact = 0;    // groups of compact slices
 };
+
+// Column access of a SELL matrix as the kernels see it.
+struct SellRef {
+  const int *sptr, *col, *cbase;
+  const unsigned short *cdel;   // null: all slices read `col`
+};
+inline SellRef sell_ref(const Sell &S) { return SellRef{S.sptr.p, S.col.p, S.cbase.p, S.cdel.p}; }
 
 struct Level {
   DevCSR A;
@@ -127,10 +145,10 @@ struct Scalars {        // PCG state living in device memory
 template <class T>
 struct TailDesc {
   int n, nc;
+  int lds;          // offset (elements of T) of the level's four LDS vectors
   const int *sptr, *col;
-  const T *val, *dinv, *pval;
+  const T *val, *pval;
   const int *agg, *mptr, *mem;
-  T *r, *x, *t;
 };
 
 struct Timing {
@@ -149,6 +167,7 @@ struct amg_hierarchy {
   amg::dvec<double> Ainv;      // inverse of the coarsest matrix, column-major
   // levels [tail_start, levels) run inside one workgroup (coarse-tail kernel)
   int tail_start = 0;
+  int tail_w = 0;              // widest SELL slice (slots) among the tail levels
   amg::dvec<unsigned char> tail_desc_d, tail_desc_f;   // TailDesc<double> / <float> arrays
   // PCG vectors
   amg::dvec<double> u, r, w, v, d, q;

@@ -61,6 +61,7 @@ int64_t device_bytes(const amg_hierarchy *h) {
   for (const Level &L : h->L) {
     b += L.A.rp.bytes() + L.A.ci.bytes() + L.A.v.bytes();
     b += L.S.sptr.bytes() + L.S.col.bytes() + L.S.val.bytes() + L.S.valf.bytes();
+    b += L.S.cbase.bytes() + L.S.cdel.bytes();
     b += L.dinv.bytes() + L.w.bytes() + L.dinvf.bytes() + L.agg.bytes() + L.pval.bytes();
     b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
     b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();

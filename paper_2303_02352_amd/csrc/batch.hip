@@ -110,6 +110,52 @@ __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
   for (int j = 0; j < CPL; ++j) xn[o + j] = x[o + j] + di * (rhs[o + j] - acc[j]);
 }
 
+// First post-smoothing sweep with the coarse correction folded in: the
+// iterate read at column c is y_c = x_c + p_c e[agg_c] (the value k_bprolong
+// stores), xn = y + dinv (rhs - A y); y is never written.  Rows [0, n) all
+// continue to the coarser level.
+template <class T, int NR, int CPL>
+__global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
+                                                        const int *__restrict__ sptr,
+                                                        const int *__restrict__ col,
+                                                        const T *__restrict__ val,
+                                                        const T *__restrict__ rhs,
+                                                        const T *__restrict__ x,
+                                                        const int *__restrict__ agg,
+                                                        const T *__restrict__ pval,
+                                                        const T *__restrict__ e, T *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
+  constexpr int LPR = NR / CPL;
+  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int row = gid / LPR, cb = (gid % LPR) * CPL;
+  if (row >= n) return;
+  const int s = row >> 6, lane = row & 63;
+  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
+  T acc[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) acc[j] = T(0);
+  T m = T(0);
+  for (int k = 0; k < width; ++k) {
+    const int c = col[b + k * 64 + lane];
+    const T a = val[b + k * 64 + lane];
+    m = m + fabs(a);
+    const T pc = pval[c];
+    const T *xp = x + static_cast<int64_t>(c) * NR + cb;
+    const T *ep = e + static_cast<int64_t>(agg[c]) * NR + cb;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a * (xp[j] + pc * ep[j]);
+  }
+  const T di = T(1) / m;
+  const T pr = pval[row];
+  const int64_t o = static_cast<int64_t>(row) * NR + cb;
+  const T *er = e + static_cast<int64_t>(agg[row]) * NR + cb;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const T y = x[o + j] + pr * er[j];
+    xn[o + j] = y + di * (rhs[o + j] - acc[j]);
+  }
+}
+
 // t = p (rhs - A x) on rows [0, n)
 template <class T, int NR, int CPL>
 __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
@@ -499,6 +545,23 @@ void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, 
                      s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t);
 }
 
+template <class T, int NR, int CPL>
+void launch_bsweep_corr(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
+                        hipStream_t s) {
+  constexpr int LPR = NR / CPL;
+  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock),
+                     0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p,
+                     bpval<T>(L.L), e, xn);
+}
+
+template <class T, int NR>
+void corr_sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
+                    hipStream_t s) {
+  if (NR % 4 == 0 && L.cpl == 4) launch_bsweep_corr<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, e, x, xn, s);
+  else if (NR % 2 == 0 && L.cpl == 2) launch_bsweep_corr<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, e, x, xn, s);
+  else launch_bsweep_corr<T, NR, 1>(skip, L, n, rhs, e, x, xn, s);
+}
+
 template <class T, int NR>
 void sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
   if (NR % 4 == 0 && L.cpl == 4) launch_bsweep<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, x, xn, s);
@@ -551,9 +614,14 @@ void bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, 
   hipLaunchKernelGGL((k_bagg<T, NR>), grid_for(static_cast<int64_t>(C.n) * NR), dim3(kBlock), 0, s, skip,
                      C.n, L.L.mptr.p, L.L.mem.p, Bf, bv_r<T>(C), bdinv<T>(C.L), xc);
   bvcycle_level<T, NR>(bt, skip, k + 1, bv_r<T>(C), bv_x<T>(C), xc != nullptr);
-  hipLaunchKernelGGL((k_bprolong<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
-                     skip, nc0, L.L.agg.p, bpval<T>(L.L), bv_x<T>(C), A);
-  for (int qq = 0; qq < P.post_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
+  if (P.post_sweeps == 0) {
+    hipLaunchKernelGGL((k_bprolong<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+                       skip, nc0, L.L.agg.p, bpval<T>(L.L), bv_x<T>(C), A);
+    return;
+  }
+  corr_sweep_any<T, NR>(skip, L, nc0, rhs, bv_x<T>(C), A, Bf, s);
+  std::swap(A, Bf);
+  for (int qq = 1; qq < P.post_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
 }
 
 template <int NR>

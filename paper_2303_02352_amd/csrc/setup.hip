@@ -223,38 +223,87 @@ __device__ __forceinline__ bool key_gt(double wa, int ha, int la, double wb, int
 }
 
 // Matching by locally dominant edges: every undecided vertex names its
-// heaviest eligible edge to an undecided neighbour; mutual choices are
-// matched.  Under the strict total order this reproduces the sequential
-// greedy matching (and Suitor's result) whatever the round structure.
-__global__ void k_match_cand(int n, const int *rp, const int *ci, const double *wgt,
-                             const int *mate, int *cand) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || mate[i] != kFree) return;
-  int best = -1, bh = 0, bl = 0;
-  double bw = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const double x = wgt[k];
-    if (!(x > 0.0)) continue;
-    const int j = ci[k];
-    if (mate[j] != kFree) continue;
-    const int hi = j > i ? j : i, lo = j > i ? i : j;
-    if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
+// heaviest eligible edge to an undecided neighbour (its candidate); mutual
+// choices are matched.  Under the strict total order this reproduces the
+// sequential greedy matching (and Suitor's result) whatever the round
+// structure.
+//
+// Rounds run on worklists.  A candidate stays the best choice until it is
+// matched itself (the undecided set only shrinks), so after round 0 (all
+// vertices) only the undecided neighbours that had named a newly matched
+// vertex recompute their candidate, and a new mutual pair always contains
+// such a vertex: round t = notify (matched list of t-1 -> recompute list),
+// candidates of the recompute list, commit over the recompute list.  The
+// state after every round equals that of all-vertex rounds; the matching
+// ends when a recompute list is empty.  Lists are unordered (atomic
+// appends); the result does not depend on their order.
+//
+// List kernels run grid-stride over a device-side count; list == nullptr
+// means "every vertex 0..n-1".
+__global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *list, const int *cnt,
+                                                    const int *rp, const int *ci,
+                                                    const double *wgt, const int *mate,
+                                                    int *cand) {
+  const int m = list ? *cnt : n;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+    const int i = list ? list[q] : q;
+    if (mate[i] != kFree) continue;
+    int best = -1, bh = 0, bl = 0;
+    double bw = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const double x = wgt[k];
+      if (!(x > 0.0)) continue;
+      const int j = ci[k];
+      if (mate[j] != kFree) continue;
+      const int hi = j > i ? j : i, lo = j > i ? i : j;
+      if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
+    }
+    cand[i] = best;
   }
-  cand[i] = best;
 }
 
-// nfree counts the wavefronts that still hold an undecided vertex (only
-// zero / non-zero matters), one atomic per wavefront.
-__global__ void k_match_commit(int n, int *mate, const int *cand, int *nfree) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool open = false;
-  if (i < n && mate[i] == kFree) {
+// Mutual candidates are matched and appended to the matched list: both
+// endpoints may be on the list, so the thread that claims the smaller
+// endpoint (compare-and-swap from undecided) writes the pair, once.
+// Vertices without a candidate become singletons.
+__global__ void __launch_bounds__(kBlock) k_mm_commit(int n, const int *list, const int *cnt,
+                                                      int *mate, const int *cand, int *mlist,
+                                                      int *mcnt) {
+  const int m = list ? *cnt : n;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+    const int i = list ? list[q] : q;
+    if (mate[i] != kFree) continue;
     const int c = cand[i];
-    if (c < 0) mate[i] = kSingle;
-    else if (cand[c] == i) mate[i] = c;
-    else open = true;
+    if (c < 0) {
+      mate[i] = kSingle;
+    } else if (cand[c] == i) {
+      const int lo = c < i ? c : i, hi = c < i ? i : c;
+      if (atomicCAS(&mate[lo], kFree, hi) == kFree) {
+        mate[hi] = lo;
+        const int pos = atomicAdd(mcnt, 2);
+        mlist[pos] = lo;
+        mlist[pos + 1] = hi;
+      }
+    }
   }
-  if (__ballot(open) != 0ull && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(nfree, 1);
+}
+
+// Undecided neighbours whose candidate was just matched go on the recompute
+// list, once per round (stamp).
+__global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const int *mcnt,
+                                                      const int *rp, const int *ci,
+                                                      const double *wgt, const int *mate,
+                                                      const int *cand, int *stamp, int round,
+                                                      int *rlist, int *rcnt) {
+  const int m = *mcnt;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
+    const int v = mlist[q];
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = ci[k];
+      if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
+      if (atomicExch(&stamp[u], round) != round) rlist[atomicAdd(rcnt, 1)] = u;
+    }
+  }
 }
 
 // ------------------------------------------------------------ aggregation
@@ -450,6 +499,44 @@ __global__ void k_sell_fill(int n, int nslices, const int *rp, const int *ci, co
   }
 }
 
+// One wavefront per slice: base and 16-bit offsets of every slot group, or
+// cbase = -1 for the whole slice when some group spans more than 16 bits.
+// Counts the matrix entries (row lengths) and groups of compact slices.
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sell_compact(int n, int nslices, const int *rp,
+                                                         const int *sptr, const int *scol,
+                                                         int *cbase, unsigned short *cdel,
+                                                         unsigned long long *count) {
+  const int s = blockIdx.x * (kBlock / kWave) + static_cast<int>(threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (s >= nslices) return;   // whole wavefront
+  const int b = sptr[s], width = (sptr[s + 1] - b) / kSlice;
+  bool fits = true;
+  for (int k = 0; k < width; ++k) {
+    const int c = scol[b + k * kSlice + lane];
+    fits = fits && (wave_max_i(c) - wave_min_i(c) <= 65535);
+  }
+  for (int k = 0; k < width; ++k) {
+    const int c = scol[b + k * kSlice + lane];
+    const int mn = wave_min_i(c);
+    if (fits) cdel[b + k * kSlice + lane] = static_cast<unsigned short>(c - mn);
+    if (lane == 0) cbase[b / kSlice + k] = fits ? mn : -1;
+  }
+  if (lane == 0 && fits) {
+    const int r0 = s * kSlice, r1 = min(n, r0 + kSlice);
+    atomicAdd(&count[0], static_cast<unsigned long long>(rp[r1] - rp[r0]));
+    atomicAdd(&count[1], static_cast<unsigned long long>(width));
+  }
+}
+
 __global__ void k_d2f(int64_t n, const double *a, float *b) {
   int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) b[i] = static_cast<float>(a[i]);
@@ -548,6 +635,18 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
   hipLaunchKernelGGL(k_sell_fill, grid_for(static_cast<int64_t>(S.nslices) * kSlice), dim3(kBlock),
                      0, s, n, S.nslices, Lv.A.rp.p, Lv.A.ci.p, Lv.A.v.p, S.sptr.p, S.col.p, S.val.p);
   AMG_LAUNCH_CHECK();
+  S.cbase.alloc(S.nslots / kSlice);
+  S.cdel.alloc(S.nslots);
+  dvec<unsigned long long> cnt(2);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(k_sell_compact, grid_for(static_cast<int64_t>(S.nslices) * kWave), dim3(kBlock),
+                     0, s, n, S.nslices, Lv.A.rp.p, S.sptr.p, S.col.p, S.cbase.p, S.cdel.p, cnt.p);
+  AMG_LAUNCH_CHECK();
+  unsigned long long hc[2];
+  AMG_HIP(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  S.nnz_compact = static_cast<int64_t>(hc[0]);
+  S.groups_compact = static_cast<int64_t>(hc[1]);
   if (want_float) {
     S.valf.alloc(S.nslots);
     hipLaunchKernelGGL(k_d2f, grid_for(S.nslots), dim3(kBlock), 0, s, S.nslots, S.val.p, S.valf.p);
@@ -573,26 +672,50 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
   AMG_LAUNCH_CHECK();
   out.mate.alloc(n);
-  dvec<int> cand(n), nfree(64);
+  dvec<int> cand(n), stamp(n), rlist(n), mbuf[2] = {dvec<int>(n), dvec<int>(n)};
   {
     std::vector<int> init(n, kFree);
     AMG_HIP(hipMemcpyAsync(out.mate.p, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    std::fill(init.begin(), init.end(), -1);
+    AMG_HIP(hipMemcpyAsync(stamp.p, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
     AMG_HIP(hipStreamSynchronize(s));
   }
-  // Rounds are issued in batches; each round counts the vertices left undecided.
-  int rounds = 0;
-  const int kBatch = 16;
+  // Rounds are issued in batches of kBatch with one host read per batch.
+  // cnt[2q] = matched-list length of the round before round q of the batch,
+  // cnt[2q+1] = recompute-list length of round q.  Each vertex enters a
+  // matched list once and a recompute list at most once per round, so n
+  // entries bound every list; matched lists alternate between two buffers.
+  const int kBatch = 16;   // even: round 0 of every batch reads mbuf[0]
+  const dim3 gl(static_cast<unsigned>(std::min(2048, std::max(1, ceil_div(n, kBlock)))));
+  dvec<int> cnt(2 * kBatch + 2);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (2 * kBatch + 2), s));
+  hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, nullptr, nullptr, A.rp.p, A.ci.p, wgt.p, out.mate.p,
+                     cand.p);
+  hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, nullptr, nullptr, out.mate.p, cand.p, mbuf[0].p,
+                     cnt.p);
+  AMG_LAUNCH_CHECK();
+  int rounds = 1;
   for (;;) {
-    AMG_HIP(hipMemsetAsync(nfree.p, 0, sizeof(int) * kBatch, s));
+    // cnt[0] holds the matched-list length left by the previous round
+    AMG_HIP(hipMemsetAsync(cnt.p + 1, 0, sizeof(int) * (2 * kBatch + 1), s));
     for (int q = 0; q < kBatch; ++q) {
-      hipLaunchKernelGGL(k_match_cand, g, b, 0, s, n, A.rp.p, A.ci.p, wgt.p, out.mate.p, cand.p);
-      hipLaunchKernelGGL(k_match_commit, g, b, 0, s, n, out.mate.p, cand.p, nfree.p + q);
+      const int *mc = cnt.p + 2 * q;
+      int *rc = cnt.p + 2 * q + 1;
+      int *mc_next = cnt.p + 2 * q + 2;
+      hipLaunchKernelGGL(k_mm_notify, gl, b, 0, s, mbuf[q % 2].p, mc, A.rp.p, A.ci.p, wgt.p,
+                         out.mate.p, cand.p, stamp.p, rounds + q, rlist.p, rc);
+      hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, rlist.p, rc, A.rp.p, A.ci.p, wgt.p, out.mate.p,
+                         cand.p);
+      hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, rlist.p, rc, out.mate.p, cand.p,
+                         mbuf[(q + 1) % 2].p, mc_next);
     }
     AMG_LAUNCH_CHECK();
     rounds += kBatch;
-    const int left = read_int(nfree.p + kBatch - 1, s);
+    const int left = read_int(cnt.p + 2 * kBatch - 1, s);
     if (left == 0) break;
     if (rounds > n + 2 * kBatch) fail(AMG_ERR_DEVICE, "matching did not terminate");
+    // carry the last matched-list length into cnt[0]
+    AMG_HIP(hipMemcpyAsync(cnt.p, cnt.p + 2 * kBatch, sizeof(int), hipMemcpyDeviceToDevice, s));
   }
   tm.rounds += rounds;
   dvec<int> flag(n), pos(n + 1);

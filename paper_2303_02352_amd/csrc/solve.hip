@@ -34,57 +34,143 @@ inline dim3 grid_for(int64_t n, int block = kBlock) {
 // Row r of slice s: slots sptr[s] + k*64 + lane, k < width(s).  Streamed
 // (non-temporal) loads for matrices read once per pass; plain loads in the
 // coarse-tail kernel, whose working set stays in cache.
-template <class T, bool kStream = true>
-__device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
-                                         const T *__restrict__ val, const T *__restrict__ x, int r,
-                                         T &sum, T &l1) {
-  const int s = r >> 6, lane = r & 63;
-  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
-  const int *cp = col + b + lane;
-  const T *vp = val + b + lane;
-  auto ldc = [](const int *p) { return kStream ? ld_stream(p) : *p; };
+// Fold of one SELL row: slots k = 0 .. width-1 in order, acc += a_k x(c_k),
+// l1 += |a_k|.  Slots are taken eight at a time, the last 1-7 in one
+// predicated batch (width is the same on the whole wavefront), so all loads
+// of a batch are in flight together.
+template <class T, bool kStream, class Cols, class G>
+__device__ __forceinline__ void row_fold(Cols cols, const T *__restrict__ vp, G x, int width, T &sum,
+                                         T &l1) {
   auto ldv = [](const T *p) { return kStream ? ld_stream(p) : *p; };
   T acc = T(0), m = T(0);
   int k = 0;
-  for (; k + 4 <= width; k += 4) {
-    const int c0 = ldc(cp + (k + 0) * 64), c1 = ldc(cp + (k + 1) * 64);
-    const int c2 = ldc(cp + (k + 2) * 64), c3 = ldc(cp + (k + 3) * 64);
-    const T a0 = ldv(vp + (k + 0) * 64), a1 = ldv(vp + (k + 1) * 64);
-    const T a2 = ldv(vp + (k + 2) * 64), a3 = ldv(vp + (k + 3) * 64);
-    const T x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-    acc = acc + a0 * x0; m = m + fabs(a0);
-    acc = acc + a1 * x1; m = m + fabs(a1);
-    acc = acc + a2 * x2; m = m + fabs(a2);
-    acc = acc + a3 * x3; m = m + fabs(a3);
+  for (; k + 8 <= width; k += 8) {
+    int c[8];
+    T a[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = cols(k + u);
+      a[u] = ldv(vp + (k + u) * 64);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x(c[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc = acc + a[u] * xv[u];
+      m = m + fabs(a[u]);
+    }
   }
-  for (; k < width; ++k) {
-    const int c = ldc(cp + k * 64);
-    const T a = ldv(vp + k * 64);
-    acc = acc + a * x[c];
-    m = m + fabs(a);
+  const int rem = width - k;
+  if (rem > 0) {
+    int c[7];
+    T a[7], xv[7];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (u < rem) {
+        c[u] = cols(k + u);
+        a[u] = ldv(vp + (k + u) * 64);
+      }
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (u < rem) xv[u] = x(c[u]);
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (u < rem) {
+        acc = acc + a[u] * xv[u];
+        m = m + fabs(a[u]);
+      }
   }
   sum = acc;
   l1 = m;
 }
 
+template <bool kStream>
+struct PlainCols {      // int32 column of slot k
+  const int *__restrict__ cp;
+  __device__ __forceinline__ int operator()(int k) const {
+    return kStream ? ld_stream(cp + k * 64) : cp[k * 64];
+  }
+};
+
+template <bool kStream>
+struct CompactCols {    // group base + 16-bit offset of slot k
+  const int *__restrict__ bp;
+  const unsigned short *__restrict__ dp;
+  __device__ __forceinline__ int operator()(int k) const {
+    return bp[k] + static_cast<int>(kStream ? ld_stream(dp + k * 64) : dp[k * 64]);
+  }
+};
+
+template <class T, bool kStream, class G>
+__device__ __forceinline__ void sell_row_g(const int *__restrict__ sptr, const int *__restrict__ col,
+                                           const T *__restrict__ val, G x, int r, T &sum, T &l1) {
+  const int s = r >> 6, lane = r & 63;
+  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
+  row_fold<T, kStream>(PlainCols<kStream>{col + b + lane}, val + b + lane, x, width, sum, l1);
+}
+
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_spmv(int n, const int *__restrict__ sptr,
-                                                 const int *__restrict__ col,
-                                                 const T *__restrict__ val, const T *__restrict__ x,
-                                                 T *__restrict__ y) {
+struct Plain {          // x_c
+  const T *__restrict__ x;
+  __device__ __forceinline__ T operator()(int c) const { return x[c]; }
+};
+
+template <class T>
+struct Corrected {      // (x + P e)_c = x_c + p_c e[agg_c], the prolongation's value
+  const T *__restrict__ x;
+  const T *__restrict__ pval;
+  const int *__restrict__ agg;
+  const T *__restrict__ e;
+  __device__ __forceinline__ T operator()(int c) const { return x[c] + pval[c] * e[agg[c]]; }
+};
+
+template <class T, bool kStream = true>
+__device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
+                                         const T *__restrict__ val, const T *__restrict__ x, int r,
+                                         T &sum, T &l1) {
+  sell_row_g<T, kStream>(sptr, col, val, Plain<T>{x}, r, sum, l1);
+}
+
+// Same row through the compact column form (16-bit offsets from a per-group
+// base).  The rows of a wavefront must lie in one slice (rows are handed out
+// in whole slices), so the slice bounds and group bases are wavefront-uniform
+// and read with scalar loads.  Slices without the compact form fall back to
+// the int32 columns.  The fold is the same: identical bits either way.
+template <class T, bool kStream, class G>
+__device__ __forceinline__ void sell_row_g(const SellRef &S, const T *__restrict__ val, G x, int r,
+                                           T &sum, T &l1) {
+  const int s = __builtin_amdgcn_readfirstlane(r >> 6);
+  const int b = S.sptr[s], width = (S.sptr[s + 1] - b) >> 6;
+  const int g = b >> 6;
+  if (!S.cdel || width == 0 || S.cbase[g] < 0) {
+    sell_row_g<T, kStream>(S.sptr, S.col, val, x, r, sum, l1);
+    return;
+  }
+  const int lane = r & 63;
+  row_fold<T, kStream>(CompactCols<kStream>{S.cbase + g, S.cdel + b + lane}, val + b + lane, x, width,
+                       sum, l1);
+}
+
+template <class T, bool kStream = true>
+__device__ __forceinline__ void sell_row(const SellRef &S, const T *__restrict__ val,
+                                         const T *__restrict__ x, int r, T &sum, T &l1) {
+  sell_row_g<T, kStream>(S, val, Plain<T>{x}, r, sum, l1);
+}
+
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, const T *__restrict__ val,
+                                                 const T *__restrict__ x, T *__restrict__ y) {
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
-  sell_row(sptr, col, val, x, r, s, m);
+  sell_row<T, kStream>(S, val, x, r, s, m);
   y[r] = s;
 }
 
 // l1-Jacobi sweep: xn = x + dinv * (r - A x), dinv = 1 / sum_j |a_ij| taken
 // from the streamed row (the same fold that defines the stored diagonal).
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n,
-                                                  const int *__restrict__ sptr,
-                                                  const int *__restrict__ col,
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRef S,
                                                   const T *__restrict__ val,
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ x, T *__restrict__ xn) {
@@ -92,9 +178,30 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n,
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
-  sell_row(sptr, col, val, x, r, s, m);
+  sell_row<T, kStream>(S, val, x, r, s, m);
   const T di = T(1) / m;
   xn[r] = x[r] + di * (rhs[r] - s);
+}
+
+// First post-smoothing sweep with the coarse-grid correction folded in:
+// y = x + P e is formed where it is read (the value k_prolong would store)
+// and xn = y + dinv (rhs - A y); y itself is never written.
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_sweep_corr(const int *skip, int n, SellRef S,
+                                                       const T *__restrict__ val,
+                                                       const T *__restrict__ rhs,
+                                                       const T *__restrict__ x,
+                                                       const int *__restrict__ agg,
+                                                       const T *__restrict__ pval,
+                                                       const T *__restrict__ e, T *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
+  const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (r >= n) return;
+  const Corrected<T> y{x, pval, agg, e};
+  T s, m;
+  sell_row_g<T, kStream>(S, val, y, r, s, m);
+  const T di = T(1) / m;
+  xn[r] = y(r) + di * (rhs[r] - s);
 }
 
 // First sweep from x = 0: x = dinv * r.
@@ -109,10 +216,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_first(const int *skip, int n,
 }
 
 // Restriction, pass 1 (row parallel): t_i = p_i (r_i - (A x)_i).
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n,
-                                                         const int *__restrict__ sptr,
-                                                         const int *__restrict__ col,
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n, SellRef S,
                                                          const T *__restrict__ val,
                                                          const T *__restrict__ pval,
                                                          const T *__restrict__ rhs,
@@ -122,7 +227,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n,
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
-  sell_row(sptr, col, val, x, r, s, m);
+  sell_row<T, kStream>(S, val, x, r, s, m);
   t[r] = pval[r] * (rhs[r] - s);
 }
 
@@ -185,118 +290,181 @@ __global__ void k_f2d(const int *skip, int n, const float *__restrict__ a, doubl
 }
 
 // ------------------------------------------------------ coarse-tail kernel
-// Levels [kt, nl) of the V-cycle in ONE workgroup: every phase (sweep,
-// scaled residual, aggregate sum, prolongation, coarsest solve) loops over
-// the level's rows and ends with a workgroup barrier, so the small levels
-// cost no kernel launches and their data stays in this CU's caches.  The
-// per-row folds are the ones of the multi-workgroup kernels.
+// Levels [kt, nl) of the V-cycle in ONE workgroup, thread i owning row i
+// (and aggregate i) of every level.  All vectors of these levels live in
+// LDS (r, two iterates, scaled residual: 4 n_j entries per level); a
+// thread keeps its matrix row in registers while it works on a level
+// (slots beyond W are re-read from memory), so a smoothing sweep costs LDS
+// gathers and one workgroup barrier.  Every fold is the one of the
+// multi-workgroup kernels: slots in order for rows and l1 norms, members in
+// ascending order for the restriction.
 // Coarsest level: z = A^-1 r with the column-major inverse, row i folded
-// over j ascending, in binary64 (also for the binary32 cycle).
-template <class T>
-__device__ __forceinline__ T *tail_first(const TailDesc<T> &L, bool coarsest, int dense, int pre,
-                                         int post, int csw, T *out) {
-  if (coarsest) {
-    if (dense) return nullptr;
-    return ((csw - 1) % 2 == 0) ? out : L.t;
-  }
-  if (pre == 0) return nullptr;
-  return (((pre - 1) + post) % 2 == 0) ? out : L.t;
+// over j ascending, in binary64 (also for the binary32 cycle); or l1-Jacobi
+// sweeps.
+template <class T, int W>
+struct TailRow {
+  T v[W];
+  int c[W];
+  int w;             // slots of the row's slice (k >= W read through cp / vp)
+  const int *cp;
+  const T *vp;
+  T dinv;            // 1 / sum_k |a_k|, the fold of the stored diagonal
+};
+
+template <class T, int W>
+__device__ __forceinline__ void tail_load(const TailDesc<T> &L, int r, TailRow<T, W> &R) {
+  const int s = r >> 6, lane = r & 63;
+  const int b = L.sptr[s];
+  R.w = (L.sptr[s + 1] - b) >> 6;
+  R.cp = L.col + b + lane;
+  R.vp = L.val + b + lane;
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (k < R.w) {
+      R.c[k] = R.cp[k * 64];
+      R.v[k] = R.vp[k * 64];
+    }
+  T m = T(0);
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (k < R.w) m = m + fabs(R.v[k]);
+  for (int k = W; k < R.w; ++k) m = m + fabs(R.vp[k * 64]);
+  R.dinv = T(1) / m;
 }
 
-template <class T>
+template <class T, int W>
+__device__ __forceinline__ T tail_dot(const TailRow<T, W> &R, const T *X) {
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (k < R.w) acc = acc + R.v[k] * X[R.c[k]];
+  for (int k = W; k < R.w; ++k) acc = acc + R.vp[k * 64] * X[R.cp[k * 64]];
+  return acc;
+}
+
+template <class T, int W>
 __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(
     const int *skip, int m, const TailDesc<T> *__restrict__ D, const double *__restrict__ Ainv,
-    int dense, int pre, int post, int csw, const T *__restrict__ top_rhs, T *__restrict__ top_out,
-    int first_done) {
+    int dense, int pre, int post, int csw, const T *__restrict__ top_rhs, T *__restrict__ top_out) {
   AMG_SKIP_IF_DONE();
-  __shared__ T *Abuf[AMG_MAX_LEVELS], *Bbuf[AMG_MAX_LEVELS];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ T lds[kTailLds];
+  const int t = threadIdx.x, nt = blockDim.x;
+  // level j: R = lds + off, X0 = R + n, X1 = R + 2n, Tt = R + 3n; bit j of
+  // `sel` says which iterate holds the level's current x (uniform)
+  unsigned long long sel = 0;
+  {
+    const TailDesc<T> L = D[0];
+    for (int i = t; i < L.n; i += nt) lds[L.lds + i] = top_rhs[i];
+  }
+  __syncthreads();
   // ---- descent
-  for (int j = 0; j < m; ++j) {
+  for (int j = 0; j < m - 1; ++j) {
     const TailDesc<T> L = D[j];
-    const T *rhs = (j == 0) ? top_rhs : L.r;
-    T *out = (j == 0) ? top_out : L.x;
-    const bool coarsest = (j == m - 1);
-    const bool have_first = (j == 0) ? (first_done != 0) : true;
-    if (coarsest) {
-      if (dense) {
-        for (int i = tid; i < L.n; i += nt) {
-          double acc = 0.0;
-          for (int c = 0; c < L.n; ++c)
-            acc = acc + Ainv[static_cast<int64_t>(c) * L.n + i] * static_cast<double>(rhs[c]);
-          out[i] = static_cast<T>(acc);
-        }
-      } else {
-        T *A = tail_first<T>(L, true, dense, pre, post, csw, out);
-        T *B = (A == out) ? L.t : out;
-        if (!have_first)
-          for (int i = tid; i < L.n; i += nt) A[i] = L.dinv[i] * rhs[i];
-        __syncthreads();
-        for (int q = 1; q < csw; ++q) {
-          for (int i = tid; i < L.n; i += nt) {
-            T sm, l1;
-            sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
-            B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
-          }
-          __syncthreads();
-          T *tmp = A; A = B; B = tmp;
-        }
-      }
-      __syncthreads();
-      break;
+    const TailDesc<T> C = D[j + 1];
+    const int n = L.n;
+    const T *rhs = lds + L.lds;
+    T *X = lds + L.lds + n, *Y = lds + L.lds + 2 * n, *Tt = lds + L.lds + 3 * n;
+    TailRow<T, W> R;
+    T pv = T(0);
+    // members of aggregate t (up to 8 kept in registers), read ahead of use
+    int mb = 0, mc = 0, mm[8];
+    if (t < L.nc) {
+      mb = L.mptr[t];
+      mc = L.mptr[t + 1] - mb;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < mc) mm[k] = L.mem[mb + k];
     }
-    const int swaps = (pre > 0 ? pre - 1 : 0) + post;
-    T *A = (swaps % 2 == 0) ? out : L.t;
-    T *B = (A == out) ? L.t : out;
-    if (pre == 0) {
-      for (int i = tid; i < L.n; i += nt) A[i] = T(0);
-    } else if (!have_first) {
-      for (int i = tid; i < L.n; i += nt) A[i] = L.dinv[i] * rhs[i];
+    if (t < n) {
+      tail_load<T, W>(L, t, R);
+      pv = L.pval[t];
+      X[t] = (pre > 0) ? R.dinv * rhs[t] : T(0);
     }
     __syncthreads();
     for (int q = 1; q < pre; ++q) {
-      for (int i = tid; i < L.n; i += nt) {
-        T sm, l1;
-        sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
-        B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
-      }
+      if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<T, W>(R, X));
       __syncthreads();
-      T *tmp = A; A = B; B = tmp;
+      T *tmp = X; X = Y; Y = tmp;
     }
-    for (int i = tid; i < L.n; i += nt) {
-      T sm, l1;
-      sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
-      B[i] = L.pval[i] * (rhs[i] - sm);
-    }
+    if (t < n) Tt[t] = pv * (rhs[t] - tail_dot<T, W>(R, X));
+    if (X != lds + L.lds + n) sel |= 1ull << j;
     __syncthreads();
-    const TailDesc<T> C = D[j + 1];
-    T *xc = tail_first<T>(C, j + 1 == m - 1, dense, pre, post, csw, C.x);
-    for (int I = tid; I < L.nc; I += nt) {
+    if (t < L.nc) {
       T acc = T(0);
-      for (int q = L.mptr[I]; q < L.mptr[I + 1]; ++q) acc = acc + B[L.mem[q]];
-      C.r[I] = acc;
-      if (xc) xc[I] = C.dinv[I] * acc;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k < mc) acc = acc + Tt[mm[k]];
+      for (int k = 8; k < mc; ++k) acc = acc + Tt[L.mem[mb + k]];
+      lds[C.lds + t] = acc;
     }
-    if (tid == 0) { Abuf[j] = A; Bbuf[j] = B; }
     __syncthreads();
   }
-  // ---- ascent
-  for (int j = m - 2; j >= 0; --j) {
+  // ---- coarsest level (result in its X0 or X1, recorded in sel)
+  {
+    const int j = m - 1;
     const TailDesc<T> L = D[j];
-    const T *rhs = (j == 0) ? top_rhs : L.r;
-    const T *e = D[j + 1].x;
-    T *A = Abuf[j], *B = Bbuf[j];
-    for (int i = tid; i < L.n; i += nt) A[i] = A[i] + L.pval[i] * e[L.agg[i]];
-    __syncthreads();
-    for (int q = 0; q < post; ++q) {
-      for (int i = tid; i < L.n; i += nt) {
-        T sm, l1;
-        sell_row<T, false>(L.sptr, L.col, L.val, A, i, sm, l1);
-        B[i] = A[i] + (T(1) / l1) * (rhs[i] - sm);
+    const int n = L.n;
+    const T *rhs = lds + L.lds;
+    T *X = lds + L.lds + n, *Y = lds + L.lds + 2 * n;
+    if (dense) {
+      for (int i = t; i < n; i += nt) {
+        double acc = 0.0;
+        const double *col = Ainv + i;
+        int c = 0;
+        for (; c + 4 <= n; c += 4) {
+          const double a0 = col[static_cast<int64_t>(c) * n], a1 = col[static_cast<int64_t>(c + 1) * n];
+          const double a2 = col[static_cast<int64_t>(c + 2) * n], a3 = col[static_cast<int64_t>(c + 3) * n];
+          acc = acc + a0 * static_cast<double>(rhs[c]);
+          acc = acc + a1 * static_cast<double>(rhs[c + 1]);
+          acc = acc + a2 * static_cast<double>(rhs[c + 2]);
+          acc = acc + a3 * static_cast<double>(rhs[c + 3]);
+        }
+        for (; c < n; ++c) acc = acc + col[static_cast<int64_t>(c) * n] * static_cast<double>(rhs[c]);
+        X[i] = static_cast<T>(acc);
+      }
+    } else {
+      TailRow<T, W> R;
+      if (t < n) {
+        tail_load<T, W>(L, t, R);
+        X[t] = R.dinv * rhs[t];
       }
       __syncthreads();
-      T *tmp = A; A = B; B = tmp;
+      for (int q = 1; q < csw; ++q) {
+        if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<T, W>(R, X));
+        __syncthreads();
+        T *tmp = X; X = Y; Y = tmp;
+      }
     }
+    if (X != lds + L.lds + n) sel |= 1ull << j;
+    __syncthreads();
+  }
+  // ---- ascent: x += P e, then the post-smoothing sweeps
+  for (int j = m - 2; j >= 0; --j) {
+    const TailDesc<T> L = D[j];
+    const TailDesc<T> C = D[j + 1];
+    const int n = L.n;
+    const T *rhs = lds + L.lds;
+    T *X = lds + L.lds + ((sel >> j) & 1 ? 2 * n : n);
+    T *Y = lds + L.lds + ((sel >> j) & 1 ? n : 2 * n);
+    const T *e = lds + C.lds + ((sel >> (j + 1)) & 1 ? 2 * C.n : C.n);
+    TailRow<T, W> R;
+    if (t < n) {
+      X[t] = X[t] + L.pval[t] * e[L.agg[t]];
+      if (post > 0) tail_load<T, W>(L, t, R);
+    }
+    __syncthreads();
+    for (int q = 0; q < post; ++q) {
+      if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<T, W>(R, X));
+      __syncthreads();
+      T *tmp = X; X = Y; Y = tmp;
+    }
+    if (X != lds + L.lds + n) sel |= 1ull << j;
+    else sel &= ~(1ull << j);
+  }
+  {
+    const TailDesc<T> L = D[0];
+    const T *X = lds + L.lds + ((sel & 1) ? 2 * L.n : L.n);
+    for (int i = t; i < L.n; i += nt) top_out[i] = X[i];
   }
 }
 
@@ -367,8 +535,8 @@ __device__ __forceinline__ void first_out(const FirstOut &fo, int i, double ri) 
 }
 
 // r = b - A u, partial ||r||^2 per workgroup (kRowsDot rows per thread).
-__global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const int *__restrict__ sptr,
-                                                     const int *__restrict__ col,
+template <bool kStream>
+__global__ void __launch_bounds__(kBlock) k_pcg_init(int n, SellRef S,
                                                      const double *__restrict__ val,
                                                      const double *__restrict__ b,
                                                      const double *__restrict__ u,
@@ -382,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, const int *__restric
     const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
     if (row < n) {
       double s, m;
-      sell_row(sptr, col, val, u, row, s, m);
+      sell_row<double, kStream>(S, val, u, row, s, m);
       const double ri = b[row] - s;
       r[row] = ri;
       first_out(fo, row, ri);
@@ -415,9 +583,9 @@ __global__ void __launch_bounds__(kFinish) k_pcg_init_finish(int nb, const doubl
 }
 
 // v = A w and partial dots alpha = w.r, beta = w.v, gamma = w.q.
+template <bool kStream>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
-    const int *skip, int n, const int *__restrict__ sptr, const int *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ w, const double *__restrict__ r,
+    const int *skip, int n, SellRef S, const double *__restrict__ val, const double *__restrict__ w, const double *__restrict__ r,
     const double *__restrict__ q, double *__restrict__ v, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock / kWave];
@@ -428,7 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
     const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
     if (row < n) {
       double s, m;
-      sell_row(sptr, col, val, w, row, s, m);
+      sell_row<double, kStream>(S, val, w, row, s, m);
       v[row] = s;
       const double wi = w[row];
       al = al + wi * r[row];
@@ -564,20 +732,83 @@ template <> const TailDesc<float> *tail_desc<float>(amg_hierarchy *h) {
   return reinterpret_cast<const TailDesc<float> *>(h->tail_desc_f.p);
 }
 
+// Matrices at least this large are read with non-temporal loads; smaller
+// ones use plain loads, so that a level's matrix can stay in the last-level
+// cache (256 MB on MI355X) between the passes of one V-cycle.
+#ifndef AMG_STREAM_MIN_MB
+#define AMG_STREAM_MIN_MB 160
+#endif
+template <class T>
+bool streamed(const Level &L) {
+  const double bytes = static_cast<double>(L.S.nslots) * (sizeof(T) + 2.0);
+  return bytes >= AMG_STREAM_MIN_MB * 1048576.0;
+}
+
 template <class T>
 void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s) {
   const int n = L.A.n;
-  hipLaunchKernelGGL(k_sweep<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.S.sptr.p, L.S.col.p,
-                     vals<T>(L.S), rhs, x, xn);
+  if (streamed<T>(L))
+    hipLaunchKernelGGL((k_sweep<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
+                       vals<T>(L.S), rhs, x, xn);
+  else
+    hipLaunchKernelGGL((k_sweep<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
+                       vals<T>(L.S), rhs, x, xn);
+}
+
+template <class T>
+void launch_resid(const int *skip, const Level &L, const T *rhs, const T *x, T *t, hipStream_t s) {
+  const int n = L.A.n;
+  if (streamed<T>(L))
+    hipLaunchKernelGGL((k_resid_scaled<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n,
+                       sell_ref(L.S), vals<T>(L.S), pval_of<T>(L), rhs, x, t);
+  else
+    hipLaunchKernelGGL((k_resid_scaled<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n,
+                       sell_ref(L.S), vals<T>(L.S), pval_of<T>(L), rhs, x, t);
+}
+
+// Prolongation fused into the first post-sweep: 0 never, 1 on cached
+// levels only (a streamed level runs them apart: there the four gathers per
+// slot of the fused kernel cost more than the extra vector pass), 2 always.
+#ifndef AMG_FUSE_PROLONG
+#define AMG_FUSE_PROLONG 1
+#endif
+// x + P e followed by one sweep, xn the result (A: level k, e: level k+1 output).
+template <class T>
+void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e, T *x, T *xn,
+                       hipStream_t s) {
+  const int n = L.A.n;
+  if (AMG_FUSE_PROLONG == 0 || (AMG_FUSE_PROLONG == 1 && streamed<T>(L))) {
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
+                       e, x);
+    launch_sweep<T>(skip, L, rhs, x, xn, s);
+  } else if (streamed<T>(L)) {
+    hipLaunchKernelGGL((k_sweep_corr<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n,
+                       sell_ref(L.S), vals<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
+  } else {
+    hipLaunchKernelGGL((k_sweep_corr<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n,
+                       sell_ref(L.S), vals<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
+  }
+}
+
+void launch_spmv(const Level &L, const double *x, double *y, hipStream_t s) {
+  const int n = L.A.n;
+  if (streamed<double>(L))
+    hipLaunchKernelGGL((k_spmv<double, true>), grid_for(n), dim3(kBlock), 0, s, n, sell_ref(L.S),
+                       L.S.val.p, x, y);
+  else
+    hipLaunchKernelGGL((k_spmv<double, false>), grid_for(n), dim3(kBlock), 0, s, n, sell_ref(L.S),
+                       L.S.val.p, x, y);
 }
 
 // Where level k puts the first smoothing iterate so that, after all its
 // ping-pong sweeps, the level's result lands in `out`.  nullptr when the
-// level has no first sweep (direct coarsest solve, or no pre-smoothing).
+// level has no first sweep (direct coarsest solve, or no pre-smoothing) or
+// runs in the coarse-tail kernel, which forms its own.
 template <class T>
 T *first_buffer(amg_hierarchy *h, int k, T *out) {
   Level &L = h->L[k];
   const amg_params &P = h->p;
+  if (k >= h->tail_start) return nullptr;
   if (k == static_cast<int>(h->L.size()) - 1) {
     if (h->coarse_dense) return nullptr;
     return ((P.coarse_sweeps - 1) % 2 == 0) ? out : tbuf<T>(L);
@@ -597,9 +828,10 @@ void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
   const int nl = static_cast<int>(h->L.size());
   const amg_params &P = h->p;
   if (k >= h->tail_start) {
-    hipLaunchKernelGGL(k_vcycle_tail<T>, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k,
+    auto kern = (h->tail_w <= 8) ? k_vcycle_tail<T, 8> : k_vcycle_tail<T, 16>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k,
                        tail_desc<T>(h) + (k - h->tail_start), h->Ainv.p, h->coarse_dense,
-                       P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out, first_done ? 1 : 0);
+                       P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out);
     return;
   }
   if (k == nl - 1) {
@@ -625,16 +857,20 @@ void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
     for (int q = 1; q < P.pre_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
   }
   // restriction of the residual; B is free until the first post-sweep
-  hipLaunchKernelGGL(k_resid_scaled<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.S.sptr.p,
-                     L.S.col.p, vals<T>(L.S), pval_of<T>(L), rhs, A, B);
+  launch_resid<T>(skip, L, rhs, A, B, s);
   Level &C = h->L[k + 1];
   T *xc = first_buffer<T>(h, k + 1, xbuf<T>(C));
   hipLaunchKernelGGL(k_agg_sum<T>, grid_for(L.nc), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p, L.mem.p,
                      B, rbuf<T>(C), dinv_of<T>(C), xc);
   vcycle_level<T>(h, skip, k + 1, rbuf<T>(C), xbuf<T>(C), xc != nullptr);
-  hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
-                     xbuf<T>(C), A);
-  for (int q = 0; q < P.post_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
+  if (P.post_sweeps == 0) {
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
+                       xbuf<T>(C), A);
+    return;
+  }
+  launch_corr_sweep<T>(skip, L, rhs, xbuf<T>(C), A, B, s);
+  std::swap(A, B);
+  for (int q = 1; q < P.post_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
 }
 
 // Mixed precision: the residual is rounded to binary32 on entry (fused with
@@ -688,6 +924,17 @@ FirstOut first_out_for(amg_hierarchy *h, double *z) {
 int nb_dot(int n) { return std::max(1, ceil_div(n, kBlock * kRowsDot)); }
 int nb_upd(int n) { return std::max(1, ceil_div(n, kBlock * kRowsUpd)); }
 
+void launch_spmv_dots(amg_hierarchy *h, const int *skip) {
+  const Level &L0 = h->L[0];
+  const int n = L0.A.n, nbd = nb_dot(n);
+  if (streamed<double>(L0))
+    hipLaunchKernelGGL(k_pcg_spmv_dots<true>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
+                       sell_ref(L0.S), L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+  else
+    hipLaunchKernelGGL(k_pcg_spmv_dots<false>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
+                       sell_ref(L0.S), L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+}
+
 void enqueue_iteration(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   const Level &L0 = h->L[0];
@@ -695,8 +942,7 @@ void enqueue_iteration(amg_hierarchy *h) {
   const int *skip = &h->sc.p->done;
   const FirstOut fo = first_out_for(h, h->w.p);
   vcycle_any(h, skip, h->r.p, h->w.p, /*first_done=*/true);
-  hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(nbd), dim3(kBlock), 0, s, skip, n, L0.S.sptr.p,
-                     L0.S.col.p, L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+  launch_spmv_dots(h, skip);
   hipLaunchKernelGGL(k_pcg_dots_finish, dim3(1), dim3(kFinish), 0, s, skip, nbd, h->partials.p,
                      h->sc.p);
   hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, skip, n, h->w.p, h->v.p, h->d.p,
@@ -709,24 +955,24 @@ void enqueue_iteration(amg_hierarchy *h) {
 template <class T>
 void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32) {
   std::vector<TailDesc<T>> D;
+  int lds = 0;
   for (size_t k = h->tail_start; k < h->L.size(); ++k) {
     Level &L = h->L[k];
     TailDesc<T> t{};
     t.n = L.A.n;
     t.nc = L.nc;
+    t.lds = lds;
+    lds += 4 * L.A.n;
     t.sptr = L.S.sptr.p;
     t.col = L.S.col.p;
     t.val = vals<T>(L.S);
-    t.dinv = dinv_of<T>(L);
     t.pval = pval_of<T>(L);
     t.agg = L.agg.p;
     t.mptr = L.mptr.p;
     t.mem = L.mem.p;
-    t.r = rbuf<T>(L);
-    t.x = xbuf<T>(L);
-    t.t = tbuf<T>(L);
     D.push_back(t);
   }
+  if (lds > kTailLds) fail(AMG_ERR_DEVICE, "coarse tail exceeds its LDS budget");
   (void)fp32;
   dst.alloc(sizeof(TailDesc<T>) * std::max<size_t>(1, D.size()));
   if (!D.empty())
@@ -755,13 +1001,27 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   const int n = h->L[0].A.n;
   h->u.alloc(n); h->r.alloc(n); h->w.alloc(n); h->v.alloc(n); h->d.alloc(n); h->q.alloc(n);
   h->partials.alloc(static_cast<size_t>(nb_dot(n)) * 3);
-  // levels small enough for the single-workgroup coarse tail (sizes decrease
-  // down the hierarchy, so the tail is a suffix)
+  // The single-workgroup coarse tail: the longest suffix of levels with at
+  // most kTailRows rows each whose vectors (4 per row) fit its LDS array.
   const int nl = static_cast<int>(h->L.size());
   h->tail_start = nl;
-  for (int k = 0; k < nl; ++k)
-    if (h->L[k].A.n <= kTailRows) { h->tail_start = k; break; }
+  int used = 0;
+  for (int k = nl - 1; k >= 0; --k) {
+    const int nk = h->L[k].A.n;
+    if (nk > kTailRows || used + 4 * nk > kTailLds) break;
+    used += 4 * nk;
+    h->tail_start = k;
+  }
   if (h->coarse_dense && h->tail_start > nl - 1) fail(AMG_ERR_DEVICE, "dense coarsest level outside the tail");
+  // widest slice of the tail levels: rows up to 8 slots stay in registers
+  // whole, wider ones keep 16 there
+  h->tail_w = 0;
+  for (int k = h->tail_start; k < nl; ++k) {
+    const Sell &S = h->L[k].S;
+    std::vector<int> sp(S.nslices + 1);
+    AMG_HIP(hipMemcpy(sp.data(), S.sptr.p, sizeof(int) * sp.size(), hipMemcpyDeviceToHost));
+    for (int q = 0; q < S.nslices; ++q) h->tail_w = std::max(h->tail_w, (sp[q + 1] - sp[q]) / kSlice);
+  }
   upload_tail<double>(h, h->tail_desc_d, false);
   if (mixed) upload_tail<float>(h, h->tail_desc_f, true);
   h->sc.alloc(1);
@@ -776,9 +1036,7 @@ void alloc_solve_buffers(amg_hierarchy *h) {
 void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z) { vcycle_any(h, nullptr, r, z); }
 
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y) {
-  const Level &L = h->L[k];
-  hipLaunchKernelGGL(k_spmv<double>, grid_for(L.A.n), dim3(kBlock), 0, h->stream, L.A.n, L.S.sptr.p,
-                     L.S.col.p, L.S.val.p, x, y);
+  launch_spmv(h->L[k], x, y, h->stream);
   AMG_LAUNCH_CHECK();
 }
 
@@ -806,8 +1064,12 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
   AMG_HIP(hipMemcpyAsync(h->u.p, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->d.p);
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->q.p);
-  hipLaunchKernelGGL(k_pcg_init, dim3(nb), dim3(kBlock), 0, s, n, L0.S.sptr.p, L0.S.col.p, L0.S.val.p,
-                     b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
+  if (streamed<double>(L0))
+    hipLaunchKernelGGL(k_pcg_init<true>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), L0.S.val.p,
+                       b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
+  else
+    hipLaunchKernelGGL(k_pcg_init<false>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), L0.S.val.p,
+                       b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
   hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, h->partials.p, h->sc.p, rtol,
                      maxit);
   AMG_LAUNCH_CHECK();
@@ -861,28 +1123,22 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   Level &L = h->L[k];
   const int n = L.A.n;
   const double nnz = static_cast<double>(L.A.nnz);
-  const int nbd = nb_dot(n), nbu = nb_upd(n);
+  const int nbu = nb_upd(n);
   const bool has_coarse = k + 1 < static_cast<int>(h->L.size());
-  if ((kernel == 2 || kernel == 3) && !has_coarse) fail(AMG_ERR_INVALID, "no coarser level");
+  if ((kernel == 2 || kernel == 3 || kernel == 5) && !has_coarse) fail(AMG_ERR_INVALID, "no coarser level");
   if (kernel == 4 && k != 0) fail(AMG_ERR_INVALID, "the PCG update exists on level 0 only");
-  if (kernel < 0 || kernel > 4) fail(AMG_ERR_INVALID, "unknown kernel id");
+  if (kernel < 0 || kernel > 5) fail(AMG_ERR_INVALID, "unknown kernel id");
   auto launch = [&]() {
     switch (kernel) {
       case 0:
-        if (k == 0) {
-          hipLaunchKernelGGL(k_pcg_spmv_dots, dim3(nbd), dim3(kBlock), 0, s, nullptr, n, L.S.sptr.p,
-                             L.S.col.p, L.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
-        } else {
-          hipLaunchKernelGGL(k_spmv<double>, grid_for(n), dim3(kBlock), 0, s, n, L.S.sptr.p,
-                             L.S.col.p, L.S.val.p, L.x.p, L.t.p);
-        }
+        if (k == 0) launch_spmv_dots(h, nullptr);
+        else launch_spmv(L, L.x.p, L.t.p, s);
         break;
       case 1:
         launch_sweep<double>(nullptr, L, L.r.p, L.x.p, L.t.p, s);
         break;
       case 2:
-        hipLaunchKernelGGL(k_resid_scaled<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n,
-                           L.S.sptr.p, L.S.col.p, L.S.val.p, L.pval.p, L.r.p, L.x.p, L.t.p);
+        launch_resid<double>(nullptr, L, L.r.p, L.x.p, L.t.p, s);
         hipLaunchKernelGGL(k_agg_sum<double>, grid_for(L.nc), dim3(kBlock), 0, s, nullptr, L.nc,
                            L.mptr.p, L.mem.p, L.t.p, h->L[k + 1].r.p, h->L[k + 1].dinv.p,
                            h->L[k + 1].x.p);
@@ -890,6 +1146,9 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
       case 3:
         hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, L.agg.p,
                            L.pval.p, h->L[k + 1].x.p, L.t.p);
+        break;
+      case 5:
+        launch_corr_sweep<double>(nullptr, L, L.r.p, h->L[k + 1].x.p, L.x.p, L.t.p, s);
         break;
       default:
         hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, nullptr, n, h->w.p, h->v.p,
@@ -922,14 +1181,20 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = static_cast<double>(ms) / std::max(1, reps);
-  // algorithmic bytes: matrix values + column indices streamed once, vectors once
+  // algorithmic bytes: the matrix once in the form the kernel reads (values,
+  // column offsets or columns, group bases, slice pointers), vectors once
   const double bv = 8.0, nd = static_cast<double>(n), ncd = static_cast<double>(L.nc);
+  const Sell &S = L.S;
+  const double idx = S.cdel.p ? 2.0 * S.nnz_compact + 4.0 * (nnz - S.nnz_compact) + 4.0 * S.groups_compact
+                              : 4.0 * nnz;
+  const double mat = bv * nnz + idx + 4.0 * (S.nslices + 1);
   switch (kernel) {
-    case 0: *bytes = (bv + 4) * nnz + 2 * bv * nd + (k == 0 ? 2 * bv * nd : 0.0); break;
-    case 1: *bytes = (bv + 4) * nnz + 3 * bv * nd; break;
-    case 2: *bytes = (bv + 4) * nnz + 5 * bv * nd + 4 * nd + 4 * (ncd + 1) + 3 * bv * ncd; break;
+    case 0: *bytes = mat + 2 * bv * nd + (k == 0 ? 2 * bv * nd : 0.0); break;
+    case 1: *bytes = mat + 3 * bv * nd; break;
+    case 2: *bytes = mat + 5 * bv * nd + 4 * nd + 4 * (ncd + 1) + 3 * bv * ncd; break;
     case 3: *bytes = 3 * bv * nd + 4 * nd + bv * ncd; break;
-    default: {
+    case 5: *bytes = mat + 4 * bv * nd + 4 * nd + bv * ncd; break;
+    case 4: {
       const FirstOut fo = first_out_for(h, h->w.p);
       *bytes = 10 * bv * nd + (fo.x ? 16 * nd : 0.0) + (fo.rf ? 4 * nd : 0.0) + (fo.xf ? 8 * nd : 0.0);
       break;

@@ -37,6 +37,9 @@ CASES = {
     "poisson12_maxlev2": (lambda: W.poisson7(12), dict(max_levels=2)),
     "poisson4_single_level": (lambda: W.poisson7(4), {}),
     "poisson1_n1": (lambda: W.poisson7(1), {}),
+    # rows past 70304 shuffled: slot groups spanning more than 16 bits of
+    # column offsets next to compact ones
+    "poisson52_halfperm": (lambda: W.permute_tail(W.poisson7(52), 9, 52 ** 3 // 2), {}),
 }
 
 
@@ -52,7 +55,8 @@ def test_setup_bit_exact(case):
     assert inf["coarse_dense"] == Ho.coarse_dense
 
 
-@pytest.mark.parametrize("case", ["poisson33_ragged", "diffusion27_14_relax", "lognormal7_20_relax"])
+@pytest.mark.parametrize("case", ["poisson33_ragged", "diffusion27_14_relax", "lognormal7_20_relax",
+                                  "poisson52_halfperm"])
 def test_spmv_and_sweep_bit_exact_every_level(case):
     make, params = CASES[case]
     A = make()
@@ -246,3 +250,29 @@ def test_mixed_precision_vcycle_and_pcg(case):
     assert st == 0 and sto == 0 and abs(it - ito) <= 1 and rel <= 1e-6
     xg = host(x)
     assert np.linalg.norm(b - A.scipy() @ xg) / np.linalg.norm(b) <= 1e-6 * 1.01
+
+
+def test_time_kernel_ids_and_byte_model():
+    """amg_time_kernel: every kernel id runs on a level that has it, reports a
+    positive duration, and its algorithmic bytes follow the stated model
+    (sweep: the matrix in its compact form plus three vectors)."""
+    import paper_2303_02352_amd as amd
+    A = W.poisson7(24)
+    Hg = gpu_hierarchy(A)
+    for kid in (amd.KERNEL_SPMV, amd.KERNEL_SWEEP, amd.KERNEL_RESTRICT, amd.KERNEL_PROLONG,
+                amd.KERNEL_UPDATE, amd.KERNEL_CORR_SWEEP):
+        ms, by = Hg.time_kernel(kid, 0, 3)
+        say("  kernel", kid, "ms %.4f bytes %.0f" % (ms, by))
+        assert ms > 0 and by > 0
+    ms, sweep_bytes = Hg.time_kernel(amd.KERNEL_SWEEP, 0, 1)
+    nnz, n = A.nnz, A.n
+    # n = 13824 < 65536: every slice is compact (2-byte offsets + one base per 64 slots)
+    lo = 8 * nnz + 2 * nnz + 24 * n
+    nslices = -(-n // 64)
+    assert lo < sweep_bytes <= lo + 4 * 7 * nslices + 4 * (nslices + 1)
+    for bad in (-1, 6):
+        with pytest.raises(amd.AMGError):
+            Hg.time_kernel(bad, 0, 1)
+    last = Hg.info()["levels"] - 1
+    with pytest.raises(amd.AMGError):
+        Hg.time_kernel(amd.KERNEL_CORR_SWEEP, last, 1)

@@ -207,6 +207,25 @@ def lognormal7(N: int, seed: int, sigma2: float = 2.0, ell: float = 8.0) -> CSR:
     return _face_operator(N, kappa, offs, boundary_adds_cell=True)
 
 
+def permute_tail(A: CSR, seed: int, start: int) -> CSR:
+    """Symmetric relabelling of A: indices below `start` keep their place,
+    the others are shuffled by a seeded permutation (P A P^T).  Rows of the
+    kept part stay banded; rows of the shuffled part couple to columns spread
+    over [start, n).  Column order within each row is ascending again."""
+    n = A.n
+    perm = np.arange(n, dtype=np.int64)
+    tail = n - start
+    if tail > 0:
+        perm[start:] = start + np.argsort(uniform(seed, tail), kind="stable")
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))
+    r2, c2 = perm[rows], perm[A.col.astype(np.int64)]
+    order = np.lexsort((c2, r2))
+    r2, c2, v2 = r2[order], c2[order], A.val[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r2, minlength=n), out=row_ptr[1:])
+    return CSR(n, row_ptr.astype(np.int32), c2.astype(np.int32), v2.astype(np.float64))
+
+
 def spmv_input(A: CSR, x: np.ndarray) -> np.ndarray:
     """b = A x for building right-hand sides (scipy's CSR product)."""
     return A.scipy() @ x
