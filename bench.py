@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper"],
+                    help="only: run one form's leg and print its record (for profiling)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only: build the 160^3 hierarchy, launch the fine-level sweep "
                          "--kernel-reps times, then copy 1 GiB (counter calibration)")
@@ -252,6 +254,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.only:
+        leg = dict(batched=batched_leg, mixed27=mixed27_leg, learned=learned_leg, paper=paper_leg)[args.only]
+        log("only", args.only)
+        print(json.dumps({"form": args.only, "record": leg(amd, torch, W, np, dev)}), flush=True)
+        return
     log("generating 160^3 Poisson")
     A = W.poisson7(N_EDGE)
     xs, b = W.manufactured_rhs(A, SEED)

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "amg_internal.hpp"
@@ -28,7 +29,10 @@
 namespace amg {
 namespace {
 
-constexpr int kBTile = 256;   // rows per reduction tile of the level-0 PCG kernels
+#ifndef AMG_BATCH_TILE
+#define AMG_BATCH_TILE 256
+#endif
+constexpr int kBTile = AMG_BATCH_TILE;   // rows per reduction tile of the level-0 PCG kernels
 
 struct BScalars {
   double rho, c, a, rr, nr0, thr;
@@ -58,6 +62,30 @@ inline dim3 grid_for(int64_t n, int block = kBlock) {
 #define AMG_SKIP_IF_DONE() \
   if (skip && *skip) return
 
+// Grids are capped at kMaxGrid workgroups: logical workgroup lb (XCD-
+// contiguous order) takes the virtual blocks lb, lb + G, lb + 2G, ... of
+// kBlock threads each (G = grid size), so the resident workgroups always
+// work on one contiguous range of rows and share its neighbours in L2.  An
+// iteration queued after convergence then costs little dispatch work.
+#ifndef AMG_BATCH_MAX_GRID
+#define AMG_BATCH_MAX_GRID 4096
+#endif
+constexpr int kMaxGrid = AMG_BATCH_MAX_GRID;
+
+inline dim3 vgrid(int64_t threads) {
+  const int64_t nvb = std::max<int64_t>(1, (threads + kBlock - 1) / kBlock);
+  return dim3(static_cast<unsigned>(std::min<int64_t>(nvb, kMaxGrid)));
+}
+
+struct VSpan {
+  int64_t b, e, step;
+};
+
+__device__ __forceinline__ VSpan vspan(int64_t threads) {
+  const int64_t nvb = (threads + kBlock - 1) / kBlock;
+  return VSpan{xcd_block(blockIdx.x, gridDim.x), nvb, gridDim.x};
+}
+
 // ------------------------------------------------------------ stacking
 __global__ void k_add_copy(int n, const int *__restrict__ src, int *__restrict__ dst, int add) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,12 +95,53 @@ __global__ void k_add_copy(int n, const int *__restrict__ src, int *__restrict__
 __global__ void k_set_one(int *p, int v) { *p = v; }
 
 // --------------------------------------------------------- SELL, NR columns
+// CPL consecutive columns of one row of an RHS-interleaved vector, moved in
+// 16-byte pieces when they fill them (rows are NR * sizeof(T) bytes apart and
+// cb is a multiple of CPL, so such pieces are 16-byte aligned).
+template <class T, int CPL>
+__device__ __forceinline__ void ldcols(const T *__restrict__ p, T (&v)[CPL]) {
+  constexpr int kVec = 16 / static_cast<int>(sizeof(T));
+  if constexpr (CPL % kVec == 0) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+#pragma unroll
+    for (int q = 0; q < CPL / kVec; ++q) {
+      const V t = reinterpret_cast<const V *>(p)[q];
+      __builtin_memcpy(&v[q * kVec], &t, 16);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) v[j] = p[j];
+  }
+}
+
+template <class T, int CPL>
+__device__ __forceinline__ void stcols(T *__restrict__ p, const T (&v)[CPL]) {
+  constexpr int kVec = 16 / static_cast<int>(sizeof(T));
+  if constexpr (CPL % kVec == 0) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+#pragma unroll
+    for (int q = 0; q < CPL / kVec; ++q) {
+      V t;
+      __builtin_memcpy(&t, &v[q * kVec], 16);
+      reinterpret_cast<V *>(p)[q] = t;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) p[j] = v[j];
+  }
+}
+
 // Row `row`, columns cb .. cb+CPL-1: acc[j] = sum_k a_k x[col_k * NR + cb + j]
-// folded in CSR order; l1 = sum_k |a_k|.
-template <class T, int NR, int CPL>
+// folded in CSR order; l1 = sum_k |a_k|.  The iterate read at column c is
+// x_c, or with a correction (e != nullptr) x_c + p_c e[agg_c] (the value the
+// prolongation stores).
+template <class T, int NR, int CPL, bool kCorr = false>
 __device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__restrict__ col,
                                      const T *__restrict__ val, const T *__restrict__ x, int row,
-                                     int cb, T (&acc)[CPL], T &l1) {
+                                     int cb, T (&acc)[CPL], T &l1,
+                                     const int *__restrict__ agg = nullptr,
+                                     const T *__restrict__ pval = nullptr,
+                                     const T *__restrict__ e = nullptr) {
   const int s = row >> 6, lane = row & 63;
   const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
 #pragma unroll
@@ -82,32 +151,50 @@ __device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__
     const int c = col[b + k * 64 + lane];
     const T a = val[b + k * 64 + lane];
     m = m + fabs(a);
-    const T *xp = x + static_cast<int64_t>(c) * NR + cb;
+    T xv[CPL];
+    ldcols<T, CPL>(x + static_cast<int64_t>(c) * NR + cb, xv);
+    if constexpr (kCorr) {
+      const T pc = pval[c];
+      T ev[CPL];
+      ldcols<T, CPL>(e + static_cast<int64_t>(agg[c]) * NR + cb, ev);
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a * xp[j];
+      for (int j = 0; j < CPL; ++j) xv[j] = xv[j] + pc * ev[j];
+    }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a * xv[j];
   }
   l1 = m;
 }
 
-// xn = x + dinv (rhs - A x) on rows [0, n)
-template <class T, int NR, int CPL>
+// xn = x + dinv (rhs - A x) on rows [0, n).  TO = double with T = float
+// writes the binary32 result widened (exactly) to binary64: the last sweep
+// of a binary32 cycle then delivers the binary64 output itself.
+template <class T, int NR, int CPL, class TO = T>
 __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
                                                    const int *__restrict__ sptr,
                                                    const int *__restrict__ col,
                                                    const T *__restrict__ val,
                                                    const T *__restrict__ rhs,
-                                                   const T *__restrict__ x, T *__restrict__ xn) {
+                                                   const T *__restrict__ x, TO *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
   constexpr int LPR = NR / CPL;
-  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int row = gid / LPR, cb = (gid % LPR) * CPL;
-  if (row >= n) return;
+  const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+  const int64_t gid = vb * kBlock + threadIdx.x;
+  const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
+  if (row >= n) continue;
   T acc[CPL], l1;
   brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
   const T di = T(1) / l1;
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
+  T xo[CPL], bo[CPL];
+  TO out[CPL];
+  ldcols<T, CPL>(x + o, xo);
+  ldcols<T, CPL>(rhs + o, bo);
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) xn[o + j] = x[o + j] + di * (rhs[o + j] - acc[j]);
+  for (int j = 0; j < CPL; ++j) out[j] = static_cast<TO>(xo[j] + di * (bo[j] - acc[j]));
+  stcols<TO, CPL>(xn + o, out);
+  }
 }
 
 // First post-smoothing sweep with the coarse correction folded in: the
@@ -126,33 +213,26 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
                                                         const T *__restrict__ e, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
   constexpr int LPR = NR / CPL;
-  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int row = gid / LPR, cb = (gid % LPR) * CPL;
-  if (row >= n) return;
-  const int s = row >> 6, lane = row & 63;
-  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
-  T acc[CPL];
-#pragma unroll
-  for (int j = 0; j < CPL; ++j) acc[j] = T(0);
-  T m = T(0);
-  for (int k = 0; k < width; ++k) {
-    const int c = col[b + k * 64 + lane];
-    const T a = val[b + k * 64 + lane];
-    m = m + fabs(a);
-    const T pc = pval[c];
-    const T *xp = x + static_cast<int64_t>(c) * NR + cb;
-    const T *ep = e + static_cast<int64_t>(agg[c]) * NR + cb;
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a * (xp[j] + pc * ep[j]);
-  }
+  const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+  const int64_t gid = vb * kBlock + threadIdx.x;
+  const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
+  if (row >= n) continue;
+  T acc[CPL], m;
+  brow<T, NR, CPL, true>(sptr, col, val, x, row, cb, acc, m, agg, pval, e);
   const T di = T(1) / m;
   const T pr = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
-  const T *er = e + static_cast<int64_t>(agg[row]) * NR + cb;
+  T xo[CPL], eo[CPL], bo[CPL], out[CPL];
+  ldcols<T, CPL>(x + o, xo);
+  ldcols<T, CPL>(e + static_cast<int64_t>(agg[row]) * NR + cb, eo);
+  ldcols<T, CPL>(rhs + o, bo);
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
-    const T y = x[o + j] + pr * er[j];
-    xn[o + j] = y + di * (rhs[o + j] - acc[j]);
+    const T y = xo[j] + pr * eo[j];
+    out[j] = y + di * (bo[j] - acc[j]);
+  }
+  stcols<T, CPL>(xn + o, out);
   }
 }
 
@@ -167,15 +247,21 @@ __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
                                                    const T *__restrict__ x, T *__restrict__ t) {
   AMG_SKIP_IF_DONE();
   constexpr int LPR = NR / CPL;
-  const int gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int row = gid / LPR, cb = (gid % LPR) * CPL;
-  if (row >= n) return;
+  const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+  const int64_t gid = vb * kBlock + threadIdx.x;
+  const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
+  if (row >= n) continue;
   T acc[CPL], l1;
   brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
   const T p = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
+  T bo[CPL], out[CPL];
+  ldcols<T, CPL>(rhs + o, bo);
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) t[o + j] = p * (rhs[o + j] - acc[j]);
+  for (int j = 0; j < CPL; ++j) out[j] = p * (bo[j] - acc[j]);
+  stcols<T, CPL>(t + o, out);
+  }
 }
 
 // x = dinv * rhs on rows [0, n)
@@ -185,8 +271,12 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_first(const int *skip, int n,
                                                          const T *__restrict__ rhs,
                                                          T *__restrict__ x) {
   AMG_SKIP_IF_DONE();
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e < static_cast<int64_t>(n) * NR) x[e] = dinv[e / NR] * rhs[e];
+  const int64_t m = static_cast<int64_t>(n) * NR;
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t e = vb * kBlock + threadIdx.x;
+    if (e < m) x[e] = dinv[e / NR] * rhs[e];
+  }
 }
 
 // rc[I] = sum over members (ascending) of t; xc[I] = dinv_c[I] rc[I] when asked
@@ -197,13 +287,17 @@ __global__ void __launch_bounds__(kBlock) k_bagg(const int *skip, int nc,
                                                  const T *__restrict__ t, T *__restrict__ rc,
                                                  const T *__restrict__ dinvc, T *__restrict__ xc) {
   AMG_SKIP_IF_DONE();
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e >= static_cast<int64_t>(nc) * NR) return;
-  const int I = static_cast<int>(e / NR), c = static_cast<int>(e % NR);
-  T acc = T(0);
-  for (int q = mptr[I]; q < mptr[I + 1]; ++q) acc = acc + t[static_cast<int64_t>(mem[q]) * NR + c];
-  rc[e] = acc;
-  if (xc) xc[e] = dinvc[I] * acc;
+  const int64_t m = static_cast<int64_t>(nc) * NR;
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t e = vb * kBlock + threadIdx.x;
+    if (e >= m) continue;
+    const int I = static_cast<int>(e / NR), c = static_cast<int>(e % NR);
+    T acc = T(0);
+    for (int q = mptr[I]; q < mptr[I + 1]; ++q) acc = acc + t[static_cast<int64_t>(mem[q]) * NR + c];
+    rc[e] = acc;
+    if (xc) xc[e] = dinvc[I] * acc;
+  }
 }
 
 // x += p e[agg] on rows [0, n)
@@ -213,14 +307,22 @@ __global__ void __launch_bounds__(kBlock) k_bprolong(const int *skip, int n,
                                                      const T *__restrict__ pval,
                                                      const T *__restrict__ e, T *__restrict__ x) {
   AMG_SKIP_IF_DONE();
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (q >= static_cast<int64_t>(n) * NR) return;
-  const int i = static_cast<int>(q / NR), c = static_cast<int>(q % NR);
-  x[q] = x[q] + pval[i] * e[static_cast<int64_t>(agg[i]) * NR + c];
+  const int64_t m = static_cast<int64_t>(n) * NR;
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t q = vb * kBlock + threadIdx.x;
+    if (q >= m) continue;
+    const int i = static_cast<int>(q / NR), c = static_cast<int>(q % NR);
+    x[q] = x[q] + pval[i] * e[static_cast<int64_t>(agg[i]) * NR + c];
+  }
 }
 
 // Terminal systems: z = A_c^-1 r, one workgroup per system, binary64 fold
 // over j ascending (column-major inverse), NR columns at once.
+// Systems of up to kBCoarseLds coarsest rows first copy the inverse and the
+// right-hand sides into LDS (same fold, same bits).
+constexpr int kBCoarseLds = 100;
+
 template <class T, int NR>
 __global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *__restrict__ toff,
                                                     const int *__restrict__ tn,
@@ -228,9 +330,24 @@ __global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *
                                                     const double *__restrict__ pool,
                                                     const T *__restrict__ rhs, T *__restrict__ out) {
   AMG_SKIP_IF_DONE();
+  __shared__ double sA[kBCoarseLds * kBCoarseLds];
+  __shared__ double sR[kBCoarseLds * NR];
   const int sys = blockIdx.x;
   const int off = toff[sys], n = tn[sys];
   const double *Ai = pool + tinv[sys];
+  if (n <= kBCoarseLds) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) sA[e] = Ai[e];
+    for (int e = threadIdx.x; e < n * NR; e += blockDim.x)
+      sR[e] = static_cast<double>(rhs[static_cast<int64_t>(off) * NR + e]);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * NR; e += blockDim.x) {
+      const int i = e / NR, c = e % NR;
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc = acc + sA[j * n + i] * sR[j * NR + c];
+      out[static_cast<int64_t>(off + i) * NR + c] = static_cast<T>(acc);
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < n * NR; e += blockDim.x) {
     const int i = e / NR, c = e % NR;
     double acc = 0.0;
@@ -241,30 +358,51 @@ __global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *
   }
 }
 
-__global__ void k_bd2f(int64_t m, const double *__restrict__ a, float *__restrict__ b,
-                       const int *skip) {
+// Entry of the binary32 cycle: rf = (float) r on all m entries and, on the
+// first m1 entries (rows that smooth), the first iterate x = dinv_f * rf.
+template <int NR>
+__global__ void k_bd2f_first(int64_t m, int64_t m1, const double *__restrict__ r,
+                             const float *__restrict__ dinv, float *__restrict__ rf,
+                             float *__restrict__ x, const int *skip) {
   AMG_SKIP_IF_DONE();
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e < m) b[e] = static_cast<float>(a[e]);
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t e = vb * kBlock + threadIdx.x;
+    if (e >= m) continue;
+    const float b = static_cast<float>(r[e]);
+    rf[e] = b;
+    if (x && e < m1) x[e] = dinv[e / NR] * b;
+  }
 }
 
 __global__ void k_bf2d(int64_t m, const float *__restrict__ a, double *__restrict__ b,
                        const int *skip) {
   AMG_SKIP_IF_DONE();
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e < m) b[e] = static_cast<double>(a[e]);
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t e = vb * kBlock + threadIdx.x;
+    if (e < m) b[e] = static_cast<double>(a[e]);
+  }
 }
 
 template <class T>
 __global__ void k_bzero(int64_t m, T *x) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (e < m) x[e] = T(0);
+  const VSpan sp = vspan(m);
+  for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
+    const int64_t e = vb * kBlock + threadIdx.x;
+    if (e < m) x[e] = T(0);
+  }
 }
 
 // ------------------------------------------------------- level-0 PCG kernels
-// A tile is <= kBTile rows of one system.  Thread (rsub, c): rows r0 + rsub,
-// r0 + rsub + 256/NR, ...; the partial of column c folds the threads with
-// that column in increasing rsub.
+// A tile is <= kBTile rows of one system.  In the SpMV kernels a thread
+// handles PC = min(4, NR) consecutive columns of one row at a time (lanes
+// per row NR / PC); thread (rsub, cg) takes rows r0 + rsub, r0 + rsub +
+// kBlock / (NR / PC), ...  The partial of column c folds the threads with that
+// column in increasing rsub.
+template <int NR>
+constexpr int pcg_cols() { return NR < 4 ? NR : 4; }
+
 template <int NR>
 __device__ __forceinline__ double tile_column_sum(double v, double *red) {
   red[threadIdx.x] = v;
@@ -272,6 +410,23 @@ __device__ __forceinline__ double tile_column_sum(double v, double *red) {
   double s = 0.0;
   if (threadIdx.x < NR)
     for (int g = 0; g < kBlock / NR; ++g) s = s + red[g * NR + threadIdx.x];
+  __syncthreads();
+  return s;
+}
+
+// Column sums of per-thread values v[j] (column cg * PC + j); the result for
+// column c is returned to thread c < NR.
+template <int NR, int PC>
+__device__ __forceinline__ double tile_column_sum_v(const double (&v)[PC], double *red) {
+  constexpr int LPR = NR / PC;
+#pragma unroll
+  for (int j = 0; j < PC; ++j) red[threadIdx.x * PC + j] = v[j];
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < NR) {
+    const int cg = threadIdx.x / PC, j = threadIdx.x % PC;
+    for (int g = 0; g < kBlock / LPR; ++g) s = s + red[(g * LPR + cg) * PC + j];
+  }
   __syncthreads();
   return s;
 }
@@ -286,65 +441,99 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
                                                       const double *__restrict__ u,
                                                       double *__restrict__ r,
                                                       double *__restrict__ part) {
-  __shared__ double red[kBlock];
+  constexpr int PC = pcg_cols<NR>(), LPR = NR / PC;
+  __shared__ double red[kBlock * PC];
   const int tile = xcd_block(blockIdx.x, gridDim.x);
-  const int c = threadIdx.x % NR;
-  double rr = 0.0;
-  for (int row = trow0[tile] + threadIdx.x / NR; row < trow1[tile]; row += kBlock / NR) {
-    double acc[1], l1;
-    brow<double, NR, 1>(sptr, col, val, u, row, c, acc, l1);
-    const int64_t o = static_cast<int64_t>(row) * NR + c;
-    const double ri = b[o] - acc[0];
-    r[o] = ri;
-    rr = rr + ri * ri;
+  const int cb = (threadIdx.x % LPR) * PC;
+  double rr[PC];
+#pragma unroll
+  for (int j = 0; j < PC; ++j) rr[j] = 0.0;
+  for (int row = trow0[tile] + threadIdx.x / LPR; row < trow1[tile]; row += kBlock / LPR) {
+    double acc[PC], l1, bo[PC], ro[PC];
+    brow<double, NR, PC>(sptr, col, val, u, row, cb, acc, l1);
+    const int64_t o = static_cast<int64_t>(row) * NR + cb;
+    ldcols<double, PC>(b + o, bo);
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+      ro[j] = bo[j] - acc[j];
+      rr[j] = rr[j] + ro[j] * ro[j];
+    }
+    stcols<double, PC>(r + o, ro);
   }
-  rr = tile_column_sum<NR>(rr, red);
-  if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + c) * 3] = rr;
+  const double t = tile_column_sum_v<NR, PC>(rr, red);
+  if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + threadIdx.x) * 3] = t;
 }
 
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
-    const int *skip, const int *__restrict__ trow0, const int *__restrict__ trow1,
+    const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ sptr, const int *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
     double *__restrict__ v, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
-  __shared__ double red[kBlock];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  const int c = threadIdx.x % NR;
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int row = trow0[tile] + threadIdx.x / NR; row < trow1[tile]; row += kBlock / NR) {
-    double acc[1], l1;
-    brow<double, NR, 1>(sptr, col, val, w, row, c, acc, l1);
-    const int64_t o = static_cast<int64_t>(row) * NR + c;
-    v[o] = acc[0];
-    const double wi = w[o];
-    al = al + wi * r[o];
-    be = be + wi * acc[0];
-    ga = ga + wi * q[o];
+  constexpr int PC = pcg_cols<NR>(), LPR = NR / PC;
+  __shared__ double red[kBlock * PC];
+  const int cb = (threadIdx.x % LPR) * PC;
+  const VSpan sp = vspan(static_cast<int64_t>(ntiles) * kBlock);
+  for (int64_t vt = sp.b; vt < sp.e; vt += sp.step) {
+  const int tile = static_cast<int>(vt);
+  double al[PC], be[PC], ga[PC];
+#pragma unroll
+  for (int j = 0; j < PC; ++j) al[j] = be[j] = ga[j] = 0.0;
+  for (int row = trow0[tile] + threadIdx.x / LPR; row < trow1[tile]; row += kBlock / LPR) {
+    double acc[PC], l1, wo[PC], ro[PC], qo[PC];
+    brow<double, NR, PC>(sptr, col, val, w, row, cb, acc, l1);
+    const int64_t o = static_cast<int64_t>(row) * NR + cb;
+    stcols<double, PC>(v + o, acc);
+    ldcols<double, PC>(w + o, wo);
+    ldcols<double, PC>(r + o, ro);
+    ldcols<double, PC>(q + o, qo);
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+      al[j] = al[j] + wo[j] * ro[j];
+      be[j] = be[j] + wo[j] * acc[j];
+      ga[j] = ga[j] + wo[j] * qo[j];
+    }
   }
-  al = tile_column_sum<NR>(al, red);
-  be = tile_column_sum<NR>(be, red);
-  ga = tile_column_sum<NR>(ga, red);
+  const double sa = tile_column_sum_v<NR, PC>(al, red);
+  const double sb = tile_column_sum_v<NR, PC>(be, red);
+  const double sg = tile_column_sum_v<NR, PC>(ga, red);
   if (threadIdx.x < NR) {
-    const int64_t o = (static_cast<int64_t>(tile) * NR + c) * 3;
-    part[o] = al;
-    part[o + 1] = be;
-    part[o + 2] = ga;
+    const int64_t o = (static_cast<int64_t>(tile) * NR + threadIdx.x) * 3;
+    part[o] = sa;
+    part[o + 1] = sb;
+    part[o + 2] = sg;
+  }
   }
 }
 
 // Fold the tiles of system `blockIdx.x` per column: thread (g, c) folds tiles
-// g, g + G, ... in order; then the G group sums are folded in order.
+// g, g + G, ... in order (loads issued four tiles at a time); then the G
+// group sums are folded in order.  One workgroup of kBFinish threads.
+constexpr int kBFinish = 1024;
+
 template <int NR, int NQ>
 __device__ __forceinline__ void system_fold(const int *tile_ptr, const double *part, double *red,
                                             double (&out)[NQ]) {
-  constexpr int G = kBlock / NR;
+  constexpr int G = kBFinish / NR;
   const int sys = blockIdx.x, c = threadIdx.x % NR, g = threadIdx.x / NR;
   double acc[NQ];
 #pragma unroll
   for (int o = 0; o < NQ; ++o) acc[o] = 0.0;
-  for (int t = tile_ptr[sys] + g; t < tile_ptr[sys + 1]; t += G)
+  const int t1 = tile_ptr[sys + 1];
+  int t = tile_ptr[sys] + g;
+  for (; t + 3 * G < t1; t += 4 * G) {
+    double v[4][NQ];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int o = 0; o < NQ; ++o) v[u][o] = part[(static_cast<int64_t>(t + u * G) * NR + c) * 3 + o];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + v[u][o];
+  }
+  for (; t < t1; t += G)
 #pragma unroll
     for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + part[(static_cast<int64_t>(t) * NR + c) * 3 + o];
 #pragma unroll
@@ -360,10 +549,10 @@ __device__ __forceinline__ void system_fold(const int *tile_ptr, const double *p
 }
 
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_bpcg_init_finish(const int *tile_ptr,
+__global__ void __launch_bounds__(kBFinish) k_bpcg_init_finish(const int *tile_ptr,
                                                              const double *part, BScalars *sc,
                                                              double rtol, int *active) {
-  __shared__ double red[kBlock];
+  __shared__ double red[kBFinish];
   double t[1];
   system_fold<NR, 1>(tile_ptr, part, red, t);
   if (threadIdx.x < NR) {
@@ -384,10 +573,10 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init_finish(const int *tile_ptr
 }
 
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_bpcg_dots_finish(const int *skip, const int *tile_ptr,
+__global__ void __launch_bounds__(kBFinish) k_bpcg_dots_finish(const int *skip, const int *tile_ptr,
                                                              const double *part, BScalars *sc) {
   AMG_SKIP_IF_DONE();
-  __shared__ double red[kBlock];
+  __shared__ double red[kBFinish];
   double t[3];
   system_fold<NR, 3>(tile_ptr, part, red, t);
   if (threadIdx.x < NR) {
@@ -416,14 +605,16 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_dots_finish(const int *skip, co
 // d = w - c d; u += a d; q = v - c q; r -= a q for live pairs; partial ||r||^2.
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_bpcg_update(
-    const int *skip, const int *__restrict__ trow0, const int *__restrict__ trow1,
+    const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ tsys, const double *__restrict__ w, const double *__restrict__ v,
     double *__restrict__ d, double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
     const BScalars *__restrict__ sc, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock];
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int c = threadIdx.x % NR;
+  const VSpan sp = vspan(static_cast<int64_t>(ntiles) * kBlock);
+  for (int64_t vt = sp.b; vt < sp.e; vt += sp.step) {
+  const int tile = static_cast<int>(vt);
   const BScalars &S = sc[tsys[tile] * NR + c];
   const bool live = !S.done;
   const double cc = S.c, a = S.a;
@@ -443,14 +634,15 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_update(
   }
   rr = tile_column_sum<NR>(rr, red);
   if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + c) * 3] = rr;
+  }
 }
 
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_bpcg_norm_finish(const int *skip, const int *tile_ptr,
+__global__ void __launch_bounds__(kBFinish) k_bpcg_norm_finish(const int *skip, const int *tile_ptr,
                                                              const double *part, BScalars *sc,
                                                              int maxit, int *active) {
   AMG_SKIP_IF_DONE();
-  __shared__ double red[kBlock];
+  __shared__ double red[kBFinish];
   double t[1];
   system_fold<NR, 1>(tile_ptr, part, red, t);
   if (threadIdx.x < NR) {
@@ -534,14 +726,22 @@ template <> const float *bpval<float>(const Level &L) { return L.pvalf.p; }
 template <class T, int NR, int CPL>
 void launch_bsweep(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
                      s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn);
+}
+
+template <int NR, int CPL>
+void launch_bsweep_widen(const int *skip, BLevel &L, int n, const float *rhs, const float *x,
+                         double *xn, hipStream_t s) {
+  constexpr int LPR = NR / CPL;
+  hipLaunchKernelGGL((k_bsweep<float, NR, CPL, double>), vgrid(static_cast<int64_t>(n) * LPR),
+                     dim3(kBlock), 0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, L.L.S.valf.p, rhs, x, xn);
 }
 
 template <class T, int NR, int CPL>
 void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
                      s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t);
 }
 
@@ -549,31 +749,42 @@ template <class T, int NR, int CPL>
 void launch_bsweep_corr(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
                         hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), grid_for(static_cast<int64_t>(n) * LPR), dim3(kBlock),
+  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock),
                      0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p,
                      bpval<T>(L.L), e, xn);
+}
+
+// Calls f(std::integral_constant<int, C>) with C = cpl when cpl divides NR
+// and is one of 1, 2, 4, 8, 16; else with C = 1.
+template <int NR, class F>
+void with_cpl(int cpl, F &&f) {
+  if constexpr (NR % 16 == 0) if (cpl == 16) return f(std::integral_constant<int, 16>{});
+  if constexpr (NR % 8 == 0) if (cpl == 8) return f(std::integral_constant<int, 8>{});
+  if constexpr (NR % 4 == 0) if (cpl == 4) return f(std::integral_constant<int, 4>{});
+  if constexpr (NR % 2 == 0) if (cpl == 2) return f(std::integral_constant<int, 2>{});
+  return f(std::integral_constant<int, 1>{});
 }
 
 template <class T, int NR>
 void corr_sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
                     hipStream_t s) {
-  if (NR % 4 == 0 && L.cpl == 4) launch_bsweep_corr<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, e, x, xn, s);
-  else if (NR % 2 == 0 && L.cpl == 2) launch_bsweep_corr<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, e, x, xn, s);
-  else launch_bsweep_corr<T, NR, 1>(skip, L, n, rhs, e, x, xn, s);
+  with_cpl<NR>(L.cpl, [&](auto C) { launch_bsweep_corr<T, NR, decltype(C)::value>(skip, L, n, rhs, e, x, xn, s); });
 }
 
 template <class T, int NR>
 void sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
-  if (NR % 4 == 0 && L.cpl == 4) launch_bsweep<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, x, xn, s);
-  else if (NR % 2 == 0 && L.cpl == 2) launch_bsweep<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, x, xn, s);
-  else launch_bsweep<T, NR, 1>(skip, L, n, rhs, x, xn, s);
+  with_cpl<NR>(L.cpl, [&](auto C) { launch_bsweep<T, NR, decltype(C)::value>(skip, L, n, rhs, x, xn, s); });
+}
+
+template <int NR>
+void sweep_widen_any(const int *skip, BLevel &L, int n, const float *rhs, const float *x, double *xn,
+                     hipStream_t s) {
+  with_cpl<NR>(L.cpl, [&](auto C) { launch_bsweep_widen<NR, decltype(C)::value>(skip, L, n, rhs, x, xn, s); });
 }
 
 template <class T, int NR>
 void resid_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
-  if (NR % 4 == 0 && L.cpl == 4) launch_bresid<T, NR, (NR % 4 == 0 ? 4 : 1)>(skip, L, n, rhs, x, t, s);
-  else if (NR % 2 == 0 && L.cpl == 2) launch_bresid<T, NR, (NR % 2 == 0 ? 2 : 1)>(skip, L, n, rhs, x, t, s);
-  else launch_bresid<T, NR, 1>(skip, L, n, rhs, x, t, s);
+  with_cpl<NR>(L.cpl, [&](auto C) { launch_bresid<T, NR, decltype(C)::value>(skip, L, n, rhs, x, t, s); });
 }
 
 // first iterate location of level k (nullptr: no smoothing on this level)
@@ -586,8 +797,11 @@ T *bfirst(amg_batch *bt, int k, T *out) {
   return (swaps % 2 == 0) ? out : bv_t<T>(L);
 }
 
+// z64 (binary32 cycle, level 0 only): the last post-sweep writes its rows
+// there, widened, instead of into `out`; returns whether it did.
 template <class T, int NR>
-void bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, bool first_done) {
+bool bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, bool first_done,
+                   double *z64 = nullptr) {
   hipStream_t s = bt->stream;
   BLevel &L = bt->B[k];
   const amg_params &P = bt->p;
@@ -595,33 +809,42 @@ void bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, 
   if (L.nterm > 0)
     hipLaunchKernelGGL((k_bcoarse<T, NR>), dim3(L.nterm), dim3(kBlock), 0, s, skip, L.term_off.p,
                        L.term_n.p, L.term_inv.p, L.inv_pool.p, rhs, out);
-  if (nc0 == 0) return;
+  if (nc0 == 0) return false;
   const int swaps = (P.pre_sweeps > 0 ? P.pre_sweeps - 1 : 0) + P.post_sweeps;
   T *A = (swaps % 2 == 0) ? out : bv_t<T>(L);
   T *Bf = (A == out) ? bv_t<T>(L) : out;
   if (P.pre_sweeps == 0) {
-    hipLaunchKernelGGL(k_bzero<T>, grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_bzero<T>, vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
                        static_cast<int64_t>(nc0) * NR, A);
   } else {
     if (!first_done)
-      hipLaunchKernelGGL((k_bsweep_first<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock),
+      hipLaunchKernelGGL((k_bsweep_first<T, NR>), vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock),
                          0, s, skip, nc0, bdinv<T>(L.L), rhs, A);
     for (int qq = 1; qq < P.pre_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
   }
   resid_any<T, NR>(skip, L, nc0, rhs, A, Bf, s);
   BLevel &C = bt->B[k + 1];
   T *xc = bfirst<T>(bt, k + 1, bv_x<T>(C));
-  hipLaunchKernelGGL((k_bagg<T, NR>), grid_for(static_cast<int64_t>(C.n) * NR), dim3(kBlock), 0, s, skip,
+  hipLaunchKernelGGL((k_bagg<T, NR>), vgrid(static_cast<int64_t>(C.n) * NR), dim3(kBlock), 0, s, skip,
                      C.n, L.L.mptr.p, L.L.mem.p, Bf, bv_r<T>(C), bdinv<T>(C.L), xc);
-  bvcycle_level<T, NR>(bt, skip, k + 1, bv_r<T>(C), bv_x<T>(C), xc != nullptr);
+  (void)bvcycle_level<T, NR>(bt, skip, k + 1, bv_r<T>(C), bv_x<T>(C), xc != nullptr);
   if (P.post_sweeps == 0) {
-    hipLaunchKernelGGL((k_bprolong<T, NR>), grid_for(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_bprolong<T, NR>), vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
                        skip, nc0, L.L.agg.p, bpval<T>(L.L), bv_x<T>(C), A);
-    return;
+    return false;
   }
   corr_sweep_any<T, NR>(skip, L, nc0, rhs, bv_x<T>(C), A, Bf, s);
   std::swap(A, Bf);
-  for (int qq = 1; qq < P.post_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
+  const bool widen = std::is_same<T, float>::value && z64 && P.post_sweeps >= 2;
+  for (int qq = 1; qq < P.post_sweeps; ++qq) {
+    if (widen && qq == P.post_sweeps - 1) {
+      if constexpr (std::is_same<T, float>::value) sweep_widen_any<NR>(skip, L, nc0, rhs, A, z64, s);
+      return true;
+    }
+    sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s);
+    std::swap(A, Bf);
+  }
+  return false;
 }
 
 template <int NR>
@@ -634,9 +857,13 @@ void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
   }
   if (bt->p.precision == AMG_PREC_MIXED) {
     BLevel &L = bt->B[0];
-    hipLaunchKernelGGL(k_bd2f, grid_for(m), dim3(kBlock), 0, s, m, r, L.rf.p, skip);
-    bvcycle_level<float, NR>(bt, skip, 0, L.rf.p, L.xf.p, false);
-    hipLaunchKernelGGL(k_bf2d, grid_for(m), dim3(kBlock), 0, s, m, L.xf.p, z, skip);
+    float *x1 = bfirst<float>(bt, 0, L.xf.p);
+    hipLaunchKernelGGL((k_bd2f_first<NR>), vgrid(m), dim3(kBlock), 0, s, m,
+                       static_cast<int64_t>(L.n_cont) * NR, r, L.L.dinvf.p, L.rf.p, x1, skip);
+    const bool widened = bvcycle_level<float, NR>(bt, skip, 0, L.rf.p, L.xf.p, x1 != nullptr, z);
+    // rows the last sweep did not write (all rows, or those of single-level
+    // systems, which the binary64 solve below overwrites anyway)
+    if (!widened) hipLaunchKernelGGL(k_bf2d, vgrid(m), dim3(kBlock), 0, s, m, L.xf.p, z, skip);
     // single-level systems: their whole cycle is the binary64 direct solve
     if (L.nterm > 0)
       hipLaunchKernelGGL((k_bcoarse<double, NR>), dim3(L.nterm), dim3(kBlock), 0, s, skip,
@@ -653,15 +880,17 @@ void benqueue_iteration(amg_batch *bt, int maxit) {
   const BLevel &L0 = bt->B[0];
   const int *skip = bt->all_done.p;
   bvcycle<NR>(bt, skip, bt->r.p, bt->w.p);
-  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, skip, bt->trow0.p,
+  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR>), vgrid(static_cast<int64_t>(bt->ntiles) * kBlock), dim3(kBlock), 0,
+                     s, skip, bt->ntiles, bt->trow0.p,
                      bt->trow1.p, L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p,
                      bt->v.p, bt->partials.p);
-  hipLaunchKernelGGL((k_bpcg_dots_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, skip,
+  hipLaunchKernelGGL((k_bpcg_dots_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, skip,
                      bt->tile_ptr.p, bt->partials.p, bt->sc.p);
-  hipLaunchKernelGGL((k_bpcg_update<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, skip, bt->trow0.p,
+  hipLaunchKernelGGL((k_bpcg_update<NR>), vgrid(static_cast<int64_t>(bt->ntiles) * kBlock), dim3(kBlock), 0,
+                     s, skip, bt->ntiles, bt->trow0.p,
                      bt->trow1.p, bt->tsys.p, bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p,
                      bt->sc.p, bt->partials.p);
-  hipLaunchKernelGGL((k_bpcg_norm_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, skip,
+  hipLaunchKernelGGL((k_bpcg_norm_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, skip,
                      bt->tile_ptr.p, bt->partials.p, bt->sc.p, maxit, bt->active.p);
   hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p,
                      bt->host_flag_dev);
@@ -681,9 +910,9 @@ void autotune(amg_batch *bt) {
     if (L.n_cont == 0 || NR == 1) continue;
     const int64_t m = static_cast<int64_t>(L.n) * NR;
     T *x = bv_x<T>(L), *t = bv_t<T>(L), *r = bv_r<T>(L);
-    for (T *p : {x, t, r}) hipLaunchKernelGGL(k_bzero<T>, grid_for(m), dim3(kBlock), 0, s, m, p);
+    for (T *p : {x, t, r}) hipLaunchKernelGGL(k_bzero<T>, vgrid(m), dim3(kBlock), 0, s, m, p);
     float best = 1e30f;
-    for (int cpl : {1, 2, 4}) {
+    for (int cpl : {1, 2, 4, 8, 16}) {
       if (NR % cpl != 0) continue;
       L.cpl = cpl;
       sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s);   // warm
@@ -930,13 +1159,13 @@ int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int
   const BLevel &L0 = bt->B[0];
   batch_permute<NR>(bt, Bu, bt->bint.p, true);
   batch_permute<NR>(bt, Xu, bt->u.p, true);
-  hipLaunchKernelGGL(k_bzero<double>, grid_for(m0), dim3(kBlock), 0, s, m0, bt->d.p);
-  hipLaunchKernelGGL(k_bzero<double>, grid_for(m0), dim3(kBlock), 0, s, m0, bt->q.p);
+  hipLaunchKernelGGL(k_bzero<double>, vgrid(m0), dim3(kBlock), 0, s, m0, bt->d.p);
+  hipLaunchKernelGGL(k_bzero<double>, vgrid(m0), dim3(kBlock), 0, s, m0, bt->q.p);
   AMG_HIP(hipMemsetAsync(bt->active.p, 0, sizeof(int), s));
   hipLaunchKernelGGL((k_bpcg_init<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, bt->trow0.p, bt->trow1.p,
                      L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->bint.p, bt->u.p, bt->r.p,
                      bt->partials.p);
-  hipLaunchKernelGGL((k_bpcg_init_finish<NR>), dim3(bt->nsys), dim3(kBlock), 0, s, bt->tile_ptr.p,
+  hipLaunchKernelGGL((k_bpcg_init_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, bt->tile_ptr.p,
                      bt->partials.p, bt->sc.p, rtol, bt->active.p);
   hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p, bt->host_flag_dev);
   AMG_LAUNCH_CHECK();

@@ -766,18 +766,20 @@ void launch_resid(const int *skip, const Level &L, const T *rhs, const T *x, T *
                        sell_ref(L.S), vals<T>(L.S), pval_of<T>(L), rhs, x, t);
 }
 
-// Prolongation fused into the first post-sweep: 0 never, 1 on cached
-// levels only (a streamed level runs them apart: there the four gathers per
-// slot of the fused kernel cost more than the extra vector pass), 2 always.
+// Prolongation fused into the first post-sweep: 0 never, 1 on levels of at
+// most kFuseMaxRows rows, whose kernels are launch- and latency-bound (on
+// larger levels the four gathers per slot of the fused kernel cost more
+// than the separate vector pass), 2 always.
 #ifndef AMG_FUSE_PROLONG
 #define AMG_FUSE_PROLONG 1
 #endif
+constexpr int kFuseMaxRows = 131072;
 // x + P e followed by one sweep, xn the result (A: level k, e: level k+1 output).
 template <class T>
 void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e, T *x, T *xn,
                        hipStream_t s) {
   const int n = L.A.n;
-  if (AMG_FUSE_PROLONG == 0 || (AMG_FUSE_PROLONG == 1 && streamed<T>(L))) {
+  if (AMG_FUSE_PROLONG == 0 || (AMG_FUSE_PROLONG == 1 && n > kFuseMaxRows)) {
     hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
                        e, x);
     launch_sweep<T>(skip, L, rhs, x, xn, s);
