@@ -139,8 +139,10 @@ def learned_leg(amd, torch, W, np, dev):
         H1, t_ones = timed(lambda: amd.Hierarchy(*csr, max_levels=1))
         H1.close()
         Hp, tsp = timed(lambda: amd.Hierarchy(*csr, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20))
+        ip = Hp.info()
         plain = dict(setup_s=tsp, wgen_s=max(0.0, t_relax - t_ones), **solve(Hp),
-                     levels=Hp.info()["n"], opc=Hp.info()["opc"])
+                     levels=ip["n"], opc=ip["opc"], matching_rounds=ip["matching_rounds"],
+                     setup_match_ms=ip["setup_match_ms"], setup_rap_ms=ip["setup_rap_ms"])
         Hp.close()
         w, t_inf = timed(lambda: surrogate.learned_smooth_vector(net, csr, torch))
         fallback = w is None
@@ -148,8 +150,10 @@ def learned_leg(amd, torch, W, np, dev):
             Hl, tsl = timed(lambda: amd.Hierarchy(*csr, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20))
         else:
             Hl, tsl = timed(lambda: amd.Hierarchy(*csr, smooth_vector=w))
+        il = Hl.info()
         learned = dict(setup_s=tsl, wgen_s=t_inf, fallback_to_relax=fallback, **solve(Hl),
-                       levels=Hl.info()["n"], opc=Hl.info()["opc"])
+                       levels=il["n"], opc=il["opc"], matching_rounds=il["matching_rounds"],
+                       setup_match_ms=il["setup_match_ms"], setup_rap_ms=il["setup_rap_ms"])
         Hl.close()
         res = dict(workload="lognormal7 128^3 seed 7 (sigma^2 = 2, ell = 8)", plain=plain, learned=learned)
     p, l = res["plain"], res["learned"]
