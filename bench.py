@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper"],
+    ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160"],
                     help="only: run one form's leg and print its record (for profiling)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only: build the 160^3 hierarchy, launch the fine-level sweep "
@@ -258,7 +258,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.only:
+    if args.only and args.only != "mixed160":
         leg = dict(batched=batched_leg, mixed27=mixed27_leg, learned=learned_leg, paper=paper_leg)[args.only]
         log("only", args.only)
         print(json.dumps({"form": args.only, "record": leg(amd, torch, W, np, dev)}), flush=True)
@@ -298,6 +298,16 @@ def main():
             t2 = time.perf_counter()
         return H, x, dict(status=st, iters=it, relres=rel, setup_s=t1 - t0,
                           solve_s=e0.elapsed_time(e1) / 1e3, wall_solve_s=t2 - t1)
+
+    if args.only == "mixed160":
+        recs = []
+        for _ in range(3):
+            Hm, xm, rm = one_step(amd.AMG_PREC_MIXED)
+            Hm.close()
+            recs.append(rm)
+        print(json.dumps({"form": "mixed160", "record": recs[-1],
+                          "solve_s_each": [r["solve_s"] for r in recs]}), flush=True)
+        return
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):

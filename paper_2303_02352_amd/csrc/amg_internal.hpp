@@ -65,6 +65,40 @@ struct dvec {
   T *get() const { return p; }
 };
 
+// Stream-ordered scratch array for work inside one host function: allocated
+// and freed in order on `s` from the device's memory pool (which keeps the
+// memory for reuse), so temporaries cost no device-wide synchronisation.
+template <class T>
+struct tvec {
+  T *p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  tvec() = default;
+  tvec(size_t count, hipStream_t st) { alloc(count, st); }
+  tvec(const tvec &) = delete;
+  tvec &operator=(const tvec &) = delete;
+  tvec(tvec &&o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  tvec &operator=(tvec &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~tvec() { release(); }
+  void alloc(size_t count, hipStream_t st) {
+    release();
+    n = count;
+    s = st;
+    if (count) AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), sizeof(T) * count, st));
+  }
+  void release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Keep freed pool memory cached for later setups (called once per device).
+void keep_pool_memory();
+
 // ---------------------------------------------------------------- layouts
 
 constexpr int kWave = 64;          // CDNA wavefront

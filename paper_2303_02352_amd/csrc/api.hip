@@ -117,6 +117,7 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
     h->own_stream = 1;
   }
   st = guarded([&] {
+    amg::keep_pool_memory();
     amg::build_hierarchy(h, A);
     return AMG_OK;
   });

@@ -1242,6 +1242,7 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
     bt->own_stream = 1;
   }
   int st = amg::api_guarded([&] {
+    amg::keep_pool_memory();
     amg::batch_build(bt, nsys, A);
     return AMG_OK;
   });

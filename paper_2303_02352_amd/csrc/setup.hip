@@ -6,6 +6,11 @@
 // on its own, in the orders stated at each kernel.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+#include <mutex>
+#include <type_traits>
+#include <utility>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -68,7 +73,7 @@ __global__ void k_set_total(int *out, int n, const int *tile_off, const int *til
 void exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
   constexpr int kTile = kBlock * 4;
   const int ntiles = std::max(1, ceil_div(n, kTile));
-  dvec<int> tsum(ntiles), toff(ntiles + 1);
+  tvec<int> tsum(ntiles, s), toff(ntiles + 1, s);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, in, out, tsum.p, n);
   AMG_LAUNCH_CHECK();
   if (ntiles > 1) {
@@ -80,7 +85,6 @@ void exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, toff.p, tsum.p, ntiles);
   AMG_LAUNCH_CHECK();
-  AMG_HIP(hipStreamSynchronize(s));   // temporaries are freed on return
 }
 
 int read_int(const int *dptr, hipStream_t s) {
@@ -232,34 +236,40 @@ __device__ __forceinline__ bool key_gt(double wa, int ha, int la, double wb, int
 // matched itself (the undecided set only shrinks), so after round 0 (all
 // vertices) only the undecided neighbours that had named a newly matched
 // vertex recompute their candidate, and a new mutual pair always contains
-// such a vertex: round t = notify (matched list of t-1 -> recompute list),
-// candidates of the recompute list, commit over the recompute list.  The
+// such a vertex: round t = notify (matched list of t-1 -> recompute list,
+// whose candidates are recomputed there), commit over the recompute list.  The
 // state after every round equals that of all-vertex rounds; the matching
 // ends when a recompute list is empty.  Lists are unordered (atomic
 // appends); the result does not depend on their order.
 //
 // List kernels run grid-stride over a device-side count; list == nullptr
 // means "every vertex 0..n-1".
-__global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *list, const int *cnt,
-                                                    const int *rp, const int *ci,
+__global__ void k_fill_int(int n, int *a, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// Heaviest eligible edge of i to an undecided neighbour (-1: none).
+__device__ __forceinline__ int best_candidate(int i, const int *rp, const int *ci, const double *wgt,
+                                              const int *mate) {
+  int best = -1, bh = 0, bl = 0;
+  double bw = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const double x = wgt[k];
+    if (!(x > 0.0)) continue;
+    const int j = ci[k];
+    if (mate[j] != kFree) continue;
+    const int hi = j > i ? j : i, lo = j > i ? i : j;
+    if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
+  }
+  return best;
+}
+
+__global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *rp, const int *ci,
                                                     const double *wgt, const int *mate,
                                                     int *cand) {
-  const int m = list ? *cnt : n;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
-    const int i = list ? list[q] : q;
-    if (mate[i] != kFree) continue;
-    int best = -1, bh = 0, bl = 0;
-    double bw = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      const double x = wgt[k];
-      if (!(x > 0.0)) continue;
-      const int j = ci[k];
-      if (mate[j] != kFree) continue;
-      const int hi = j > i ? j : i, lo = j > i ? i : j;
-      if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
-    }
-    cand[i] = best;
-  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (mate[i] == kFree) cand[i] = best_candidate(i, rp, ci, wgt, mate);
 }
 
 // Mutual candidates are matched and appended to the matched list: both
@@ -289,11 +299,14 @@ __global__ void __launch_bounds__(kBlock) k_mm_commit(int n, const int *list, co
 }
 
 // Undecided neighbours whose candidate was just matched go on the recompute
-// list, once per round (stamp).
+// list, once per round (stamp), and the thread that lists u recomputes its
+// candidate at once (mate does not change in this kernel; a new candidate is
+// undecided, so it never equals a matched vertex another thread compares
+// against).
 __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const int *mcnt,
                                                       const int *rp, const int *ci,
                                                       const double *wgt, const int *mate,
-                                                      const int *cand, int *stamp, int round,
+                                                      int *cand, int *stamp, int round,
                                                       int *rlist, int *rcnt) {
   const int m = *mcnt;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
@@ -301,7 +314,10 @@ __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const in
     for (int k = rp[v]; k < rp[v + 1]; ++k) {
       const int u = ci[k];
       if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
-      if (atomicExch(&stamp[u], round) != round) rlist[atomicAdd(rcnt, 1)] = u;
+      if (atomicExch(&stamp[u], round) != round) {
+        cand[u] = best_candidate(u, rp, ci, wgt, mate);
+        rlist[atomicAdd(rcnt, 1)] = u;
+      }
     }
   }
 }
@@ -354,16 +370,6 @@ __global__ void k_pair_restrict_w(int nc, const int *rep, const int *mate, const
 // agg(j) = J.  Terms of one coarse entry are folded in ascending (u, v),
 // u = the fine index on the side of min(I,J), v = the other, so entries
 // (I,J) and (J,I) fold identical term sequences (bitwise-symmetric A_c).
-__global__ void k_rap_count_terms(int nc, const int *rep, const int *mate, const int *rp,
-                                  int *cnt) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  const int lo = rep[I], hi = mate[lo];
-  int c = rp[lo + 1] - rp[lo];
-  if (hi >= 0) c += rp[hi + 1] - rp[hi];
-  cnt[I] = c;
-}
-
 __device__ __forceinline__ bool term_lt(int Ja, unsigned long long ka, int Jb,
                                         unsigned long long kb) {
   return Ja < Jb || (Ja == Jb && ka < kb);
@@ -374,6 +380,7 @@ __global__ void k_rap_terms(int nc, const int *rep, const int *mate, const int *
                             int *tJ, unsigned long long *tK, double *tT, int *ucnt) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
+  if (toff[I] == toff[I + 1]) return;   // row sorted in registers (k_rap_reg)
   const int lo = rep[I], hi = mate[lo];
   const int base = toff[I];
   int c = 0;
@@ -408,10 +415,132 @@ __global__ void k_rap_terms(int nc, const int *rep, const int *mate, const int *
   ucnt[I] = u;
 }
 
+// Coarse rows whose pair has at most kRapReg terms (the common case) sort
+// and fold their terms in registers: gather, a bitonic network on the
+// (J, key) order, then the runs of equal J folded from their first term --
+// the order and the fold of k_rap_terms + k_rap_fold.  The row's entries go
+// to slots [I * kRapReg, I * kRapReg + ucnt[I]) of (uJ, uV) and are copied
+// to their CSR place once the row lengths are scanned (k_rap_place).  Wider
+// rows get tcnt = their term count and take the general path; narrow rows
+// get tcnt = 0.
+constexpr int kRapReg = 16;
+
+// Compile-time loop: f(integral_constant<int, i>) for i = 0 .. N-1, so that
+// register arrays are only ever indexed by constants.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__global__ void __launch_bounds__(kBlock) k_rap_reg(int nc, const int *__restrict__ rep,
+                                                    const int *__restrict__ mate,
+                                                    const int *__restrict__ rp,
+                                                    const int *__restrict__ ci,
+                                                    const double *__restrict__ v,
+                                                    const int *__restrict__ agg,
+                                                    const double *__restrict__ p,
+                                                    int *__restrict__ tcnt, int *__restrict__ ucnt,
+                                                    int *__restrict__ uJ, double *__restrict__ uV) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int lo = rep[I], hi = mate[lo];
+  const int b0 = rp[lo], n0 = rp[lo + 1] - b0;
+  const int b1 = hi >= 0 ? rp[hi] : 0, n1 = hi >= 0 ? rp[hi + 1] - b1 : 0;
+  const int c = n0 + n1;
+  if (c > kRapReg) {
+    tcnt[I] = c;
+    return;
+  }
+  int J[kRapReg];
+  unsigned long long K[kRapReg];
+  double T[kRapReg];
+  static_for<kRapReg>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    J[q] = INT_MAX;
+    K[q] = ~0ull;
+    T[q] = 0.0;
+    if (q < c) {
+      const int i = q < n0 ? lo : hi;
+      const int e = q < n0 ? b0 + q : b1 + (q - n0);
+      const int j = ci[e];
+      const int Jq = agg[j];
+      const unsigned u = static_cast<unsigned>(I <= Jq ? i : j);
+      const unsigned w2 = static_cast<unsigned>(I <= Jq ? j : i);
+      J[q] = Jq;
+      K[q] = (static_cast<unsigned long long>(u) << 32) | w2;
+      T[q] = (p[i] * p[j]) * v[e];
+    }
+  });
+  // bitonic sort, ascending by (J, K); padding (INT_MAX, ~0) sorts last.
+  // Stages (k, j) = (2,1) (4,2) (4,1) (8,4) (8,2) (8,1) (16,8) (16,4) (16,2) (16,1).
+  static_assert(kRapReg == 16, "the stage table below is for 16 slots");
+  static_for<10>([&](auto st) {
+    constexpr int kk[10] = {2, 4, 4, 8, 8, 8, 16, 16, 16, 16};
+    constexpr int jv[10] = {1, 2, 1, 4, 2, 1, 8, 4, 2, 1};
+    constexpr int k = kk[decltype(st)::value], jj = jv[decltype(st)::value];
+    static_for<kRapReg>([&](auto ai) {
+      constexpr int a = decltype(ai)::value, bb = a ^ jj;
+      if constexpr (bb > a) {
+        const bool lt = J[bb] < J[a] || (J[bb] == J[a] && K[bb] < K[a]);   // (b) < (a)
+        const bool gt = J[a] < J[bb] || (J[a] == J[bb] && K[a] < K[bb]);   // (a) < (b)
+        const bool sw = ((a & k) == 0) ? lt : gt;
+        const int ja = J[a], jb = J[bb];
+        const unsigned long long ka = K[a], kb = K[bb];
+        const double ta = T[a], tb = T[bb];
+        J[a] = sw ? jb : ja;
+        J[bb] = sw ? ja : jb;
+        K[a] = sw ? kb : ka;
+        K[bb] = sw ? ka : kb;
+        T[a] = sw ? tb : ta;
+        T[bb] = sw ? ta : tb;
+      }
+    });
+  });
+  // runs of equal J: T[q] becomes the run's partial sum (started from its
+  // first term); a run's last slot is an output
+  int u = 0;
+  const int64_t base = static_cast<int64_t>(I) * kRapReg;
+  static_for<kRapReg>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    if (q < c) {
+      if constexpr (q > 0)
+        if (J[q] == J[q - 1]) T[q] = T[q - 1] + T[q];
+      bool end = (q + 1 == c);
+      if constexpr (q + 1 < kRapReg) end = end || (J[q + 1] != J[q]);
+      if (end) {
+        uJ[base + u] = J[q];
+        uV[base + u] = T[q];
+        ++u;
+      }
+    }
+  });
+  tcnt[I] = 0;
+  ucnt[I] = u;
+}
+
+__global__ void k_rap_place(int nc, const int *__restrict__ tcnt_off, const int *__restrict__ uJ,
+                            const double *__restrict__ uV, const int *__restrict__ crp,
+                            int *__restrict__ cci, double *__restrict__ cv) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  if (tcnt_off[I] != tcnt_off[I + 1]) return;   // general path
+  const int64_t base = static_cast<int64_t>(I) * kRapReg;
+  const int b = crp[I], e = crp[I + 1];
+  for (int q = 0; q < e - b; ++q) {
+    cci[b + q] = uJ[base + q];
+    cv[b + q] = uV[base + q];
+  }
+}
+
 __global__ void k_rap_fold(int nc, const int *toff, const int *tJ, const double *tT,
                            const int *crp, int *cci, double *cv) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
+  if (toff[I] == toff[I + 1]) return;   // row folded in registers
   const int b = toff[I], e = toff[I + 1];
   int out = crp[I];
   for (int q = b; q < e;) {
@@ -623,7 +752,7 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
   const int n = Lv.A.n;
   S.n = n;
   S.nslices = ceil_div(n, kSlice);
-  dvec<int> slots(S.nslices);
+  tvec<int> slots(S.nslices, s);
   S.sptr.alloc(S.nslices + 1);
   hipLaunchKernelGGL(k_sell_width, grid_for(S.nslices), dim3(kBlock), 0, s, n, S.nslices,
                      Lv.A.rp.p, slots.p);
@@ -637,7 +766,7 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
   AMG_LAUNCH_CHECK();
   S.cbase.alloc(S.nslots / kSlice);
   S.cdel.alloc(S.nslots);
-  dvec<unsigned long long> cnt(2);
+  tvec<unsigned long long> cnt(2, s);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_sell_compact, grid_for(static_cast<int64_t>(S.nslices) * kWave), dim3(kBlock),
                      0, s, n, S.nslices, Lv.A.rp.p, S.sptr.p, S.col.p, S.cbase.p, S.cdel.p, cnt.p);
@@ -657,8 +786,9 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
 // One pairwise step on (A, w): matching, aggregates, P values, w_c, A_c.
 struct PairStep {
   int nc = 0;
-  dvec<int> agg, rep, mate;
-  dvec<double> p, wc;
+  tvec<int> agg, rep, mate;    // temporaries of the step (stream-ordered)
+  tvec<double> p;
+  dvec<double> wc;             // these two become the next level
   DevCSR Ac;
 };
 
@@ -666,32 +796,28 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   const int n = A.n;
   const dim3 g = grid_for(n), b(kBlock);
   double t0 = now_ms();
-  dvec<double> d(n), wgt(A.nnz);
+  tvec<double> d(n, s), wgt(A.nnz, s);
   hipLaunchKernelGGL(k_diag, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p);
   AMG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
   AMG_LAUNCH_CHECK();
-  out.mate.alloc(n);
-  dvec<int> cand(n), stamp(n), rlist(n), mbuf[2] = {dvec<int>(n), dvec<int>(n)};
-  {
-    std::vector<int> init(n, kFree);
-    AMG_HIP(hipMemcpyAsync(out.mate.p, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-    std::fill(init.begin(), init.end(), -1);
-    AMG_HIP(hipMemcpyAsync(stamp.p, init.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-    AMG_HIP(hipStreamSynchronize(s));
-  }
+  out.mate.alloc(n, s);
+  tvec<int> cand(n, s), stamp(n, s), rlist(n, s), mbuf0(n, s), mbuf1(n, s);
+  int *mbuf[2] = {mbuf0.p, mbuf1.p};
+  hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, out.mate.p, kFree);
+  hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, stamp.p, -1);
+  AMG_LAUNCH_CHECK();
   // Rounds are issued in batches of kBatch with one host read per batch.
   // cnt[2q] = matched-list length of the round before round q of the batch,
   // cnt[2q+1] = recompute-list length of round q.  Each vertex enters a
   // matched list once and a recompute list at most once per round, so n
   // entries bound every list; matched lists alternate between two buffers.
   const int kBatch = 16;   // even: round 0 of every batch reads mbuf[0]
-  const dim3 gl(static_cast<unsigned>(std::min(2048, std::max(1, ceil_div(n, kBlock)))));
-  dvec<int> cnt(2 * kBatch + 2);
+  const dim3 gl(static_cast<unsigned>(std::min(1024, std::max(1, ceil_div(n, kBlock)))));
+  tvec<int> cnt(2 * kBatch + 2, s);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (2 * kBatch + 2), s));
-  hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, nullptr, nullptr, A.rp.p, A.ci.p, wgt.p, out.mate.p,
-                     cand.p);
-  hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, nullptr, nullptr, out.mate.p, cand.p, mbuf[0].p,
+  hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, A.rp.p, A.ci.p, wgt.p, out.mate.p, cand.p);
+  hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, nullptr, nullptr, out.mate.p, cand.p, mbuf[0],
                      cnt.p);
   AMG_LAUNCH_CHECK();
   int rounds = 1;
@@ -702,12 +828,10 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
       const int *mc = cnt.p + 2 * q;
       int *rc = cnt.p + 2 * q + 1;
       int *mc_next = cnt.p + 2 * q + 2;
-      hipLaunchKernelGGL(k_mm_notify, gl, b, 0, s, mbuf[q % 2].p, mc, A.rp.p, A.ci.p, wgt.p,
+      hipLaunchKernelGGL(k_mm_notify, gl, b, 0, s, mbuf[q % 2], mc, A.rp.p, A.ci.p, wgt.p,
                          out.mate.p, cand.p, stamp.p, rounds + q, rlist.p, rc);
-      hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, rlist.p, rc, A.rp.p, A.ci.p, wgt.p, out.mate.p,
-                         cand.p);
       hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, rlist.p, rc, out.mate.p, cand.p,
-                         mbuf[(q + 1) % 2].p, mc_next);
+                         mbuf[(q + 1) % 2], mc_next);
     }
     AMG_LAUNCH_CHECK();
     rounds += kBatch;
@@ -718,15 +842,15 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
     AMG_HIP(hipMemcpyAsync(cnt.p, cnt.p + 2 * kBatch, sizeof(int), hipMemcpyDeviceToDevice, s));
   }
   tm.rounds += rounds;
-  dvec<int> flag(n), pos(n + 1);
+  tvec<int> flag(n, s), pos(n + 1, s);
   hipLaunchKernelGGL(k_agg_flags, g, b, 0, s, n, out.mate.p, flag.p);
   AMG_LAUNCH_CHECK();
   exclusive_scan(flag.p, pos.p, n, s);
   const int nc = read_int(pos.p + n, s);
   out.nc = nc;
-  out.agg.alloc(n);
-  out.rep.alloc(nc);
-  out.p.alloc(n);
+  out.agg.alloc(n, s);
+  out.rep.alloc(nc, s);
+  out.p.alloc(n, s);
   out.wc.alloc(nc);
   hipLaunchKernelGGL(k_agg_ids, g, b, 0, s, n, out.mate.p, pos.p, out.agg.p, out.rep.p);
   hipLaunchKernelGGL(k_pair_pvals, g, b, 0, s, n, out.mate.p, w, out.p.p);
@@ -739,14 +863,16 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
 
   // Galerkin product
   const dim3 gc = grid_for(nc);
-  dvec<int> tcnt(nc), toff(nc + 1), ucnt(nc);
-  hipLaunchKernelGGL(k_rap_count_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, tcnt.p);
+  tvec<int> tcnt(nc, s), toff(nc + 1, s), ucnt(nc, s), uJ(static_cast<size_t>(nc) * kRapReg, s);
+  tvec<double> uV(static_cast<size_t>(nc) * kRapReg, s);
+  hipLaunchKernelGGL(k_rap_reg, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
+                     out.agg.p, out.p.p, tcnt.p, ucnt.p, uJ.p, uV.p);
   AMG_LAUNCH_CHECK();
   exclusive_scan(tcnt.p, toff.p, nc, s);
   const int nterms = read_int(toff.p + nc, s);
-  dvec<int> tJ(nterms);
-  dvec<unsigned long long> tK(nterms);
-  dvec<double> tT(nterms);
+  tvec<int> tJ(nterms, s);
+  tvec<unsigned long long> tK(nterms, s);
+  tvec<double> tT(nterms, s);
   hipLaunchKernelGGL(k_rap_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
                      out.agg.p, out.p.p, toff.p, tJ.p, tK.p, tT.p, ucnt.p);
   AMG_LAUNCH_CHECK();
@@ -757,6 +883,8 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   out.Ac.ci.alloc(out.Ac.nnz);
   out.Ac.v.alloc(out.Ac.nnz);
   hipLaunchKernelGGL(k_rap_fold, gc, b, 0, s, nc, toff.p, tJ.p, tT.p, out.Ac.rp.p, out.Ac.ci.p,
+                     out.Ac.v.p);
+  hipLaunchKernelGGL(k_rap_place, gc, b, 0, s, nc, toff.p, uJ.p, uV.p, out.Ac.rp.p, out.Ac.ci.p,
                      out.Ac.v.p);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipStreamSynchronize(s));
@@ -778,7 +906,7 @@ void finish_level(Level &Lv, hipStream_t s, bool want_float) {
 
 void build_members(Level &Lv, hipStream_t s) {
   const int n = Lv.A.n, nc = Lv.nc;
-  dvec<int> cnt(nc), fill(nc);
+  tvec<int> cnt(nc, s), fill(nc, s);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * nc, s));
   AMG_HIP(hipMemsetAsync(fill.p, 0, sizeof(int) * nc, s));
   hipLaunchKernelGGL(k_count_members, grid_for(n), dim3(kBlock), 0, s, n, Lv.agg.p, cnt.p);
@@ -793,6 +921,25 @@ void build_members(Level &Lv, hipStream_t s) {
 }
 
 }  // namespace
+
+// Pool memory freed by setup temporaries stays cached up to this amount, so
+// repeated setups do not map and unmap memory.
+constexpr uint64_t kPoolKeepBytes = 8ull << 30;
+
+void keep_pool_memory() {
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::vector<int> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(done.size()) <= dev) done.resize(dev + 1, 0);
+  if (done[dev]) return;
+  hipMemPool_t pool;
+  AMG_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = kPoolKeepBytes;
+  AMG_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done[dev] = 1;
+}
 
 // Entry points for the other translation units (batched hierarchy).
 void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s) { exclusive_scan(in, out, n, s); }
