@@ -99,6 +99,34 @@ struct tvec {
 // Keep freed pool memory cached for later setups (called once per device).
 void keep_pool_memory();
 
+// Grow-only device workspace carved into temporaries (256-byte aligned);
+// reset() makes the whole buffer available again.  Work that used earlier
+// carvings must be ordered before later users on the same stream.
+struct Arena {
+  dvec<unsigned char> buf;
+  size_t off = 0;
+  void reserve(size_t bytes) {
+    if (buf.n < bytes) buf.alloc(bytes);
+    off = 0;
+  }
+  void reset() { off = 0; }
+  template <class T>
+  T *take(size_t count) {
+    const size_t a = (off + 255) & ~static_cast<size_t>(255);
+    if (a + sizeof(T) * count > buf.n) fail(AMG_ERR_DEVICE, "setup workspace exhausted");
+    off = a + sizeof(T) * count;
+    return reinterpret_cast<T *>(buf.p + a);
+  }
+};
+
+// A typed carving of an Arena (member `p` like the owning arrays).
+template <class T>
+struct wsv {
+  T *p = nullptr;
+  wsv() = default;
+  wsv(Arena &a, size_t count) : p(a.take<T>(count)) {}
+};
+
 // ---------------------------------------------------------------- layouts
 
 constexpr int kWave = 64;          // CDNA wavefront

@@ -70,27 +70,86 @@ __global__ void k_set_total(int *out, int n, const int *tile_off, const int *til
   out[n] = tile_off[ntiles - 1] + tile_sum[ntiles - 1];
 }
 
-void exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
-  constexpr int kTile = kBlock * 4;
-  const int ntiles = std::max(1, ceil_div(n, kTile));
-  tvec<int> tsum(ntiles, s), toff(ntiles + 1, s);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, in, out, tsum.p, n);
+__global__ void k_fill_int(int n, int *a, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+constexpr int kScanTile = kBlock * 4;
+
+// Scan of n ints with tile sums and offsets carved from `scratch` (each
+// recursion level takes 2 ntiles + 1 ints, then passes the rest on).
+void scan_impl(const int *in, int *out, int n, hipStream_t s, int *scratch) {
+  const int ntiles = std::max(1, ceil_div(n, kScanTile));
+  int *tsum = scratch, *toff = scratch + ntiles;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, in, out, tsum, n);
   AMG_LAUNCH_CHECK();
   if (ntiles > 1) {
-    exclusive_scan(tsum.p, toff.p, ntiles, s);
-    hipLaunchKernelGGL(k_scan_add, grid_for(n), dim3(kBlock), 0, s, out, toff.p, n);
+    scan_impl(tsum, toff, ntiles, s, toff + ntiles + 1);
+    hipLaunchKernelGGL(k_scan_add, grid_for(n), dim3(kBlock), 0, s, out, toff, n);
     AMG_LAUNCH_CHECK();
   } else {
-    AMG_HIP(hipMemsetAsync(toff.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(1), 0, s, 1, toff, 0);
   }
-  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, toff.p, tsum.p, ntiles);
+  hipLaunchKernelGGL(k_set_total, dim3(1), dim3(1), 0, s, out, n, toff, tsum, ntiles);
   AMG_LAUNCH_CHECK();
+}
+
+// Scratch ints a scan of n entries needs over all recursion levels.
+size_t scan_scratch_ints(int n) {
+  size_t total = 0;
+  for (int m = n;;) {
+    const int nt = std::max(1, ceil_div(m, kScanTile));
+    total += 2 * static_cast<size_t>(nt) + 1;
+    if (nt == 1) break;
+    m = nt;
+  }
+  return total;
+}
+
+// Per-thread, per-device grow-only scan scratch (scans of one thread are
+// ordered on its streams; the buffer lives until the thread ends).
+int *scan_scratch(int n) {
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  thread_local std::vector<dvec<int>> bufs;
+  if (static_cast<int>(bufs.size()) <= dev) bufs.resize(dev + 1);
+  const size_t need = scan_scratch_ints(n);
+  if (bufs[dev].n < need) bufs[dev].alloc(std::max<size_t>(need, 1 << 16));
+  return bufs[dev].p;
+}
+
+void exclusive_scan(const int *in, int *out, int n, hipStream_t s) {
+  scan_impl(in, out, n, s, scan_scratch(n));
+}
+
+// Small device-to-host reads go through a per-thread pinned buffer (a copy
+// into pageable memory is staged by the runtime and costs tens of
+// microseconds more per read).
+struct PinnedSlot {
+  void *p = nullptr;
+  ~PinnedSlot() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+void *pinned_slot() {
+  thread_local PinnedSlot slot;
+  if (!slot.p) AMG_HIP(hipHostMalloc(&slot.p, 64, hipHostMallocDefault));
+  return slot.p;
+}
+
+// Copy `bytes` (<= 64) from device memory to `dst` on the host; synchronises s.
+void read_small(void *dst, const void *dptr, size_t bytes, hipStream_t s) {
+  void *h = pinned_slot();
+  AMG_HIP(hipMemcpyAsync(h, dptr, bytes, hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipStreamSynchronize(s));
+  std::memcpy(dst, h, bytes);
 }
 
 int read_int(const int *dptr, hipStream_t s) {
   int v = 0;
-  AMG_HIP(hipMemcpyAsync(&v, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  read_small(&v, dptr, sizeof(int), s);
   return v;
 }
 
@@ -244,16 +303,12 @@ __device__ __forceinline__ bool key_gt(double wa, int ha, int la, double wb, int
 //
 // List kernels run grid-stride over a device-side count; list == nullptr
 // means "every vertex 0..n-1".
-__global__ void k_fill_int(int n, int *a, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
-}
-
 // Heaviest eligible edge of i to an undecided neighbour (-1: none).
 __device__ __forceinline__ int best_candidate(int i, const int *rp, const int *ci, const double *wgt,
                                               const int *mate) {
   int best = -1, bh = 0, bl = 0;
   double bw = 0.0;
+#pragma unroll 8
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const double x = wgt[k];
     if (!(x > 0.0)) continue;
@@ -272,6 +327,11 @@ __global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *rp, const 
     if (mate[i] == kFree) cand[i] = best_candidate(i, rp, ci, wgt, mate);
 }
 
+// Appends to the round lists are staged per workgroup in LDS and reserved
+// in the global list with one atomic per workgroup pass (the lists are
+// unordered); a full stage falls back to one atomic per entry.
+constexpr int kStage = 1024;
+
 // Mutual candidates are matched and appended to the matched list: both
 // endpoints may be on the list, so the thread that claims the smaller
 // endpoint (compare-and-swap from undecided) writes the pair, once.
@@ -279,22 +339,42 @@ __global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *rp, const 
 __global__ void __launch_bounds__(kBlock) k_mm_commit(int n, const int *list, const int *cnt,
                                                       int *mate, const int *cand, int *mlist,
                                                       int *mcnt) {
+  __shared__ int sbuf[kStage];
+  __shared__ int scnt, sbase;
   const int m = list ? *cnt : n;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
-    const int i = list ? list[q] : q;
-    if (mate[i] != kFree) continue;
-    const int c = cand[i];
-    if (c < 0) {
-      mate[i] = kSingle;
-    } else if (cand[c] == i) {
-      const int lo = c < i ? c : i, hi = c < i ? i : c;
-      if (atomicCAS(&mate[lo], kFree, hi) == kFree) {
-        mate[hi] = lo;
-        const int pos = atomicAdd(mcnt, 2);
-        mlist[pos] = lo;
-        mlist[pos + 1] = hi;
+  for (int base = blockIdx.x * blockDim.x; base < m; base += gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) scnt = 0;
+    __syncthreads();
+    const int q = base + threadIdx.x;
+    if (q < m) {
+      const int i = list ? list[q] : q;
+      if (mate[i] == kFree) {
+        const int c = cand[i];
+        if (c < 0) {
+          mate[i] = kSingle;
+        } else if (cand[c] == i) {
+          const int lo = c < i ? c : i, hi = c < i ? i : c;
+          if (atomicCAS(&mate[lo], kFree, hi) == kFree) {
+            mate[hi] = lo;
+            const int pos = atomicAdd(&scnt, 2);
+            if (pos + 1 < kStage) {
+              sbuf[pos] = lo;
+              sbuf[pos + 1] = hi;
+            } else {
+              const int g = atomicAdd(mcnt, 2);
+              mlist[g] = lo;
+              mlist[g + 1] = hi;
+            }
+          }
+        }
       }
     }
+    __syncthreads();
+    const int c = min(scnt, kStage) & ~1;
+    if (threadIdx.x == 0) sbase = c ? atomicAdd(mcnt, c) : 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < c; e += blockDim.x) mlist[sbase + e] = sbuf[e];
+    __syncthreads();
   }
 }
 
@@ -302,23 +382,43 @@ __global__ void __launch_bounds__(kBlock) k_mm_commit(int n, const int *list, co
 // list, once per round (stamp), and the thread that lists u recomputes its
 // candidate at once (mate does not change in this kernel; a new candidate is
 // undecided, so it never equals a matched vertex another thread compares
-// against).
+// against).  A team of kTeam lanes per matched vertex, lane l taking its row
+// entries l, l + kTeam, ...
+constexpr int kTeam = 8;
+
 __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const int *mcnt,
                                                       const int *rp, const int *ci,
                                                       const double *wgt, const int *mate,
                                                       int *cand, int *stamp, int round,
                                                       int *rlist, int *rcnt) {
-  const int m = *mcnt;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) {
-    const int v = mlist[q];
-    for (int k = rp[v]; k < rp[v + 1]; ++k) {
-      const int u = ci[k];
-      if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
-      if (atomicExch(&stamp[u], round) != round) {
-        cand[u] = best_candidate(u, rp, ci, wgt, mate);
-        rlist[atomicAdd(rcnt, 1)] = u;
+  __shared__ int sbuf[kStage];
+  __shared__ int scnt, sbase;
+  const int64_t total = static_cast<int64_t>(*mcnt) * kTeam;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < total;
+       base += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (threadIdx.x == 0) scnt = 0;
+    __syncthreads();
+    const int64_t g = base + threadIdx.x;
+    if (g < total) {
+      const int v = mlist[g / kTeam];
+      const int l = static_cast<int>(g % kTeam);
+      for (int k = rp[v] + l; k < rp[v + 1]; k += kTeam) {
+        const int u = ci[k];
+        if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
+        if (atomicExch(&stamp[u], round) != round) {
+          cand[u] = best_candidate(u, rp, ci, wgt, mate);
+          const int pos = atomicAdd(&scnt, 1);
+          if (pos < kStage) sbuf[pos] = u;
+          else rlist[atomicAdd(rcnt, 1)] = u;
+        }
       }
     }
+    __syncthreads();
+    const int c = min(scnt, kStage);
+    if (threadIdx.x == 0) sbase = c ? atomicAdd(rcnt, c) : 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < c; e += blockDim.x) rlist[sbase + e] = sbuf[e];
+    __syncthreads();
   }
 }
 
@@ -739,8 +839,7 @@ double now_ms() {
 
 void check_flags(const dvec<int> &flags, hipStream_t s) {
   int f[4] = {0, 0, 0, 0};
-  AMG_HIP(hipMemcpyAsync(f, flags.p, sizeof(f), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  read_small(f, flags.p, sizeof(f), s);
   if (f[0]) fail(AMG_ERR_INVALID, "malformed CSR (row_ptr, column range or ordering)");
   if (f[2]) fail(AMG_ERR_NONFINITE, "non-finite matrix value");
   if (f[1]) fail(AMG_ERR_NOT_SPD, "missing or non-positive diagonal entry");
@@ -772,8 +871,7 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
                      0, s, n, S.nslices, Lv.A.rp.p, S.sptr.p, S.col.p, S.cbase.p, S.cdel.p, cnt.p);
   AMG_LAUNCH_CHECK();
   unsigned long long hc[2];
-  AMG_HIP(hipMemcpyAsync(hc, cnt.p, sizeof(hc), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  read_small(hc, cnt.p, sizeof(hc), s);
   S.nnz_compact = static_cast<int64_t>(hc[0]);
   S.groups_compact = static_cast<int64_t>(hc[1]);
   if (want_float) {
@@ -786,23 +884,32 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
 // One pairwise step on (A, w): matching, aggregates, P values, w_c, A_c.
 struct PairStep {
   int nc = 0;
-  tvec<int> agg, rep, mate;    // temporaries of the step (stream-ordered)
-  tvec<double> p;
+  wsv<int> agg, rep, mate;     // carved from the setup workspace
+  wsv<double> p;
   dvec<double> wc;             // these two become the next level
   DevCSR Ac;
 };
 
-void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &out, Timing &tm) {
+// Workspace bytes of one pairwise step on (n rows, nnz entries): matching
+// arrays, aggregation, the pair's outputs, the Galerkin staging (at most n
+// coarse rows of kRapReg slots) and the general-path terms (at most nnz).
+size_t pair_workspace_bytes(int64_t n, int64_t nnz) {
+  return static_cast<size_t>(264 * n + 28 * nnz) + 64 * 256 + 4096;
+}
+
+void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &out, Timing &tm,
+                   Arena &ws) {
   const int n = A.n;
   const dim3 g = grid_for(n), b(kBlock);
   double t0 = now_ms();
-  tvec<double> d(n, s), wgt(A.nnz, s);
+  ws.reserve(pair_workspace_bytes(n, A.nnz));
+  wsv<double> d(ws, n), wgt(ws, A.nnz);
   hipLaunchKernelGGL(k_diag, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p);
   AMG_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
   AMG_LAUNCH_CHECK();
-  out.mate.alloc(n, s);
-  tvec<int> cand(n, s), stamp(n, s), rlist(n, s), mbuf0(n, s), mbuf1(n, s);
+  out.mate = wsv<int>(ws, n);
+  wsv<int> cand(ws, n), stamp(ws, n), rlist(ws, n), mbuf0(ws, n), mbuf1(ws, n);
   int *mbuf[2] = {mbuf0.p, mbuf1.p};
   hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, out.mate.p, kFree);
   hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, stamp.p, -1);
@@ -814,7 +921,7 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   // entries bound every list; matched lists alternate between two buffers.
   const int kBatch = 16;   // even: round 0 of every batch reads mbuf[0]
   const dim3 gl(static_cast<unsigned>(std::min(1024, std::max(1, ceil_div(n, kBlock)))));
-  tvec<int> cnt(2 * kBatch + 2, s);
+  wsv<int> cnt(ws, 2 * kBatch + 2);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (2 * kBatch + 2), s));
   hipLaunchKernelGGL(k_mm_cand, gl, b, 0, s, n, A.rp.p, A.ci.p, wgt.p, out.mate.p, cand.p);
   hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, nullptr, nullptr, out.mate.p, cand.p, mbuf[0],
@@ -842,15 +949,15 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
     AMG_HIP(hipMemcpyAsync(cnt.p, cnt.p + 2 * kBatch, sizeof(int), hipMemcpyDeviceToDevice, s));
   }
   tm.rounds += rounds;
-  tvec<int> flag(n, s), pos(n + 1, s);
+  wsv<int> flag(ws, n), pos(ws, n + 1);
   hipLaunchKernelGGL(k_agg_flags, g, b, 0, s, n, out.mate.p, flag.p);
   AMG_LAUNCH_CHECK();
   exclusive_scan(flag.p, pos.p, n, s);
   const int nc = read_int(pos.p + n, s);
   out.nc = nc;
-  out.agg.alloc(n, s);
-  out.rep.alloc(nc, s);
-  out.p.alloc(n, s);
+  out.agg = wsv<int>(ws, n);
+  out.rep = wsv<int>(ws, nc);
+  out.p = wsv<double>(ws, n);
   out.wc.alloc(nc);
   hipLaunchKernelGGL(k_agg_ids, g, b, 0, s, n, out.mate.p, pos.p, out.agg.p, out.rep.p);
   hipLaunchKernelGGL(k_pair_pvals, g, b, 0, s, n, out.mate.p, w, out.p.p);
@@ -863,16 +970,16 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
 
   // Galerkin product
   const dim3 gc = grid_for(nc);
-  tvec<int> tcnt(nc, s), toff(nc + 1, s), ucnt(nc, s), uJ(static_cast<size_t>(nc) * kRapReg, s);
-  tvec<double> uV(static_cast<size_t>(nc) * kRapReg, s);
+  wsv<int> tcnt(ws, nc), toff(ws, nc + 1), ucnt(ws, nc), uJ(ws, static_cast<size_t>(nc) * kRapReg);
+  wsv<double> uV(ws, static_cast<size_t>(nc) * kRapReg);
   hipLaunchKernelGGL(k_rap_reg, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
                      out.agg.p, out.p.p, tcnt.p, ucnt.p, uJ.p, uV.p);
   AMG_LAUNCH_CHECK();
   exclusive_scan(tcnt.p, toff.p, nc, s);
   const int nterms = read_int(toff.p + nc, s);
-  tvec<int> tJ(nterms, s);
-  tvec<unsigned long long> tK(nterms, s);
-  tvec<double> tT(nterms, s);
+  wsv<int> tJ(ws, nterms);
+  wsv<unsigned long long> tK(ws, nterms);
+  wsv<double> tT(ws, nterms);
   hipLaunchKernelGGL(k_rap_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
                      out.agg.p, out.p.p, toff.p, tJ.p, tK.p, tT.p, ucnt.p);
   AMG_LAUNCH_CHECK();
@@ -1014,6 +1121,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     }
   }
 
+  Arena ws;   // setup temporaries of the pairwise steps (largest first)
   const int maxlev = std::min(P.max_levels, AMG_MAX_LEVELS);
   while (P.precond && static_cast<int>(h->L.size()) < maxlev && h->L.back().A.n > P.coarse_max) {
     const int k = static_cast<int>(h->L.size()) - 1;
@@ -1029,7 +1137,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
       const double *wcur = owned ? cur.wc.p : h->L[k].w.p;
       if (step > 0 && Acur.n <= P.coarse_max) break;
       PairStep nxt;
-      pairwise_step(Acur, wcur, s, nxt, h->tm);
+      pairwise_step(Acur, wcur, s, nxt, h->tm, ws);
       hipLaunchKernelGGL(k_compose, grid_for(nk), dim3(kBlock), 0, s, nk, agg.p, pv.p, nxt.agg.p,
                          nxt.p.p);
       AMG_LAUNCH_CHECK();
