@@ -782,29 +782,56 @@ __global__ void k_densify(int n, const int *rp, const int *ci, const double *v, 
 // triangle.  Entry (i,l) receives the updates -L_ij L_lj for j = 0, 1, ...
 // in ascending order, the same fold as the left-looking definition
 // L_il = (a_il - sum_{j<l} L_ij L_lj) / L_ll.
-__global__ void k_cholesky(int n, double *D, int *flag) {
+// Right-looking Cholesky in one workgroup (n <= kDenseMax), in panels of
+// kPanel columns: inside a panel, step j takes the pivot, scales column j
+// (kept in LDS) and updates the panel's remaining columns; after the panel
+// the trailing lower triangle receives the panel's kPanel updates, applied
+// in column order, in one pass (a wavefront per row, lanes along the row).
+// Entry (i, l) thus receives - L_ik L_lk for k = 0, 1, ... in order: the
+// fold of the column-by-column definition.
+constexpr int kPanel = 8;
+
+__global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int *flag) {
   __shared__ int bad;
+  __shared__ double col[kPanel][kDenseMax];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      const double piv = D[static_cast<int64_t>(j) * n + j];
-      if (!(piv > 0.0)) bad = 1;
-      else D[static_cast<int64_t>(j) * n + j] = sqrt(piv);
+  for (int j0 = 0; j0 < n; j0 += kPanel) {
+    const int j1 = min(n, j0 + kPanel);
+    for (int j = j0; j < j1; ++j) {
+      if (threadIdx.x == 0) {
+        const double piv = D[static_cast<int64_t>(j) * n + j];
+        if (!(piv > 0.0)) bad = 1;
+        else D[static_cast<int64_t>(j) * n + j] = sqrt(piv);
+      }
+      __syncthreads();
+      if (bad) break;
+      const double ljj = D[static_cast<int64_t>(j) * n + j];
+      double *cj = col[j - j0];
+      for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+        const double v = D[static_cast<int64_t>(i) * n + j] / ljj;
+        D[static_cast<int64_t>(i) * n + j] = v;
+        cj[i] = v;
+      }
+      __syncthreads();
+      // panel columns l in (j, j1): rows i >= l
+      for (int t = threadIdx.x; t < (j1 - j - 1) * n; t += blockDim.x) {
+        const int l = j + 1 + t / n, i = t % n;
+        if (i >= l) D[static_cast<int64_t>(i) * n + l] = D[static_cast<int64_t>(i) * n + l] - cj[i] * cj[l];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (bad) break;
-    const double ljj = D[static_cast<int64_t>(j) * n + j];
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x)
-      D[static_cast<int64_t>(i) * n + j] = D[static_cast<int64_t>(i) * n + j] / ljj;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int64_t t = threadIdx.x; t < static_cast<int64_t>(m) * m; t += blockDim.x) {
-      const int ii = static_cast<int>(t / m), ll = static_cast<int>(t % m);
-      if (ll > ii) continue;
-      const int i = j + 1 + ii, l = j + 1 + ll;
-      D[static_cast<int64_t>(i) * n + l] =
-          D[static_cast<int64_t>(i) * n + l] - D[static_cast<int64_t>(i) * n + j] * D[static_cast<int64_t>(l) * n + j];
+    // trailing block: rows i >= j1, columns l in [j1, i]
+    const int kb = j1 - j0;
+    for (int i = j1 + wid; i < n; i += nw) {
+      double *row = D + static_cast<int64_t>(i) * n;
+      for (int l = j1 + lane; l <= i; l += kWave) {
+        double x = row[l];
+        for (int k = 0; k < kb; ++k) x = x - col[k][i] * col[k][l];
+        row[l] = x;
+      }
     }
     __syncthreads();
   }
@@ -814,19 +841,61 @@ __global__ void k_cholesky(int n, double *D, int *flag) {
 // Inverse of the coarsest matrix from its Cholesky factor L (row-major lower
 // triangle of D): thread j solves L y = e_j (k ascending), then L^T x = y
 // (k descending) and stores x as column j of the column-major inverse.
-__global__ void k_chol_inverse(int n, const double *D, double *Ainv) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  double *x = Ainv + static_cast<int64_t>(j) * n;
-  for (int i = 0; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = 0; k < i; ++k) s = s - D[static_cast<int64_t>(i) * n + k] * x[k];
-    x[i] = s / D[static_cast<int64_t>(i) * n + i];
+// Columns of A^-1: lane jj of the workgroup solves L y = e_j (k ascending),
+// then L^T x = y (k descending), j = 16 g + jj -- the fold order of the
+// direct solve.  The 16 solution vectors of a workgroup live in LDS (entry k
+// of column jj at Xs[k][jj]), the factor entries are common to all lanes, and
+// terms are loaded kB at a time ahead of the sequential fold.  The whole
+// workgroup then writes the columns to Ainv (column-major: column c at
+// Ainv[c n ..]).
+constexpr int kInvCols = 16;
+
+__global__ void __launch_bounds__(kWave) k_chol_inverse(int n, const double *__restrict__ D,
+                                                        double *__restrict__ Ainv) {
+  __shared__ double Xs[kDenseMax][kInvCols];
+  const int jj = threadIdx.x, j0 = blockIdx.x * kInvCols;
+  const int j = j0 + jj;
+  constexpr int kB = 32;
+  if (jj < kInvCols && j < n) {
+    for (int i = 0; i < n; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+      const double *Li = D + static_cast<int64_t>(i) * n;
+      int k = 0;
+      for (; k + kB <= i; k += kB) {
+        double a[kB], b[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          a[u] = Li[k + u];
+          b[u] = Xs[k + u][jj];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) s = s - a[u] * b[u];
+      }
+      for (; k < i; ++k) s = s - Li[k] * Xs[k][jj];
+      Xs[i][jj] = s / Li[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = Xs[i][jj];
+      int k = n - 1;
+      for (; k - kB >= i; k -= kB) {
+        double a[kB], b[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          a[u] = D[static_cast<int64_t>(k - u) * n + i];
+          b[u] = Xs[k - u][jj];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) s = s - a[u] * b[u];
+      }
+      for (; k > i; --k) s = s - D[static_cast<int64_t>(k) * n + i] * Xs[k][jj];
+      Xs[i][jj] = s / D[static_cast<int64_t>(i) * n + i];
+    }
   }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = x[i];
-    for (int k = n - 1; k > i; --k) s = s - D[static_cast<int64_t>(k) * n + i] * x[k];
-    x[i] = s / D[static_cast<int64_t>(i) * n + i];
+  __syncthreads();
+  const int nc = min(kInvCols, n - j0);
+  for (int t = threadIdx.x; t < nc * n; t += blockDim.x) {
+    const int c = t / n, i = t % n;
+    Ainv[static_cast<int64_t>(j0 + c) * n + i] = Xs[i][c];
   }
 }
 
@@ -1186,7 +1255,7 @@ void coarse_factor(amg_hierarchy *h) {
   AMG_LAUNCH_CHECK();
   if (read_int(flag.p, s)) fail(AMG_ERR_NOT_SPD, "coarsest matrix has a non-positive Cholesky pivot");
   h->Ainv.alloc(nn);
-  hipLaunchKernelGGL(k_chol_inverse, grid_for(n), dim3(kBlock), 0, s, n, D.p, h->Ainv.p);
+  hipLaunchKernelGGL(k_chol_inverse, dim3(ceil_div(n, kInvCols)), dim3(kWave), 0, s, n, D.p, h->Ainv.p);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipStreamSynchronize(s));
 }
