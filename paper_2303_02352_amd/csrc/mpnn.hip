@@ -91,24 +91,59 @@ __global__ void k_feat2(int n, const int *__restrict__ rp, const int *__restrict
 }
 
 // ----------------------------------------------------------- aggregation
-// out_i = sum_{j != i} |a_ij| H_j / s_i, F threads per row, binary32 fold in CSR order.
+// out_i = sum_{j != i} |a_ij| H_j / s_i, binary32 fold in CSR order.  A lane
+// handles 8 features (one 16-byte load of a bfloat16 row piece), F / 8 lanes
+// per row; the row's entries are taken 8 at a time with all loads of a batch
+// in flight together.
 template <int F>
 __global__ void __launch_bounds__(kBlock) k_agg(int n, const int *__restrict__ rp,
                                                 const int *__restrict__ ci,
                                                 const double *__restrict__ v,
                                                 const float *__restrict__ s,
                                                 const bf16 *__restrict__ H, bf16 *__restrict__ out) {
+  static_assert(F % 8 == 0, "8 features per lane");
+  constexpr int LPR = F / 8;
   const int64_t t = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  const int i = static_cast<int>(t / F), f = static_cast<int>(t % F);
+  const int i = static_cast<int>(t / LPR), f0 = static_cast<int>(t % LPR) * 8;
   if (i >= n) return;
-  float acc = 0.0f;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const int j = ci[k];
-    if (j == i) continue;
-    acc = acc + static_cast<float>(fabs(v[k])) * bf2f(H[static_cast<int64_t>(j) * F + f]);
+  float acc[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc[e] = 0.0f;
+  const int kb = rp[i], ke = rp[i + 1];
+  for (int k0 = kb; k0 < ke; k0 += 8) {
+    int jv[8];
+    float av[8];
+    uint4 hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      jv[u] = -1;
+      if (k0 + u < ke) {
+        jv[u] = ci[k0 + u];
+        av[u] = static_cast<float>(fabs(v[k0 + u]));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jv[u] >= 0 && jv[u] != i)
+        hv[u] = *reinterpret_cast<const uint4 *>(H + static_cast<int64_t>(jv[u]) * F + f0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (jv[u] >= 0 && jv[u] != i) {
+        const unsigned w[4] = {hv[u].x, hv[u].y, hv[u].z, hv[u].w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bf16 h = static_cast<bf16>((w[e / 2] >> (16 * (e % 2))) & 0xFFFFu);
+          acc[e] = acc[e] + av[u] * bf2f(h);
+        }
+      }
+    }
   }
   const float si = s[i];
-  out[static_cast<int64_t>(i) * F + f] = f2bf(si > 0.0f ? acc / si : 0.0f);
+  unsigned o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    o[e / 2] |= static_cast<unsigned>(f2bf(si > 0.0f ? acc[e] / si : 0.0f)) << (16 * (e % 2));
+  *reinterpret_cast<uint4 *>(out + static_cast<int64_t>(i) * F + f0) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // (Ahat^T D)_i added to acc: sum_{j != i} (|a_ij| / s_j) D_j (symmetric pattern and values).
@@ -402,12 +437,12 @@ void mpnn_forward(amg_mpnn *m, const amg_csr *A, double *w_out) {
   const double *v = A->val;
   hipLaunchKernelGGL(k_feat1, grid_for(n), dim3(kBlock), 0, s, n, rp, ci, v, m->X0.p, m->s.p, m->w1.p);
   hipLaunchKernelGGL(k_feat2, grid_for(n), dim3(kBlock), 0, s, n, rp, ci, v, m->w1.p, m->X0.p);
-  hipLaunchKernelGGL(k_agg<kF0>, grid_for(static_cast<int64_t>(n) * kF0), dim3(kBlock), 0, s, n, rp, ci,
+  hipLaunchKernelGGL(k_agg<kF0>, grid_for(static_cast<int64_t>(n) * (kF0 / 8)), dim3(kBlock), 0, s, n, rp, ci,
                      v, m->s.p, m->X0.p, m->N0.p);
   const dim3 gd = grid_for(ceil_div(n, 16), kBlock / kWave);
   hipLaunchKernelGGL(k_dense<2 * kF0>, gd, dim3(kBlock), 0, s, n, m->X0.p, m->N0.p, m->Wt1.p,
                      m->theta.p + ob1, m->h1.p);
-  hipLaunchKernelGGL(k_agg<kHid>, grid_for(static_cast<int64_t>(n) * kHid), dim3(kBlock), 0, s, n, rp,
+  hipLaunchKernelGGL(k_agg<kHid>, grid_for(static_cast<int64_t>(n) * (kHid / 8)), dim3(kBlock), 0, s, n, rp,
                      ci, v, m->s.p, m->h1.p, m->N1.p);
   hipLaunchKernelGGL(k_dense<2 * kHid>, gd, dim3(kBlock), 0, s, n, m->h1.p, m->N1.p, m->Wt2.p,
                      m->theta.p + ob2, m->h2.p);

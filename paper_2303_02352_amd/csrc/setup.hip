@@ -841,62 +841,112 @@ __global__ void __launch_bounds__(1024) k_cholesky(int n, double *D, int *flag) 
 // Inverse of the coarsest matrix from its Cholesky factor L (row-major lower
 // triangle of D): thread j solves L y = e_j (k ascending), then L^T x = y
 // (k descending) and stores x as column j of the column-major inverse.
-// Columns of A^-1: lane jj of the workgroup solves L y = e_j (k ascending),
-// then L^T x = y (k descending), j = 16 g + jj -- the fold order of the
-// direct solve.  The 16 solution vectors of a workgroup live in LDS (entry k
-// of column jj at Xs[k][jj]), the factor entries are common to all lanes, and
-// terms are loaded kB at a time ahead of the sequential fold.  The whole
-// workgroup then writes the columns to Ainv (column-major: column c at
-// Ainv[c n ..]).
+// Columns of A^-1: lane jj (< kInvCols) of the one-wavefront workgroup
+// solves L y = e_j (k ascending), then L^T x = y (k descending), j = 16 g + jj
+// -- the fold order of the direct solve.  The 16 solution vectors live in LDS
+// (entry k of column jj at Xs[k][jj]); the factor row needed at step i (row i
+// of L forward, row i of L^T = Dt backward) is in LDS too, the next one
+// loaded into registers by the whole wavefront during the current fold.
+// Terms are read kB at a time ahead of the sequential fold.  The workgroup
+// finally writes its columns to Ainv (column-major: column c at Ainv[c n ..]).
 constexpr int kInvCols = 16;
 
+template <bool kBack>
+__device__ __forceinline__ void inv_fetch(const double *__restrict__ M, int n, int row, int lo,
+                                          int hi, double (&pre)[kDenseMax / kWave]) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kDenseMax / kWave; ++q) {
+    const int idx = q * kWave + lane;
+    if (idx >= lo && idx <= hi) pre[q] = M[static_cast<int64_t>(row) * n + idx];
+  }
+}
+
+__device__ __forceinline__ void inv_store(double *Lr, int lo, int hi,
+                                          const double (&pre)[kDenseMax / kWave]) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kDenseMax / kWave; ++q) {
+    const int idx = q * kWave + lane;
+    if (idx >= lo && idx <= hi) Lr[idx] = pre[q];
+  }
+}
+
 __global__ void __launch_bounds__(kWave) k_chol_inverse(int n, const double *__restrict__ D,
+                                                        const double *__restrict__ Dt,
                                                         double *__restrict__ Ainv) {
   __shared__ double Xs[kDenseMax][kInvCols];
+  __shared__ double Lr[2][kDenseMax];
   const int jj = threadIdx.x, j0 = blockIdx.x * kInvCols;
   const int j = j0 + jj;
+  const bool act = jj < kInvCols && j < n;
   constexpr int kB = 32;
-  if (jj < kInvCols && j < n) {
-    for (int i = 0; i < n; ++i) {
+  double pre[kDenseMax / kWave];
+  // forward: step i uses row i of L, entries 0..i
+  inv_fetch<false>(D, n, 0, 0, 0, pre);
+  inv_store(Lr[0], 0, 0, pre);
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {
+    const double *L = Lr[i & 1];
+    if (i + 1 < n) inv_fetch<false>(D, n, i + 1, 0, i + 1, pre);
+    if (act) {
       double s = (i == j) ? 1.0 : 0.0;
-      const double *Li = D + static_cast<int64_t>(i) * n;
       int k = 0;
       for (; k + kB <= i; k += kB) {
         double a[kB], b[kB];
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
-          a[u] = Li[k + u];
+          a[u] = L[k + u];
           b[u] = Xs[k + u][jj];
         }
 #pragma unroll
         for (int u = 0; u < kB; ++u) s = s - a[u] * b[u];
       }
-      for (; k < i; ++k) s = s - Li[k] * Xs[k][jj];
-      Xs[i][jj] = s / Li[i];
+      for (; k < i; ++k) s = s - L[k] * Xs[k][jj];
+      Xs[i][jj] = s / L[i];
     }
-    for (int i = n - 1; i >= 0; --i) {
+    if (i + 1 < n) inv_store(Lr[(i + 1) & 1], 0, i + 1, pre);
+    __syncthreads();
+  }
+  // backward: step i uses row i of L^T (column i of L), entries i..n-1
+  inv_fetch<true>(Dt, n, n - 1, n - 1, n - 1, pre);
+  inv_store(Lr[(n - 1) & 1], n - 1, n - 1, pre);
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const double *L = Lr[i & 1];
+    if (i > 0) inv_fetch<true>(Dt, n, i - 1, i - 1, n - 1, pre);
+    if (act) {
       double s = Xs[i][jj];
       int k = n - 1;
       for (; k - kB >= i; k -= kB) {
         double a[kB], b[kB];
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
-          a[u] = D[static_cast<int64_t>(k - u) * n + i];
+          a[u] = L[k - u];
           b[u] = Xs[k - u][jj];
         }
 #pragma unroll
         for (int u = 0; u < kB; ++u) s = s - a[u] * b[u];
       }
-      for (; k > i; --k) s = s - D[static_cast<int64_t>(k) * n + i] * Xs[k][jj];
-      Xs[i][jj] = s / D[static_cast<int64_t>(i) * n + i];
+      for (; k > i; --k) s = s - L[k] * Xs[k][jj];
+      Xs[i][jj] = s / L[i];
     }
+    if (i > 0) inv_store(Lr[(i - 1) & 1], i - 1, n - 1, pre);
+    __syncthreads();
   }
-  __syncthreads();
   const int nc = min(kInvCols, n - j0);
   for (int t = threadIdx.x; t < nc * n; t += blockDim.x) {
     const int c = t / n, i = t % n;
     Ainv[static_cast<int64_t>(j0 + c) * n + i] = Xs[i][c];
   }
+}
+
+// out = in^T for an n x n row-major matrix.
+__global__ void k_transpose_sq(int n, const double *__restrict__ in, double *__restrict__ out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(n) * n) return;
+  const int r = static_cast<int>(t / n), c = static_cast<int>(t % n);
+  out[static_cast<int64_t>(c) * n + r] = in[t];
 }
 
 // --------------------------------------------------------- host helpers
@@ -1255,7 +1305,10 @@ void coarse_factor(amg_hierarchy *h) {
   AMG_LAUNCH_CHECK();
   if (read_int(flag.p, s)) fail(AMG_ERR_NOT_SPD, "coarsest matrix has a non-positive Cholesky pivot");
   h->Ainv.alloc(nn);
-  hipLaunchKernelGGL(k_chol_inverse, dim3(ceil_div(n, kInvCols)), dim3(kWave), 0, s, n, D.p, h->Ainv.p);
+  dvec<double> Dt(nn);
+  hipLaunchKernelGGL(k_transpose_sq, grid_for(nn), dim3(kBlock), 0, s, n, D.p, Dt.p);
+  hipLaunchKernelGGL(k_chol_inverse, dim3(ceil_div(n, kInvCols)), dim3(kWave), 0, s, n, D.p, Dt.p,
+                     h->Ainv.p);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipStreamSynchronize(s));
 }
