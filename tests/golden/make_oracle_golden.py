@@ -2,8 +2,8 @@
 
 Runs the oracle (and the seeded input generators) on the full-size
 workloads whose end-to-end results the GPU tests cannot recompute within a
-test's time limit, and stores iteration counts, residuals and hierarchy
-sizes.  Usage: python tests/golden/make_oracle_golden.py
+test's time limit, and stores iteration counts, residuals, hierarchy sizes and sampled entries
+of one V-cycle (binary64 and binary32) as hex floats.  Usage: python tests/golden/make_oracle_golden.py
 """
 import json
 import os
@@ -19,7 +19,17 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 
-def run(name, A, seed, params):
+# One V-cycle on a seeded residual, sampled: VCYCLE_SEED feeds the residual,
+# SAMPLE_SEED the row indices (SAMPLES of them, plus the first and last row).
+VCYCLE_SEED, SAMPLE_SEED, SAMPLES = 77, 78, 256
+
+
+def sample_rows(n):
+    idx = np.floor(W.uniform(SAMPLE_SEED, SAMPLES) * n).astype(np.int64)
+    return sorted(set(idx.tolist()) | {0, n - 1})
+
+
+def run(name, A, seed, params, f32=False):
     t0 = time.time()
     xs, b = W.manufactured_rhs(A, seed)
     H = oracle.Hierarchy(A, params)
@@ -27,18 +37,27 @@ def run(name, A, seed, params):
     x, it, rel, st = H.pcg(b, rtol=1e-6, maxit=1000)
     t2 = time.time()
     true_rel = float(np.linalg.norm(b - A.scipy() @ x) / np.linalg.norm(b))
+    r = W.uniform_pm1(VCYCLE_SEED, A.n)
+    rows = sample_rows(A.n)
+    z = H.vcycle(r)
     rec = dict(workload=name, seed=seed, status=st, iterations=it, relres=rel, true_relres=true_rel,
                levels=[list(s) for s in H.sizes()], opc=H.opc(), oracle_setup_s=t1 - t0,
-               oracle_solve_s=t2 - t1, params={k: int(v) for k, v in params.__dict__.items()})
-    print(json.dumps(rec), flush=True)
+               oracle_solve_s=t2 - t1, params={k: int(v) for k, v in params.__dict__.items()},
+               vcycle=dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z[i]).hex() for i in rows]))
+    if f32:
+        z32 = H.vcycle_f32(r)
+        rec["vcycle_f32"] = dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z32[i]).hex() for i in rows])
+        xm, itm, relm, stm = H.pcg(b, rtol=1e-6, maxit=1000, mixed=True)
+        rec["mixed"] = dict(status=stm, iterations=itm, relres=relm)
+    print(json.dumps({k: v for k, v in rec.items() if k not in ("vcycle", "vcycle_f32")}), flush=True)
     return rec
 
 
 def main():
     out = {}
-    out["poisson7_160"] = run("poisson7_160", W.poisson7(160), 2, oracle.AMGParams())
+    out["poisson7_160"] = run("poisson7_160", W.poisson7(160), 2, oracle.AMGParams(), f32=True)
     out["diffusion27_128"] = run("diffusion27_128", W.diffusion27(128, 3), 4,
-                                 oracle.AMGParams(smooth_vec=1))
+                                 oracle.AMGParams(smooth_vec=1), f32=True)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_full_size.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
