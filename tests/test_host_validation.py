@@ -1,0 +1,72 @@
+"""Host-side argument checks of the C ABI (CPU only: every case below is
+rejected before the library touches a device).
+
+Empty and malformed CSR headers, NULL arguments and out-of-range parameters
+must come back as AMG_ERR_INVALID with a message and no hierarchy; the status
+strings cover every code the header defines.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import paper_2303_02352_amd as amd
+
+
+def _setup(A, p):
+    h = C.c_void_p()
+    st = amd.load().amg_setup(C.byref(A), C.byref(p), C.byref(h))
+    return st, h
+
+
+def _csr(n, nnz, arrays=True):
+    # the header is rejected before any array is read: small arrays suffice
+    rp = np.zeros(max(n, 0) + 1, dtype=np.int32)
+    ci = np.zeros(8, dtype=np.int32)
+    va = np.ones(8)
+    keep = (rp, ci, va)
+    if not arrays:
+        return amd.amg_csr(n, nnz, None, None, None, 0), keep
+    return amd.amg_csr(n, nnz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, 0), keep
+
+
+@pytest.mark.parametrize("n,nnz,arrays", [(0, 0, True), (-3, 0, True), (4, 3, True), (4, 4, False),
+                                          (4, 2 ** 31, True)])
+def test_bad_csr_header_is_invalid(n, nnz, arrays):
+    A, keep = _csr(n, nnz, arrays)
+    st, h = _setup(A, amd.default_params())
+    assert st == amd.AMG_ERR_INVALID and not h.value
+    assert amd.load().amg_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [("aggr_steps", 0), ("max_levels", 0), ("coarse_max", 0),
+                                         ("coarse_sweeps", 0), ("pre_sweeps", -1), ("post_sweeps", -1),
+                                         ("smooth_sweeps", -1), ("coarse_solver", 7), ("smooth_vec", 5),
+                                         ("smooth_vec", amd.AMG_SMOOTH_GIVEN), ("precision", 3),
+                                         ("precond", 2)])
+def test_bad_parameter_is_invalid(field, value):
+    A, keep = _csr(1, 1)
+    p = amd.default_params()
+    setattr(p, field, value)
+    st, h = _setup(A, p)
+    assert st == amd.AMG_ERR_INVALID and not h.value
+    assert amd.load().amg_last_error().decode()
+
+
+def test_null_arguments():
+    L = amd.load()
+    A, keep = _csr(1, 1)
+    p = amd.default_params()
+    h = C.c_void_p()
+    assert L.amg_setup(None, C.byref(p), C.byref(h)) == amd.AMG_ERR_INVALID
+    assert L.amg_setup(C.byref(A), None, C.byref(h)) == amd.AMG_ERR_INVALID
+    assert L.amg_setup(C.byref(A), C.byref(p), None) == amd.AMG_ERR_INVALID
+    assert L.amg_params_default(None) == amd.AMG_ERR_INVALID
+
+
+def test_status_strings_cover_every_code():
+    L = amd.load()
+    codes = [amd.AMG_OK, amd.AMG_NOT_CONVERGED, amd.AMG_ERR_INVALID, amd.AMG_ERR_NOT_SPD,
+             amd.AMG_ERR_NONFINITE, amd.AMG_ERR_NOMEM, amd.AMG_ERR_DEVICE, amd.AMG_ERR_UNSUPPORTED]
+    msgs = [L.amg_strerror(c).decode() for c in codes]
+    assert all(msgs) and len(set(msgs)) == len(codes)
