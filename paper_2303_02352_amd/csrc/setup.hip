@@ -470,55 +470,153 @@ __global__ void k_pair_restrict_w(int nc, const int *rep, const int *mate, const
 // agg(j) = J.  Terms of one coarse entry are folded in ascending (u, v),
 // u = the fine index on the side of min(I,J), v = the other, so entries
 // (I,J) and (J,I) fold identical term sequences (bitwise-symmetric A_c).
-__device__ __forceinline__ bool term_lt(int Ja, unsigned long long ka, int Jb,
-                                        unsigned long long kb) {
-  return Ja < Jb || (Ja == Jb && ka < kb);
+// Within one coarse row a term's position in that order is the 64-bit key
+// (J << 32) | k32, J = agg(j) for the fine entry a_ij, i = member m of the
+// pair (0 = lo, 1 = hi): for J >= I, u = i and v = j, so the lo terms come
+// first, each member's by j, and k32 = m * 2^31 + j; for J < I, u = j and
+// v = i, so k32 = 2 j + m.  Keys of one row are distinct (a fine row holds a
+// column once).
+__device__ __forceinline__ unsigned long long rap_key(int I, int J, int j, int m) {
+  const unsigned k32 = (I <= J) ? ((static_cast<unsigned>(m) << 31) | static_cast<unsigned>(j))
+                                : ((static_cast<unsigned>(j) << 1) | static_cast<unsigned>(m));
+  return (static_cast<unsigned long long>(static_cast<unsigned>(J)) << 32) | k32;
 }
 
-__global__ void k_rap_terms(int nc, const int *rep, const int *mate, const int *rp, const int *ci,
-                            const double *v, const int *agg, const double *p, const int *toff,
-                            int *tJ, unsigned long long *tK, double *tT, int *ucnt) {
+// Rows wider than the wavefront sort takes: one thread inserts the row's
+// terms into key order in (tK, tT) at toff[I], then folds the runs of equal J
+// in place, leaving the row's entries in (tJ, tT) from toff[I] on.
+constexpr int kRapWaveMax = 512;
+
+__global__ void __launch_bounds__(kBlock) k_rap_terms(int nc, const int *rep, const int *mate,
+                                                      const int *rp, const int *ci, const double *v,
+                                                      const int *agg, const double *p,
+                                                      const int *toff, int *tJ,
+                                                      unsigned long long *tK, double *tT,
+                                                      int *ucnt) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
-  if (toff[I] == toff[I + 1]) return;   // row sorted in registers (k_rap_reg)
+  const int base = toff[I], c = toff[I + 1] - base;
+  if (c <= kRapWaveMax) return;   // register or wavefront sort
   const int lo = rep[I], hi = mate[lo];
-  const int base = toff[I];
-  int c = 0;
+  int q = 0;
   for (int m = 0; m < 2; ++m) {
     const int i = (m == 0) ? lo : hi;
     if (i < 0) break;
     const double pi = p[i];
     for (int k = rp[i]; k < rp[i + 1]; ++k) {
       const int j = ci[k];
-      const int J = agg[j];
-      const unsigned u = static_cast<unsigned>(I <= J ? i : j);
-      const unsigned w2 = static_cast<unsigned>(I <= J ? j : i);
-      const unsigned long long key = (static_cast<unsigned long long>(u) << 32) | w2;
+      const unsigned long long key = rap_key(I, agg[j], j, m);
       const double t = (pi * p[j]) * v[k];
-      // insertion into the sorted prefix [base, base + c)
-      int q = c;
-      while (q > 0 && term_lt(J, key, tJ[base + q - 1], tK[base + q - 1])) {
-        tJ[base + q] = tJ[base + q - 1];
-        tK[base + q] = tK[base + q - 1];
-        tT[base + q] = tT[base + q - 1];
-        --q;
+      int r = q;
+      while (r > 0 && key < tK[base + r - 1]) {
+        tK[base + r] = tK[base + r - 1];
+        tT[base + r] = tT[base + r - 1];
+        --r;
       }
-      tJ[base + q] = J;
-      tK[base + q] = key;
-      tT[base + q] = t;
-      ++c;
+      tK[base + r] = key;
+      tT[base + r] = t;
+      ++q;
     }
   }
+  // runs of equal J, each folded from its first term; the u-th run's entry
+  // overwrites slot u, which no later run reads
   int u = 0;
-  for (int q = 0; q < c; ++q)
-    if (q == 0 || tJ[base + q] != tJ[base + q - 1]) ++u;
+  for (int r = 0; r < c;) {
+    const unsigned J = static_cast<unsigned>(tK[base + r] >> 32);
+    double sum = tT[base + r];
+    int e = r + 1;
+    while (e < c && static_cast<unsigned>(tK[base + e] >> 32) == J) { sum = sum + tT[base + e]; ++e; }
+    tJ[base + u] = static_cast<int>(J);
+    tT[base + u] = sum;
+    ++u;
+    r = e;
+  }
   ucnt[I] = u;
+}
+
+// Rows of kRapReg < c <= kRapWaveMax terms: one wavefront per coarse row.
+// The terms go to LDS under their keys, padded to a power of two with keys
+// that sort last; a bitonic network sorts them; the lane holding a run's
+// first term folds the run in order and writes it to (tJ, tT) at toff[I] +
+// the run's rank (a ballot prefix count).
+__global__ void __launch_bounds__(kWave) k_rap_wave(int nc, const int *__restrict__ rep,
+                                                    const int *__restrict__ mate,
+                                                    const int *__restrict__ rp,
+                                                    const int *__restrict__ ci,
+                                                    const double *__restrict__ v,
+                                                    const int *__restrict__ agg,
+                                                    const double *__restrict__ p,
+                                                    const int *__restrict__ toff,
+                                                    int *__restrict__ tJ, double *__restrict__ tT,
+                                                    int *__restrict__ ucnt) {
+  __shared__ unsigned long long sk[kRapWaveMax];
+  __shared__ double st[kRapWaveMax];
+  const int lane = threadIdx.x;
+  for (int I = blockIdx.x; I < nc; I += gridDim.x) {   // uniform in the workgroup
+    const int base = toff[I], c = toff[I + 1] - base;
+    if (c == 0 || c > kRapWaveMax) continue;
+    const int lo = rep[I], hi = mate[lo];
+    const int b0 = rp[lo], n0 = rp[lo + 1] - b0;
+    const int b1 = hi >= 0 ? rp[hi] : 0;
+    const double plo = p[lo], phi = hi >= 0 ? p[hi] : 0.0;
+    int P = kWave / 2;
+    while (P < c) P <<= 1;
+    for (int q = lane; q < P; q += kWave) {
+      unsigned long long key = ~0ull;
+      double t = 0.0;
+      if (q < c) {
+        const int m = q < n0 ? 0 : 1;
+        const int e = m ? b1 + (q - n0) : b0 + q;
+        const int j = ci[e];
+        key = rap_key(I, agg[j], j, m);
+        t = ((m ? phi : plo) * p[j]) * v[e];
+      }
+      sk[q] = key;
+      st[q] = t;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int t = lane; t < (P >> 1); t += kWave) {
+          const int a = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+          const int bq = a + jj;
+          const unsigned long long ka = sk[a], kb = sk[bq];
+          const bool sw = ((a & k) == 0) ? (kb < ka) : (ka < kb);
+          if (sw) {
+            const double ta = st[a], tb = st[bq];
+            sk[a] = kb;
+            sk[bq] = ka;
+            st[a] = tb;
+            st[bq] = ta;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    int done = 0;
+    for (int q0 = 0; q0 < c; q0 += kWave) {
+      const int q = q0 + lane;
+      const unsigned J = q < c ? static_cast<unsigned>(sk[q] >> 32) : 0u;
+      const bool head = q < c && (q == 0 || static_cast<unsigned>(sk[q - 1] >> 32) != J);
+      const unsigned long long mask = __ballot(head);
+      if (head) {
+        double sum = st[q];
+        for (int r = q + 1; r < c && static_cast<unsigned>(sk[r] >> 32) == J; ++r) sum = sum + st[r];
+        const int rank = done + __popcll(mask & ((1ull << lane) - 1ull));
+        tJ[base + rank] = static_cast<int>(J);
+        tT[base + rank] = sum;
+      }
+      done += __popcll(mask);
+    }
+    if (lane == 0) ucnt[I] = done;
+    __syncthreads();   // the next row overwrites sk, st
+  }
 }
 
 // Coarse rows whose pair has at most kRapReg terms (the common case) sort
 // and fold their terms in registers: gather, a bitonic network on the
 // (J, key) order, then the runs of equal J folded from their first term --
-// the order and the fold of k_rap_terms + k_rap_fold.  The row's entries go
+// the order and the fold of the wide-row kernels.  The row's entries go
 // to slots [I * kRapReg, I * kRapReg + ucnt[I]) of (uJ, uV) and are copied
 // to their CSR place once the row lengths are scanned (k_rap_place).  Wider
 // rows get tcnt = their term count and take the general path; narrow rows
@@ -622,36 +720,22 @@ __global__ void __launch_bounds__(kBlock) k_rap_reg(int nc, const int *__restric
   ucnt[I] = u;
 }
 
-__global__ void k_rap_place(int nc, const int *__restrict__ tcnt_off, const int *__restrict__ uJ,
-                            const double *__restrict__ uV, const int *__restrict__ crp,
+// Entries of narrow rows from slots I * kRapReg of (uJ, uV), of wide rows
+// from toff[I] of (tJ, tT), to their CSR place.
+__global__ void k_rap_place(int nc, const int *__restrict__ toff, const int *__restrict__ uJ,
+                            const double *__restrict__ uV, const int *__restrict__ tJ,
+                            const double *__restrict__ tT, const int *__restrict__ crp,
                             int *__restrict__ cci, double *__restrict__ cv) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
-  if (tcnt_off[I] != tcnt_off[I + 1]) return;   // general path
-  const int64_t base = static_cast<int64_t>(I) * kRapReg;
+  const bool wide = toff[I] != toff[I + 1];
+  const int64_t base = wide ? static_cast<int64_t>(toff[I]) : static_cast<int64_t>(I) * kRapReg;
+  const int *sJ = wide ? tJ : uJ;
+  const double *sV = wide ? tT : uV;
   const int b = crp[I], e = crp[I + 1];
   for (int q = 0; q < e - b; ++q) {
-    cci[b + q] = uJ[base + q];
-    cv[b + q] = uV[base + q];
-  }
-}
-
-__global__ void k_rap_fold(int nc, const int *toff, const int *tJ, const double *tT,
-                           const int *crp, int *cci, double *cv) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  if (toff[I] == toff[I + 1]) return;   // row folded in registers
-  const int b = toff[I], e = toff[I + 1];
-  int out = crp[I];
-  for (int q = b; q < e;) {
-    const int J = tJ[q];
-    double s = tT[q];
-    int r = q + 1;
-    while (r < e && tJ[r] == J) { s = s + tT[r]; ++r; }
-    cci[out] = J;
-    cv[out] = s;
-    ++out;
-    q = r;
+    cci[b + q] = sJ[base + q];
+    cv[b + q] = sV[base + q];
   }
 }
 
@@ -1099,19 +1183,23 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   wsv<int> tJ(ws, nterms);
   wsv<unsigned long long> tK(ws, nterms);
   wsv<double> tT(ws, nterms);
-  hipLaunchKernelGGL(k_rap_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
-                     out.agg.p, out.p.p, toff.p, tJ.p, tK.p, tT.p, ucnt.p);
-  AMG_LAUNCH_CHECK();
+  if (nterms > 0) {
+    const unsigned gw = static_cast<unsigned>(std::min(nc, 1 << 20));
+    hipLaunchKernelGGL(k_rap_wave, dim3(gw), dim3(kWave), 0, s, nc, out.rep.p,
+                       out.mate.p, A.rp.p, A.ci.p, A.v.p, out.agg.p, out.p.p, toff.p, tJ.p, tT.p,
+                       ucnt.p);
+    hipLaunchKernelGGL(k_rap_terms, gc, b, 0, s, nc, out.rep.p, out.mate.p, A.rp.p, A.ci.p, A.v.p,
+                       out.agg.p, out.p.p, toff.p, tJ.p, tK.p, tT.p, ucnt.p);
+    AMG_LAUNCH_CHECK();
+  }
   out.Ac.n = nc;
   out.Ac.rp.alloc(nc + 1);
   exclusive_scan(ucnt.p, out.Ac.rp.p, nc, s);
   out.Ac.nnz = read_int(out.Ac.rp.p + nc, s);
   out.Ac.ci.alloc(out.Ac.nnz);
   out.Ac.v.alloc(out.Ac.nnz);
-  hipLaunchKernelGGL(k_rap_fold, gc, b, 0, s, nc, toff.p, tJ.p, tT.p, out.Ac.rp.p, out.Ac.ci.p,
-                     out.Ac.v.p);
-  hipLaunchKernelGGL(k_rap_place, gc, b, 0, s, nc, toff.p, uJ.p, uV.p, out.Ac.rp.p, out.Ac.ci.p,
-                     out.Ac.v.p);
+  hipLaunchKernelGGL(k_rap_place, gc, b, 0, s, nc, toff.p, uJ.p, uV.p, tJ.p, tT.p, out.Ac.rp.p,
+                     out.Ac.ci.p, out.Ac.v.p);
   AMG_LAUNCH_CHECK();
   AMG_HIP(hipStreamSynchronize(s));
   tm.rap_ms += now_ms() - t1;

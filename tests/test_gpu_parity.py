@@ -40,6 +40,9 @@ CASES = {
     # rows past 70304 shuffled: slot groups spanning more than 16 bits of
     # column offsets next to compact ones
     "poisson52_halfperm": (lambda: W.permute_tail(W.poisson7(52), 9, 52 ** 3 // 2), {}),
+    # long rows: coarse rows of more than 512 Galerkin terms (one-thread
+    # sort), of 17..512 (wavefront sort) and of at most 16 (registers)
+    "poisson12_hubs": (lambda: W.with_hubs(W.poisson7(12), [(100, 2), (900, 5), (1500, 13)]), {}),
 }
 
 

@@ -186,9 +186,19 @@ def test_two_steps_give_boxes_and_box_stencil():
     assert np.allclose(Ac, Pbar.T @ A.scipy().toarray() @ Pbar, atol=1e-13, rtol=0)
 
 
-@pytest.mark.parametrize("maker", ["diffusion27", "lognormal7"])
+@pytest.mark.parametrize("maker", ["diffusion27", "lognormal7", "hubs"])
 def test_galerkin_dense_variable_coefficients(maker):
-    A = W.diffusion27(5, 3) if maker == "diffusion27" else W.lognormal7(6, 7, ell=2.0)
+    if maker == "diffusion27":
+        A = W.diffusion27(5, 3)
+    elif maker == "lognormal7":
+        A = W.lognormal7(6, 7, ell=2.0)
+    else:   # two long rows (108 and 72 entries) on a 7-point grid
+        A = W.with_hubs(W.poisson7(6), [(10, 2), (150, 3)])
+        assert np.diff(A.row_ptr).max() >= 100
+        S = A.scipy()
+        assert abs(S - S.T).max() == 0.0
+        d = S.diagonal()
+        assert np.all(d >= np.asarray(abs(S).sum(axis=1)).ravel() - d - 1e-12)
     H = oracle.Hierarchy(A, oracle.AMGParams(aggr_steps=2, coarse_max=8, smooth_vec=1,
                                              smooth_sweeps=5))
     assert H.nlevels >= 3

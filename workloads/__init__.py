@@ -226,6 +226,36 @@ def permute_tail(A: CSR, seed: int, start: int) -> CSR:
     return CSR(n, row_ptr.astype(np.int32), c2.astype(np.int32), v2.astype(np.float64))
 
 
+def with_hubs(A: CSR, hubs, eps: float = 0.05) -> CSR:
+    """A plus dense couplings: for each (h, stride) in `hubs`, vertex h gets
+    the entry -eps to every stride-th vertex j != h (both triangles), and the
+    diagonals of h and j grow by the same amount, so a diagonally dominant A
+    stays symmetric and diagonally dominant.  Rows of the hubs are long."""
+    n = A.n
+    rows = [np.repeat(np.arange(n, dtype=np.int64), np.diff(A.row_ptr))]
+    cols = [A.col.astype(np.int64)]
+    vals = [A.val.astype(np.float64)]
+    for h, stride in hubs:
+        js = np.arange(0, n, stride, dtype=np.int64)
+        js = js[js != h]
+        rows += [np.full(js.size, h), js, np.array([h]), js]
+        cols += [js, np.full(js.size, h), np.array([h]), js]
+        vals += [np.full(js.size, -eps), np.full(js.size, -eps), np.array([eps * js.size]),
+                 np.full(js.size, eps)]
+    r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    first = np.ones(r.size, dtype=bool)
+    first[1:] = (r[1:] != r[:-1]) | (c[1:] != c[:-1])
+    grp = np.cumsum(first) - 1
+    val = np.zeros(int(first.sum()))
+    np.add.at(val, grp, v)
+    r, c = r[first], c[first]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=row_ptr[1:])
+    return CSR(n, row_ptr.astype(np.int32), c.astype(np.int32), val)
+
+
 def spmv_input(A: CSR, x: np.ndarray) -> np.ndarray:
     """b = A x for building right-hand sides (scipy's CSR product)."""
     return A.scipy() @ x
