@@ -239,6 +239,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--values", choices=["auto", "plain"], default="auto",
+                    help="matrix values of the solve kernels: coded where a level has at most "
+                         "256 distinct values (auto), or plain binary64 arrays")
     ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160"],
                     help="only: run one form's leg and print its record (for profiling)")
     ap.add_argument("--kernel-profile", action="store_true",
@@ -271,9 +274,10 @@ def main():
     stream = torch.cuda.Stream()          # default priority
     torch.cuda.synchronize()
 
+    coding = amd.AMG_VALUES_AUTO if args.values == "auto" else amd.AMG_VALUES_PLAIN
     if args.kernel_profile:
         with torch.cuda.stream(stream):
-            H = amd.Hierarchy(rp, ci, va)
+            H = amd.Hierarchy(rp, ci, va, value_coding=coding)
             ms, by = H.time_kernel(amd.KERNEL_SWEEP, 0, args.kernel_reps)
             src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
             dst = torch.empty_like(src)
@@ -284,10 +288,10 @@ def main():
                           "source_hash": kernel_source_hash()}), flush=True)
         return
 
-    def one_step(precision=amd.AMG_PREC_DOUBLE):
+    def one_step(precision=amd.AMG_PREC_DOUBLE, value_coding=coding):
         with torch.cuda.stream(stream):
             t0 = time.perf_counter()
-            H = amd.Hierarchy(rp, ci, va, precision=precision)
+            H = amd.Hierarchy(rp, ci, va, precision=precision, value_coding=value_coding)
             t1 = time.perf_counter()
             x = torch.zeros(A.n, dtype=torch.float64, device=dev)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -348,6 +352,20 @@ def main():
     H.close()
 
     forms = {}
+    if not args.no_forms and coding == amd.AMG_VALUES_AUTO:
+        # the same solve with every level read from plain binary64 value arrays
+        log("plain-value comparison")
+        Hq, xq, rq = one_step(value_coding=amd.AMG_VALUES_PLAIN)
+        Hq.close()
+        Hq, xq, rq = one_step(value_coding=amd.AMG_VALUES_PLAIN)
+        msq, byq = Hq.time_kernel(amd.KERNEL_SWEEP, 0, args.kernel_reps)
+        forms["plain_values"] = dict(solve_s=rq["solve_s"], setup_s=rq["setup_s"], iters=rq["iters"],
+                                     bitwise_equal_solution=bool(torch.equal(xq, x)),
+                                     coded_speedup_solve=rq["solve_s"] / solve_s,
+                                     sweep=dict(avg_ms=msq, bytes=byq, gbps=byq / (msq * 1e-3) / 1e9,
+                                                frac=byq / (msq * 1e-3) / 1e9 / HBM_PEAK_GBPS))
+        Hq.close()
+        log("plain values", json.dumps(forms["plain_values"]))
     if not args.no_forms:
         log("mixed-precision form")
         Hm, xm, rm = one_step(amd.AMG_PREC_MIXED)
@@ -393,13 +411,15 @@ def main():
         "config": {"workload": "3D Poisson 7-point 160^3 (4,096,000 rows, 28,518,400 nnz, CSR "
                                "FP64, int32 indices), b = A x*, x* ~ U[-1,1) seed 2",
                    "rtol": RTOL, "aggr_steps": 2, "coarse_max": 100, "pre_post_sweeps": [4, 4],
-                   "coarsest": "dense FP64 Cholesky", "step": "amg_setup + amg_pcg_solve"},
+                   "coarsest": "dense FP64 Cholesky", "step": "amg_setup + amg_pcg_solve",
+                   "values": args.values},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"iterations": last["iters"], "relres": last["relres"], "true_relres": true_rel,
                    "solve_s_each": [r["solve_s"] for r in recs],
                    "setup_s": setup_s, "titer_ms": solve_s / max(1, last["iters"]) * 1e3,
                    "levels": info["n"], "opc": info["opc"],
+                   "value_table_sizes": info["dict_size"],
                    "matching_rounds": info["matching_rounds"],
                    "kernels_fine_level": kt, "forms": forms,
                    "spmv_gbps": kt["spmv_dots"]["gbps"],

@@ -55,6 +55,12 @@ extern "C" {
 #define AMG_PREC_DOUBLE 0         /* everything in binary64 */
 #define AMG_PREC_MIXED 1          /* V-cycle below the coarsest level in binary32; PCG,
                                      residuals, dots and the coarsest solve in binary64 */
+/* value_coding: how the solve kernels read matrix values (results are the
+ * same bits either way) */
+#define AMG_VALUES_PLAIN 0        /* one binary64 (binary32) value per stored entry */
+#define AMG_VALUES_AUTO 1         /* a level whose stored values take at most 256 distinct
+                                     bit patterns keeps one byte per entry, an index into a
+                                     per-level table of those values; other levels plain */
 
 /* Square sparse matrix in CSR form.
  *   row_ptr: n+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
@@ -78,7 +84,7 @@ typedef struct {
  *   aggr_steps 2 (aggregates of at most 4), max_levels 40, coarse_max 100,
  *   coarse_solver CHOLESKY, coarse_sweeps 20, pre/post sweeps 4/4,
  *   smooth_vec ONES, smooth_sweeps 20, precond 1, precision DOUBLE,
- *   smooth_vector NULL, stream NULL.
+ *   value_coding AUTO, smooth_vector NULL, stream NULL.
  * The paper's own runs (Sec. 5, Appendix A) use aggr_steps 3, coarse_max
  * 40*nd, coarse_solver JACOBI with 20 sweeps. */
 typedef struct {
@@ -93,6 +99,7 @@ typedef struct {
   int32_t smooth_sweeps;   /* >= 0 */
   int32_t precond;         /* 1: AMG V-cycle; 0: B = I, plain CG (Appendix A) */
   int32_t precision;       /* AMG_PREC_* */
+  int32_t value_coding;    /* AMG_VALUES_* */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
   void *stream;            /* hipStream_t on which all work is ordered; NULL = null stream */
 } amg_params;
@@ -111,6 +118,7 @@ typedef struct {
   double setup_match_ms;        /* part spent in weights + matching + aggregation */
   double setup_rap_ms;          /* part spent in Galerkin products */
   int64_t device_bytes;         /* device memory held by the hierarchy */
+  int32_t dict_size[AMG_MAX_LEVELS]; /* distinct values of a coded level's table, 0 = plain */
 } amg_info_t;
 
 /* Fill *p with the defaults above.  Returns AMG_OK or AMG_ERR_INVALID (p NULL). */

@@ -23,6 +23,7 @@ AMG_ERR_NOMEM, AMG_ERR_DEVICE, AMG_ERR_UNSUPPORTED = -4, -5, -6
 AMG_COARSE_CHOLESKY, AMG_COARSE_JACOBI = 0, 1
 AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN = 0, 1, 2
 AMG_PREC_DOUBLE, AMG_PREC_MIXED = 0, 1
+AMG_VALUES_PLAIN, AMG_VALUES_AUTO = 0, 1
 AMG_MAX_LEVELS = 64
 KERNEL_SPMV, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_UPDATE, KERNEL_CORR_SWEEP = 0, 1, 2, 3, 4, 5
 
@@ -35,7 +36,8 @@ class amg_csr(C.Structure):
 class amg_params(C.Structure):
     _fields_ = [(f, C.c_int32) for f in (
         "aggr_steps", "max_levels", "coarse_max", "coarse_solver", "coarse_sweeps",
-        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond", "precision")] + [
+        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond", "precision",
+        "value_coding")] + [
         ("smooth_vector", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -44,7 +46,8 @@ class amg_info_t(C.Structure):
                 ("nnz", C.c_int64 * AMG_MAX_LEVELS), ("opc", C.c_double),
                 ("coarse_dense", C.c_int32), ("matching_rounds", C.c_int32),
                 ("setup_ms", C.c_double), ("setup_match_ms", C.c_double),
-                ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64)]
+                ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64),
+                ("dict_size", C.c_int32 * AMG_MAX_LEVELS)]
 
 
 class amg_batch_info_t(C.Structure):
@@ -195,7 +198,8 @@ class Hierarchy:
         return dict(levels=L, n=list(inf.n[:L]), nnz=list(inf.nnz[:L]), opc=inf.opc,
                     coarse_dense=bool(inf.coarse_dense), matching_rounds=inf.matching_rounds,
                     setup_ms=inf.setup_ms, setup_match_ms=inf.setup_match_ms,
-                    setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes)
+                    setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes,
+                    dict_size=list(inf.dict_size[:L]))
 
     def export_level(self, k) -> dict:
         inf = self.info()

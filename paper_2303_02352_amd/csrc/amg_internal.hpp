@@ -161,21 +161,57 @@ struct Sell {
   dvec<float> valf;   // binary32 copy for the mixed-precision V-cycle
   // Compact column form read by the streaming kernels: the 64 slots k of a
   // slice (one "group", index sptr[s]/64 + k) share cbase[group] = smallest
-  // column among them and keep col - cbase as 16 bits in cdel.  A slice whose
-  // group spans more than 65535 columns keeps cbase = -1 on all its groups and
-  // is read from `col`.
+  // column among them and keep col - cbase as 16 bits.  A slice whose group
+  // spans more than 65535 columns keeps cbase = -1 on all its groups and is
+  // read from `col`.  The 16-bit offsets (and the value codes below) are
+  // stored by quads: slots 4t .. 4t+3 of one lane are adjacent, so a lane
+  // reads four slots with one load.  Slot k of lane l in slice s sits at
+  // ((qptr[s] + k/4) * 64 + l) * 4 + k%4; a slice holds ceil(width/4) quads
+  // (padding slots 0).
   dvec<int> cbase;               // nslots / 64
-  dvec<unsigned short> cdel;     // nslots
+  dvec<int> qptr;                // nslices + 1 quad offsets
+  dvec<unsigned short> cdel;     // 256 per quad
+  int64_t nquads = 0;
   int64_t nnz_compact = 0;       // matrix entries in compact slices
   int64_t groups_compact = 0;    // groups of compact slices
+  // Coded values: when the slots (padding included) hold at most kDictMax
+  // distinct bit patterns, each slot's byte indexes the level's table of
+  // them, in ascending bit-pattern order (dict; dictf = its binary32 image),
+  // and the streaming kernels read codes instead of val / valf.  Codes are
+  // stored by quads like the 16-bit column offsets.  ndict = 0: plain.
+  dvec<unsigned char> code;      // 256 per quad
+  dvec<double> dict;
+  dvec<float> dictf;
+  int ndict = 0;
+};
+
+constexpr int kDictMax = 256;
+
+// Value access of a SELL matrix as the kernels see it: val, or code + dict.
+template <class T>
+struct ValRef {
+  const T *val;
+  const unsigned char *code;   // null: read val
+  const T *dict;
+  int ndict;
 };
 
 // Column access of a SELL matrix as the kernels see it.
 struct SellRef {
-  const int *sptr, *col, *cbase;
+  const int *sptr, *col, *cbase, *qptr;
   const unsigned short *cdel;   // null: all slices read `col`
 };
-inline SellRef sell_ref(const Sell &S) { return SellRef{S.sptr.p, S.col.p, S.cbase.p, S.cdel.p}; }
+inline SellRef sell_ref(const Sell &S) { return SellRef{S.sptr.p, S.col.p, S.cbase.p, S.qptr.p, S.cdel.p}; }
+template <class T>
+ValRef<T> val_ref(const Sell &S);
+template <>
+inline ValRef<double> val_ref<double>(const Sell &S) {
+  return ValRef<double>{S.val.p, S.ndict ? S.code.p : nullptr, S.dict.p, S.ndict};
+}
+template <>
+inline ValRef<float> val_ref<float>(const Sell &S) {
+  return ValRef<float>{S.valf.p, S.ndict ? S.code.p : nullptr, S.dictf.p, S.ndict};
+}
 
 struct Level {
   DevCSR A;

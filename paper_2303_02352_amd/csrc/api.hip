@@ -45,6 +45,8 @@ int check_params(const amg_params *p) {
     return set_error(AMG_ERR_INVALID, "smooth_vec = GIVEN needs smooth_vector");
   if (p->precision != AMG_PREC_DOUBLE && p->precision != AMG_PREC_MIXED)
     return set_error(AMG_ERR_INVALID, "unknown precision");
+  if (p->value_coding != AMG_VALUES_PLAIN && p->value_coding != AMG_VALUES_AUTO)
+    return set_error(AMG_ERR_INVALID, "unknown value_coding");
   if (p->precond != 0 && p->precond != 1) return set_error(AMG_ERR_INVALID, "precond must be 0 or 1");
   return AMG_OK;
 }
@@ -61,7 +63,8 @@ int64_t device_bytes(const amg_hierarchy *h) {
   for (const Level &L : h->L) {
     b += L.A.rp.bytes() + L.A.ci.bytes() + L.A.v.bytes();
     b += L.S.sptr.bytes() + L.S.col.bytes() + L.S.val.bytes() + L.S.valf.bytes();
-    b += L.S.cbase.bytes() + L.S.cdel.bytes();
+    b += L.S.cbase.bytes() + L.S.cdel.bytes() + L.S.qptr.bytes();
+    b += L.S.code.bytes() + L.S.dict.bytes() + L.S.dictf.bytes();
     b += L.dinv.bytes() + L.w.bytes() + L.dinvf.bytes() + L.agg.bytes() + L.pval.bytes();
     b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
     b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();
@@ -89,6 +92,7 @@ int amg_params_default(amg_params *p) {
   p->smooth_sweeps = 20;
   p->precond = 1;
   p->precision = AMG_PREC_DOUBLE;
+  p->value_coding = AMG_VALUES_AUTO;
   p->smooth_vector = nullptr;
   p->stream = nullptr;
   return AMG_OK;
@@ -185,6 +189,7 @@ int amg_info(const amg_hierarchy *h, amg_info_t *out) {
   for (size_t k = 0; k < h->L.size(); ++k) {
     out->n[k] = h->L[k].A.n;
     out->nnz[k] = h->L[k].A.nnz;
+    out->dict_size[k] = h->L[k].S.ndict;
     tot += static_cast<double>(h->L[k].A.nnz);
   }
   out->opc = tot / static_cast<double>(h->L[0].A.nnz);

@@ -956,6 +956,7 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
     H[sid] = new amg_hierarchy();
     H[sid]->p = bt->p;
     H[sid]->p.smooth_vector = nullptr;
+    H[sid]->p.value_coding = AMG_VALUES_PLAIN;   // the batched kernels read plain values
     if (bt->p.smooth_vec == AMG_SMOOTH_GIVEN) fail(AMG_ERR_UNSUPPORTED, "batched setup takes no given smooth vector");
     H[sid]->stream = s;
     build_hierarchy(H[sid], &A[sid]);

@@ -825,22 +825,29 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_sell_compact(int n, int nslices, const int *rp,
-                                                         const int *sptr, const int *scol,
-                                                         int *cbase, unsigned short *cdel,
+                                                         const int *sptr, const int *qptr,
+                                                         const int *scol, int *cbase,
+                                                         unsigned short *cdel,
                                                          unsigned long long *count) {
   const int s = blockIdx.x * (kBlock / kWave) + static_cast<int>(threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (s >= nslices) return;   // whole wavefront
   const int b = sptr[s], width = (sptr[s + 1] - b) / kSlice;
+  const int64_t q0 = static_cast<int64_t>(qptr[s]) * kSlice;
   bool fits = true;
   for (int k = 0; k < width; ++k) {
     const int c = scol[b + k * kSlice + lane];
     fits = fits && (wave_max_i(c) - wave_min_i(c) <= 65535);
   }
-  for (int k = 0; k < width; ++k) {
+  for (int k = 0; k < 4 * (qptr[s + 1] - qptr[s]); ++k) {
+    const int64_t at = ((q0 + (k >> 2) * kSlice) + lane) * 4 + (k & 3);
+    if (k >= width) {
+      cdel[at] = 0;
+      continue;
+    }
     const int c = scol[b + k * kSlice + lane];
     const int mn = wave_min_i(c);
-    if (fits) cdel[b + k * kSlice + lane] = static_cast<unsigned short>(c - mn);
+    cdel[at] = fits ? static_cast<unsigned short>(c - mn) : 0;
     if (lane == 0) cbase[b / kSlice + k] = fits ? mn : -1;
   }
   if (lane == 0 && fits) {
@@ -848,6 +855,11 @@ __global__ void __launch_bounds__(kBlock) k_sell_compact(int n, int nslices, con
     atomicAdd(&count[0], static_cast<unsigned long long>(rp[r1] - rp[r0]));
     atomicAdd(&count[1], static_cast<unsigned long long>(width));
   }
+}
+
+__global__ void k_sell_quads(int nslices, const int *sptr, int *quads) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nslices) quads[s] = ((sptr[s + 1] - sptr[s]) / kSlice + 3) / 4;
 }
 
 __global__ void k_d2f(int64_t n, const double *a, float *b) {
@@ -1049,7 +1061,153 @@ void check_flags(const dvec<int> &flags, hipStream_t s) {
   if (f[3]) fail(AMG_ERR_INVALID, "matrix is not bitwise symmetric");
 }
 
-void build_sell(Level &Lv, hipStream_t s, bool want_float) {
+// ----------------------------------------------------- coded SELL values
+// Distinct bit patterns of the slot values go into an open-addressing table
+// of kDictSlots keys (linear probing; kDictEmpty, a signalling-NaN pattern
+// that arithmetic never produces, marks a free slot).  count > kDictMax
+// means "too many": the level stays plain.
+constexpr int kDictSlots = 1024;
+constexpr unsigned long long kDictEmpty = 0x7ff4a5a5a5a5a5a5ull;
+
+__device__ __forceinline__ unsigned dict_hash(unsigned long long k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  return static_cast<unsigned>(k) & (kDictSlots - 1);
+}
+
+// Slot of key k in the table, or -1 (absent; the table is never full).
+__device__ __forceinline__ int dict_find(const unsigned long long *tab, unsigned long long k) {
+  unsigned h = dict_hash(k);
+  for (int probe = 0; probe < kDictSlots; ++probe) {
+    const unsigned long long t = tab[h];
+    if (t == k) return static_cast<int>(h);
+    if (t == kDictEmpty) return -1;
+    h = (h + 1) & (kDictSlots - 1);
+  }
+  return -1;
+}
+
+// Inserts k unless present; counts new keys.  Stops adding once the count
+// passes kDictMax, so at most kDictMax + (concurrent inserters) keys land and
+// the table never fills.
+__device__ __forceinline__ void dict_insert(unsigned long long *tab, int *count, unsigned long long k) {
+  unsigned h = dict_hash(k);
+  for (int probe = 0; probe < kDictSlots; ++probe) {
+    unsigned long long t = tab[h];   // plain read first: present keys cost no atomic
+    if (t == k) return;
+    if (t == kDictEmpty) {
+      if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > kDictMax) return;
+      t = atomicCAS(&tab[h], kDictEmpty, k);
+      if (t == kDictEmpty) {
+        atomicAdd(count, 1);
+        return;
+      }
+      if (t == k) return;
+    }
+    h = (h + 1) & (kDictSlots - 1);
+  }
+}
+
+// One wavefront removes duplicates among its 64 values before touching the
+// table: the first lane still holding an unseen key inserts it for every
+// lane with the same key.
+__global__ void __launch_bounds__(kBlock) k_dict_insert(int64_t m, const double *__restrict__ v,
+                                                        unsigned long long *tab, int *count) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+       i - lane < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int seen = __shfl(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 0);
+    if (seen > kDictMax) return;   // wavefront-uniform
+    const unsigned long long k = i < m ? static_cast<unsigned long long>(__double_as_longlong(v[i])) : 0ull;
+    bool pending = i < m;
+    for (;;) {
+      const unsigned long long ball = __ballot(pending);
+      if (ball == 0) break;
+      const int leader = __ffsll(ball) - 1;
+      const unsigned long long lk = __shfl(k, leader);
+      if (lane == leader) dict_insert(tab, count, lk);
+      if (pending && k == lk) pending = false;
+    }
+  }
+}
+
+// One workgroup: the occupied keys ranked by bit pattern (rank = number of
+// smaller keys), rank[slot] for the encoder, dict[rank] = the value.
+__global__ void __launch_bounds__(kBlock) k_dict_rank(const unsigned long long *tab, int *rank,
+                                                      double *dict, float *dictf) {
+  __shared__ unsigned long long keys[kDictSlots];
+  for (int h = threadIdx.x; h < kDictSlots; h += blockDim.x) keys[h] = tab[h];
+  __syncthreads();
+  for (int h = threadIdx.x; h < kDictSlots; h += blockDim.x) {
+    const unsigned long long k = keys[h];
+    if (k == kDictEmpty) {
+      rank[h] = -1;
+      continue;
+    }
+    int r = 0;
+    for (int q = 0; q < kDictSlots; ++q) r += (keys[q] != kDictEmpty && keys[q] < k) ? 1 : 0;
+    rank[h] = r;
+    const double x = __longlong_as_double(static_cast<long long>(k));
+    dict[r] = x;
+    if (dictf) dictf[r] = static_cast<float>(x);
+  }
+}
+
+// One wavefront per slice: the code of every slot, stored by quads (padding 0).
+__global__ void __launch_bounds__(kBlock) k_dict_encode(int nslices, const int *__restrict__ sptr,
+                                                        const int *__restrict__ qptr,
+                                                        const double *__restrict__ v,
+                                                        const unsigned long long *__restrict__ tab,
+                                                        const int *__restrict__ rank,
+                                                        unsigned char *__restrict__ code) {
+  const int s = blockIdx.x * (kBlock / kWave) + static_cast<int>(threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (s >= nslices) return;
+  const int b = sptr[s], width = (sptr[s + 1] - b) / kSlice;
+  const int64_t q0 = static_cast<int64_t>(qptr[s]) * kSlice;
+  for (int k = 0; k < 4 * (qptr[s + 1] - qptr[s]); ++k) {
+    int c = 0;
+    if (k < width) {   // every slot value was inserted
+      const int h = dict_find(tab, static_cast<unsigned long long>(__double_as_longlong(v[b + k * kSlice + lane])));
+      c = h >= 0 ? rank[h] : 0;
+    }
+    code[((q0 + (k >> 2) * kSlice) + lane) * 4 + (k & 3)] = static_cast<unsigned char>(c);
+  }
+}
+
+__global__ void k_fill_u64(int n, unsigned long long *a, unsigned long long x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = x;
+}
+
+// Table of the slot values of S (padding included) and their codes, when
+// there are at most kDictMax distinct bit patterns.
+void build_codes(Sell &S, hipStream_t s, bool want_float) {
+  S.ndict = 0;
+  if (S.nslots == 0) return;
+  tvec<unsigned long long> tab(kDictSlots, s);
+  tvec<int> cnt(1, s), rank(kDictSlots, s);
+  hipLaunchKernelGGL(k_fill_u64, dim3(kDictSlots / kBlock), dim3(kBlock), 0, s, kDictSlots, tab.p,
+                     kDictEmpty);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+  const unsigned gi = static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(S.nslots, kBlock)));
+  hipLaunchKernelGGL(k_dict_insert, dim3(gi), dim3(kBlock), 0, s, S.nslots, S.val.p, tab.p, cnt.p);
+  AMG_LAUNCH_CHECK();
+  const int nd = read_int(cnt.p, s);
+  if (nd < 1 || nd > kDictMax) return;
+  S.dict.alloc(nd);
+  if (want_float) S.dictf.alloc(nd);
+  S.code.alloc(S.nquads * kSlice * 4);
+  hipLaunchKernelGGL(k_dict_rank, dim3(1), dim3(kBlock), 0, s, tab.p, rank.p, S.dict.p,
+                     want_float ? S.dictf.p : nullptr);
+  hipLaunchKernelGGL(k_dict_encode, grid_for(static_cast<int64_t>(S.nslices) * kWave), dim3(kBlock), 0, s,
+                     S.nslices, S.sptr.p, S.qptr.p, S.val.p, tab.p, rank.p, S.code.p);
+  AMG_LAUNCH_CHECK();
+  S.ndict = nd;
+}
+
+void build_sell(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   Sell &S = Lv.S;
   const int n = Lv.A.n;
   S.n = n;
@@ -1067,11 +1225,17 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
                      0, s, n, S.nslices, Lv.A.rp.p, Lv.A.ci.p, Lv.A.v.p, S.sptr.p, S.col.p, S.val.p);
   AMG_LAUNCH_CHECK();
   S.cbase.alloc(S.nslots / kSlice);
-  S.cdel.alloc(S.nslots);
+  S.qptr.alloc(S.nslices + 1);
+  hipLaunchKernelGGL(k_sell_quads, grid_for(S.nslices), dim3(kBlock), 0, s, S.nslices, S.sptr.p, slots.p);
+  AMG_LAUNCH_CHECK();
+  exclusive_scan(slots.p, S.qptr.p, S.nslices, s);
+  S.nquads = read_int(S.qptr.p + S.nslices, s);
+  S.cdel.alloc(S.nquads * kSlice * 4);
   tvec<unsigned long long> cnt(2, s);
   AMG_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_sell_compact, grid_for(static_cast<int64_t>(S.nslices) * kWave), dim3(kBlock),
-                     0, s, n, S.nslices, Lv.A.rp.p, S.sptr.p, S.col.p, S.cbase.p, S.cdel.p, cnt.p);
+                     0, s, n, S.nslices, Lv.A.rp.p, S.sptr.p, S.qptr.p, S.col.p, S.cbase.p, S.cdel.p,
+                     cnt.p);
   AMG_LAUNCH_CHECK();
   unsigned long long hc[2];
   read_small(hc, cnt.p, sizeof(hc), s);
@@ -1082,6 +1246,7 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float) {
     hipLaunchKernelGGL(k_d2f, grid_for(S.nslots), dim3(kBlock), 0, s, S.nslots, S.val.p, S.valf.p);
     AMG_LAUNCH_CHECK();
   }
+  if (want_codes) build_codes(S, s, want_float);
 }
 
 // One pairwise step on (A, w): matching, aggregates, P values, w_c, A_c.
@@ -1205,12 +1370,12 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   tm.rap_ms += now_ms() - t1;
 }
 
-void finish_level(Level &Lv, hipStream_t s, bool want_float) {
+void finish_level(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   const int n = Lv.A.n;
   Lv.dinv.alloc(n);
   hipLaunchKernelGGL(k_l1_dinv, grid_for(n), dim3(kBlock), 0, s, n, Lv.A.rp.p, Lv.A.v.p, Lv.dinv.p);
   AMG_LAUNCH_CHECK();
-  build_sell(Lv, s, want_float);
+  build_sell(Lv, s, want_float, want_codes);
   if (want_float) {
     Lv.dinvf.alloc(n);
     hipLaunchKernelGGL(k_l1_dinv_f, grid_for(n), dim3(kBlock), 0, s, n, Lv.A.rp.p, Lv.A.v.p, Lv.dinvf.p);
@@ -1258,7 +1423,7 @@ void keep_pool_memory() {
 // Entry points for the other translation units (batched hierarchy).
 void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s) { exclusive_scan(in, out, n, s); }
 int device_read_int(const int *p, hipStream_t s) { return read_int(p, s); }
-void finalize_level(Level &Lv, hipStream_t s, bool want_float) { finish_level(Lv, s, want_float); }
+void finalize_level(Level &Lv, hipStream_t s, bool want_float) { finish_level(Lv, s, want_float, false); }
 double wall_ms() { return now_ms(); }
 
 // ===================================================== hierarchy builder
@@ -1292,7 +1457,8 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     AMG_LAUNCH_CHECK();
     check_flags(flags, s);
   }
-  finish_level(L0, s, want_float);
+  const bool want_codes = P.value_coding == AMG_VALUES_AUTO;
+  finish_level(L0, s, want_float, want_codes);
 
   // smooth vector of the fine level
   L0.w.alloc(n);
@@ -1368,7 +1534,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     next.A = std::move(cur.Ac);
     next.w = std::move(cur.wc);
     h->L.push_back(std::move(next));
-    finish_level(h->L.back(), s, want_float);
+    finish_level(h->L.back(), s, want_float, want_codes);
   }
   AMG_HIP(hipStreamSynchronize(s));
   coarse_factor(h);

@@ -35,78 +35,129 @@ inline dim3 grid_for(int64_t n, int block = kBlock) {
 // (non-temporal) loads for matrices read once per pass; plain loads in the
 // coarse-tail kernel, whose working set stays in cache.
 // Fold of one SELL row: slots k = 0 .. width-1 in order, acc += a_k x(c_k),
-// l1 += |a_k|.  Slots are taken eight at a time, the last 1-7 in one
-// predicated batch (width is the same on the whole wavefront), so all loads
-// of a batch are in flight together.
-template <class T, bool kStream, class Cols, class G>
-__device__ __forceinline__ void row_fold(Cols cols, const T *__restrict__ vp, G x, int width, T &sum,
-                                         T &l1) {
-  auto ldv = [](const T *p) { return kStream ? ld_stream(p) : *p; };
+// l1 += |a_k|.  Slots are taken eight at a time (two quads), the last 1-7
+// in one predicated batch (width is the same on the whole wavefront), so all
+// loads of a batch are in flight together.  Column and value sources fill
+// one quad of slots at a time: load4(t, nv, out) sets out[j] for slot
+// 4t + j, j < nv.
+template <class T, bool kStream, class Cols, class Vals, class G>
+__device__ __forceinline__ void row_fold(Cols cols, Vals vals, G x, int width, T &sum, T &l1) {
   T acc = T(0), m = T(0);
-  int k = 0;
-  for (; k + 8 <= width; k += 8) {
-    int c[8];
-    T a[8], xv[8];
+  int t = 0;
+  for (; 4 * t + 8 <= width; t += 2) {
+    int c0[4], c1[4];
+    T a0[4], a1[4], x0[4], x1[4];
+    cols.load4(t, 4, c0);
+    cols.load4(t + 1, 4, c1);
+    vals.load4(t, 4, a0);
+    vals.load4(t + 1, 4, a1);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      c[u] = cols(k + u);
-      a[u] = ldv(vp + (k + u) * 64);
+    for (int u = 0; u < 4; ++u) {
+      x0[u] = x(c0[u]);
+      x1[u] = x(c1[u]);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xv[u] = x(c[u]);
+    for (int u = 0; u < 4; ++u) {
+      acc = acc + a0[u] * x0[u];
+      m = m + fabs(a0[u]);
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc = acc + a[u] * xv[u];
-      m = m + fabs(a[u]);
+    for (int u = 0; u < 4; ++u) {
+      acc = acc + a1[u] * x1[u];
+      m = m + fabs(a1[u]);
     }
   }
-  const int rem = width - k;
+  const int rem = width - 4 * t;
   if (rem > 0) {
-    int c[7];
-    T a[7], xv[7];
+    const int n0 = rem < 4 ? rem : 4, n1 = rem - n0;
+    int c0[4], c1[4];
+    T a0[4], a1[4], x0[4], x1[4];
+    cols.load4(t, n0, c0);
+    vals.load4(t, n0, a0);
+    if (n1 > 0) {
+      cols.load4(t + 1, n1, c1);
+      vals.load4(t + 1, n1, a1);
+    }
 #pragma unroll
-    for (int u = 0; u < 7; ++u)
-      if (u < rem) {
-        c[u] = cols(k + u);
-        a[u] = ldv(vp + (k + u) * 64);
+    for (int u = 0; u < 4; ++u) {
+      if (u < n0) x0[u] = x(c0[u]);
+      if (u < n1) x1[u] = x(c1[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < n0) {
+        acc = acc + a0[u] * x0[u];
+        m = m + fabs(a0[u]);
       }
 #pragma unroll
-    for (int u = 0; u < 7; ++u)
-      if (u < rem) xv[u] = x(c[u]);
-#pragma unroll
-    for (int u = 0; u < 7; ++u)
-      if (u < rem) {
-        acc = acc + a[u] * xv[u];
-        m = m + fabs(a[u]);
+    for (int u = 0; u < 3; ++u)
+      if (u < n1) {
+        acc = acc + a1[u] * x1[u];
+        m = m + fabs(a1[u]);
       }
   }
   sum = acc;
   l1 = m;
 }
 
+template <class V, bool kStream>
+__device__ __forceinline__ V ldx(const V *p) {
+  return kStream ? ld_stream(p) : *p;
+}
+
 template <bool kStream>
-struct PlainCols {      // int32 column of slot k
+struct PlainCols {      // int32 column of slot k (slot-major layout)
   const int *__restrict__ cp;
-  __device__ __forceinline__ int operator()(int k) const {
-    return kStream ? ld_stream(cp + k * 64) : cp[k * 64];
+  __device__ __forceinline__ void load4(int t, int nv, int (&c)[4]) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nv) c[j] = ldx<int, kStream>(cp + (4 * t + j) * 64);
   }
 };
 
 template <bool kStream>
-struct CompactCols {    // group base + 16-bit offset of slot k
-  const int *__restrict__ bp;
-  const unsigned short *__restrict__ dp;
-  __device__ __forceinline__ int operator()(int k) const {
-    return bp[k] + static_cast<int>(kStream ? ld_stream(dp + k * 64) : dp[k * 64]);
+struct QuadCols {       // group base + 16-bit offset, four slots per load
+  const int *__restrict__ bp;                  // cbase of the slice's first group
+  const unsigned long long *__restrict__ dq;   // the lane's first quad
+  __device__ __forceinline__ void load4(int t, int nv, int (&c)[4]) const {
+    const unsigned long long d = ldx<unsigned long long, kStream>(dq + t * 64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nv) c[j] = bp[4 * t + j] + static_cast<int>((d >> (16 * j)) & 0xffffu);
   }
 };
 
-template <class T, bool kStream, class G>
-__device__ __forceinline__ void sell_row_g(const int *__restrict__ sptr, const int *__restrict__ col,
-                                           const T *__restrict__ val, G x, int r, T &sum, T &l1) {
-  const int s = r >> 6, lane = r & 63;
-  const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
-  row_fold<T, kStream>(PlainCols<kStream>{col + b + lane}, val + b + lane, x, width, sum, l1);
+template <class T, bool kStream>
+struct PlainVals {      // binary64 / binary32 value of slot k (slot-major layout)
+  const T *__restrict__ vp;
+  __device__ __forceinline__ void load4(int t, int nv, T (&a)[4]) const {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nv) a[j] = ldx<T, kStream>(vp + (4 * t + j) * 64);
+  }
+};
+
+template <class T, bool kStream>
+struct QuadCodedVals {  // table entries named by the four code bytes of a quad
+  const unsigned *__restrict__ cq;   // the lane's first quad
+  const T *dict;                     // the table, staged in LDS
+  __device__ __forceinline__ void load4(int t, int nv, T (&a)[4]) const {
+    const unsigned w = ldx<unsigned, kStream>(cq + t * 64);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nv) a[j] = dict[(w >> (8 * j)) & 0xffu];
+  }
+};
+
+// The value table of a coded matrix copied to LDS by the whole workgroup
+// (every thread must call this, before any early return); the returned
+// reference reads it there.
+template <class T>
+__device__ __forceinline__ ValRef<T> stage_dict(const ValRef<T> &V, T *sdict) {
+  if (!V.code) return V;   // uniform: a kernel argument
+  for (int i = threadIdx.x; i < V.ndict; i += blockDim.x) sdict[i] = V.dict[i];
+  __syncthreads();
+  return ValRef<T>{V.val, V.code, sdict, V.ndict};
 }
 
 template <class T>
@@ -124,42 +175,110 @@ struct Corrected {      // (x + P e)_c = x_c + p_c e[agg_c], the prolongation's 
   __device__ __forceinline__ T operator()(int c) const { return x[c] + pval[c] * e[agg[c]]; }
 };
 
-template <class T, bool kStream = true>
-__device__ __forceinline__ void sell_row(const int *__restrict__ sptr, const int *__restrict__ col,
-                                         const T *__restrict__ val, const T *__restrict__ x, int r,
-                                         T &sum, T &l1) {
-  sell_row_g<T, kStream>(sptr, col, val, Plain<T>{x}, r, sum, l1);
-}
-
-// Same row through the compact column form (16-bit offsets from a per-group
-// base).  The rows of a wavefront must lie in one slice (rows are handed out
+// Row r through the compact column form (16-bit offsets from a per-group
+// base) where its slice has one, else the int32 columns; values plain or
+// coded.  The rows of a wavefront must lie in one slice (rows are handed out
 // in whole slices), so the slice bounds and group bases are wavefront-uniform
-// and read with scalar loads.  Slices without the compact form fall back to
-// the int32 columns.  The fold is the same: identical bits either way.
+// and read with scalar loads.  Every combination folds the same terms in the
+// same order: identical bits.
 template <class T, bool kStream, class G>
-__device__ __forceinline__ void sell_row_g(const SellRef &S, const T *__restrict__ val, G x, int r,
-                                           T &sum, T &l1) {
+__device__ __forceinline__ void sell_row_g(const SellRef &S, const ValRef<T> &V, G x, int r, T &sum,
+                                           T &l1) {
   const int s = __builtin_amdgcn_readfirstlane(r >> 6);
   const int b = S.sptr[s], width = (S.sptr[s + 1] - b) >> 6;
   const int g = b >> 6;
-  if (!S.cdel || width == 0 || S.cbase[g] < 0) {
-    sell_row_g<T, kStream>(S.sptr, S.col, val, x, r, sum, l1);
-    return;
-  }
   const int lane = r & 63;
-  row_fold<T, kStream>(CompactCols<kStream>{S.cbase + g, S.cdel + b + lane}, val + b + lane, x, width,
-                       sum, l1);
+  const bool compact = S.cdel && width > 0 && S.cbase[g] >= 0;
+  const int q = S.qptr[s];
+  const int64_t lq = static_cast<int64_t>(q) * 64 + lane;   // the lane's first quad
+  const QuadCols<kStream> qcols{S.cbase + g, reinterpret_cast<const unsigned long long *>(S.cdel) + lq};
+  const PlainCols<kStream> pcols{S.col + b + lane};
+  if (V.code) {
+    const QuadCodedVals<T, kStream> vals{reinterpret_cast<const unsigned *>(V.code) + lq, V.dict};
+    if (compact) row_fold<T, kStream>(qcols, vals, x, width, sum, l1);
+    else row_fold<T, kStream>(pcols, vals, x, width, sum, l1);
+  } else {
+    const PlainVals<T, kStream> vals{V.val + b + lane};
+    if (compact) row_fold<T, kStream>(qcols, vals, x, width, sum, l1);
+    else row_fold<T, kStream>(pcols, vals, x, width, sum, l1);
+  }
 }
 
 template <class T, bool kStream = true>
-__device__ __forceinline__ void sell_row(const SellRef &S, const T *__restrict__ val,
+__device__ __forceinline__ void sell_row(const SellRef &S, const ValRef<T> &V,
                                          const T *__restrict__ x, int r, T &sum, T &l1) {
-  sell_row_g<T, kStream>(S, val, Plain<T>{x}, r, sum, l1);
+  sell_row_g<T, kStream>(S, V, Plain<T>{x}, r, sum, l1);
+}
+
+// Two rows of one lane, in slices sa and sb (wavefront-uniform), folded
+// together when both slices are compact and coded with at most 8 slots:
+// every load of both rows is issued before the first use, which doubles the
+// loads in flight per wavefront on these short rows.  Slots past a row's
+// width are read at clamped, in-range places and left out of the fold, so
+// the fold is the one of row_fold.  Returns false (nothing done) otherwise.
+template <class T, bool kStream, class G>
+__device__ __forceinline__ bool fold2_short(const SellRef &S, const ValRef<T> &V, G x, int sa, int sb,
+                                            int lane, T &sum0, T &l10, T &sum1, T &l11) {
+  if (!V.code || !S.cdel) return false;
+  const int ba = S.sptr[sa], wa = (S.sptr[sa + 1] - ba) >> 6;
+  const int bb = S.sptr[sb], wb = (S.sptr[sb + 1] - bb) >> 6;
+  if (wa < 1 || wb < 1 || wa > 8 || wb > 8) return false;
+  const int ga = ba >> 6, gb = bb >> 6;
+  if (S.cbase[ga] < 0 || S.cbase[gb] < 0) return false;
+  const unsigned long long *cd = reinterpret_cast<const unsigned long long *>(S.cdel);
+  const unsigned *cc = reinterpret_cast<const unsigned *>(V.code);
+  const int64_t qa = static_cast<int64_t>(S.qptr[sa]) * 64 + lane;
+  const int64_t qb = static_cast<int64_t>(S.qptr[sb]) * 64 + lane;
+  const int ta = wa > 4 ? 64 : 0, tb = wb > 4 ? 64 : 0;   // second quad, or the first again
+  const unsigned long long da0 = ldx<unsigned long long, kStream>(cd + qa);
+  const unsigned long long da1 = ldx<unsigned long long, kStream>(cd + qa + ta);
+  const unsigned long long db0 = ldx<unsigned long long, kStream>(cd + qb);
+  const unsigned long long db1 = ldx<unsigned long long, kStream>(cd + qb + tb);
+  const unsigned ka0 = ldx<unsigned, kStream>(cc + qa), ka1 = ldx<unsigned, kStream>(cc + qa + ta);
+  const unsigned kb0 = ldx<unsigned, kStream>(cc + qb), kb1 = ldx<unsigned, kStream>(cc + qb + tb);
+  const int rowa = sa * 64, rowb = sb * 64;   // in-range stand-ins for unused slots (rows < n)
+  int ca[8], cb[8];
+  T xa[8], xb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned long long dA = j < 4 ? da0 : da1, dB = j < 4 ? db0 : db1;
+    const int offA = static_cast<int>((dA >> (16 * (j & 3))) & 0xffffu);
+    const int offB = static_cast<int>((dB >> (16 * (j & 3))) & 0xffffu);
+    ca[j] = j < wa ? S.cbase[ga + j] + offA : rowa;
+    cb[j] = j < wb ? S.cbase[gb + j] + offB : rowb;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xa[j] = x(ca[j]);
+    xb[j] = x(cb[j]);
+  }
+  T acc0 = T(0), m0 = T(0), acc1 = T(0), m1 = T(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned kA = j < 4 ? ka0 : ka1, kB = j < 4 ? kb0 : kb1;
+    const T aA = V.dict[(kA >> (8 * (j & 3))) & 0xffu];
+    const T aB = V.dict[(kB >> (8 * (j & 3))) & 0xffu];
+    if (j < wa) {
+      acc0 = acc0 + aA * xa[j];
+      m0 = m0 + fabs(aA);
+    }
+    if (j < wb) {
+      acc1 = acc1 + aB * xb[j];
+      m1 = m1 + fabs(aB);
+    }
+  }
+  sum0 = acc0;
+  l10 = m0;
+  sum1 = acc1;
+  l11 = m1;
+  return true;
 }
 
 template <class T, bool kStream>
-__global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, const T *__restrict__ val,
+__global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, ValRef<T> vref,
                                                  const T *__restrict__ x, T *__restrict__ y) {
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -171,10 +290,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, const T *__re
 // from the streamed row (the same fold that defines the stored diagonal).
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRef S,
-                                                  const T *__restrict__ val,
+                                                  ValRef<T> vref,
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ x, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -183,18 +304,74 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRe
   xn[r] = x[r] + di * (rhs[r] - s);
 }
 
+// Rows r0 and r0 + 256 of a 512-row workgroup (two slices per wavefront),
+// for coded levels: out(r, sum, l1) for each row below n.
+template <class T, bool kStream, class G, class F>
+__device__ __forceinline__ void rows2(const SellRef &S, const ValRef<T> &V, G x, int n, int r0, F out) {
+  const int r1 = r0 + kBlock;
+  const int sa = __builtin_amdgcn_readfirstlane(r0 >> 6), sb = sa + kBlock / 64;
+  const int nsl = (n + 63) >> 6;
+  if (sa >= nsl) return;   // whole wavefront
+  T s0, m0, s1, m1;
+  if (sb < nsl && fold2_short<T, kStream>(S, V, x, sa, sb, r0 & 63, s0, m0, s1, m1)) {
+    if (r0 < n) out(r0, s0, m0);
+    if (r1 < n) out(r1, s1, m1);
+    return;
+  }
+  if (r0 < n) {
+    sell_row_g<T, kStream>(S, V, x, r0, s0, m0);
+    out(r0, s0, m0);
+  }
+  if (sb < nsl && r1 < n) {
+    sell_row_g<T, kStream>(S, V, x, r1, s1, m1);
+    out(r1, s1, m1);
+  }
+}
+
+// The sweep and the scaled residual, two slices per wavefront.
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_sweep2(const int *skip, int n, SellRef S,
+                                                   ValRef<T> vref,
+                                                   const T *__restrict__ rhs,
+                                                   const T *__restrict__ x, T *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
+  rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T l1) {
+    const T di = T(1) / l1;
+    xn[r] = x[r] + di * (rhs[r] - sum);
+  });
+}
+
+template <class T, bool kStream>
+__global__ void __launch_bounds__(kBlock) k_resid_scaled2(const int *skip, int n, SellRef S,
+                                                          ValRef<T> vref,
+                                                          const T *__restrict__ pval,
+                                                          const T *__restrict__ rhs,
+                                                          const T *__restrict__ x,
+                                                          T *__restrict__ t) {
+  AMG_SKIP_IF_DONE();
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
+  rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T) { t[r] = pval[r] * (rhs[r] - sum); });
+}
+
 // First post-smoothing sweep with the coarse-grid correction folded in:
 // y = x + P e is formed where it is read (the value k_prolong would store)
 // and xn = y + dinv (rhs - A y); y itself is never written.
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_sweep_corr(const int *skip, int n, SellRef S,
-                                                       const T *__restrict__ val,
+                                                       ValRef<T> vref,
                                                        const T *__restrict__ rhs,
                                                        const T *__restrict__ x,
                                                        const int *__restrict__ agg,
                                                        const T *__restrict__ pval,
                                                        const T *__restrict__ e, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   const Corrected<T> y{x, pval, agg, e};
@@ -218,12 +395,14 @@ __global__ void __launch_bounds__(kBlock) k_sweep_first(const int *skip, int n,
 // Restriction, pass 1 (row parallel): t_i = p_i (r_i - (A x)_i).
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n, SellRef S,
-                                                         const T *__restrict__ val,
+                                                         ValRef<T> vref,
                                                          const T *__restrict__ pval,
                                                          const T *__restrict__ rhs,
                                                          const T *__restrict__ x,
                                                          T *__restrict__ t) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sdict[kDictMax];
+  const ValRef<T> val = stage_dict(vref, sdict);
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -537,12 +716,14 @@ __device__ __forceinline__ void first_out(const FirstOut &fo, int i, double ri) 
 // r = b - A u, partial ||r||^2 per workgroup (kRowsDot rows per thread).
 template <bool kStream>
 __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, SellRef S,
-                                                     const double *__restrict__ val,
+                                                     ValRef<double> vref,
                                                      const double *__restrict__ b,
                                                      const double *__restrict__ u,
                                                      double *__restrict__ r,
                                                      double *__restrict__ part, FirstOut fo) {
   __shared__ double red[kBlock / kWave];
+  __shared__ double sdict[kDictMax];
+  const ValRef<double> val = stage_dict(vref, sdict);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   double rr = 0.0;
 #pragma unroll
@@ -585,25 +766,24 @@ __global__ void __launch_bounds__(kFinish) k_pcg_init_finish(int nb, const doubl
 // v = A w and partial dots alpha = w.r, beta = w.v, gamma = w.q.
 template <bool kStream>
 __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
-    const int *skip, int n, SellRef S, const double *__restrict__ val, const double *__restrict__ w, const double *__restrict__ r,
+    const int *skip, int n, SellRef S, ValRef<double> vref, const double *__restrict__ w,
+    const double *__restrict__ r,
     const double *__restrict__ q, double *__restrict__ v, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock / kWave];
+  __shared__ double sdict[kDictMax];
+  const ValRef<double> val = stage_dict(vref, sdict);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-  for (int h = 0; h < kRowsDot; ++h) {
-    const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
-    if (row < n) {
-      double s, m;
-      sell_row<double, kStream>(S, val, w, row, s, m);
-      v[row] = s;
-      const double wi = w[row];
-      al = al + wi * r[row];
-      be = be + wi * s;
-      ga = ga + wi * q[row];
-    }
-  }
+  static_assert(kRowsDot == 2, "rows r and r + kBlock of the workgroup's 2 kBlock rows");
+  rows2<double, kStream>(S, val, Plain<double>{w}, n, lb * kRowsDot * kBlock + threadIdx.x,
+                         [&](int row, double s, double) {
+                           v[row] = s;
+                           const double wi = w[row];
+                           al = al + wi * r[row];
+                           be = be + wi * s;
+                           ga = ga + wi * q[row];
+                         });
   al = group_sum<kBlock>(al, red);
   be = group_sum<kBlock>(be, red);
   ga = group_sum<kBlock>(ga, red);
@@ -705,9 +885,6 @@ __global__ void __launch_bounds__(kFinish) k_pcg_norm_finish(const int *skip, in
 }
 
 // ------------------------------------------------------------ V-cycle
-template <class T> const T *vals(const Sell &S);
-template <> const double *vals<double>(const Sell &S) { return S.val.p; }
-template <> const float *vals<float>(const Sell &S) { return S.valf.p; }
 template <class T> const T *dinv_of(const Level &L);
 template <> const double *dinv_of<double>(const Level &L) { return L.dinv.p; }
 template <> const float *dinv_of<float>(const Level &L) { return L.dinvf.p; }
@@ -742,30 +919,48 @@ template <> const TailDesc<float> *tail_desc<float>(amg_hierarchy *h) {
 #endif
 template <class T>
 bool streamed(const Level &L) {
-  const double bytes = static_cast<double>(L.S.nslots) * (sizeof(T) + 2.0);
+  const double bytes = static_cast<double>(L.S.nslots) * ((L.S.ndict ? 1.0 : sizeof(T)) + 2.0);
   return bytes >= AMG_STREAM_MIN_MB * 1048576.0;
 }
 
 template <class T>
 void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s) {
   const int n = L.A.n;
+  if (L.S.ndict) {
+    if (streamed<T>(L))
+      hipLaunchKernelGGL((k_sweep2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn);
+    else
+      hipLaunchKernelGGL((k_sweep2<T, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn);
+    return;
+  }
   if (streamed<T>(L))
     hipLaunchKernelGGL((k_sweep<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
-                       vals<T>(L.S), rhs, x, xn);
+                       val_ref<T>(L.S), rhs, x, xn);
   else
     hipLaunchKernelGGL((k_sweep<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
-                       vals<T>(L.S), rhs, x, xn);
+                       val_ref<T>(L.S), rhs, x, xn);
 }
 
 template <class T>
 void launch_resid(const int *skip, const Level &L, const T *rhs, const T *x, T *t, hipStream_t s) {
   const int n = L.A.n;
+  if (L.S.ndict) {
+    if (streamed<T>(L))
+      hipLaunchKernelGGL((k_resid_scaled2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip,
+                         n, sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
+    else
+      hipLaunchKernelGGL((k_resid_scaled2<T, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip,
+                         n, sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
+    return;
+  }
   if (streamed<T>(L))
     hipLaunchKernelGGL((k_resid_scaled<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n,
-                       sell_ref(L.S), vals<T>(L.S), pval_of<T>(L), rhs, x, t);
+                       sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
   else
     hipLaunchKernelGGL((k_resid_scaled<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n,
-                       sell_ref(L.S), vals<T>(L.S), pval_of<T>(L), rhs, x, t);
+                       sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
 }
 
 // Prolongation fused into the first post-sweep: 0 never, 1 on levels of at
@@ -787,10 +982,10 @@ void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e
     launch_sweep<T>(skip, L, rhs, x, xn, s);
   } else if (streamed<T>(L)) {
     hipLaunchKernelGGL((k_sweep_corr<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n,
-                       sell_ref(L.S), vals<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
+                       sell_ref(L.S), val_ref<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
   } else {
     hipLaunchKernelGGL((k_sweep_corr<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n,
-                       sell_ref(L.S), vals<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
+                       sell_ref(L.S), val_ref<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
   }
 }
 
@@ -798,10 +993,10 @@ void launch_spmv(const Level &L, const double *x, double *y, hipStream_t s) {
   const int n = L.A.n;
   if (streamed<double>(L))
     hipLaunchKernelGGL((k_spmv<double, true>), grid_for(n), dim3(kBlock), 0, s, n, sell_ref(L.S),
-                       L.S.val.p, x, y);
+                       val_ref<double>(L.S), x, y);
   else
     hipLaunchKernelGGL((k_spmv<double, false>), grid_for(n), dim3(kBlock), 0, s, n, sell_ref(L.S),
-                       L.S.val.p, x, y);
+                       val_ref<double>(L.S), x, y);
 }
 
 // Where level k puts the first smoothing iterate so that, after all its
@@ -933,10 +1128,10 @@ void launch_spmv_dots(amg_hierarchy *h, const int *skip) {
   const int n = L0.A.n, nbd = nb_dot(n);
   if (streamed<double>(L0))
     hipLaunchKernelGGL(k_pcg_spmv_dots<true>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
-                       sell_ref(L0.S), L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
   else
     hipLaunchKernelGGL(k_pcg_spmv_dots<false>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
-                       sell_ref(L0.S), L0.S.val.p, h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
 }
 
 void enqueue_iteration(amg_hierarchy *h) {
@@ -969,7 +1164,7 @@ void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32) {
     lds += 4 * L.A.n;
     t.sptr = L.S.sptr.p;
     t.col = L.S.col.p;
-    t.val = vals<T>(L.S);
+    t.val = val_ref<T>(L.S).val;   // the tail reads plain values
     t.pval = pval_of<T>(L);
     t.agg = L.agg.p;
     t.mptr = L.mptr.p;
@@ -1069,10 +1264,10 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->d.p);
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->q.p);
   if (streamed<double>(L0))
-    hipLaunchKernelGGL(k_pcg_init<true>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), L0.S.val.p,
+    hipLaunchKernelGGL(k_pcg_init<true>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
                        b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
   else
-    hipLaunchKernelGGL(k_pcg_init<false>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), L0.S.val.p,
+    hipLaunchKernelGGL(k_pcg_init<false>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
                        b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
   hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, h->partials.p, h->sc.p, rtol,
                      maxit);
@@ -1185,13 +1380,15 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *avg_ms = static_cast<double>(ms) / std::max(1, reps);
-  // algorithmic bytes: the matrix once in the form the kernel reads (values,
-  // column offsets or columns, group bases, slice pointers), vectors once
+  // algorithmic bytes: the matrix once in the form the kernel reads (values
+  // or value codes and their table, column offsets or columns, group bases,
+  // slice pointers), vectors once
   const double bv = 8.0, nd = static_cast<double>(n), ncd = static_cast<double>(L.nc);
   const Sell &S = L.S;
   const double idx = S.cdel.p ? 2.0 * S.nnz_compact + 4.0 * (nnz - S.nnz_compact) + 4.0 * S.groups_compact
                               : 4.0 * nnz;
-  const double mat = bv * nnz + idx + 4.0 * (S.nslices + 1);
+  const double vbytes = S.ndict ? 1.0 * nnz + bv * S.ndict : bv * nnz;
+  const double mat = vbytes + idx + 4.0 * (S.nslices + 1);
   switch (kernel) {
     case 0: *bytes = mat + 2 * bv * nd + (k == 0 ? 2 * bv * nd : 0.0); break;
     case 1: *bytes = mat + 3 * bv * nd; break;

@@ -267,11 +267,19 @@ def test_time_kernel_ids_and_byte_model():
         ms, by = Hg.time_kernel(kid, 0, 3)
         say("  kernel", kid, "ms %.4f bytes %.0f" % (ms, by))
         assert ms > 0 and by > 0
-    ms, sweep_bytes = Hg.time_kernel(amd.KERNEL_SWEEP, 0, 1)
     nnz, n = A.nnz, A.n
-    # n = 13824 < 65536: every slice is compact (2-byte offsets + one base per 64 slots)
-    lo = 8 * nnz + 2 * nnz + 24 * n
     nslices = -(-n // 64)
+    # n = 13824 < 65536: every slice is compact (2-byte offsets + one base per
+    # 64 slots); values plain (8 bytes) or coded (1 byte + the table: the
+    # 7-point matrix holds 6, -1 and the padding 0)
+    assert Hg.info()["dict_size"][0] == 3
+    ms, sweep_bytes = Hg.time_kernel(amd.KERNEL_SWEEP, 0, 1)
+    lo = 1 * nnz + 8 * 3 + 2 * nnz + 24 * n
+    assert lo < sweep_bytes <= lo + 4 * 7 * nslices + 4 * (nslices + 1)
+    Hp = gpu_hierarchy(A, value_coding=amd.AMG_VALUES_PLAIN)
+    assert Hp.info()["dict_size"][0] == 0
+    ms, sweep_bytes = Hp.time_kernel(amd.KERNEL_SWEEP, 0, 1)
+    lo = 8 * nnz + 2 * nnz + 24 * n
     assert lo < sweep_bytes <= lo + 4 * 7 * nslices + 4 * (nslices + 1)
     for bad in (-1, 6):
         with pytest.raises(amd.AMGError):
@@ -279,3 +287,42 @@ def test_time_kernel_ids_and_byte_model():
     last = Hg.info()["levels"] - 1
     with pytest.raises(amd.AMGError):
         Hg.time_kernel(amd.KERNEL_CORR_SWEEP, last, 1)
+
+
+@pytest.mark.parametrize("case", ["poisson33_ragged", "lognormal7_20_relax", "poisson12_hubs"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coded_values_equal_plain_values(case, precision):
+    """Levels whose values take at most 256 bit patterns are read as one-byte
+    codes into a table: V-cycle and PCG give the same bits as the plain
+    value arrays, and the table holds exactly the distinct values (padding
+    zero included) of the level."""
+    import paper_2303_02352_amd as amd
+    make, params = CASES[case]
+    A = make()
+    say("coded vs plain values", case, "precision", precision)
+    Hc = gpu_hierarchy(A, precision=precision, **params)
+    Hp = gpu_hierarchy(A, precision=precision, value_coding=amd.AMG_VALUES_PLAIN, **params)
+    ic, ip = Hc.info(), Hp.info()
+    assert ip["dict_size"] == [0] * ip["levels"]
+    for k in range(ic["levels"]):
+        vals = Hc.export_level(k)["val"]
+        distinct = np.unique(bits(np.concatenate((vals, [0.0])))).size
+        # the padding zero is present unless every slice is exactly full
+        assert ic["dict_size"][k] in ((distinct, distinct - 1) if distinct <= 256 else (0,))
+    if case.startswith("poisson"):
+        assert ic["dict_size"][0] > 0
+    else:
+        assert ic["dict_size"][0] == 0
+    r = dev(W.uniform_pm1(31, A.n))
+    z = [torch.empty(A.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    Hc.vcycle(r, z[0])
+    Hp.vcycle(r, z[1])
+    assert np.array_equal(bits(host(z[0])), bits(host(z[1])))
+    xs, b = W.manufactured_rhs(A, 2)
+    outs = []
+    for H in (Hc, Hp):
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        st, it, rel = H.solve(dev(b), x)
+        outs.append((st, it, rel, host(x)))
+    assert outs[0][:3] == outs[1][:3]
+    assert np.array_equal(bits(outs[0][3]), bits(outs[1][3]))
