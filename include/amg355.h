@@ -119,6 +119,7 @@ typedef struct {
   double setup_rap_ms;          /* part spent in Galerkin products */
   int64_t device_bytes;         /* device memory held by the hierarchy */
   int32_t dict_size[AMG_MAX_LEVELS]; /* distinct values of a coded level's table, 0 = plain */
+  double setup_smooth_ms;       /* part spent on the fine smooth vector (relaxation or copy) */
 } amg_info_t;
 
 /* Fill *p with the defaults above.  Returns AMG_OK or AMG_ERR_INVALID (p NULL). */

@@ -47,7 +47,7 @@ class amg_info_t(C.Structure):
                 ("coarse_dense", C.c_int32), ("matching_rounds", C.c_int32),
                 ("setup_ms", C.c_double), ("setup_match_ms", C.c_double),
                 ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64),
-                ("dict_size", C.c_int32 * AMG_MAX_LEVELS)]
+                ("dict_size", C.c_int32 * AMG_MAX_LEVELS), ("setup_smooth_ms", C.c_double)]
 
 
 class amg_batch_info_t(C.Structure):
@@ -199,7 +199,7 @@ class Hierarchy:
                     coarse_dense=bool(inf.coarse_dense), matching_rounds=inf.matching_rounds,
                     setup_ms=inf.setup_ms, setup_match_ms=inf.setup_match_ms,
                     setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes,
-                    dict_size=list(inf.dict_size[:L]))
+                    dict_size=list(inf.dict_size[:L]), setup_smooth_ms=inf.setup_smooth_ms)
 
     def export_level(self, k) -> dict:
         inf = self.info()

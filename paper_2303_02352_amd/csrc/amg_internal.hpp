@@ -250,7 +250,7 @@ struct TailDesc {
 };
 
 struct Timing {
-  double setup_ms = 0, match_ms = 0, rap_ms = 0;
+  double setup_ms = 0, match_ms = 0, rap_ms = 0, smooth_ms = 0;
   int rounds = 0;
 };
 

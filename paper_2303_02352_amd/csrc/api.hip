@@ -198,6 +198,7 @@ int amg_info(const amg_hierarchy *h, amg_info_t *out) {
   out->setup_ms = h->tm.setup_ms;
   out->setup_match_ms = h->tm.match_ms;
   out->setup_rap_ms = h->tm.rap_ms;
+  out->setup_smooth_ms = h->tm.smooth_ms;
   out->device_bytes = amg::device_bytes(h);
   return AMG_OK;
 }

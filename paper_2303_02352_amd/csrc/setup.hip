@@ -232,13 +232,23 @@ __global__ void k_fill(int n, double *x, double val) {
   if (i < n) x[i] = val;
 }
 
-// max |x| by atomicMax on the IEEE bit pattern (order independent for x >= 0).
-__global__ void k_absmax(int n, const double *x, unsigned long long *out, int *nonfinite) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a = fabs(x[i]);
-  if (!isfinite(a)) { atomicOr(nonfinite, 1); return; }
-  atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(a)));
+// max |x| by atomicMax on the IEEE bit pattern (order independent for
+// x >= 0), one atomic per wavefront after a wavefront maximum.
+__global__ void __launch_bounds__(kBlock) k_absmax(int n, const double *x, unsigned long long *out,
+                                                   int *nonfinite) {
+  unsigned long long m = 0;
+  bool bad = false;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double a = fabs(x[i]);
+    if (!isfinite(a)) bad = true;
+    else m = max(m, static_cast<unsigned long long>(__double_as_longlong(a)));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = max(m, static_cast<unsigned long long>(__shfl_xor(m, o, 64)));
+  const unsigned long long anybad = __ballot(bad);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (m) atomicMax(out, m);
+    if (anybad) atomicOr(nonfinite, 1);
+  }
 }
 
 __global__ void k_scale_by_max(int n, double *x, const unsigned long long *mx) {
@@ -1461,6 +1471,8 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   finish_level(L0, s, want_float, want_codes);
 
   // smooth vector of the fine level
+  AMG_HIP(hipStreamSynchronize(s));
+  const double t_w = now_ms();
   L0.w.alloc(n);
   if (P.smooth_vec == AMG_SMOOTH_GIVEN) {
     AMG_HIP(hipMemcpyAsync(L0.w.p, P.smooth_vector, sizeof(double) * n, kind, s));
@@ -1483,7 +1495,8 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
       dvec<int> nf(1);
       AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
       AMG_HIP(hipMemsetAsync(nf.p, 0, sizeof(int), s));
-      hipLaunchKernelGGL(k_absmax, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, mx.p, nf.p);
+      hipLaunchKernelGGL(k_absmax, dim3(std::min(1024, ceil_div(n, kBlock))), dim3(kBlock), 0, s, n, L0.w.p,
+                         mx.p, nf.p);
       AMG_LAUNCH_CHECK();
       if (read_int(nf.p, s)) {
         hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, 1.0);
@@ -1493,6 +1506,8 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
       AMG_LAUNCH_CHECK();
     }
   }
+  AMG_HIP(hipStreamSynchronize(s));
+  h->tm.smooth_ms = now_ms() - t_w;
 
   Arena ws;   // setup temporaries of the pairwise steps (largest first)
   const int maxlev = std::min(P.max_levels, AMG_MAX_LEVELS);

@@ -841,11 +841,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(const int *skip, int n,
   for (int h = 0; h < kRowsUpd; ++h) {
     const int i = (lb * kRowsUpd + h) * kBlock + threadIdx.x;
     if (i < n) {
-      const double di = w[i] - c * d[i];
-      d[i] = di;
-      u[i] = u[i] + a * di;
-      const double qi = v[i] - c * q[i];
-      q[i] = qi;
+      // w, v, d, u, q are not read again before the next update: non-temporal
+      // accesses keep them from displacing the fine matrix and r, which the
+      // V-cycle reads next, from the last-level cache
+      const double di = ld_stream(w + i) - c * ld_stream(d + i);
+      __builtin_nontemporal_store(di, d + i);
+      __builtin_nontemporal_store(ld_stream(u + i) + a * di, u + i);
+      const double qi = ld_stream(v + i) - c * ld_stream(q + i);
+      __builtin_nontemporal_store(qi, q + i);
       const double ri = r[i] - a * qi;
       r[i] = ri;
       first_out(fo, i, ri);

@@ -326,3 +326,36 @@ def test_coded_values_equal_plain_values(case, precision):
         outs.append((st, it, rel, host(x)))
     assert outs[0][:3] == outs[1][:3]
     assert np.array_equal(bits(outs[0][3]), bits(outs[1][3]))
+
+
+def _k_valued(N, K):
+    """7-point pattern on N^3 with K distinct off-diagonal values
+    -(0.5 + 0.5 ((i + j) mod K) / K) (symmetric), diagonal 6.5: diagonally
+    dominant, and K + 1 distinct stored values (K + 2 slot values with the
+    padding zero of the boundary rows)."""
+    A = W.poisson7(N)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    off = rows != A.col
+    val = np.full(A.nnz, 6.5)
+    val[off] = -(0.5 + 0.5 * ((rows[off] + A.col[off]) % K) / K)
+    return W.CSR(A.n, A.row_ptr, A.col, val)
+
+
+@pytest.mark.parametrize("K,table", [(254, 256), (255, 0)])
+def test_value_table_limit(K, table):
+    """A level with exactly 256 distinct slot values is coded, one with 257
+    is not; both give the oracle's V-cycle and the plain path's bits."""
+    import paper_2303_02352_amd as amd
+    A = _k_valued(12, K)
+    say("value table limit K=%d" % K)
+    Hc = gpu_hierarchy(A)
+    assert Hc.info()["dict_size"][0] == table
+    Hp = gpu_hierarchy(A, value_coding=amd.AMG_VALUES_PLAIN)
+    Ho = oracle.Hierarchy(A, oracle_params())
+    r = W.uniform_pm1(5, A.n)
+    zo = Ho.vcycle(r)
+    z = [torch.empty(A.n, dtype=torch.float64, device="cuda") for _ in range(2)]
+    Hc.vcycle(dev(r), z[0])
+    Hp.vcycle(dev(r), z[1])
+    assert np.array_equal(bits(host(z[0])), bits(host(z[1])))
+    assert np.max(np.abs(host(z[0]) - zo)) <= 1e-12 * np.max(np.abs(zo))
