@@ -168,7 +168,7 @@ struct Sell {
   // reads four slots with one load.  Slot k of lane l in slice s sits at
   // ((qptr[s] + k/4) * 64 + l) * 4 + k%4; a slice holds ceil(width/4) quads
   // (padding slots 0).
-  dvec<int> cbase;               // nslots / 64
+  dvec<int> cbase;               // nslots / 64 + kGroupPad (the padding reads as 0)
   dvec<int> qptr;                // nslices + 1 quad offsets
   dvec<unsigned short> cdel;     // 256 per quad
   int64_t nquads = 0;
@@ -186,6 +186,7 @@ struct Sell {
 };
 
 constexpr int kDictMax = 256;
+constexpr int kGroupPad = 8;   // cbase entries past the last group, so 8-slot reads stay in range
 
 // Value access of a SELL matrix as the kernels see it: val, or code + dict.
 template <class T>

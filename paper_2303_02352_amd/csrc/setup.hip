@@ -1234,7 +1234,8 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   hipLaunchKernelGGL(k_sell_fill, grid_for(static_cast<int64_t>(S.nslices) * kSlice), dim3(kBlock),
                      0, s, n, S.nslices, Lv.A.rp.p, Lv.A.ci.p, Lv.A.v.p, S.sptr.p, S.col.p, S.val.p);
   AMG_LAUNCH_CHECK();
-  S.cbase.alloc(S.nslots / kSlice);
+  S.cbase.alloc(S.nslots / kSlice + kGroupPad);
+  AMG_HIP(hipMemsetAsync(S.cbase.p + S.nslots / kSlice, 0, sizeof(int) * kGroupPad, s));
   S.qptr.alloc(S.nslices + 1);
   hipLaunchKernelGGL(k_sell_quads, grid_for(S.nslices), dim3(kBlock), 0, s, S.nslices, S.sptr.p, slots.p);
   AMG_LAUNCH_CHECK();

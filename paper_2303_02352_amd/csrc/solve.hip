@@ -121,9 +121,12 @@ struct QuadCols {       // group base + 16-bit offset, four slots per load
   const unsigned long long *__restrict__ dq;   // the lane's first quad
   __device__ __forceinline__ void load4(int t, int nv, int (&c)[4]) const {
     const unsigned long long d = ldx<unsigned long long, kStream>(dq + t * 64);
+    int base[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) base[j] = bp[4 * t + j];   // in range: cbase is padded
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < nv) c[j] = bp[4 * t + j] + static_cast<int>((d >> (16 * j)) & 0xffffu);
+      if (j < nv) c[j] = base[j] + static_cast<int>((d >> (16 * j)) & 0xffffu);
   }
 };
 
@@ -149,15 +152,42 @@ struct QuadCodedVals {  // table entries named by the four code bytes of a quad
   }
 };
 
-// The value table of a coded matrix copied to LDS by the whole workgroup
-// (every thread must call this, before any early return); the returned
-// reference reads it there.
+// Device-side view of a matrix's values.  For a coded matrix each
+// wavefront keeps its own copy of the value table in LDS (sdict holds
+// kDictMax entries per wavefront): a table of at most 64 entries is loaded
+// one entry per lane into a register when the kernel starts and written to
+// LDS (publish) only before the first lookup, so its load overlaps the first
+// loads of the rows; a larger table is copied at once.  A wavefront's LDS
+// accesses complete in issue order, so no workgroup barrier is needed.
 template <class T>
-__device__ __forceinline__ ValRef<T> stage_dict(const ValRef<T> &V, T *sdict) {
-  if (!V.code) return V;   // uniform: a kernel argument
-  for (int i = threadIdx.x; i < V.ndict; i += blockDim.x) sdict[i] = V.dict[i];
-  __syncthreads();
-  return ValRef<T>{V.val, V.code, sdict, V.ndict};
+struct ValDev {
+  const T *val;
+  const unsigned char *code;   // null: read val
+  T *mine;                     // this wavefront's table in LDS
+  T reg;                       // entry `lane` of a small table
+  int ndict;
+  __device__ __forceinline__ void publish() const {
+    if (code && ndict <= kWave) {   // uniform
+      const int lane = threadIdx.x & (kWave - 1);
+      if (lane < ndict) mine[lane] = reg;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+};
+
+template <class T>
+__device__ __forceinline__ ValDev<T> stage_dict(const ValRef<T> &V, T *sdict) {
+  ValDev<T> D{V.val, V.code, nullptr, T(0), V.ndict};
+  if (!V.code) return D;   // uniform: a kernel argument
+  const int lane = threadIdx.x & (kWave - 1);
+  D.mine = sdict + (threadIdx.x / kWave) * kDictMax;
+  if (V.ndict <= kWave) {
+    D.reg = V.dict[lane < V.ndict ? lane : 0];
+  } else {
+    for (int i = lane; i < V.ndict; i += kWave) D.mine[i] = V.dict[i];
+    __builtin_amdgcn_wave_barrier();
+  }
+  return D;
 }
 
 template <class T>
@@ -182,7 +212,7 @@ struct Corrected {      // (x + P e)_c = x_c + p_c e[agg_c], the prolongation's 
 // and read with scalar loads.  Every combination folds the same terms in the
 // same order: identical bits.
 template <class T, bool kStream, class G>
-__device__ __forceinline__ void sell_row_g(const SellRef &S, const ValRef<T> &V, G x, int r, T &sum,
+__device__ __forceinline__ void sell_row_g(const SellRef &S, const ValDev<T> &V, G x, int r, T &sum,
                                            T &l1) {
   const int s = __builtin_amdgcn_readfirstlane(r >> 6);
   const int b = S.sptr[s], width = (S.sptr[s + 1] - b) >> 6;
@@ -193,8 +223,8 @@ __device__ __forceinline__ void sell_row_g(const SellRef &S, const ValRef<T> &V,
   const int64_t lq = static_cast<int64_t>(q) * 64 + lane;   // the lane's first quad
   const QuadCols<kStream> qcols{S.cbase + g, reinterpret_cast<const unsigned long long *>(S.cdel) + lq};
   const PlainCols<kStream> pcols{S.col + b + lane};
-  if (V.code) {
-    const QuadCodedVals<T, kStream> vals{reinterpret_cast<const unsigned *>(V.code) + lq, V.dict};
+  if (V.code) {   // V.publish() has run on the whole wavefront
+    const QuadCodedVals<T, kStream> vals{reinterpret_cast<const unsigned *>(V.code) + lq, V.mine};
     if (compact) row_fold<T, kStream>(qcols, vals, x, width, sum, l1);
     else row_fold<T, kStream>(pcols, vals, x, width, sum, l1);
   } else {
@@ -205,7 +235,7 @@ __device__ __forceinline__ void sell_row_g(const SellRef &S, const ValRef<T> &V,
 }
 
 template <class T, bool kStream = true>
-__device__ __forceinline__ void sell_row(const SellRef &S, const ValRef<T> &V,
+__device__ __forceinline__ void sell_row(const SellRef &S, const ValDev<T> &V,
                                          const T *__restrict__ x, int r, T &sum, T &l1) {
   sell_row_g<T, kStream>(S, V, Plain<T>{x}, r, sum, l1);
 }
@@ -217,18 +247,27 @@ __device__ __forceinline__ void sell_row(const SellRef &S, const ValRef<T> &V,
 // width are read at clamped, in-range places and left out of the fold, so
 // the fold is the one of row_fold.  Returns false (nothing done) otherwise.
 template <class T, bool kStream, class G>
-__device__ __forceinline__ bool fold2_short(const SellRef &S, const ValRef<T> &V, G x, int sa, int sb,
+__device__ __forceinline__ bool fold2_short(const SellRef &S, const ValDev<T> &V, G x, int sa, int sb,
                                             int lane, T &sum0, T &l10, T &sum1, T &l11) {
   if (!V.code || !S.cdel) return false;
-  const int ba = S.sptr[sa], wa = (S.sptr[sa + 1] - ba) >> 6;
-  const int bb = S.sptr[sb], wb = (S.sptr[sb + 1] - bb) >> 6;
-  if (wa < 1 || wb < 1 || wa > 8 || wb > 8) return false;
+  // every scalar read first (slice bounds, quad offsets, then the 8 group
+  // bases of each slice, in range through the padding), the tests after
+  const int ba = S.sptr[sa], ea = S.sptr[sa + 1], bb = S.sptr[sb], eb = S.sptr[sb + 1];
+  const int qsa = S.qptr[sa], qsb = S.qptr[sb];
+  const int wa = (ea - ba) >> 6, wb = (eb - bb) >> 6;
   const int ga = ba >> 6, gb = bb >> 6;
-  if (S.cbase[ga] < 0 || S.cbase[gb] < 0) return false;
+  int basea[8], baseb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    basea[j] = S.cbase[ga + j];
+    baseb[j] = S.cbase[gb + j];
+  }
+  if (wa < 1 || wb < 1 || wa > 8 || wb > 8) return false;
+  if (basea[0] < 0 || baseb[0] < 0) return false;
   const unsigned long long *cd = reinterpret_cast<const unsigned long long *>(S.cdel);
   const unsigned *cc = reinterpret_cast<const unsigned *>(V.code);
-  const int64_t qa = static_cast<int64_t>(S.qptr[sa]) * 64 + lane;
-  const int64_t qb = static_cast<int64_t>(S.qptr[sb]) * 64 + lane;
+  const int64_t qa = static_cast<int64_t>(qsa) * 64 + lane;
+  const int64_t qb = static_cast<int64_t>(qsb) * 64 + lane;
   const int ta = wa > 4 ? 64 : 0, tb = wb > 4 ? 64 : 0;   // second quad, or the first again
   const unsigned long long da0 = ldx<unsigned long long, kStream>(cd + qa);
   const unsigned long long da1 = ldx<unsigned long long, kStream>(cd + qa + ta);
@@ -244,20 +283,21 @@ __device__ __forceinline__ bool fold2_short(const SellRef &S, const ValRef<T> &V
     const unsigned long long dA = j < 4 ? da0 : da1, dB = j < 4 ? db0 : db1;
     const int offA = static_cast<int>((dA >> (16 * (j & 3))) & 0xffffu);
     const int offB = static_cast<int>((dB >> (16 * (j & 3))) & 0xffffu);
-    ca[j] = j < wa ? S.cbase[ga + j] + offA : rowa;
-    cb[j] = j < wb ? S.cbase[gb + j] + offB : rowb;
+    ca[j] = j < wa ? basea[j] + offA : rowa;
+    cb[j] = j < wb ? baseb[j] + offB : rowb;
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     xa[j] = x(ca[j]);
     xb[j] = x(cb[j]);
   }
+  V.publish();
   T acc0 = T(0), m0 = T(0), acc1 = T(0), m1 = T(0);
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const unsigned kA = j < 4 ? ka0 : ka1, kB = j < 4 ? kb0 : kb1;
-    const T aA = V.dict[(kA >> (8 * (j & 3))) & 0xffu];
-    const T aB = V.dict[(kB >> (8 * (j & 3))) & 0xffu];
+    const T aA = V.mine[(kA >> (8 * (j & 3))) & 0xffu];
+    const T aB = V.mine[(kB >> (8 * (j & 3))) & 0xffu];
     if (j < wa) {
       acc0 = acc0 + aA * xa[j];
       m0 = m0 + fabs(aA);
@@ -277,8 +317,9 @@ __device__ __forceinline__ bool fold2_short(const SellRef &S, const ValRef<T> &V
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, ValRef<T> vref,
                                                  const T *__restrict__ x, T *__restrict__ y) {
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
+  val.publish();   // before any lane leaves
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -294,8 +335,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRe
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ x, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
+  val.publish();   // before any lane leaves
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -307,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRe
 // Rows r0 and r0 + 256 of a 512-row workgroup (two slices per wavefront),
 // for coded levels: out(r, sum, l1) for each row below n.
 template <class T, bool kStream, class G, class F>
-__device__ __forceinline__ void rows2(const SellRef &S, const ValRef<T> &V, G x, int n, int r0, F out) {
+__device__ __forceinline__ void rows2(const SellRef &S, const ValDev<T> &V, G x, int n, int r0, F out) {
   const int r1 = r0 + kBlock;
   const int sa = __builtin_amdgcn_readfirstlane(r0 >> 6), sb = sa + kBlock / 64;
   const int nsl = (n + 63) >> 6;
@@ -318,6 +360,7 @@ __device__ __forceinline__ void rows2(const SellRef &S, const ValRef<T> &V, G x,
     if (r1 < n) out(r1, s1, m1);
     return;
   }
+  V.publish();   // every lane still active
   if (r0 < n) {
     sell_row_g<T, kStream>(S, V, x, r0, s0, m0);
     out(r0, s0, m0);
@@ -335,8 +378,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep2(const int *skip, int n, SellR
                                                    const T *__restrict__ rhs,
                                                    const T *__restrict__ x, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
   const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
   rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T l1) {
     const T di = T(1) / l1;
@@ -352,8 +395,8 @@ __global__ void __launch_bounds__(kBlock) k_resid_scaled2(const int *skip, int n
                                                           const T *__restrict__ x,
                                                           T *__restrict__ t) {
   AMG_SKIP_IF_DONE();
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
   const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
   rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T) { t[r] = pval[r] * (rhs[r] - sum); });
 }
@@ -370,8 +413,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_corr(const int *skip, int n, S
                                                        const T *__restrict__ pval,
                                                        const T *__restrict__ e, T *__restrict__ xn) {
   AMG_SKIP_IF_DONE();
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
+  val.publish();   // before any lane leaves
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   const Corrected<T> y{x, pval, agg, e};
@@ -401,8 +445,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_scaled(const int *skip, int n,
                                                          const T *__restrict__ x,
                                                          T *__restrict__ t) {
   AMG_SKIP_IF_DONE();
-  __shared__ T sdict[kDictMax];
-  const ValRef<T> val = stage_dict(vref, sdict);
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<T> val = stage_dict(vref, sdict);
+  val.publish();   // before any lane leaves
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (r >= n) return;
   T s, m;
@@ -722,8 +767,9 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, SellRef S,
                                                      double *__restrict__ r,
                                                      double *__restrict__ part, FirstOut fo) {
   __shared__ double red[kBlock / kWave];
-  __shared__ double sdict[kDictMax];
-  const ValRef<double> val = stage_dict(vref, sdict);
+  __shared__ double sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<double> val = stage_dict(vref, sdict);
+  val.publish();   // before any lane leaves
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   double rr = 0.0;
 #pragma unroll
@@ -771,8 +817,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_spmv_dots(
     const double *__restrict__ q, double *__restrict__ v, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock / kWave];
-  __shared__ double sdict[kDictMax];
-  const ValRef<double> val = stage_dict(vref, sdict);
+  __shared__ double sdict[kDictMax * (kBlock / kWave)];
+  const ValDev<double> val = stage_dict(vref, sdict);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   double al = 0.0, be = 0.0, ga = 0.0;
   static_assert(kRowsDot == 2, "rows r and r + kBlock of the workgroup's 2 kBlock rows");
