@@ -22,8 +22,9 @@
  * message for the last failure on the calling thread.
  *
  * Threading: a hierarchy may be used by one host thread at a time.  All work
- * is ordered on the hierarchy's stream (amg_params.stream, NULL = the null
- * stream); calls that return host-visible results synchronise that stream.
+ * is ordered on the hierarchy's stream (amg_params.stream, or a library-owned
+ * stream that is ordered with null-stream work when it is NULL); calls that
+ * return host-visible results synchronise that stream.
  */
 #ifndef AMG355_H
 #define AMG355_H
@@ -101,7 +102,13 @@ typedef struct {
   int32_t precision;       /* AMG_PREC_* */
   int32_t value_coding;    /* AMG_VALUES_* */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
-  void *stream;            /* hipStream_t on which all work is ordered; NULL = null stream */
+  void *stream;            /* hipStream_t on which all work is ordered; NULL = the library's
+                              own stream on the current device (one per device, shared by
+                              every hierarchy set up with NULL; pass distinct streams to
+                              use hierarchies from several threads at once).  A caller's
+                              stream must stay valid until amg_destroy: the hierarchy's
+                              device memory comes from the device's memory pool in that
+                              stream's order. */
 } amg_params;
 
 typedef struct amg_hierarchy amg_hierarchy;   /* opaque, owned by the library */

@@ -41,29 +41,98 @@ template <class T>
 struct dvec {
   T *p = nullptr;
   size_t n = 0;
+  hipStream_t st = nullptr;   // stream of a pooled allocation
+  bool pooled = false;
   dvec() = default;
   explicit dvec(size_t count) { alloc(count); }
   dvec(const dvec &) = delete;
   dvec &operator=(const dvec &) = delete;
-  dvec(dvec &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  dvec(dvec &&o) noexcept : p(o.p), n(o.n), st(o.st), pooled(o.pooled) { o.p = nullptr; o.n = 0; }
   dvec &operator=(dvec &&o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; st = o.st; pooled = o.pooled;
+      o.p = nullptr; o.n = 0;
+    }
     return *this;
   }
   ~dvec() { release(); }
-  void alloc(size_t count) {
-    release();
-    n = count;
-    if (count) AMG_HIP(hipMalloc(reinterpret_cast<void **>(&p), sizeof(T) * count));
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
+  void alloc(size_t count);
+  void release();
   size_t bytes() const { return sizeof(T) * n; }
   T *get() const { return p; }
 };
+
+// While a PoolScope is alive on a host thread, the dvec allocations it makes
+// come from the device's memory pool, ordered on the scope's stream, and are
+// freed in order on that stream (which must outlive them): no device-wide
+// synchronisation per allocation or free, and memory released by one
+// hierarchy is reused by the next.  Outside a scope dvec uses hipMalloc.
+struct PoolScope {
+  static hipStream_t &stream() {
+    static thread_local hipStream_t s = nullptr;
+    return s;
+  }
+  static bool &active() {
+    static thread_local bool on = false;
+    return on;
+  }
+  // stream on which pooled releases are ordered instead of their own (set
+  // by FreeOn), or null
+  static hipStream_t &free_override() {
+    static thread_local hipStream_t s = nullptr;
+    return s;
+  }
+  hipStream_t prev_s;
+  bool prev_on;
+  explicit PoolScope(hipStream_t s) : prev_s(stream()), prev_on(active()) {
+    stream() = s;
+    active() = true;
+  }
+  ~PoolScope() {
+    stream() = prev_s;
+    active() = prev_on;
+  }
+  PoolScope(const PoolScope &) = delete;
+  PoolScope &operator=(const PoolScope &) = delete;
+};
+
+// Pooled releases made while a FreeOn is alive are ordered on its stream,
+// for objects whose own stream is synchronised and may not outlive them.
+struct FreeOn {
+  hipStream_t prev;
+  explicit FreeOn(hipStream_t s) : prev(PoolScope::free_override()) { PoolScope::free_override() = s; }
+  ~FreeOn() { PoolScope::free_override() = prev; }
+  FreeOn(const FreeOn &) = delete;
+  FreeOn &operator=(const FreeOn &) = delete;
+};
+
+// The library's own stream on the current device: created on first use and
+// kept for the life of the process (pool memory freed on a stream must not
+// outlive it).  A blocking stream, so it stays ordered with null-stream
+// work.  nullptr if it cannot be created.
+hipStream_t library_stream();
+
+template <class T>
+void dvec<T>::release() {
+  if (p) {
+    if (pooled) (void)hipFreeAsync(p, PoolScope::free_override() ? PoolScope::free_override() : st);
+    else (void)hipFree(p);
+  }
+  p = nullptr;
+  n = 0;
+}
+
+template <class T>
+void dvec<T>::alloc(size_t count) {
+  release();
+  n = count;
+  pooled = PoolScope::active();
+  st = pooled ? PoolScope::stream() : nullptr;
+  if (!count) return;
+  if (pooled) AMG_HIP(hipMallocAsync(reinterpret_cast<void **>(&p), sizeof(T) * count, st));
+  else AMG_HIP(hipMalloc(reinterpret_cast<void **>(&p), sizeof(T) * count));
+}
 
 // Stream-ordered scratch array for work inside one host function: allocated
 // and freed in order on `s` from the device's memory pool (which keeps the
@@ -260,7 +329,6 @@ struct Timing {
 struct amg_hierarchy {
   amg_params p{};
   hipStream_t stream = nullptr;
-  int own_stream = 0;
   std::vector<amg::Level> L;
   int coarse_dense = 0;
   amg::dvec<double> Ainv;      // inverse of the coarsest matrix, column-major

@@ -3,6 +3,9 @@
 // across the boundary.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -74,6 +77,17 @@ int64_t device_bytes(const amg_hierarchy *h) {
   b += h->partials.bytes() + h->sc.bytes();
   return b;
 }
+
+hipStream_t library_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  std::lock_guard<std::mutex> lock(mu);
+  if (static_cast<int>(streams.size()) <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev] && hipStreamCreate(&streams[dev]) != hipSuccess) streams[dev] = nullptr;
+  return streams[dev];
+}
 }  // namespace amg
 
 extern "C" {
@@ -112,16 +126,17 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
   if (p->stream) {
     h->stream = static_cast<hipStream_t>(p->stream);
   } else {
-    // The null stream cannot be captured into a graph: work goes to a
-    // library-owned blocking stream, which stays ordered with null-stream work.
-    if (hipStreamCreate(&h->stream) != hipSuccess) {
+    // The null stream cannot be captured into a graph: work goes to the
+    // library's own blocking stream, which stays ordered with null-stream work.
+    h->stream = amg::library_stream();
+    if (!h->stream) {
       delete h;
       return set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
     }
-    h->own_stream = 1;
   }
   st = guarded([&] {
     amg::keep_pool_memory();
+    amg::PoolScope pool(h->stream);
     amg::build_hierarchy(h, A);
     return AMG_OK;
   });
@@ -159,10 +174,8 @@ void amg_destroy(amg_hierarchy *h) {
   amg::destroy_graph(h);
   if (h->sc_host) (void)hipHostFree(h->sc_host);
   h->sc_host = nullptr;
-  hipStream_t s = h->stream;
-  const int own = h->own_stream;
+  amg::FreeOn on(amg::library_stream());   // h->stream is idle and may be the caller's
   delete h;   // frees all device buffers
-  if (own) (void)hipStreamDestroy(s);
 }
 
 const char *amg_strerror(int code) {

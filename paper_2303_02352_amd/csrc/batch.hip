@@ -678,7 +678,6 @@ __global__ void k_ball_done(int *active, int *all_done, int *host_flag) {
 struct amg_batch {
   amg_params p{};
   hipStream_t stream = nullptr;
-  int own_stream = 0;
   int nsys = 0;
   std::vector<int> order;              // internal position -> user system id
   std::vector<int> pos_of;             // user system id -> internal position
@@ -1236,14 +1235,15 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   if (p->stream) {
     bt->stream = static_cast<hipStream_t>(p->stream);
   } else {
-    if (hipStreamCreate(&bt->stream) != hipSuccess) {
+    bt->stream = amg::library_stream();
+    if (!bt->stream) {
       delete bt;
       return amg::api_set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
     }
-    bt->own_stream = 1;
   }
   int st = amg::api_guarded([&] {
     amg::keep_pool_memory();
+    amg::PoolScope pool(bt->stream);
     amg::batch_build(bt, nsys, A);
     return AMG_OK;
   });
@@ -1309,10 +1309,8 @@ void amg_batch_destroy(amg_batch *bt) {
   (void)hipStreamSynchronize(bt->stream);
   amg::batch_release_graph(bt);
   if (bt->host_flag) (void)hipHostFree(bt->host_flag);
-  hipStream_t s = bt->stream;
-  const int own = bt->own_stream;
+  amg::FreeOn on(amg::library_stream());   // bt->stream is idle and may be the caller's
   delete bt;
-  if (own) (void)hipStreamDestroy(s);
 }
 
 }  // extern "C"

@@ -1267,7 +1267,8 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   for (int k = h->tail_start; k < nl; ++k) {
     const Sell &S = h->L[k].S;
     std::vector<int> sp(S.nslices + 1);
-    AMG_HIP(hipMemcpy(sp.data(), S.sptr.p, sizeof(int) * sp.size(), hipMemcpyDeviceToHost));
+    AMG_HIP(hipMemcpyAsync(sp.data(), S.sptr.p, sizeof(int) * sp.size(), hipMemcpyDeviceToHost, h->stream));
+    AMG_HIP(hipStreamSynchronize(h->stream));
     for (int q = 0; q < S.nslices; ++q) h->tail_w = std::max(h->tail_w, (sp[q + 1] - sp[q]) / kSlice);
   }
   upload_tail<double>(h, h->tail_desc_d, false);
