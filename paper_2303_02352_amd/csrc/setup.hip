@@ -389,18 +389,18 @@ __global__ void __launch_bounds__(kBlock) k_mm_commit(int n, const int *list, co
 }
 
 // Undecided neighbours whose candidate was just matched go on the recompute
-// list, once per round (stamp), and the thread that lists u recomputes its
-// candidate at once (mate does not change in this kernel; a new candidate is
-// undecided, so it never equals a matched vertex another thread compares
-// against).  A team of kTeam lanes per matched vertex, lane l taking its row
-// entries l, l + kTeam, ...
+// list, and the thread that lists u recomputes its candidate at once.  Each
+// such u is found exactly once: its candidate is one vertex, which is on the
+// matched list once (commit writes a pair once) and holds u once in its row;
+// the new candidate is undecided (mate does not change in this kernel), so it
+// never equals a matched vertex another thread compares against.  A team of
+// kTeam lanes per matched vertex, lane l taking its row entries l, l + kTeam, ...
 constexpr int kTeam = 8;
 
 __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const int *mcnt,
                                                       const int *rp, const int *ci,
                                                       const double *wgt, const int *mate,
-                                                      int *cand, int *stamp, int round,
-                                                      int *rlist, int *rcnt) {
+                                                      int *cand, int *rlist, int *rcnt) {
   __shared__ int sbuf[kStage];
   __shared__ int scnt, sbase;
   const int64_t total = static_cast<int64_t>(*mcnt) * kTeam;
@@ -415,12 +415,10 @@ __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const in
       for (int k = rp[v] + l; k < rp[v + 1]; k += kTeam) {
         const int u = ci[k];
         if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
-        if (atomicExch(&stamp[u], round) != round) {
-          cand[u] = best_candidate(u, rp, ci, wgt, mate);
-          const int pos = atomicAdd(&scnt, 1);
-          if (pos < kStage) sbuf[pos] = u;
-          else rlist[atomicAdd(rcnt, 1)] = u;
-        }
+        cand[u] = best_candidate(u, rp, ci, wgt, mate);
+        const int pos = atomicAdd(&scnt, 1);
+        if (pos < kStage) sbuf[pos] = u;
+        else rlist[atomicAdd(rcnt, 1)] = u;
       }
     }
     __syncthreads();
@@ -1288,10 +1286,9 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
   AMG_LAUNCH_CHECK();
   out.mate = wsv<int>(ws, n);
-  wsv<int> cand(ws, n), stamp(ws, n), rlist(ws, n), mbuf0(ws, n), mbuf1(ws, n);
+  wsv<int> cand(ws, n), rlist(ws, n), mbuf0(ws, n), mbuf1(ws, n);
   int *mbuf[2] = {mbuf0.p, mbuf1.p};
   hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, out.mate.p, kFree);
-  hipLaunchKernelGGL(k_fill_int, g, b, 0, s, n, stamp.p, -1);
   AMG_LAUNCH_CHECK();
   // Rounds are issued in batches of kBatch with one host read per batch.
   // cnt[2q] = matched-list length of the round before round q of the batch,
@@ -1315,7 +1312,7 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
       int *rc = cnt.p + 2 * q + 1;
       int *mc_next = cnt.p + 2 * q + 2;
       hipLaunchKernelGGL(k_mm_notify, gl, b, 0, s, mbuf[q % 2], mc, A.rp.p, A.ci.p, wgt.p,
-                         out.mate.p, cand.p, stamp.p, rounds + q, rlist.p, rc);
+                         out.mate.p, cand.p, rlist.p, rc);
       hipLaunchKernelGGL(k_mm_commit, gl, b, 0, s, n, rlist.p, rc, out.mate.p, cand.p,
                          mbuf[(q + 1) % 2], mc_next);
     }
