@@ -1084,10 +1084,19 @@ __device__ __forceinline__ unsigned dict_hash(unsigned long long k) {
   return static_cast<unsigned>(k) & (kDictSlots - 1);
 }
 
-// Slot of key k in the table, or -1 (absent; the table is never full).
+// Probes are bounded: a key that does not find its place within kDictProbe
+// slots marks the level as too varied (count > kDictMax), so no probe ever
+// walks a crowded table.
+constexpr int kDictProbe = 64;
+
+__device__ __forceinline__ int dict_count(const int *count) {
+  return __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Slot of key k in the table, or -1 (absent).
 __device__ __forceinline__ int dict_find(const unsigned long long *tab, unsigned long long k) {
   unsigned h = dict_hash(k);
-  for (int probe = 0; probe < kDictSlots; ++probe) {
+  for (int probe = 0; probe < kDictProbe; ++probe) {
     const unsigned long long t = tab[h];
     if (t == k) return static_cast<int>(h);
     if (t == kDictEmpty) return -1;
@@ -1096,16 +1105,15 @@ __device__ __forceinline__ int dict_find(const unsigned long long *tab, unsigned
   return -1;
 }
 
-// Inserts k unless present; counts new keys.  Stops adding once the count
-// passes kDictMax, so at most kDictMax + (concurrent inserters) keys land and
-// the table never fills.
+// Inserts k unless present; counts new keys.  Does nothing once the count
+// has passed kDictMax (the level stays plain then).
 __device__ __forceinline__ void dict_insert(unsigned long long *tab, int *count, unsigned long long k) {
+  if (dict_count(count) > kDictMax) return;
   unsigned h = dict_hash(k);
-  for (int probe = 0; probe < kDictSlots; ++probe) {
+  for (int probe = 0; probe < kDictProbe; ++probe) {
     unsigned long long t = tab[h];   // plain read first: present keys cost no atomic
     if (t == k) return;
     if (t == kDictEmpty) {
-      if (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > kDictMax) return;
       t = atomicCAS(&tab[h], kDictEmpty, k);
       if (t == kDictEmpty) {
         atomicAdd(count, 1);
@@ -1115,6 +1123,7 @@ __device__ __forceinline__ void dict_insert(unsigned long long *tab, int *count,
     }
     h = (h + 1) & (kDictSlots - 1);
   }
+  atomicAdd(count, kDictSlots);   // no place within the probe bound
 }
 
 // One wavefront removes duplicates among its 64 values before touching the
@@ -1125,11 +1134,10 @@ __global__ void __launch_bounds__(kBlock) k_dict_insert(int64_t m, const double 
   const int lane = threadIdx.x & (kWave - 1);
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
        i - lane < m; i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int seen = __shfl(__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), 0);
-    if (seen > kDictMax) return;   // wavefront-uniform
     const unsigned long long k = i < m ? static_cast<unsigned long long>(__double_as_longlong(v[i])) : 0ull;
     bool pending = i < m;
-    for (;;) {
+    for (int it = 0;; ++it) {
+      if ((it & 7) == 0 && __shfl(dict_count(count), 0) > kDictMax) return;   // wavefront-uniform
       const unsigned long long ball = __ballot(pending);
       if (ball == 0) break;
       const int leader = __ffsll(ball) - 1;
