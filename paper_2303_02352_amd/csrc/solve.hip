@@ -1301,6 +1301,12 @@ void destroy_graph(amg_hierarchy *h) {
   h->graph = nullptr;
 }
 
+// Iterations the host keeps queued beyond the one it waits for.
+#ifndef AMG_QUEUE_AHEAD
+#define AMG_QUEUE_AHEAD 1
+#endif
+constexpr int kAhead = AMG_QUEUE_AHEAD;
+
 // Alg. 1.  One iteration = one graph launch [V-cycle, v = A w + dots,
 // scalars, vector updates + ||r||^2, convergence test, copy of the scalars
 // to pinned host memory].  The host keeps one further iteration queued and
@@ -1336,24 +1342,25 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
       if (h->graph_exec) AMG_HIP(hipGraphLaunch(h->graph_exec, s));
       else enqueue_iteration(h);
     };
-    hipEvent_t ev[2];
-    AMG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    AMG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    launch();
-    AMG_HIP(hipEventRecord(ev[1], s));
+    // iteration k (from 1) records ev[k % (kAhead + 1)]; before waiting on
+    // iteration j at most j + kAhead have been launched, so its event is intact
+    hipEvent_t ev[kAhead + 1];
+    for (hipEvent_t &e : ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    int launched = 0;
+    auto push = [&]() {
+      launch();
+      ++launched;
+      AMG_HIP(hipEventRecord(ev[launched % (kAhead + 1)], s));
+    };
+    for (int k = 0; k < kAhead && launched < maxit; ++k) push();
     for (int j = 1;; ++j) {
-      const bool more = j + 1 <= maxit;
-      if (more) {
-        launch();
-        AMG_HIP(hipEventRecord(ev[(j + 1) % 2], s));
-      }
-      AMG_HIP(hipEventSynchronize(ev[j % 2]));
+      if (launched < maxit) push();
+      AMG_HIP(hipEventSynchronize(ev[j % (kAhead + 1)]));
       const volatile int *done = &h->sc_host->done;
-      if (*done || !more) break;
+      if (*done || j >= maxit) break;
     }
     AMG_HIP(hipStreamSynchronize(s));
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
+    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
     st = *h->sc_host;
   }
   AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
