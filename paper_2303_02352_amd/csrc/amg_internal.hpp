@@ -97,6 +97,16 @@ struct PoolScope {
   PoolScope &operator=(const PoolScope &) = delete;
 };
 
+// Allocations made while a NoPool is alive use hipMalloc even inside a
+// PoolScope: for buffers that outlive the scope's stream (per-thread caches).
+struct NoPool {
+  bool prev;
+  NoPool() : prev(PoolScope::active()) { PoolScope::active() = false; }
+  ~NoPool() { PoolScope::active() = prev; }
+  NoPool(const NoPool &) = delete;
+  NoPool &operator=(const NoPool &) = delete;
+};
+
 // Pooled releases made while a FreeOn is alive are ordered on its stream,
 // for objects whose own stream is synchronised and may not outlive them.
 struct FreeOn {
@@ -107,11 +117,13 @@ struct FreeOn {
   FreeOn &operator=(const FreeOn &) = delete;
 };
 
-// The library's own stream on the current device: created on first use and
-// kept for the life of the process (pool memory freed on a stream must not
-// outlive it).  A blocking stream, so it stays ordered with null-stream
-// work.  nullptr if it cannot be created.
-hipStream_t library_stream();
+// The library's own streams on the current device (slot 0: the stream of
+// hierarchies given none; slots 1..kBuildThreads: setup worker threads):
+// created on first use and kept for the life of the process (pool memory
+// freed on a stream must not outlive it).  Blocking streams, so they stay
+// ordered with null-stream work.  nullptr if one cannot be created.
+constexpr int kBuildThreads = 8;   // host threads building a batch's hierarchies
+hipStream_t library_stream(int slot = 0);
 
 template <class T>
 void dvec<T>::release() {

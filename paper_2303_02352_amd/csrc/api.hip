@@ -78,15 +78,16 @@ int64_t device_bytes(const amg_hierarchy *h) {
   return b;
 }
 
-hipStream_t library_stream() {
+hipStream_t library_stream(int slot) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (slot < 0 || slot > kBuildThreads || hipGetDevice(&dev) != hipSuccess) return nullptr;
   static std::mutex mu;
-  static std::vector<hipStream_t> streams;
+  static std::vector<hipStream_t> streams;   // (kBuildThreads + 1) per device
   std::lock_guard<std::mutex> lock(mu);
-  if (static_cast<int>(streams.size()) <= dev) streams.resize(dev + 1, nullptr);
-  if (!streams[dev] && hipStreamCreate(&streams[dev]) != hipSuccess) streams[dev] = nullptr;
-  return streams[dev];
+  const size_t at = static_cast<size_t>(dev) * (kBuildThreads + 1) + slot;
+  if (streams.size() <= at) streams.resize(at + 1, nullptr);
+  if (!streams[at] && hipStreamCreate(&streams[at]) != hipSuccess) streams[at] = nullptr;
+  return streams[at];
 }
 }  // namespace amg
 

@@ -18,9 +18,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <new>
 #include <numeric>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -943,25 +947,66 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
   std::vector<amg_hierarchy *> H(nsys, nullptr);
   struct Cleanup {
     std::vector<amg_hierarchy *> &H;
+    hipStream_t s;
     ~Cleanup() {
+      (void)hipStreamSynchronize(s);   // the copies below read the systems' buffers
       for (auto *h : H)
         if (h) { destroy_graph(h); if (h->sc_host) (void)hipHostFree(h->sc_host); delete h; }
     }
-  } cleanup{H};
+  } cleanup{H, s};
   bt->nsys = nsys;
   bt->nl.assign(nsys, 0);
   bt->n0.assign(nsys, 0);
-  for (int sid = 0; sid < nsys; ++sid) {
-    H[sid] = new amg_hierarchy();
-    H[sid]->p = bt->p;
-    H[sid]->p.smooth_vector = nullptr;
-    H[sid]->p.value_coding = AMG_VALUES_PLAIN;   // the batched kernels read plain values
-    if (bt->p.smooth_vec == AMG_SMOOTH_GIVEN) fail(AMG_ERR_UNSUPPORTED, "batched setup takes no given smooth vector");
-    H[sid]->stream = s;
-    build_hierarchy(H[sid], &A[sid]);
-    if (bt->p.precond && !H[sid]->coarse_dense)
-      fail(AMG_ERR_UNSUPPORTED, "batched solve needs a direct coarsest solve on every system");
+  if (bt->p.smooth_vec == AMG_SMOOTH_GIVEN) fail(AMG_ERR_UNSUPPORTED, "batched setup takes no given smooth vector");
+  // The systems' hierarchies are independent: host threads build them
+  // concurrently, each on a library stream of its own (setups are chains of
+  // small kernels and host reads, so they overlap well on the GPU).
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  const int nthreads = std::max(1, std::min(nsys, kBuildThreads));
+  std::atomic<int> next{0};
+  std::mutex emu;
+  Error first{AMG_OK, ""};
+  auto worker = [&](int w) {
+    try {
+      AMG_HIP(hipSetDevice(dev));
+      hipStream_t ws = library_stream(1 + w);
+      if (!ws) fail(AMG_ERR_DEVICE, "hipStreamCreate failed");
+      PoolScope pool(ws);
+      for (int sid = next++; sid < nsys; sid = next++) {
+        {
+          std::lock_guard<std::mutex> lock(emu);
+          if (first.code != AMG_OK) return;
+        }
+        amg_hierarchy *h = new amg_hierarchy();
+        H[sid] = h;
+        h->p = bt->p;
+        h->p.smooth_vector = nullptr;
+        h->p.value_coding = AMG_VALUES_PLAIN;   // the batched kernels read plain values
+        h->stream = ws;
+        build_hierarchy(h, &A[sid]);
+        AMG_HIP(hipStreamSynchronize(ws));
+        if (bt->p.precond && !h->coarse_dense)
+          fail(AMG_ERR_UNSUPPORTED, "batched solve needs a direct coarsest solve on every system");
+      }
+    } catch (const Error &e) {
+      std::lock_guard<std::mutex> lock(emu);
+      if (first.code == AMG_OK) first = e;
+    } catch (const std::bad_alloc &) {
+      std::lock_guard<std::mutex> lock(emu);
+      if (first.code == AMG_OK) first = Error{AMG_ERR_NOMEM, "host allocation failed"};
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(emu);
+      if (first.code == AMG_OK) first = Error{AMG_ERR_DEVICE, "unexpected error in a setup thread"};
+    }
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nthreads; ++w) pool.emplace_back(worker, w);
+    worker(0);
+    for (std::thread &th : pool) th.join();
   }
+  if (first.code != AMG_OK) fail(first.code, first.msg);
   // deepest systems first (stable): active systems on any level form a prefix
   std::vector<int> order(nsys);
   std::iota(order.begin(), order.end(), 0);

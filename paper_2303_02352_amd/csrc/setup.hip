@@ -115,7 +115,10 @@ int *scan_scratch(int n) {
   thread_local std::vector<dvec<int>> bufs;
   if (static_cast<int>(bufs.size()) <= dev) bufs.resize(dev + 1);
   const size_t need = scan_scratch_ints(n);
-  if (bufs[dev].n < need) bufs[dev].alloc(std::max<size_t>(need, 1 << 16));
+  if (bufs[dev].n < need) {
+    NoPool plain;   // the cache outlives any one setup and its stream
+    bufs[dev].alloc(std::max<size_t>(need, 1 << 16));
+  }
   return bufs[dev].p;
 }
 
