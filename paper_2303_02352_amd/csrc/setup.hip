@@ -316,21 +316,40 @@ __device__ __forceinline__ bool key_gt(double wa, int ha, int la, double wb, int
 //
 // List kernels run grid-stride over a device-side count; list == nullptr
 // means "every vertex 0..n-1".
+
+// Heaviest eligible edge of i (row entries [b, e)) to an undecided
+// neighbour, or -1.  Entries are taken eight at a time: their weights and
+// columns, then the neighbours' states, are all in flight before any test
+// (the maximum under the strict order does not depend on the scan order).
+__device__ __forceinline__ int best_candidate_in(int i, int b, int e, const int *ci, const double *wgt,
+                                                 const int *mate) {
+  int best = -1, bh = 0, bl = 0;
+  double bw = 0.0;
+  for (int k0 = b; k0 < e; k0 += 8) {
+    double x[8];
+    int j[8], mj[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u < e ? k0 + u : e - 1;
+      x[u] = wgt[k];
+      j[u] = ci[k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mj[u] = mate[j[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u >= e || !(x[u] > 0.0) || mj[u] != kFree) continue;
+      const int hi = j[u] > i ? j[u] : i, lo = j[u] > i ? i : j[u];
+      if (best < 0 || key_gt(x[u], hi, lo, bw, bh, bl)) { best = j[u]; bw = x[u]; bh = hi; bl = lo; }
+    }
+  }
+  return best;
+}
+
 // Heaviest eligible edge of i to an undecided neighbour (-1: none).
 __device__ __forceinline__ int best_candidate(int i, const int *rp, const int *ci, const double *wgt,
                                               const int *mate) {
-  int best = -1, bh = 0, bl = 0;
-  double bw = 0.0;
-#pragma unroll 8
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const double x = wgt[k];
-    if (!(x > 0.0)) continue;
-    const int j = ci[k];
-    if (mate[j] != kFree) continue;
-    const int hi = j > i ? j : i, lo = j > i ? i : j;
-    if (best < 0 || key_gt(x, hi, lo, bw, bh, bl)) { best = j; bw = x; bh = hi; bl = lo; }
-  }
-  return best;
+  return best_candidate_in(i, rp[i], rp[i + 1], ci, wgt, mate);
 }
 
 __global__ void __launch_bounds__(kBlock) k_mm_cand(int n, const int *rp, const int *ci,
@@ -416,9 +435,12 @@ __global__ void __launch_bounds__(kBlock) k_mm_notify(const int *mlist, const in
       const int v = mlist[g / kTeam];
       const int l = static_cast<int>(g % kTeam);
       for (int k = rp[v] + l; k < rp[v + 1]; k += kTeam) {
+        // the state of u and its row bounds are read together
         const int u = ci[k];
-        if (u == v || !(wgt[k] > 0.0) || mate[u] != kFree || cand[u] != v) continue;
-        cand[u] = best_candidate(u, rp, ci, wgt, mate);
+        const double wk = wgt[k];
+        const int mu = mate[u], cu = cand[u], bu = rp[u], eu = rp[u + 1];
+        if (u == v || !(wk > 0.0) || mu != kFree || cu != v) continue;
+        cand[u] = best_candidate_in(u, bu, eu, ci, wgt, mate);
         const int pos = atomicAdd(&scnt, 1);
         if (pos < kStage) sbuf[pos] = u;
         else rlist[atomicAdd(rcnt, 1)] = u;
