@@ -329,11 +329,14 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int n, SellRef S, ValRef<T> vre
 
 // l1-Jacobi sweep: xn = x + dinv * (r - A x), dinv = 1 / sum_j |a_ij| taken
 // from the streamed row (the same fold that defines the stored diagonal).
+// xw: when not null the new iterate is stored there widened to binary64
+// instead of in xn (the last sweep of a binary32 cycle).
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRef S,
                                                   ValRef<T> vref,
                                                   const T *__restrict__ rhs,
-                                                  const T *__restrict__ x, T *__restrict__ xn) {
+                                                  const T *__restrict__ x, T *__restrict__ xn,
+                                                  double *__restrict__ xw) {
   AMG_SKIP_IF_DONE();
   __shared__ T sdict[kDictMax * (kBlock / kWave)];
   const ValDev<T> val = stage_dict(vref, sdict);
@@ -343,7 +346,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep(const int *skip, int n, SellRe
   T s, m;
   sell_row<T, kStream>(S, val, x, r, s, m);
   const T di = T(1) / m;
-  xn[r] = x[r] + di * (rhs[r] - s);
+  const T v = x[r] + di * (rhs[r] - s);
+  if (xw) xw[r] = static_cast<double>(v);
+  else xn[r] = v;
 }
 
 // Rows r0 and r0 + 256 of a 512-row workgroup (two slices per wavefront),
@@ -376,14 +381,17 @@ template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) k_sweep2(const int *skip, int n, SellRef S,
                                                    ValRef<T> vref,
                                                    const T *__restrict__ rhs,
-                                                   const T *__restrict__ x, T *__restrict__ xn) {
+                                                   const T *__restrict__ x, T *__restrict__ xn,
+                                                   double *__restrict__ xw) {
   AMG_SKIP_IF_DONE();
   __shared__ T sdict[kDictMax * (kBlock / kWave)];
   const ValDev<T> val = stage_dict(vref, sdict);
   const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
   rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T l1) {
     const T di = T(1) / l1;
-    xn[r] = x[r] + di * (rhs[r] - sum);
+    const T v = x[r] + di * (rhs[r] - sum);
+    if (xw) xw[r] = static_cast<double>(v);
+    else xn[r] = v;
   });
 }
 
@@ -972,24 +980,26 @@ bool streamed(const Level &L) {
   return bytes >= AMG_STREAM_MIN_MB * 1048576.0;
 }
 
+// xw: store the new iterate widened to binary64 there instead of in xn.
 template <class T>
-void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s) {
+void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s,
+                  double *xw = nullptr) {
   const int n = L.A.n;
   if (L.S.ndict) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_sweep2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn);
+                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn, xw);
     else
       hipLaunchKernelGGL((k_sweep2<T, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn);
+                         sell_ref(L.S), val_ref<T>(L.S), rhs, x, xn, xw);
     return;
   }
   if (streamed<T>(L))
     hipLaunchKernelGGL((k_sweep<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
-                       val_ref<T>(L.S), rhs, x, xn);
+                       val_ref<T>(L.S), rhs, x, xn, xw);
   else
     hipLaunchKernelGGL((k_sweep<T, false>), grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
-                       val_ref<T>(L.S), rhs, x, xn);
+                       val_ref<T>(L.S), rhs, x, xn, xw);
 }
 
 template <class T>
@@ -1068,8 +1078,12 @@ T *first_buffer(amg_hierarchy *h, int k, T *out) {
 
 // Level k of the V-cycle in precision T; the result lands in `out`.
 // first_done: the first smoothing iterate is already in first_buffer(k).
+// wide (binary32 fine level only): when the level ends with a plain sweep,
+// that sweep stores the result widened to binary64 there instead of in out,
+// and the call returns true.
 template <class T>
-void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out, bool first_done) {
+bool vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out, bool first_done,
+                  double *wide = nullptr) {
   hipStream_t s = h->stream;
   Level &L = h->L[k];
   const int n = L.A.n;
@@ -1080,7 +1094,7 @@ void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
     hipLaunchKernelGGL(kern, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k,
                        tail_desc<T>(h) + (k - h->tail_start), h->Ainv.p, h->coarse_dense,
                        P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out);
-    return;
+    return false;
   }
   if (k == nl - 1) {
     {
@@ -1091,7 +1105,7 @@ void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
                            rhs, A);
       for (int q = 1; q < P.coarse_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
     }
-    return;
+    return false;
   }
   const int swaps = (P.pre_sweeps > 0 ? P.pre_sweeps - 1 : 0) + P.post_sweeps;
   T *A = (swaps % 2 == 0) ? out : tbuf<T>(L);
@@ -1114,11 +1128,15 @@ void vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
   if (P.post_sweeps == 0) {
     hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
                        xbuf<T>(C), A);
-    return;
+    return false;
   }
   launch_corr_sweep<T>(skip, L, rhs, xbuf<T>(C), A, B, s);
   std::swap(A, B);
-  for (int q = 1; q < P.post_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
+  for (int q = 1; q < P.post_sweeps; ++q) {
+    launch_sweep<T>(skip, L, rhs, A, B, s, q + 1 == P.post_sweeps ? wide : nullptr);
+    std::swap(A, B);
+  }
+  return wide != nullptr && P.post_sweeps >= 2;
 }
 
 // Mixed precision: the residual is rounded to binary32 on entry (fused with
@@ -1135,8 +1153,8 @@ void vcycle_mixed(amg_hierarchy *h, const int *skip, const double *r, double *z,
   float *x1 = first_buffer<float>(h, 0, L.xf.p);
   if (!first_done)
     hipLaunchKernelGGL(k_d2f_first, grid_for(n), dim3(kBlock), 0, s, skip, n, r, L.dinvf.p, L.rf.p, x1);
-  vcycle_level<float>(h, skip, 0, L.rf.p, L.xf.p, x1 != nullptr);
-  hipLaunchKernelGGL(k_f2d, grid_for(n), dim3(kBlock), 0, s, skip, n, L.xf.p, z);
+  if (!vcycle_level<float>(h, skip, 0, L.rf.p, L.xf.p, x1 != nullptr, z))
+    hipLaunchKernelGGL(k_f2d, grid_for(n), dim3(kBlock), 0, s, skip, n, L.xf.p, z);
 }
 
 // first_done: the residual kernel already wrote the first smoothing iterate
