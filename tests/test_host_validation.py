@@ -43,7 +43,7 @@ def test_bad_csr_header_is_invalid(n, nnz, arrays):
                                          ("coarse_sweeps", 0), ("pre_sweeps", -1), ("post_sweeps", -1),
                                          ("smooth_sweeps", -1), ("coarse_solver", 7), ("smooth_vec", 5),
                                          ("smooth_vec", amd.AMG_SMOOTH_GIVEN), ("precision", 3),
-                                         ("precond", 2)])
+                                         ("precond", 2), ("value_coding", 2), ("value_coding", -1)])
 def test_bad_parameter_is_invalid(field, value):
     A, keep = _csr(1, 1)
     p = amd.default_params()
@@ -51,6 +51,12 @@ def test_bad_parameter_is_invalid(field, value):
     st, h = _setup(A, p)
     assert st == amd.AMG_ERR_INVALID and not h.value
     assert amd.load().amg_last_error().decode()
+
+
+def test_default_parameters():
+    p = amd.default_params()
+    assert (p.aggr_steps, p.max_levels, p.coarse_max, p.pre_sweeps, p.post_sweeps) == (2, 40, 100, 4, 4)
+    assert p.value_coding == amd.AMG_VALUES_AUTO and p.precision == amd.AMG_PREC_DOUBLE
 
 
 def test_null_arguments():
