@@ -138,7 +138,9 @@ __device__ __forceinline__ void stcols(T *__restrict__ p, const T (&v)[CPL]) {
 // Row `row`, columns cb .. cb+CPL-1: acc[j] = sum_k a_k x[col_k * NR + cb + j]
 // folded in CSR order; l1 = sum_k |a_k|.  The iterate read at column c is
 // x_c, or with a correction (e != nullptr) x_c + p_c e[agg_c] (the value the
-// prolongation stores).
+// prolongation stores).  Slots are taken kBS at a time (columns, values,
+// then the iterate pieces of the whole batch in flight before the fold;
+// kBS keeps the batch's iterate pieces within 32 registers).
 template <class T, int NR, int CPL, bool kCorr = false>
 __device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__restrict__ col,
                                      const T *__restrict__ val, const T *__restrict__ x, int row,
@@ -146,12 +148,56 @@ __device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__
                                      const int *__restrict__ agg = nullptr,
                                      const T *__restrict__ pval = nullptr,
                                      const T *__restrict__ e = nullptr) {
+  constexpr int kBytes = CPL * static_cast<int>(sizeof(T));
+  constexpr int kBS = kCorr ? 1 : (kBytes <= 32 ? 4 : (kBytes <= 64 ? 2 : 1));
   const int s = row >> 6, lane = row & 63;
   const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
 #pragma unroll
   for (int j = 0; j < CPL; ++j) acc[j] = T(0);
   T m = T(0);
-  for (int k = 0; k < width; ++k) {
+  int k = 0;
+  if constexpr (kBS > 1) {
+    for (; k + kBS <= width; k += kBS) {
+      int c[kBS];
+      T a[kBS], xv[kBS][CPL];
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) {
+        c[u] = col[b + (k + u) * 64 + lane];
+        a[u] = val[b + (k + u) * 64 + lane];
+      }
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) ldcols<T, CPL>(x + static_cast<int64_t>(c[u]) * NR + cb, xv[u]);
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) {
+        m = m + fabs(a[u]);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a[u] * xv[u][j];
+      }
+    }
+    const int rem = width - k;   // 0 .. kBS-1, one predicated batch
+    if (rem > 0) {
+      int c[kBS];
+      T a[kBS], xv[kBS][CPL];
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < rem) {
+          c[u] = col[b + (k + u) * 64 + lane];
+          a[u] = val[b + (k + u) * 64 + lane];
+        }
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < rem) ldcols<T, CPL>(x + static_cast<int64_t>(c[u]) * NR + cb, xv[u]);
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < rem) {
+          m = m + fabs(a[u]);
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) acc[j] = acc[j] + a[u] * xv[u][j];
+        }
+      k = width;
+    }
+  }
+  for (; k < width; ++k) {
     const int c = col[b + k * 64 + lane];
     const T a = val[b + k * 64 + lane];
     m = m + fabs(a);
