@@ -245,7 +245,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU's share of the problem; runs on %d GPUs are not "
-              "supported by this build (use --gpus 1)" % args.gpus, file=sys.stderr)
+              "implemented (use --gpus 1)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

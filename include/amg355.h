@@ -43,7 +43,7 @@ extern "C" {
 #define AMG_ERR_NONFINITE (-3)    /* NaN or Inf in the input or produced by the iteration */
 #define AMG_ERR_NOMEM (-4)        /* device allocation failed */
 #define AMG_ERR_DEVICE (-5)       /* any other HIP runtime error */
-#define AMG_ERR_UNSUPPORTED (-6)  /* a parameter combination this build does not provide */
+#define AMG_ERR_UNSUPPORTED (-6)  /* a parameter combination the library does not provide */
 
 /* coarse_solver */
 #define AMG_COARSE_CHOLESKY 0     /* dense FP64 Cholesky (coarsest n <= 1024, else Jacobi sweeps) */

@@ -4,6 +4,7 @@ signature, and the ctypes structures match the C layout."""
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -79,3 +80,13 @@ def test_binding_has_no_compute_fallback():
     assert "import oracle" not in src and "from oracle" not in src
     for f in os.listdir(os.path.join(ROOT, "paper_2303_02352_amd", "csrc")):
         assert "oracle" not in open(os.path.join(ROOT, "paper_2303_02352_amd", "csrc", f)).read().lower()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message before
+    touching a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
