@@ -3,14 +3,13 @@
 // across the boundary.
 #include <hip/hip_runtime.h>
 
-#include <mutex>
-#include <vector>
-
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "amg_internal.hpp"
 

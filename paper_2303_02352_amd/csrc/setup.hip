@@ -735,8 +735,9 @@ __global__ void __launch_bounds__(kWave) k_rap_wave(int nc, const int *__restric
 // the order and the fold of the wide-row kernels.  The row's entries go
 // to slots [I * kRapReg, I * kRapReg + ucnt[I]) of (uJ, uV) and are copied
 // to their CSR place once the row lengths are scanned (k_rap_place).  Wider
-// rows get tcnt = their term count and take the general path; narrow rows
-// get tcnt = 0.
+// rows get tcnt = their term count and take the wavefront sort (k_rap_wave)
+// or, past kRapWaveMax terms, the one-thread sort (k_rap_terms); narrow
+// rows get tcnt = 0.
 constexpr int kRapReg = 16;
 
 // Compile-time loop: f(integral_constant<int, i>) for i = 0 .. N-1, so that
