@@ -9,7 +9,7 @@ differences on the CPU), with the oracle emulating the bfloat16 storage:
 and the properties the method needs: training lowers the loss, and the
 predicted vector is positive, finite and drives a working hierarchy.
 The prediction itself is "parity unpinned" beyond this (trained weights have
-no closed form); PCG iterations judge it in bench.py.
+no closed form); bench.py measures it by PCG iterations.
 """
 import numpy as np
 import pytest
