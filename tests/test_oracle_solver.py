@@ -9,6 +9,11 @@
     for step; a single-level hierarchy converges in one iteration; the true
     residual and the error against a direct solve respect rtol and
     kappa * rtol; degenerate and failure cases return the documented codes.
+  * Mixed-precision form (the same V-cycle evaluated in binary32): within a
+    few units of binary32 rounding of the dense binary64 B^k, and clearly
+    not a binary64 evaluation; exact under scaling by powers of two; the
+    binary64 flexible CG around it meets rtol on the true residual with
+    about the iteration count of the binary64 cycle.
   * Hierarchy facts the paper prints for its own parameter set (Sec. 5):
     4 levels at 130^3 on one node, 5 levels at 300^3, operator complexity
     about 1.14 (tests/golden/paper_hierarchy.json).
@@ -88,6 +93,54 @@ def test_vcycle_equals_dense_recursion_multilevel(maker):
     # symmetric positive definite operator
     assert np.max(np.abs(Bgot - Bgot.T)) <= 1e-12 * np.max(np.abs(Bgot))
     assert np.min(np.linalg.eigvalsh(0.5 * (Bgot + Bgot.T))) > 0
+
+
+U32 = 2.0 ** -24   # unit roundoff of binary32
+
+
+@pytest.mark.parametrize("maker", ["poisson", "diffusion27", "lognormal7"])
+@pytest.mark.parametrize("steps,pre,post", [(2, 4, 4), (1, 1, 2)])
+def test_binary32_vcycle_within_rounding_of_dense_operator(maker, steps, pre, post):
+    """B_32 r against B^k r (binary64, dense): the binary32 cycle rounds the
+    matrices, the l1 diagonal, P and r to binary32 and every operation after;
+    on these sizes that moves the result by about one unit of binary32
+    rounding (measured 0.9-1.7 u), so 64 u bounds it, while a dropped term,
+    a wrong sign or index moves it by O(1).  It must also differ from the
+    binary64 cycle (whose error is ~1e-16) by more than 1e-9: a binary32
+    evaluation really happened."""
+    A = {"poisson": lambda: W.poisson7(6), "diffusion27": lambda: W.diffusion27(5, 3),
+         "lognormal7": lambda: W.lognormal7(6, 7, ell=2.0)}[maker]()
+    H = oracle.Hierarchy(A, oracle.AMGParams(aggr_steps=steps, coarse_max=6, pre_sweeps=pre,
+                                             post_sweeps=post))
+    assert H.nlevels >= 4
+    B, _, _ = _dense_B(H, pre, post)
+    for seed in (77, 78):
+        r = W.uniform_pm1(seed, A.n)
+        ref = B @ r
+        err = np.max(np.abs(H.vcycle_f32(r) - ref)) / np.max(np.abs(ref))
+        assert 1e-9 < err <= 64 * U32
+        # scaling by a power of two commutes with every binary32 rounding
+        s = 2.0 ** -5
+        assert np.array_equal(H.vcycle_f32(r * s), H.vcycle_f32(r) * s)
+
+
+@pytest.mark.parametrize("maker,N", [("poisson", 16), ("diffusion27", 10), ("lognormal7", 12)])
+def test_mixed_pcg_meets_rtol(maker, N):
+    """Alg. 1 in binary64 around the binary32 cycle: the true residual
+    b - A x (scipy) meets rtol, and the flexible iteration count is within two
+    of the count with the binary64 cycle."""
+    A = {"poisson": lambda: W.poisson7(N), "diffusion27": lambda: W.diffusion27(N, 3),
+         "lognormal7": lambda: W.lognormal7(N, 7, ell=3.0)}[maker]()
+    xs, b = W.manufactured_rhs(A, 5)
+    H = oracle.Hierarchy(A, oracle.AMGParams(smooth_vec=1 if maker != "poisson" else 0))
+    assert H.nlevels >= 2
+    rtol = 1e-6
+    x, it, rel, st = H.pcg(b, rtol=rtol, mixed=True)
+    x64, it64, rel64, st64 = H.pcg(b, rtol=rtol)
+    assert st == oracle.OK and st64 == oracle.OK
+    assert rel <= rtol
+    assert np.linalg.norm(b - A.scipy() @ x) / np.linalg.norm(b) <= rtol * 1.01
+    assert abs(it - it64) <= 2
 
 
 def test_vcycle_symmetry_and_positivity_32():
