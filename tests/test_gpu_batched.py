@@ -36,7 +36,7 @@ def _batch(systems, **params):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("nrhs", [4, 16])
+@pytest.mark.parametrize("nrhs", [2, 4, 8, 16])
 def test_batched_vcycle_matches_oracle(nrhs, precision):
     systems = [W.poisson7(N) for N in EDGES]
     say("batched vcycle", nrhs, precision)
@@ -58,9 +58,11 @@ def test_batched_vcycle_matches_oracle(nrhs, precision):
             assert err <= (1e-6 if precision == 1 else 1e-12), (s, c, err)
     say("  worst rel err %.2e" % worst)
     inf = bt.info()
+    # the autotuner's pick is timing-dependent: any width that divides nrhs
     for k in range(inf["levels"]):
         if inf["n_smoothed"][k] > 0:
-            assert inf["cols_per_lane"][k] in (1, 2, 4)
+            cpl = inf["cols_per_lane"][k]
+            assert cpl in (1, 2, 4, 8, 16) and nrhs % cpl == 0
 
 
 @pytest.mark.parametrize("precision", [0, 1])
