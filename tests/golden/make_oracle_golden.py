@@ -1,9 +1,14 @@
-"""Write tests/golden/oracle_full_size.json from the CPU oracle alone.
+"""Write tests/golden/oracle_full_size.json and oracle_batched64x16.json from
+the CPU oracle alone.
 
 Runs the oracle (and the seeded input generators) on the full-size
 workloads whose end-to-end results the GPU tests cannot recompute within a
 test's time limit, and stores iteration counts, residuals, hierarchy sizes and sampled entries
-of one V-cycle (binary64 and binary32) as hex floats.  Usage: python tests/golden/make_oracle_golden.py
+of one V-cycle (binary64 and binary32) as hex floats.  The batched record
+covers sampled (system, right-hand side) pairs of the 64-system x 16
+right-hand-side batch: the oracle's mixed-precision PCG and binary32 V-cycle
+of each pair's own system.
+Usage: python tests/golden/make_oracle_golden.py [all|single|batched]
 """
 import json
 import os
@@ -53,16 +58,60 @@ def run(name, A, seed, params, f32=False):
     return rec
 
 
-def main():
-    out = {}
-    out["poisson7_160"] = run("poisson7_160", W.poisson7(160), 2, oracle.AMGParams(), f32=True)
-    out["diffusion27_128"] = run("diffusion27_128", W.diffusion27(128, 3), 4,
-                                 oracle.AMGParams(smooth_vec=1), f32=True)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_full_size.json")
+# The batch: 64 systems with edges W.batched_edges(64, 5), 16 right-hand
+# sides b_s = A_s X_s with X_s = W.batched_rhs(s, n_s, 16).T; the V-cycle
+# residual of system s is W.uniform_pm1(BATCH_R_SEED + s, n_s * 16) as an
+# (n_s, 16) row-major block.  Sampled pairs: the smallest, a median and the
+# largest system, first and last column.
+BATCH_NSYS, BATCH_SEED, BATCH_NRHS, BATCH_R_SEED = 64, 5, 16, 900
+BATCH_COLS = (0, 15)
+
+
+def batched_systems():
+    edges = W.batched_edges(BATCH_NSYS, BATCH_SEED)
+    order = sorted(range(BATCH_NSYS), key=lambda s: (edges[s], s))
+    return edges, [order[0], order[BATCH_NSYS // 2], order[-1]]
+
+
+def run_batched():
+    edges, picks = batched_systems()
+    pairs = []
+    for s in picks:
+        A = W.poisson7(edges[s])
+        t0 = time.time()
+        H = oracle.Hierarchy(A)
+        bs = A.scipy() @ W.batched_rhs(s, A.n, BATCH_NRHS).T
+        R = W.uniform_pm1(BATCH_R_SEED + s, A.n * BATCH_NRHS).reshape(A.n, BATCH_NRHS)
+        rows = sample_rows(A.n)
+        for c in BATCH_COLS:
+            x, it, rel, st = H.pcg(np.ascontiguousarray(bs[:, c]), rtol=1e-6, maxit=1000, mixed=True)
+            z32 = H.vcycle_f32(np.ascontiguousarray(R[:, c]))
+            pairs.append(dict(system=s, edge=int(edges[s]), column=c, status=st, iterations=it,
+                              relres=rel, rows=rows, z=[float(z32[i]).hex() for i in rows]))
+        print(json.dumps(dict(system=s, edge=int(edges[s]), n=A.n, oracle_s=time.time() - t0,
+                              iterations=[p["iterations"] for p in pairs if p["system"] == s])),
+              flush=True)
+    return dict(nsys=BATCH_NSYS, edges_seed=BATCH_SEED, nrhs=BATCH_NRHS, r_seed=BATCH_R_SEED,
+                edges=[int(e) for e in edges], pairs=pairs)
+
+
+def write(name, out):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)
 
 
+def main(which="all"):
+    if which in ("all", "single"):
+        out = {}
+        out["poisson7_160"] = run("poisson7_160", W.poisson7(160), 2, oracle.AMGParams(), f32=True)
+        out["diffusion27_128"] = run("diffusion27_128", W.diffusion27(128, 3), 4,
+                                     oracle.AMGParams(smooth_vec=1), f32=True)
+        write("oracle_full_size.json", out)
+    if which in ("all", "batched"):
+        write("oracle_batched64x16.json", run_batched())
+
+
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "all")

@@ -12,6 +12,13 @@ oracle's, recurrence and true relative residual <= 1e-6; sampled V-cycle
 entries within 1e-12 relative (binary64) and 1e-6 (binary32 cycle) of the
 oracle's (bit-exact expected); fine-level SpMV bit-exact against the oracle's
 SpMV over the whole vector.
+
+The batched workload (64 systems, edges 17-94, 16 right-hand sides, binary32
+V-cycle inside binary64 PCG) has its own record,
+``tests/golden/oracle_batched64x16.json``, from the same script: every pair
+must reach a true relative residual <= 1e-6, and sampled pairs must take the
+oracle's iterations +-1 and match its binary32 V-cycle on sampled rows within
+1e-6.
 """
 import json
 import os
@@ -27,6 +34,7 @@ from gpu_helpers import bits, dev, gpu_hierarchy, host, require_gpu, say, torch
 pytestmark = pytest.mark.gpu
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_full_size.json")))
+BATCH = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_batched64x16.json")))
 MAKE = {"poisson7_160": lambda: W.poisson7(160), "diffusion27_128": lambda: W.diffusion27(128, 3)}
 
 
@@ -80,3 +88,42 @@ def test_full_size_fine_spmv_bit_exact():
     y = torch.empty(A.n, dtype=torch.float64, device="cuda")
     Hg.spmv(0, dev(x), y)
     assert np.array_equal(bits(host(y)), bits(oracle.spmv(A, x)))
+
+
+def test_full_size_batched_against_oracle():
+    import paper_2303_02352_amd as amd
+    g = BATCH
+    edges = W.batched_edges(g["nsys"], g["edges_seed"])
+    assert [int(e) for e in edges] == g["edges"]
+    nrhs = g["nrhs"]
+    systems = [W.poisson7(N) for N in edges]
+    ntot = sum(A.n for A in systems)
+    say("batched full size: %d systems, %d rows x %d right-hand sides" % (len(systems), ntot, nrhs))
+    bt = amd.Batch([(dev(A.row_ptr), dev(A.col), dev(A.val)) for A in systems],
+                   precision=amd.AMG_PREC_MIXED)
+    bs = [np.ascontiguousarray(A.scipy() @ W.batched_rhs(s, A.n, nrhs).T) for s, A in enumerate(systems)]
+    Bd = dev(np.concatenate([b.reshape(-1) for b in bs]))
+    X = torch.zeros(ntot * nrhs, dtype=torch.float64, device="cuda")
+    st, its, rel, pst = bt.solve(Bd, X, nrhs, rtol=1e-6, maxit=1000)
+    assert st == 0 and np.all(pst == 0) and np.all(rel <= 1e-6)
+    Xh = host(X)
+    offs = np.cumsum([0] + [A.n * nrhs for A in systems])
+    worst = 0.0
+    for s, A in enumerate(systems):
+        blk = Xh[offs[s]:offs[s + 1]].reshape(A.n, nrhs)
+        tr = np.linalg.norm(bs[s] - A.scipy() @ blk, axis=0) / np.linalg.norm(bs[s], axis=0)
+        worst = max(worst, float(tr.max()))
+    say("  worst true relative residual %.2e, iterations %d-%d" % (worst, its.min(), its.max()))
+    assert worst <= 1e-6 * 1.01
+    for p in g["pairs"]:
+        assert abs(int(its[p["system"], p["column"]]) - p["iterations"]) <= 1, p["system"]
+    del bs, Xh, X, Bd
+    R = np.concatenate([W.uniform_pm1(g["r_seed"] + s, A.n * nrhs) for s, A in enumerate(systems)])
+    Rd = dev(R)
+    Z = torch.zeros(ntot * nrhs, dtype=torch.float64, device="cuda")
+    bt.vcycle(Rd, Z, nrhs)
+    Zh = host(Z)
+    for p in g["pairs"]:
+        s, c = p["system"], p["column"]
+        _check_samples(Zh[offs[s]:offs[s + 1]].reshape(-1, nrhs)[:, c], p, 1e-6)
+    bt.close()
