@@ -7,8 +7,11 @@ test's time limit, and stores iteration counts, residuals, hierarchy sizes and s
 of one V-cycle (binary64 and binary32) as hex floats.  The batched record
 covers sampled (system, right-hand side) pairs of the 64-system x 16
 right-hand-side batch: the oracle's mixed-precision PCG and binary32 V-cycle
-of each pair's own system.
-Usage: python tests/golden/make_oracle_golden.py [all|single|batched]
+of each pair's own system.  The learned record holds the network's forward
+prediction (float64 with bfloat16 storage emulated) on the 128^3 log-normal
+field with seeded initial weights: sampled entries and the norm of the whole
+vector.
+Usage: python tests/golden/make_oracle_golden.py [all|single|batched|learned]
 """
 import json
 import os
@@ -95,6 +98,24 @@ def run_batched():
                 edges=[int(e) for e in edges], pairs=pairs)
 
 
+# The learned form's field and weights: W.lognormal7(128, 7) (sigma^2 = 2,
+# ell = 8) and oracle.mpnn.init_params(LEARN_THETA_SEED) rounded to binary32
+# (the weights the device keeps).
+LEARN_N, LEARN_FIELD_SEED, LEARN_THETA_SEED = 128, 7, 7
+
+
+def run_learned():
+    import oracle.mpnn as M
+    A = W.lognormal7(LEARN_N, LEARN_FIELD_SEED)
+    theta = M.init_params(LEARN_THETA_SEED).astype(np.float32).astype(np.float64)
+    t0 = time.time()
+    y, _ = M.forward(theta, A, bf16=True)
+    rows = sample_rows(A.n)
+    print(json.dumps(dict(n=A.n, oracle_forward_s=time.time() - t0)), flush=True)
+    return dict(n_edge=LEARN_N, field_seed=LEARN_FIELD_SEED, theta_seed=LEARN_THETA_SEED,
+                norm_y=float(np.linalg.norm(y)), rows=rows, y=[float(y[i]).hex() for i in rows])
+
+
 def write(name, out):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as f:
@@ -111,6 +132,8 @@ def main(which="all"):
         write("oracle_full_size.json", out)
     if which in ("all", "batched"):
         write("oracle_batched64x16.json", run_batched())
+    if which in ("all", "learned"):
+        write("oracle_learned128.json", run_learned())
 
 
 if __name__ == "__main__":
