@@ -81,6 +81,29 @@ def test_full_size_against_oracle(name):
         Hg.close()
 
 
+def test_full_size_plain_values_streamed():
+    """160^3 with binary64 value arrays (bench.py --values plain): every level
+    is read from plain values and the fine level (287 MB as read) takes the
+    non-temporal path; the sampled V-cycle and the iteration count are the
+    oracle's, as for the coded default."""
+    import paper_2303_02352_amd as amd
+    g = GOLDEN["poisson7_160"]
+    A = MAKE["poisson7_160"]()
+    say("full size plain values, poisson7_160")
+    Hg = gpu_hierarchy(A, value_coding=amd.AMG_VALUES_PLAIN, **g["params"])
+    assert Hg.info()["dict_size"] == [0] * Hg.info()["levels"]
+    r = W.uniform_pm1(g["vcycle"]["r_seed"], A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    Hg.vcycle(dev(r), z)
+    _check_samples(host(z), g["vcycle"], 1e-12)
+    xs, b = W.manufactured_rhs(A, g["seed"])
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st, it, rel = Hg.solve(dev(b), x, rtol=1e-6)
+    say("  its %d (oracle %d), relres %.3e" % (it, g["iterations"], rel))
+    assert st == 0 and abs(it - g["iterations"]) <= 1 and rel <= 1e-6
+    Hg.close()
+
+
 def test_full_size_fine_spmv_bit_exact():
     A = MAKE["poisson7_160"]()
     Hg = gpu_hierarchy(A)
