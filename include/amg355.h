@@ -140,7 +140,9 @@ int amg_params_default(amg_params *p);
  * On success *h_out owns all device memory; release it with amg_destroy.
  * Errors: INVALID (NULL args, bad parameters, malformed or unsymmetric CSR),
  * NOT_SPD (a_ii <= 0 or a non-positive Cholesky pivot), NONFINITE, NOMEM,
- * DEVICE.  On error *h_out is NULL. */
+ * DEVICE, UNSUPPORTED (a level whose sliced storage -- 64 rows per slice, each
+ * slice as wide as its longest row -- would need 2^31 or more slots; slot
+ * offsets are int32).  On error *h_out is NULL. */
 int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out);
 
 /* Solve A x = b with flexible PCG (Alg. 1) preconditioned by one V-cycle

@@ -899,13 +899,21 @@ __global__ void k_sort_members(int nc, const int *mptr, int *mem) {
 }
 
 // ------------------------------------------------------------------ SELL
-__global__ void k_sell_width(int n, int nslices, const int *rp, int *slots) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslices) return;
-  int w = 0;
-  const int r0 = s * kSlice, r1 = min(n, r0 + kSlice);
-  for (int r = r0; r < r1; ++r) w = max(w, rp[r + 1] - rp[r]);
-  slots[s] = w * kSlice;
+// Slots of each slice (64 x its widest row), and their total in 64 bits:
+// the slot offsets are int32, so the host refuses a level whose total does
+// not fit before any slot is indexed.
+__global__ void k_sell_width(int n, int nslices, const int *rp, int *slots, unsigned long long *total) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = 0;
+  if (s < nslices) {
+    int w = 0;
+    const int r0 = s * kSlice, r1 = min(n, r0 + kSlice);
+    for (int r = r0; r < r1; ++r) w = max(w, rp[r + 1] - rp[r]);
+    v = static_cast<unsigned long long>(w) * kSlice;
+    slots[s] = static_cast<int>(v);   // used only when the total fits
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);   // every lane of the wavefront
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(total, v);
 }
 
 __global__ void k_sell_fill(int n, int nslices, const int *rp, const int *ci, const double *v,
@@ -1338,12 +1346,19 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   S.n = n;
   S.nslices = ceil_div(n, kSlice);
   tvec<int> slots(S.nslices, s);
+  tvec<unsigned long long> total(1, s);
   S.sptr.alloc(S.nslices + 1);
+  AMG_HIP(hipMemsetAsync(total.p, 0, sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_sell_width, grid_for(S.nslices), dim3(kBlock), 0, s, n, S.nslices,
-                     Lv.A.rp.p, slots.p);
+                     Lv.A.rp.p, slots.p, total.p);
   AMG_LAUNCH_CHECK();
+  unsigned long long nslots = 0;
+  read_small(&nslots, total.p, sizeof(nslots), s);
+  if (nslots >= (1ull << 31))
+    fail(AMG_ERR_UNSUPPORTED, "a level's SELL form needs 2^31 or more slots (rows of very different "
+                              "lengths share slices); slot offsets are int32");
   exclusive_scan(slots.p, S.sptr.p, S.nslices, s);
-  S.nslots = read_int(S.sptr.p + S.nslices, s);
+  S.nslots = static_cast<int64_t>(nslots);
   S.col.alloc(S.nslots);
   S.val.alloc(S.nslots);
   hipLaunchKernelGGL(k_sell_fill, grid_for(static_cast<int64_t>(S.nslices) * kSlice), dim3(kBlock),

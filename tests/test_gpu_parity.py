@@ -364,3 +364,31 @@ def test_value_table_limit(K, table, precision):
     assert np.array_equal(bits(host(z[0])), bits(host(z[1])))
     tol = 1e-12 if precision == 0 else 1e-6
     assert np.max(np.abs(host(z[0]) - zo)) <= tol * np.max(np.abs(zo))
+
+
+def test_slot_count_limit_is_refused():
+    """The first row of every slice is a hub coupled to all other hubs (a
+    dense, diagonally dominant block); the other rows are the identity.  nnz
+    stays far below 2^31, but the SELL form would need 5793 slices x 64 x
+    5793 slots >= 2^31, past the int32 slot offsets: amg_setup must refuse it
+    (AMG_ERR_UNSUPPORTED) before any slot is written, and leave no hierarchy."""
+    import paper_2303_02352_amd as amd
+    S, eps = 5793, 1e-3
+    n = 64 * S
+    hubs = np.arange(S, dtype=np.int64) * 64
+    lens = np.ones(n, dtype=np.int64)
+    lens[hubs] = S
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=rp[1:])
+    col = np.arange(n, dtype=np.int32)[np.repeat(np.arange(n), lens)]     # the diagonal of plain rows
+    val = np.ones(rp[-1])
+    at = (rp[hubs][:, None] + np.arange(S)[None, :]).reshape(-1)
+    col[at] = np.tile(hubs.astype(np.int32), S)
+    val[at] = -eps
+    val[rp[hubs] + np.arange(S)] = 1.0 + (S - 1) * eps                    # hub k's diagonal is its k-th entry
+    A = W.CSR(n, rp.astype(np.int32), col, val)
+    say("slot limit: n=%d nnz=%d" % (A.n, A.nnz))
+    assert A.nnz < 2 ** 26 and S * 64 * S >= 2 ** 31
+    with pytest.raises(amd.AMGError) as e:
+        gpu_hierarchy(A)
+    assert e.value.code == amd.AMG_ERR_UNSUPPORTED
