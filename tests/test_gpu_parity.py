@@ -366,6 +366,42 @@ def test_value_table_limit(K, table, precision):
     assert np.max(np.abs(host(z[0]) - zo)) <= tol * np.max(np.abs(zo))
 
 
+def test_repeated_setup_and_destroy_hold_memory_steady():
+    """Hierarchies and batches built, used and destroyed in a loop: after the
+    first cycle (the pool's steady state) the device's free memory does not
+    shrink, and every hierarchy reports the same device footprint."""
+    import paper_2303_02352_amd as amd
+    A = W.poisson7(24)
+    xs, b = W.manufactured_rhs(A, 3)
+    bd = dev(b)
+    systems = [W.poisson7(N) for N in (7, 5)]
+
+    def cycle():
+        sizes = []
+        for prec in (amd.AMG_PREC_DOUBLE, amd.AMG_PREC_MIXED):
+            H = gpu_hierarchy(A, precision=prec)
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            st, it, rel = H.solve(bd, x)
+            assert st == 0
+            sizes.append(H.info()["device_bytes"])
+            H.close()
+        bt = amd.Batch([(dev(S.row_ptr), dev(S.col), dev(S.val)) for S in systems])
+        X = torch.zeros(sum(S.n for S in systems) * 4, dtype=torch.float64, device="cuda")
+        st, its, rel, pst = bt.solve(torch.ones_like(X), X, 4)
+        assert st == 0
+        bt.close()
+        torch.cuda.synchronize()
+        return sizes
+
+    first = cycle()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(30):
+        assert cycle() == first
+    free1 = torch.cuda.mem_get_info()[0]
+    say("free device memory after 1 / 31 cycles: %d / %d MiB" % (free0 >> 20, free1 >> 20))
+    assert free1 >= free0 - (64 << 20)
+
+
 def test_slot_count_limit_is_refused():
     """The first row of every slice is a hub coupled to all other hubs (a
     dense, diagonally dominant block); the other rows are the identity.  nnz
