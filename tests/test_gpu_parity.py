@@ -366,6 +366,43 @@ def test_value_table_limit(K, table, precision):
     assert np.max(np.abs(host(z[0]) - zo)) <= tol * np.max(np.abs(zo))
 
 
+def test_caller_stream_gives_the_same_bits():
+    """A hierarchy and a batch built and used on a stream of the caller's
+    (amg_params.stream) give the bits of the library-stream runs."""
+    import paper_2303_02352_amd as amd
+    A = W.poisson7(20)
+    xs, b = W.manufactured_rhs(A, 4)
+    r = W.uniform_pm1(12, A.n)
+    systems = [W.poisson7(N) for N in (9, 6)]
+    nr = 4
+    Bh = W.uniform_pm1(13, sum(S.n for S in systems) * nr)
+
+    def run():
+        out = []
+        for prec in (amd.AMG_PREC_DOUBLE, amd.AMG_PREC_MIXED):
+            H = gpu_hierarchy(A, precision=prec)
+            z = torch.empty(A.n, dtype=torch.float64, device="cuda")
+            H.vcycle(dev(r), z)
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            st, it, rel = H.solve(dev(b), x)
+            out += [bits(host(z)), bits(host(x)), (st, it)]
+            H.close()
+        bt = amd.Batch([(dev(S.row_ptr), dev(S.col), dev(S.val)) for S in systems])
+        X = torch.zeros(Bh.size, dtype=torch.float64, device="cuda")
+        st, its, rel, pst = bt.solve(dev(Bh), X, nr)
+        out += [bits(host(X)), its.tolist()]
+        bt.close()
+        return out
+
+    ref = run()                       # torch's default stream: the library's own stream
+    s = torch.cuda.Stream()           # default priority
+    with torch.cuda.stream(s):
+        got = run()
+        s.synchronize()
+    for a, c in zip(ref, got):
+        assert np.array_equal(np.asarray(a), np.asarray(c))
+
+
 def test_repeated_setup_and_destroy_hold_memory_steady():
     """Hierarchies and batches built, used and destroyed in a loop: after the
     first cycle (the pool's steady state) the device's free memory does not
