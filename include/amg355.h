@@ -21,10 +21,12 @@
  * longjmp crosses this boundary.  amg_last_error() returns a thread-local
  * message for the last failure on the calling thread.
  *
- * Threading: a hierarchy may be used by one host thread at a time.  All work
- * is ordered on the hierarchy's stream (amg_params.stream, or a library-owned
- * stream that is ordered with null-stream work when it is NULL); calls that
- * return host-visible results synchronise that stream.
+ * Threading: a hierarchy may be used by one host thread at a time; different
+ * hierarchies may be used from different threads at once.  All work is
+ * ordered on the hierarchy's stream (amg_params.stream, or, when it is NULL,
+ * a library-owned stream of the hierarchy's own that is ordered with
+ * null-stream work); calls that return host-visible results synchronise that
+ * stream.
  */
 #ifndef AMG355_H
 #define AMG355_H
@@ -102,13 +104,13 @@ typedef struct {
   int32_t precision;       /* AMG_PREC_* */
   int32_t value_coding;    /* AMG_VALUES_* */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
-  void *stream;            /* hipStream_t on which all work is ordered; NULL = the library's
-                              own stream on the current device (one per device, shared by
-                              every hierarchy set up with NULL; pass distinct streams to
-                              use hierarchies from several threads at once).  A caller's
-                              stream must stay valid until amg_destroy: the hierarchy's
-                              device memory comes from the device's memory pool in that
-                              stream's order. */
+  void *stream;            /* hipStream_t on which all work is ordered; NULL = a blocking
+                              stream the library keeps for this hierarchy alone (reused
+                              after amg_destroy).  A caller's stream must stay valid until
+                              amg_destroy, must not be shared with another hierarchy or
+                              batch used concurrently (each solve captures its iteration
+                              graph on it), and orders the hierarchy's device memory,
+                              which comes from the device's memory pool. */
 } amg_params;
 
 typedef struct amg_hierarchy amg_hierarchy;   /* opaque, owned by the library */

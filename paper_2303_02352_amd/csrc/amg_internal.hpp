@@ -125,6 +125,49 @@ struct FreeOn {
 constexpr int kBuildThreads = 8;   // host threads building a batch's hierarchies
 hipStream_t library_stream(int slot = 0);
 
+// The stream of a hierarchy or batch created without a caller stream: one
+// per live object, because a solve captures its iteration graph on the
+// object's stream and a capture must see no other object's work (objects
+// may be used from different host threads at once).  Blocking streams, kept
+// for the life of the process and handed out again once their object is
+// destroyed.  acquire: nullptr if none can be created; *dev receives the
+// current device, which release needs back.
+hipStream_t acquire_private_stream(int *dev, unsigned flags = hipStreamDefault);
+void release_private_stream(int dev, hipStream_t s, unsigned flags = hipStreamDefault);
+
+// Records into *graph the work enqueue() puts on `stream` (an object's
+// stream field), through a non-blocking stream swapped in for the capture.
+// A blocking stream that is capturing would make the null stream depend on
+// the capture, and the runtime then refuses work on every other blocking
+// stream, other host threads' included; a non-blocking stream stays outside
+// that synchronisation.  Nothing executes on the capture stream (taken from
+// and returned to the library's free list); the graph is launched on
+// `stream` afterwards.
+template <class F>
+void capture_graph(hipStream_t &stream, hipGraph_t *graph, F enqueue) {
+  struct Swap {
+    hipStream_t &slot, orig, cs = nullptr;
+    int dev = 0;
+    bool capturing = false;
+    ~Swap() {
+      if (capturing) {   // enqueue threw: end the capture and drop what it recorded
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cs, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      }
+      slot = orig;
+      release_private_stream(dev, cs, hipStreamNonBlocking);
+    }
+  } sw{stream, stream};
+  sw.cs = acquire_private_stream(&sw.dev, hipStreamNonBlocking);
+  if (!sw.cs) fail(AMG_ERR_DEVICE, "hipStreamCreateWithFlags failed");
+  AMG_HIP(hipStreamBeginCapture(sw.cs, hipStreamCaptureModeThreadLocal));
+  sw.capturing = true;
+  stream = sw.cs;
+  enqueue();
+  sw.capturing = false;
+  AMG_HIP(hipStreamEndCapture(sw.cs, graph));
+}
+
 template <class T>
 void dvec<T>::release() {
   if (p) {
@@ -341,6 +384,8 @@ struct Timing {
 struct amg_hierarchy {
   amg_params p{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;     // stream from acquire_private_stream (on stream_dev)
+  int stream_dev = 0;
   std::vector<amg::Level> L;
   int coarse_dense = 0;
   amg::dvec<double> Ainv;      // inverse of the coarsest matrix, column-major

@@ -88,6 +88,39 @@ hipStream_t library_stream(int slot) {
   if (!streams[at] && hipStreamCreate(&streams[at]) != hipSuccess) streams[at] = nullptr;
   return streams[at];
 }
+
+namespace {
+struct IdleStream {
+  int dev;
+  unsigned flags;
+  hipStream_t s;
+};
+std::mutex g_private_mu;
+std::vector<IdleStream> g_private_free;
+}  // namespace
+
+hipStream_t acquire_private_stream(int *dev, unsigned flags) {
+  *dev = 0;
+  if (hipGetDevice(dev) != hipSuccess) return nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_private_mu);
+    for (size_t i = 0; i < g_private_free.size(); ++i)
+      if (g_private_free[i].dev == *dev && g_private_free[i].flags == flags) {
+        hipStream_t s = g_private_free[i].s;
+        g_private_free.erase(g_private_free.begin() + static_cast<std::ptrdiff_t>(i));
+        return s;
+      }
+  }
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, flags) != hipSuccess) return nullptr;
+  return s;
+}
+
+void release_private_stream(int dev, hipStream_t s, unsigned flags) {
+  if (!s) return;
+  std::lock_guard<std::mutex> lock(g_private_mu);
+  g_private_free.push_back(IdleStream{dev, flags, s});
+}
 }  // namespace amg
 
 extern "C" {
@@ -126,13 +159,15 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
   if (p->stream) {
     h->stream = static_cast<hipStream_t>(p->stream);
   } else {
-    // The null stream cannot be captured into a graph: work goes to the
-    // library's own blocking stream, which stays ordered with null-stream work.
-    h->stream = amg::library_stream();
+    // The null stream cannot be captured into a graph: work goes to a
+    // blocking stream of the hierarchy's own, which stays ordered with
+    // null-stream work.
+    h->stream = amg::acquire_private_stream(&h->stream_dev);
     if (!h->stream) {
       delete h;
       return set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
     }
+    h->own_stream = true;
   }
   st = guarded([&] {
     amg::keep_pool_memory();
@@ -174,8 +209,14 @@ void amg_destroy(amg_hierarchy *h) {
   amg::destroy_graph(h);
   if (h->sc_host) (void)hipHostFree(h->sc_host);
   h->sc_host = nullptr;
-  amg::FreeOn on(amg::library_stream());   // h->stream is idle and may be the caller's
-  delete h;   // frees all device buffers
+  const bool own = h->own_stream;
+  const int dev = h->stream_dev;
+  hipStream_t s = h->stream;
+  {
+    amg::FreeOn on(amg::library_stream());   // h->stream is idle and may be the caller's
+    delete h;   // frees all device buffers
+  }
+  if (own) amg::release_private_stream(dev, s);
 }
 
 const char *amg_strerror(int code) {

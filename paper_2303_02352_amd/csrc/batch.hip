@@ -728,6 +728,8 @@ __global__ void k_ball_done(int *active, int *all_done, int *host_flag) {
 struct amg_batch {
   amg_params p{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;     // stream from acquire_private_stream (on stream_dev)
+  int stream_dev = 0;
   int nsys = 0;
   std::vector<int> order;              // internal position -> user system id
   std::vector<int> pos_of;             // user system id -> internal position
@@ -1263,9 +1265,9 @@ int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int
   const int reps = std::min(maxit, kGraphIters);
   if (!bt->graph_exec || bt->graph_reps != reps || bt->graph_maxit != maxit) {
     batch_release_graph(bt);
-    AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < reps; ++i) benqueue_iteration<NR>(bt, maxit);
-    AMG_HIP(hipStreamEndCapture(s, &bt->graph));
+    capture_graph(bt->stream, &bt->graph, [&] {
+      for (int i = 0; i < reps; ++i) benqueue_iteration<NR>(bt, maxit);
+    });
     AMG_HIP(hipGraphInstantiate(&bt->graph_exec, bt->graph, nullptr, nullptr, 0));
     bt->graph_reps = reps;
     bt->graph_maxit = maxit;
@@ -1326,11 +1328,12 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   if (p->stream) {
     bt->stream = static_cast<hipStream_t>(p->stream);
   } else {
-    bt->stream = amg::library_stream();
+    bt->stream = amg::acquire_private_stream(&bt->stream_dev);
     if (!bt->stream) {
       delete bt;
       return amg::api_set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
     }
+    bt->own_stream = true;
   }
   int st = amg::api_guarded([&] {
     amg::keep_pool_memory();
@@ -1400,8 +1403,14 @@ void amg_batch_destroy(amg_batch *bt) {
   (void)hipStreamSynchronize(bt->stream);
   amg::batch_release_graph(bt);
   if (bt->host_flag) (void)hipHostFree(bt->host_flag);
-  amg::FreeOn on(amg::library_stream());   // bt->stream is idle and may be the caller's
-  delete bt;
+  const bool own = bt->own_stream;
+  const int dev = bt->stream_dev;
+  hipStream_t s = bt->stream;
+  {
+    amg::FreeOn on(amg::library_stream());   // bt->stream is idle and may be the caller's
+    delete bt;
+  }
+  if (own) amg::release_private_stream(dev, s);
 }
 
 }  // extern "C"

@@ -1351,9 +1351,7 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
   Scalars st = *h->sc_host;
   if (!st.done) {
     if (h->use_graph && !h->graph_exec) {
-      AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      enqueue_iteration(h);
-      AMG_HIP(hipStreamEndCapture(s, &h->graph));
+      capture_graph(h->stream, &h->graph, [&] { enqueue_iteration(h); });
       AMG_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
     }
     auto launch = [&]() {

@@ -403,6 +403,35 @@ def test_caller_stream_gives_the_same_bits():
         assert np.array_equal(np.asarray(a), np.asarray(c))
 
 
+def test_hierarchies_on_concurrent_host_threads():
+    """Different hierarchies may be built and solved from different host
+    threads at the same time (one thread per hierarchy): each thread gets the
+    bits a sequential run gives."""
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2303_02352_amd as amd
+    mats = [W.poisson7(22), W.diffusion27(12, 3), W.poisson7(19), W.lognormal7(14, 5, ell=3.0)]
+
+    def work(i):
+        A = mats[i]
+        xs, b = W.manufactured_rhs(A, 20 + i)
+        H = amd.Hierarchy(A.row_ptr, A.col, A.val, precision=i % 2)   # host CSR: library stream
+        out = []
+        for _ in range(3):
+            x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            st, it, rel = H.solve(torch.from_numpy(b).cuda(), x)
+            torch.cuda.current_stream().synchronize()
+            out.append((st, it, bits(x.cpu().numpy())))
+        H.close()
+        return out
+
+    ref = [work(i) for i in range(len(mats))]
+    with ThreadPoolExecutor(len(mats)) as ex:
+        got = list(ex.map(work, range(len(mats))))
+    for r, g in zip(ref, got):
+        for (s0, i0, x0), (s1, i1, x1) in zip(r, g):
+            assert s0 == s1 == 0 and i0 == i1 and np.array_equal(x0, x1)
+
+
 def test_repeated_setup_and_destroy_hold_memory_steady():
     """Hierarchies and batches built, used and destroyed in a loop: after the
     first cycle (the pool's steady state) the device's free memory does not
