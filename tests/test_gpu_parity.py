@@ -404,9 +404,9 @@ def test_caller_stream_gives_the_same_bits():
 
 
 def test_hierarchies_on_concurrent_host_threads():
-    """Different hierarchies may be built and solved from different host
-    threads at the same time (one thread per hierarchy): each thread gets the
-    bits a sequential run gives."""
+    """Different hierarchies and batches may be built and solved from
+    different host threads at the same time (one thread per object): each
+    thread gets the bits a sequential run gives."""
     from concurrent.futures import ThreadPoolExecutor
     import paper_2303_02352_amd as amd
     mats = [W.poisson7(22), W.diffusion27(12, 3), W.poisson7(19), W.lognormal7(14, 5, ell=3.0)]
@@ -422,6 +422,16 @@ def test_hierarchies_on_concurrent_host_threads():
             torch.cuda.current_stream().synchronize()
             out.append((st, it, bits(x.cpu().numpy())))
         H.close()
+        if i % 2:   # a batch too: its solve captures a graph of its own
+            systems = [W.poisson7(N) for N in (6 + i, 5)]
+            bt = amd.Batch([(S.row_ptr, S.col, S.val) for S in systems])
+            nr = 2
+            Bb = torch.from_numpy(W.uniform_pm1(40 + i, sum(S.n for S in systems) * nr)).cuda()
+            X = torch.zeros_like(Bb)
+            st, its, rel, pst = bt.solve(Bb, X, nr)
+            torch.cuda.current_stream().synchronize()
+            out.append((st, int(its.sum()), bits(X.cpu().numpy())))
+            bt.close()
         return out
 
     ref = [work(i) for i in range(len(mats))]
