@@ -165,7 +165,7 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
     h->stream = amg::acquire_private_stream(&h->stream_dev);
     if (!h->stream) {
       delete h;
-      return set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
+      return set_error(AMG_ERR_DEVICE, "no HIP device or stream available (hipGetDevice / hipStreamCreate failed)");
     }
     h->own_stream = true;
   }

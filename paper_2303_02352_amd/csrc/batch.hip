@@ -1331,7 +1331,7 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
     bt->stream = amg::acquire_private_stream(&bt->stream_dev);
     if (!bt->stream) {
       delete bt;
-      return amg::api_set_error(AMG_ERR_DEVICE, "hipStreamCreate failed");
+      return amg::api_set_error(AMG_ERR_DEVICE, "no HIP device or stream available (hipGetDevice / hipStreamCreate failed)");
     }
     bt->own_stream = true;
   }

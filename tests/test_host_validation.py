@@ -76,3 +76,17 @@ def test_status_strings_cover_every_code():
              amd.AMG_ERR_NONFINITE, amd.AMG_ERR_NOMEM, amd.AMG_ERR_DEVICE, amd.AMG_ERR_UNSUPPORTED]
     msgs = [L.amg_strerror(c).decode() for c in codes]
     assert all(msgs) and len(set(msgs)) == len(codes)
+
+
+def test_valid_system_without_a_device_fails_loudly():
+    """With no GPU the library has no fallback: a well-formed system is
+    refused with AMG_ERR_DEVICE and a message, and no hierarchy is made."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    import workloads as W
+    A = W.poisson7(4)
+    csr = amd.amg_csr(A.n, A.nnz, A.row_ptr.ctypes.data, A.col.ctypes.data, A.val.ctypes.data, 0)
+    st, h = _setup(csr, amd.default_params())
+    assert st == amd.AMG_ERR_DEVICE and not h.value
+    assert "device" in amd.load().amg_last_error().decode()
