@@ -104,13 +104,17 @@ typedef struct {
   int32_t precision;       /* AMG_PREC_* */
   int32_t value_coding;    /* AMG_VALUES_* */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
-  void *stream;            /* hipStream_t on which all work is ordered; NULL = a blocking
-                              stream the library keeps for this hierarchy alone (reused
-                              after amg_destroy).  A caller's stream must stay valid until
-                              amg_destroy, must not be shared with another hierarchy or
-                              batch used concurrently (each solve captures its iteration
-                              graph on it), and orders the hierarchy's device memory,
-                              which comes from the device's memory pool. */
+  void *stream;            /* hipStream_t on which the solve-phase work is ordered; NULL =
+                              a blocking stream the library keeps for this hierarchy alone
+                              (reused after amg_destroy).  A caller's stream must stay
+                              valid until amg_destroy.  amg_setup waits for the work
+                              already on it, runs on a library stream that lives for the
+                              process (the hierarchy's device memory comes from the
+                              device's memory pool and is only ever freed on such
+                              streams), and returns with the setup finished.  Objects may
+                              share a stream; their work on it is then serialised, and
+                              every call that synchronises (amg_pcg_solve, ...) waits for
+                              all of it. */
 } amg_params;
 
 typedef struct amg_hierarchy amg_hierarchy;   /* opaque, owned by the library */

@@ -120,14 +120,56 @@ def _ptr(a):
     if a is None:
         return None
     if hasattr(a, "data_ptr"):
-        assert a.is_contiguous()
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
         return C.c_void_p(a.data_ptr())
-    assert a.flags["C_CONTIGUOUS"]
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
     return C.c_void_p(a.ctypes.data)
 
 
 def _on_device(a):
     return 1 if (hasattr(a, "is_cuda") and a.is_cuda) else 0
+
+
+_DTYPES = {"float64": ("float64", "torch.float64"), "int32": ("int32", "torch.int32"),
+           "float32": ("float32", "torch.float32")}
+
+
+def _space(a):
+    """('cuda', index) for a device tensor, ('host', None) for host memory."""
+    if hasattr(a, "is_cuda") and a.is_cuda:
+        return ("cuda", a.device.index)
+    return ("host", None)
+
+
+def _arr(a, name, dtype, numel=None, space=None):
+    """Check one array argument before its address crosses the C ABI: a numpy
+    array or torch tensor of `dtype`, contiguous, with `numel` elements, in
+    `space` (('cuda', index), ('host', None), 'cuda' for any device, or None
+    for either).  Raises ValueError; returns the address."""
+    if not (hasattr(a, "data_ptr") or isinstance(a, np.ndarray)):
+        raise ValueError("%s: expected a numpy array or torch tensor, got %s" % (name, type(a).__name__))
+    if str(a.dtype) not in _DTYPES[dtype]:
+        raise ValueError("%s: dtype %s, expected %s" % (name, a.dtype, dtype))
+    contiguous = a.is_contiguous() if hasattr(a, "data_ptr") else a.flags["C_CONTIGUOUS"]
+    if not contiguous:
+        raise ValueError("%s: must be contiguous" % name)
+    size = a.numel() if hasattr(a, "data_ptr") else a.size
+    if numel is not None and size != numel:
+        raise ValueError("%s: %d elements, expected %d" % (name, size, numel))
+    sp = _space(a)
+    if space == "cuda":
+        if sp[0] != "cuda":
+            raise ValueError("%s: must be device memory (a CUDA tensor)" % name)
+    elif space is not None and sp != space:
+        raise ValueError("%s: in %s, expected %s (all arrays of a call share one memory space "
+                         "and device)" % (name, _where(sp), _where(space)))
+    return _ptr(a)
+
+
+def _where(sp):
+    return "host memory" if sp[0] == "host" else "cuda:%s" % sp[1]
 
 
 def default_params(**overrides) -> amg_params:
@@ -143,6 +185,29 @@ def current_stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _csr_args(row_ptr, col, val):
+    """amg_csr for three arrays in one memory space (checked), and n, nnz."""
+    sp = _space(val)
+    if not hasattr(row_ptr, "shape") or len(row_ptr.shape) != 1 or row_ptr.shape[0] < 1:
+        raise ValueError("row_ptr: expected a 1-D array of n + 1 entries")
+    n = int(row_ptr.shape[0]) - 1
+    nnz = int(col.shape[0]) if hasattr(col, "shape") and len(col.shape) == 1 else -1
+    if nnz < 0:
+        raise ValueError("col: expected a 1-D array")
+    prp = _arr(row_ptr, "row_ptr", "int32", n + 1, sp)
+    pci = _arr(col, "col", "int32", nnz, sp)
+    pva = _arr(val, "val", "float64", nnz, sp)
+    return amg_csr(n, nnz, prp, pci, pva, 1 if sp[0] == "cuda" else 0), n, nnz
+
+
+def _device_of(a):
+    """Device index of a CUDA tensor, else the current device."""
+    if _on_device(a):
+        return a.device.index
+    import torch
+    return torch.cuda.current_device()
+
+
 class Hierarchy:
     """AMG hierarchy built by ``amg_setup``.
 
@@ -154,13 +219,11 @@ class Hierarchy:
 
     def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, **params):
         L = load()
-        self.n = int(row_ptr.shape[0]) - 1
-        self.nnz = int(col.shape[0])
-        A = amg_csr(self.n, self.nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _on_device(val))
+        A, self.n, self.nnz = _csr_args(row_ptr, col, val)
         p = default_params(**params)
         if smooth_vector is not None:
             p.smooth_vec = AMG_SMOOTH_GIVEN
-            p.smooth_vector = _ptr(smooth_vector)
+            p.smooth_vector = _arr(smooth_vector, "smooth_vector", "float64", self.n, _space(val))
         p.stream = stream if stream is not None else (current_stream() if A.on_device else None)
         self.params = p
         h = C.c_void_p()
@@ -168,6 +231,17 @@ class Hierarchy:
         if st != AMG_OK:
             raise AMGError(st, "amg_setup")
         self.h = h
+        self.device = _device_of(val)
+        self.sizes = self.info()["n"]
+
+    def _vec(self, a, name, k=0):
+        """A device vector of level k's size on the hierarchy's device."""
+        return _arr(a, name, "float64", self.sizes[k], ("cuda", self.device))
+
+    def _level(self, k):
+        if not 0 <= int(k) < len(self.sizes):
+            raise ValueError("level %d out of range [0, %d)" % (k, len(self.sizes)))
+        return int(k)
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -183,8 +257,8 @@ class Hierarchy:
     def solve(self, b, x, rtol=1e-6, maxit=1000, check=True):
         """Flexible PCG; x (device) holds x0 on entry.  Returns (status, iters, relres)."""
         it, rel = C.c_int32(), C.c_double()
-        st = load().amg_pcg_solve(self.h, _ptr(b), _ptr(x), float(rtol), int(maxit),
-                                  C.byref(it), C.byref(rel))
+        pb, px = self._vec(b, "b"), self._vec(x, "x")
+        st = load().amg_pcg_solve(self.h, pb, px, float(rtol), int(maxit), C.byref(it), C.byref(rel))
         if check and st < 0:
             raise AMGError(st, "amg_pcg_solve")
         return st, it.value, rel.value
@@ -217,17 +291,19 @@ class Hierarchy:
         return out
 
     def vcycle(self, r, z):
-        st = load().amg_vcycle(self.h, _ptr(r), _ptr(z))
+        st = load().amg_vcycle(self.h, self._vec(r, "r"), self._vec(z, "z"))
         if st != AMG_OK:
             raise AMGError(st, "amg_vcycle")
 
     def spmv(self, k, x, y):
-        st = load().amg_spmv(self.h, int(k), _ptr(x), _ptr(y))
+        k = self._level(k)
+        st = load().amg_spmv(self.h, k, self._vec(x, "x", k), self._vec(y, "y", k))
         if st != AMG_OK:
             raise AMGError(st, "amg_spmv")
 
     def sweep(self, k, r, x, xn):
-        st = load().amg_sweep(self.h, int(k), _ptr(r), _ptr(x), _ptr(xn))
+        k = self._level(k)
+        st = load().amg_sweep(self.h, k, self._vec(r, "r", k), self._vec(x, "x", k), self._vec(xn, "xn", k))
         if st != AMG_OK:
             raise AMGError(st, "amg_sweep")
 
@@ -250,10 +326,14 @@ class Batch:
     def __init__(self, systems, stream=None, **params):
         L = load()
         self._keep = systems
+        if not systems:
+            raise ValueError("a batch needs at least one system")
         arr = (amg_csr * len(systems))()
+        space = _space(systems[0][2])
         for i, (rp, ci, va) in enumerate(systems):
-            arr[i] = amg_csr(int(rp.shape[0]) - 1, int(ci.shape[0]), _ptr(rp), _ptr(ci), _ptr(va),
-                             _on_device(va))
+            if _space(va) != space:
+                raise ValueError("system %d: every system must be in %s" % (i, _where(space)))
+            arr[i] = _csr_args(rp, ci, va)[0]
         self.sizes = [int(s[0].shape[0]) - 1 for s in systems]
         p = default_params(**params)
         p.stream = stream if stream is not None else (current_stream() if arr[0].on_device else None)
@@ -263,6 +343,12 @@ class Batch:
         if st != AMG_OK:
             raise AMGError(st, "amg_batch_setup")
         self.h = h
+        self.device = _device_of(systems[0][2])
+
+    def _block(self, a, name, nrhs):
+        if int(nrhs) not in (1, 2, 4, 8, 16):
+            raise ValueError("nrhs must be 1, 2, 4, 8 or 16")
+        return _arr(a, name, "float64", sum(self.sizes) * int(nrhs), ("cuda", self.device))
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:
@@ -281,14 +367,15 @@ class Batch:
         it = np.zeros(ns * nrhs, np.int32)
         rel = np.zeros(ns * nrhs)
         pst = np.zeros(ns * nrhs, np.int32)
-        st = load().amg_batch_solve(self.h, int(nrhs), _ptr(B), _ptr(X), float(rtol), int(maxit),
+        pB, pX = self._block(B, "B", nrhs), self._block(X, "X", nrhs)
+        st = load().amg_batch_solve(self.h, int(nrhs), pB, pX, float(rtol), int(maxit),
                                     _ptr(it), _ptr(rel), _ptr(pst))
         if check and st < 0:
             raise AMGError(st, "amg_batch_solve")
         return st, it.reshape(ns, nrhs), rel.reshape(ns, nrhs), pst.reshape(ns, nrhs)
 
     def vcycle(self, R, Z, nrhs):
-        st = load().amg_batch_vcycle(self.h, int(nrhs), _ptr(R), _ptr(Z))
+        st = load().amg_batch_vcycle(self.h, int(nrhs), self._block(R, "R", nrhs), self._block(Z, "Z", nrhs))
         if st != AMG_OK:
             raise AMGError(st, "amg_batch_vcycle")
 
@@ -309,8 +396,8 @@ class SmoothVectorNet:
     def __init__(self, params=None, stream=None):
         L = load()
         theta = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
-        if theta is not None:
-            assert theta.shape == (AMG_MPNN_NPARAMS,)
+        if theta is not None and theta.shape != (AMG_MPNN_NPARAMS,):
+            raise ValueError("params: shape %s, expected (%d,)" % (theta.shape, AMG_MPNN_NPARAMS))
         h = C.c_void_p()
         st = L.amg_mpnn_create(_ptr(theta), stream, C.byref(h))
         if st != AMG_OK:
@@ -330,8 +417,9 @@ class SmoothVectorNet:
 
     @staticmethod
     def _csr(row_ptr, col, val):
-        return amg_csr(int(row_ptr.shape[0]) - 1, int(col.shape[0]), _ptr(row_ptr), _ptr(col), _ptr(val),
-                       _on_device(val))
+        if not _on_device(val):
+            raise ValueError("the network reads a CSR in device memory")
+        return _csr_args(row_ptr, col, val)[0]
 
     def params(self):
         out = np.empty(AMG_MPNN_NPARAMS, np.float32)
@@ -352,7 +440,8 @@ class SmoothVectorNet:
         """w_out: device float64 tensor of n (exp of the prediction); returns y (host) if asked."""
         A = self._csr(row_ptr, col, val)
         y = np.empty(A.n, np.float32) if want_y else None
-        st = load().amg_mpnn_predict(self.h, C.byref(A), _ptr(w_out), _ptr(y))
+        pw = None if w_out is None else _arr(w_out, "w_out", "float64", A.n, _space(val))
+        st = load().amg_mpnn_predict(self.h, C.byref(A), pw, _ptr(y))
         if st != AMG_OK:
             raise AMGError(st, "amg_mpnn_predict")
         return y
@@ -361,7 +450,8 @@ class SmoothVectorNet:
         A = self._csr(row_ptr, col, val)
         loss = C.c_float()
         g = np.empty(AMG_MPNN_NPARAMS, np.float32) if want_grad else None
-        st = load().amg_mpnn_train_step(self.h, C.byref(A), _ptr(w_target), float(lr), C.byref(loss), _ptr(g))
+        pt = _arr(w_target, "w_target", "float64", A.n, _space(val))
+        st = load().amg_mpnn_train_step(self.h, C.byref(A), pt, float(lr), C.byref(loss), _ptr(g))
         if st != AMG_OK:
             raise AMGError(st, "amg_mpnn_train_step")
         return (loss.value, g) if want_grad else loss.value

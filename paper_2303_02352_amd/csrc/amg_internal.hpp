@@ -126,9 +126,10 @@ constexpr int kBuildThreads = 8;   // host threads building a batch's hierarchie
 hipStream_t library_stream(int slot = 0);
 
 // The stream of a hierarchy or batch created without a caller stream: one
-// per live object, because a solve captures its iteration graph on the
-// object's stream and a capture must see no other object's work (objects
-// may be used from different host threads at once).  Blocking streams, kept
+// per live object, so that objects used from different host threads at once
+// do not serialise on one stream (each solve synchronises its object's
+// stream).  Also the setup stream that stands in for a caller's stream
+// (SetupStream) and the capture streams (capture_graph).  Kept
 // for the life of the process and handed out again once their object is
 // destroyed.  acquire: nullptr if none can be created; *dev receives the
 // current device, which release needs back.
@@ -167,6 +168,44 @@ void capture_graph(hipStream_t &stream, hipGraph_t *graph, F enqueue) {
   sw.capturing = false;
   AMG_HIP(hipStreamEndCapture(sw.cs, graph));
 }
+
+// Runs an object's setup on a library stream that lives for the process in
+// place of a caller's stream: every pooled block the setup frees (its
+// temporaries) and every block the object keeps (freed at destroy) is then
+// ordered on a stream that outlives it, whatever the caller later does with
+// its own stream.  The setup stream first waits for the caller's stream (the
+// input may be produced there); the destructor synchronises it, so the
+// caller's stream sees a finished setup, and puts the caller's stream back.
+// No-op when the object owns its stream already.
+struct SetupStream {
+  hipStream_t &slot;
+  hipStream_t caller = nullptr, ss = nullptr;
+  int dev = 0;
+  SetupStream(hipStream_t &stream, bool callers_stream) : slot(stream) {
+    if (!callers_stream) return;
+    caller = stream;
+    ss = acquire_private_stream(&dev);
+    if (!ss) fail(AMG_ERR_DEVICE, "hipStreamCreate failed");
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipEventRecord(e, caller);
+    if (err == hipSuccess) err = hipStreamWaitEvent(ss, e, 0);
+    if (e) (void)hipEventDestroy(e);
+    if (err != hipSuccess) {
+      release_private_stream(dev, ss);
+      fail(AMG_ERR_DEVICE, std::string("joining the caller's stream: ") + hipGetErrorString(err));
+    }
+    slot = ss;
+  }
+  ~SetupStream() {
+    if (!ss) return;
+    (void)hipStreamSynchronize(ss);
+    slot = caller;
+    release_private_stream(dev, ss);
+  }
+  SetupStream(const SetupStream &) = delete;
+  SetupStream &operator=(const SetupStream &) = delete;
+};
 
 template <class T>
 void dvec<T>::release() {

@@ -171,6 +171,7 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
   }
   st = guarded([&] {
     amg::keep_pool_memory();
+    amg::SetupStream on(h->stream, !h->own_stream);
     amg::PoolScope pool(h->stream);
     amg::build_hierarchy(h, A);
     return AMG_OK;

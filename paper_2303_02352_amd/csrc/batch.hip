@@ -1337,6 +1337,7 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   }
   int st = amg::api_guarded([&] {
     amg::keep_pool_memory();
+    amg::SetupStream on(bt->stream, !bt->own_stream);
     amg::PoolScope pool(bt->stream);
     amg::batch_build(bt, nsys, A);
     return AMG_OK;
