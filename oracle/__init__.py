@@ -28,14 +28,31 @@ _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 
+_LIB_TIMING = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def _compile(out, flags, force):
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc"] + flags + ["-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                                                 "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile ``liboracle.so`` with gcc (plain C, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile ``liboracle.so``, the parity oracle: gcc, sequential, plain C,
+    no FMA contraction."""
+    return _compile(_LIB, ["-O2"], force)
+
+
+def build_timing(force: bool = False) -> str:
+    """Compile ``liboracle_omp.so``, the CPU-baseline timing build of the same
+    source: -O3 -march=native with OpenMP over the rows of SpMV, sweeps,
+    residuals, prolongation and PCG updates, per-thread dot partials folded
+    in thread order; setup stays sequential.  Used only to time the CPU
+    baseline on all host cores, never as the parity reference."""
+    return _compile(_LIB_TIMING, ["-O3", "-march=native", "-fopenmp"], force)
 
 
 class Params(C.Structure):
@@ -65,12 +82,27 @@ class AMGParams:
 
 
 _lib = None
+_lib_timing = None
 
 
 def lib():
+    """The parity oracle (sequential)."""
     global _lib
     if _lib is None:
-        L = C.CDLL(build())
+        _lib = _register(C.CDLL(build()))
+    return _lib
+
+
+def lib_timing():
+    """The OpenMP timing build (CPU baseline only)."""
+    global _lib_timing
+    if _lib_timing is None:
+        _lib_timing = _register(C.CDLL(build_timing()))
+    return _lib_timing
+
+
+def _register(L):
+    if True:
         L.orc_validate.argtypes = [C.c_int32, _i32p, _i32p, _f64p]
         L.orc_spmv.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_l1_dinv.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p]
@@ -106,8 +138,7 @@ def lib():
                                         C.POINTER(C.POINTER(C.c_double)),
                                         C.POINTER(C.c_int64)]
         L.orc_free_ptr.argtypes = [C.c_void_p]
-        _lib = L
-    return _lib
+    return L
 
 
 def _csr_args(A):
@@ -197,9 +228,10 @@ def pairwise_step(A, w):
 class Hierarchy:
     """Oracle AMG hierarchy: ``Hierarchy(A, AMGParams(...), w=None)``."""
 
-    def __init__(self, A, params: AMGParams | None = None, w=None):
+    def __init__(self, A, params: AMGParams | None = None, w=None, timing=False):
+        """timing=True: the OpenMP timing build (CPU baseline), not the parity oracle."""
         self.params = params or AMGParams()
-        L = lib()
+        L = self._L = lib_timing() if timing else lib()
         st = C.c_int()
         self._w = None if w is None else np.ascontiguousarray(w, np.float64)
         wp = None if self._w is None else self._w.ctypes.data_as(C.c_void_p)
@@ -212,27 +244,27 @@ class Hierarchy:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_free(self.h)
+            self._L.orc_free(self.h)
             self.h = None
 
     @property
     def nlevels(self) -> int:
-        return lib().orc_nlevels(self.h)
+        return self._L.orc_nlevels(self.h)
 
     @property
     def coarse_dense(self) -> bool:
-        return bool(lib().orc_coarse_dense(self.h))
+        return bool(self._L.orc_coarse_dense(self.h))
 
     def level_size(self, k):
         n, z = C.c_int32(), C.c_int64()
-        assert lib().orc_level_size(self.h, k, C.byref(n), C.byref(z)) == OK
+        assert self._L.orc_level_size(self.h, k, C.byref(n), C.byref(z)) == OK
         return n.value, z.value
 
     def sizes(self):
         return [self.level_size(k) for k in range(self.nlevels)]
 
     def opc(self) -> float:
-        return lib().orc_opc(self.h)
+        return self._L.orc_opc(self.h)
 
     def level(self, k):
         n, z = self.level_size(k)
@@ -244,7 +276,7 @@ class Hierarchy:
         agg = np.full(n, -1, np.int32)
         pval = np.zeros(n)
         args = [a.ctypes.data_as(C.c_void_p) for a in (rp, ci, v, w, agg, pval, dinv)]
-        assert lib().orc_export_level(self.h, k, *args) == OK
+        assert self._L.orc_export_level(self.h, k, *args) == OK
         return dict(n=n, nnz=z, row_ptr=rp, col=ci[:z], val=v[:z], w=w, dinv=dinv,
                     agg=agg if k < self.nlevels - 1 else None,
                     pval=pval if k < self.nlevels - 1 else None)
@@ -252,31 +284,31 @@ class Hierarchy:
     def coarse_factor(self):
         n, _ = self.level_size(self.nlevels - 1)
         Lf = np.empty((n, n))
-        assert lib().orc_export_coarse_factor(self.h, Lf) == OK
+        assert self._L.orc_export_coarse_factor(self.h, Lf) == OK
         return Lf
 
     def coarse_inverse(self):
         n, _ = self.level_size(self.nlevels - 1)
         Ai = np.empty((n, n))
-        assert lib().orc_export_coarse_inverse(self.h, Ai) == OK
+        assert self._L.orc_export_coarse_inverse(self.h, Ai) == OK
         return Ai
 
     def vcycle(self, r):
         z = np.empty(self.n)
-        assert lib().orc_vcycle(self.h, np.ascontiguousarray(r, np.float64), z) == OK
+        assert self._L.orc_vcycle(self.h, np.ascontiguousarray(r, np.float64), z) == OK
         return z
 
     def vcycle_f32(self, r):
         """Mixed-precision form of the V-cycle (binary32 inside, binary64 in/out)."""
         z = np.empty(self.n)
-        assert lib().orc_vcycle_f32(self.h, np.ascontiguousarray(r, np.float64), z) == OK
+        assert self._L.orc_vcycle_f32(self.h, np.ascontiguousarray(r, np.float64), z) == OK
         return z
 
     def pcg(self, b, x0=None, rtol=1e-6, maxit=1000, mixed=False):
         """Returns (x, iterations, recurrence relative residual, status)."""
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
         it, rel = C.c_int32(), C.c_double()
-        f = lib().orc_pcg_mixed if mixed else lib().orc_pcg
+        f = self._L.orc_pcg_mixed if mixed else self._L.orc_pcg
         st = f(self.h, np.ascontiguousarray(b, np.float64), x, float(rtol), int(maxit),
                C.byref(it), C.byref(rel))
         return x, it.value, rel.value, st

@@ -28,6 +28,19 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* CPU-baseline timing build only (compiled with -fopenmp; the parity build is
+ * not): the row loops of SpMV, sweeps, residuals, prolongation and the PCG
+ * vector updates run over static blocks of rows on all threads, and a dot
+ * product folds each thread's block left to right, then the per-thread
+ * partials in thread order.  Without OpenMP every loop below is the plain
+ * sequential loop. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_ROWS _Pragma("omp parallel for schedule(static)")
+#else
+#define ORC_ROWS
+#endif
+
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
 #define ORC_INVALID (-1)
@@ -134,6 +147,7 @@ int orc_validate(int32_t n, const int32_t *rp, const int32_t *ci, const double *
 
 /* y = A x, each row a left fold of a_ij * x_j in CSR order from +0.0. */
 static void spmv(const csr_t *A, const double *x, double *y) {
+  ORC_ROWS
   for (int32_t i = 0; i < A->n; i++) {
     double s = 0.0;
     for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) s = s + A->v[k] * x[A->ci[k]];
@@ -149,9 +163,27 @@ int orc_spmv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
 }
 
 static double dot(int32_t n, const double *a, const double *b) {
+#ifdef _OPENMP
+  double part[1024];
+  int nt = omp_get_max_threads();
+  if (nt > 1024) nt = 1024;
+#pragma omp parallel num_threads(nt)
+  {
+    int t = omp_get_thread_num(), m = omp_get_num_threads();
+    int64_t lo = (int64_t)n * t / m, hi = (int64_t)n * (t + 1) / m;
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; i++) s = s + a[i] * b[i];
+    part[t] = s;
+    if (t == 0) nt = m;
+  }
+  double s = 0.0;
+  for (int t = 0; t < nt; t++) s = s + part[t];
+  return s;
+#else
   double s = 0.0;
   for (int32_t i = 0; i < n; i++) s = s + a[i] * b[i];
   return s;
+#endif
 }
 
 /* l1-Jacobi (Sec. 3.1): M_ii = a_ii + sum_{j != i} |a_ij|.  The printed
@@ -174,6 +206,7 @@ int orc_l1_dinv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v
 
 /* One l1-Jacobi sweep: xn = x + dinv * (r - A x).  xn must not alias x. */
 static void sweep(const csr_t *A, const double *dinv, const double *r, const double *x, double *xn) {
+  ORC_ROWS
   for (int32_t i = 0; i < A->n; i++) {
     double s = 0.0;
     for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) s = s + A->v[k] * x[A->ci[k]];
@@ -685,6 +718,7 @@ static void smooth_from_zero(const csr_t *A, const double *dinv, const double *r
                              double *x, double *t) {
   int32_t n = A->n;
   if (nsw <= 0) { for (int32_t i = 0; i < n; i++) x[i] = 0.0; return; }
+  ORC_ROWS
   for (int32_t i = 0; i < n; i++) x[i] = dinv[i] * r[i];
   for (int s = 1; s < nsw; s++) {
     sweep(A, dinv, r, x, t);
@@ -719,12 +753,14 @@ static void vcycle(orc_h *h, int k, const double *r, double *z) {
   /* residual and restriction: r_c[I] = sum_{i in I, ascending} p_i (r - A x)_i */
   double *res = h->vres[k];
   spmv(A, x, res);
+  ORC_ROWS
   for (int32_t i = 0; i < n; i++) res[i] = r[i] - res[i];
   int32_t nc = h->A[k + 1].n;
   double *rc = h->vr[k + 1];
   restrict_fold(n, nc, h->agg[k], h->pval[k], res, rc);
   double *ec = h->ve[k + 1];
   vcycle(h, k + 1, rc, ec);
+  ORC_ROWS
   for (int32_t i = 0; i < n; i++) x[i] = x[i] + h->pval[k][i] * ec[h->agg[k][i]];
   for (int s = 0; s < h->p.post_sweeps; s++) {
     sweep(A, h->dinv[k], r, x, t);
@@ -743,9 +779,11 @@ int orc_vcycle(orc_h *h, const double *r, double *z) {
 /* ------------------------------------------------- binary32 V-cycle
  * Mixed-precision form: the same V-cycle evaluated in binary32.  Matrix
  * values and prolongator values are rounded to binary32; the l1 diagonal is
- * folded in binary32 from the rounded values; the coarsest solve converts
- * its right-hand side to binary64, uses the binary64 factor, and rounds the
- * result back.  Input and output stay binary64. */
+ * folded in binary32 from the rounded values.  The coarsest solve stays in
+ * binary64 whichever solver it uses: its right-hand side is widened to
+ * binary64, the direct solve (binary64 inverse) or the coarse_sweeps sweeps
+ * (binary64 matrix and l1 diagonal) run as in the binary64 cycle, and the
+ * result is rounded back.  Input and output stay binary64. */
 static void spmv_f(const csr_t *A, const float *v, const float *x, float *y) {
   for (int32_t i = 0; i < A->n; i++) {
     float s = 0.0f;
@@ -806,17 +844,14 @@ static void vcycle_f(orc_h *h, int k, const float *r, float *z) {
   int32_t n = A->n;
   float *x = h->fx[k], *t = h->ft[k];
   if (k == h->nlev - 1) {
-    if (h->coarse_dense) {
-      double *rd = (double *)malloc(sizeof(double) * (size_t)n);
-      double *zd = (double *)malloc(sizeof(double) * (size_t)n);
-      for (int32_t i = 0; i < n; i++) rd[i] = (double)r[i];
-      coarse_direct(h, rd, zd);
-      for (int32_t i = 0; i < n; i++) z[i] = (float)zd[i];
-      free(rd); free(zd);
-    } else {
-      smooth_from_zero_f(h, k, r, h->p.coarse_sweeps, x, t);
-      memcpy(z, x, sizeof(float) * (size_t)n);
-    }
+    double *rd = (double *)malloc(sizeof(double) * (size_t)n);
+    double *zd = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; i++) rd[i] = (double)r[i];
+    if (h->coarse_dense) coarse_direct(h, rd, zd);
+    else smooth_from_zero(A, h->dinv[k], rd, h->p.coarse_sweeps, zd, h->vt[k]);
+    for (int32_t i = 0; i < n; i++) z[i] = (float)zd[i];
+    free(rd); free(zd);
+    (void)x; (void)t;
     return;
   }
   smooth_from_zero_f(h, k, r, h->p.pre_sweeps, x, t);
@@ -909,10 +944,13 @@ static int pcg_impl(orc_h *h, const double *b, double *u, double rtol, int32_t m
     if (!(rho_new > 0.0)) { status = ORC_NOT_SPD; goto done; }
     double c = gamma / rho;
     a = alpha / rho_new;
-    for (int32_t i = 0; i < n; i++) d[i] = w[i] - c * d[i];
-    for (int32_t i = 0; i < n; i++) u[i] = u[i] + a * d[i];
-    for (int32_t i = 0; i < n; i++) q[i] = v[i] - c * q[i];
-    for (int32_t i = 0; i < n; i++) r[i] = r[i] - a * q[i];
+    ORC_ROWS
+    for (int32_t i = 0; i < n; i++) {
+      d[i] = w[i] - c * d[i];
+      u[i] = u[i] + a * d[i];
+      q[i] = v[i] - c * q[i];
+      r[i] = r[i] - a * q[i];
+    }
     rho = rho_new;
     nr = sqrt(dot(n, r, r));
     rel = nr / nr0;

@@ -13,6 +13,8 @@
 // at once, which lets the host keep the next iteration queued.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -519,6 +521,27 @@ __global__ void k_f2d(const int *skip, int n, const float *__restrict__ a, doubl
   AMG_SKIP_IF_DONE();
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) b[r] = static_cast<double>(a[r]);
+}
+
+__global__ void k_d2f(const int *skip, int n, const double *__restrict__ a, float *__restrict__ b) {
+  AMG_SKIP_IF_DONE();
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) b[r] = static_cast<float>(a[r]);
+}
+
+// Mixed precision, coarsest level solved by sweeps: the binary32 right-hand
+// side widened to binary64 (rd) and the first binary64 iterate x = dinv * rd.
+__global__ void __launch_bounds__(kBlock) k_f2d_first(const int *skip, int n,
+                                                      const float *__restrict__ rf,
+                                                      const double *__restrict__ dinv,
+                                                      double *__restrict__ rd,
+                                                      double *__restrict__ x) {
+  AMG_SKIP_IF_DONE();
+  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double b = static_cast<double>(rf[i]);
+  rd[i] = b;
+  x[i] = dinv[i] * b;
 }
 
 // ------------------------------------------------------ coarse-tail kernel
@@ -1068,7 +1091,8 @@ T *first_buffer(amg_hierarchy *h, int k, T *out) {
   const amg_params &P = h->p;
   if (k >= h->tail_start) return nullptr;
   if (k == static_cast<int>(h->L.size()) - 1) {
-    if (h->coarse_dense) return nullptr;
+    // the binary32 cycle's coarsest sweeps run in binary64 and form their own first iterate
+    if (h->coarse_dense || std::is_same<T, float>::value) return nullptr;
     return ((P.coarse_sweeps - 1) % 2 == 0) ? out : tbuf<T>(L);
   }
   if (P.pre_sweeps == 0) return nullptr;
@@ -1094,6 +1118,18 @@ bool vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
     hipLaunchKernelGGL(kern, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k,
                        tail_desc<T>(h) + (k - h->tail_start), h->Ainv.p, h->coarse_dense,
                        P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out);
+    return false;
+  }
+  if (k == nl - 1 && std::is_same<T, float>::value) {
+    // Mixed precision: the coarsest solve stays in binary64 (sweeps on the
+    // binary64 matrix and l1 diagonal from the widened right-hand side; the
+    // result is rounded back to binary32).
+    double *A = L.x.p, *B = L.t.p;
+    if ((P.coarse_sweeps - 1) % 2 != 0) std::swap(A, B);
+    hipLaunchKernelGGL(k_f2d_first, grid_for(n), dim3(kBlock), 0, s, skip, n,
+                       reinterpret_cast<const float *>(rhs), L.dinv.p, L.r.p, A);
+    for (int q = 1; q < P.coarse_sweeps; ++q) { launch_sweep<double>(skip, L, L.r.p, A, B, s); std::swap(A, B); }
+    hipLaunchKernelGGL(k_d2f, grid_for(n), dim3(kBlock), 0, s, skip, n, A, reinterpret_cast<float *>(out));
     return false;
   }
   if (k == nl - 1) {
@@ -1272,7 +1308,10 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   const int nl = static_cast<int>(h->L.size());
   h->tail_start = nl;
   int used = 0;
-  for (int k = nl - 1; k >= 0; --k) {
+  // (the binary32 cycle solves a coarsest level without a direct solve by
+  // binary64 sweeps, which the tail kernel does not provide)
+  const bool tail_ok = !(mixed && h->p.precond && !h->coarse_dense && nl > 1);
+  for (int k = nl - 1; tail_ok && k >= 0; --k) {
     const int nk = h->L[k].A.n;
     if (nk > kTailRows || used + 4 * nk > kTailLds) break;
     used += 4 * nk;

@@ -1,18 +1,25 @@
-"""Write tests/golden/oracle_full_size.json and oracle_batched64x16.json from
-the CPU oracle alone.
+"""Write tests/golden/oracle_full_size.json, oracle_batched64x16.json,
+oracle_learned128.json and oracle_paper300.json from the CPU oracle alone.
 
 Runs the oracle (and the seeded input generators) on the full-size
 workloads whose end-to-end results the GPU tests cannot recompute within a
-test's time limit, and stores iteration counts, residuals, hierarchy sizes and sampled entries
-of one V-cycle (binary64 and binary32) as hex floats.  The batched record
+test's time limit, and stores iteration counts, residuals, hierarchy sizes,
+sampled entries of one V-cycle (binary64 and binary32) as hex floats, and
+SHA-256 digests of whole arrays (every level's CSR arrays, l1 diagonal,
+smooth vector, aggregate map and P values, and the whole V-cycle outputs),
+so that the GPU tests compare complete results bit for bit.  The batched record
 covers sampled (system, right-hand side) pairs of the 64-system x 16
 right-hand-side batch: the oracle's mixed-precision PCG and binary32 V-cycle
 of each pair's own system.  The learned record holds the network's forward
 prediction (float64 with bfloat16 storage emulated) on the 128^3 log-normal
 field with seeded initial weights: sampled entries and the norm of the whole
 vector.
-Usage: python tests/golden/make_oracle_golden.py [all|single|batched|learned]
+The paper record holds the oracle's hierarchy digests and PCG result for the
+paper's own configuration (Sec. 5: s = 3, coarsest <= 40 nd by 20 sweeps,
+f = 1) at 300^3.
+Usage: python tests/golden/make_oracle_golden.py [all|single|batched|learned|paper]
 """
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +37,25 @@ import workloads as W  # noqa: E402
 # One V-cycle on a seeded residual, sampled: VCYCLE_SEED feeds the residual,
 # SAMPLE_SEED the row indices (SAMPLES of them, plus the first and last row).
 VCYCLE_SEED, SAMPLE_SEED, SAMPLES = 77, 78, 256
+
+
+def digest(a, dtype):
+    """SHA-256 of the array's little-endian bytes as `dtype` (int32 / float64)."""
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.dtype(dtype).newbyteorder("<")).tobytes()).hexdigest()
+
+
+def level_digests(H):
+    out = []
+    for k in range(H.nlevels):
+        lv = H.level(k)
+        rec = dict(row_ptr=digest(lv["row_ptr"], np.int32), col=digest(lv["col"], np.int32),
+                   val=digest(lv["val"], np.float64), dinv=digest(lv["dinv"], np.float64),
+                   w=digest(lv["w"], np.float64))
+        if k < H.nlevels - 1:
+            rec["agg"] = digest(lv["agg"], np.int32)
+            rec["pval"] = digest(lv["pval"], np.float64)
+        out.append(rec)
+    return out
 
 
 def sample_rows(n):
@@ -51,13 +77,17 @@ def run(name, A, seed, params, f32=False):
     rec = dict(workload=name, seed=seed, status=st, iterations=it, relres=rel, true_relres=true_rel,
                levels=[list(s) for s in H.sizes()], opc=H.opc(), oracle_setup_s=t1 - t0,
                oracle_solve_s=t2 - t1, params={k: int(v) for k, v in params.__dict__.items()},
-               vcycle=dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z[i]).hex() for i in rows]))
+               vcycle=dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z[i]).hex() for i in rows],
+                           sha256=digest(z, np.float64)),
+               level_sha256=level_digests(H))
     if f32:
         z32 = H.vcycle_f32(r)
-        rec["vcycle_f32"] = dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z32[i]).hex() for i in rows])
+        rec["vcycle_f32"] = dict(r_seed=VCYCLE_SEED, rows=rows, z=[float(z32[i]).hex() for i in rows],
+                                 sha256=digest(z32, np.float64))
         xm, itm, relm, stm = H.pcg(b, rtol=1e-6, maxit=1000, mixed=True)
         rec["mixed"] = dict(status=stm, iterations=itm, relres=relm)
-    print(json.dumps({k: v for k, v in rec.items() if k not in ("vcycle", "vcycle_f32")}), flush=True)
+    print(json.dumps({k: v for k, v in rec.items() if k not in ("vcycle", "vcycle_f32", "level_sha256")}),
+          flush=True)
     return rec
 
 
@@ -116,6 +146,34 @@ def run_learned():
                 norm_y=float(np.linalg.norm(y)), rows=rows, y=[float(y[i]).hex() for i in rows])
 
 
+# The paper's configuration (Sec. 5 and Appendix A) on 300^3 Poisson with the
+# unit right-hand side: parameters from tests/golden/paper_hierarchy.json.
+PAPER_ND = 300
+
+
+def run_paper():
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_hierarchy.json")))
+    gp = g["params"]
+    params = oracle.AMGParams(aggr_steps=gp["aggr_steps"], coarse_max=gp["coarse_max_per_nd"] * PAPER_ND,
+                              max_levels=gp["max_levels"], coarse_solver=1,
+                              coarse_sweeps=gp["coarse_sweeps"], pre_sweeps=gp["pre_sweeps"],
+                              post_sweeps=gp["post_sweeps"])
+    A = W.poisson7(PAPER_ND)
+    t0 = time.time()
+    H = oracle.Hierarchy(A, params)
+    t1 = time.time()
+    b = np.ones(A.n)
+    x, it, rel, st = H.pcg(b, rtol=1e-6, maxit=1000)
+    t2 = time.time()
+    rec = dict(workload="poisson7_300 paper configuration, b = 1", nd=PAPER_ND, status=st, iterations=it,
+               relres=rel, levels=[list(s) for s in H.sizes()], opc=H.opc(),
+               oracle_setup_s=t1 - t0, oracle_solve_s=t2 - t1,
+               params={k: int(v) for k, v in params.__dict__.items()},
+               solution_sha256=digest(x, np.float64), level_sha256=level_digests(H))
+    print(json.dumps({k: v for k, v in rec.items() if k != "level_sha256"}), flush=True)
+    return rec
+
+
 def write(name, out):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as f:
@@ -134,6 +192,8 @@ def main(which="all"):
         write("oracle_batched64x16.json", run_batched())
     if which in ("all", "learned"):
         write("oracle_learned128.json", run_learned())
+    if which in ("all", "paper"):
+        write("oracle_paper300.json", run_paper())
 
 
 if __name__ == "__main__":

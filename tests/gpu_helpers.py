@@ -1,4 +1,5 @@
 """Shared helpers for the GPU tests (marshalling between numpy and torch)."""
+import hashlib
 import sys
 
 import numpy as np
@@ -59,3 +60,28 @@ def assert_same_hierarchy(Hg, Ho):
             assert np.array_equal(g["agg"], o["agg"]), k
             assert np.array_equal(bits(g["pval"]), bits(o["pval"])), k
     return inf
+
+
+def digest(a, dtype):
+    """SHA-256 of the array's little-endian bytes as `dtype` (the digests the
+    oracle's golden records hold)."""
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.dtype(dtype).newbyteorder("<")).tobytes()).hexdigest()
+
+
+def assert_level_digests(Hg, recs):
+    """Every level of the GPU hierarchy hashes to the oracle's stored digests
+    (CSR arrays, l1 diagonal, smooth vector, aggregate map, P values)."""
+    inf = Hg.info()
+    assert inf["levels"] == len(recs), (inf["n"], len(recs))
+    for k, rec in enumerate(recs):
+        g = Hg.export_level(k)
+        got = dict(row_ptr=digest(g["row_ptr"], np.int32), col=digest(g["col"], np.int32),
+                   val=digest(g["val"], np.float64), dinv=digest(g["dinv"], np.float64),
+                   w=digest(g["w"], np.float64))
+        if g["agg"] is not None:
+            got["agg"] = digest(g["agg"], np.int32)
+            got["pval"] = digest(g["pval"], np.float64)
+        bad = [f for f in rec if rec[f] != got.get(f)]
+        say("  level %d (n=%d): %s" % (k, g["n"], "all arrays bit-identical" if not bad else "DIFFER: %s" % bad))
+        assert not bad, (k, bad)
+        del g

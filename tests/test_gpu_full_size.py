@@ -4,14 +4,16 @@ times (the same library calls on the same resident inputs).
 The oracle cannot rerun these inside a test, so
 ``tests/golden/oracle_full_size.json`` -- written by
 ``tests/golden/make_oracle_golden.py`` from the oracle alone -- holds its
-results: hierarchy sizes, PCG iterations and residuals, and sampled entries of
-one V-cycle (binary64 and the binary32 cycle) on a seeded residual.
+results: hierarchy sizes, PCG iterations and residuals, SHA-256 digests of
+every level's arrays and of one whole V-cycle output (binary64 and the binary32
+cycle) on a seeded residual, and sampled entries of those outputs.
 
-Bars: level sizes and nonzeros equal; PCG iterations within +-1 of the
-oracle's, recurrence and true relative residual <= 1e-6; sampled V-cycle
-entries within 1e-12 relative (binary64) and 1e-6 (binary32 cycle) of the
-oracle's (bit-exact expected); fine-level SpMV bit-exact against the oracle's
-SpMV over the whole vector.
+Bars: every level's CSR arrays, l1 diagonal, smooth vector, aggregate map and
+P values bit-identical to the oracle's (digests); the whole V-cycle output
+bit-identical (digest; the sampled entries within 1e-12 relative, binary64, or
+1e-6, binary32 cycle, are reported first as the diagnostic); PCG iterations
+within +-1 of the oracle's, recurrence and true relative residual <= 1e-6;
+fine-level SpMV bit-exact against the oracle's SpMV over the whole vector.
 
 The batched workload (64 systems, edges 17-94, 16 right-hand sides, binary32
 V-cycle inside binary64 PCG) has its own record,
@@ -29,7 +31,8 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import bits, dev, gpu_hierarchy, host, require_gpu, say, torch
+from gpu_helpers import (assert_level_digests, bits, dev, digest, gpu_hierarchy, host, require_gpu,
+                         say, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -50,6 +53,10 @@ def _check_samples(z, rec, tol):
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     say("  sampled V-cycle rel err %.2e, bitwise %s" % (err, np.array_equal(bits(got), bits(ref))))
     assert err <= tol
+    if "sha256" in rec:
+        same = digest(z, np.float64) == rec["sha256"]
+        say("  whole V-cycle output bit-identical: %s" % same)
+        assert same
 
 
 @pytest.mark.parametrize("name", list(MAKE))
@@ -63,6 +70,8 @@ def test_full_size_against_oracle(name):
         Hg = gpu_hierarchy(A, precision=prec, **params)
         inf = Hg.info()
         assert [[n, z] for n, z in zip(inf["n"], inf["nnz"])] == g["levels"]
+        if prec == amd.AMG_PREC_DOUBLE:
+            assert_level_digests(Hg, g["level_sha256"])
         r = W.uniform_pm1(g["vcycle"]["r_seed"], A.n)
         z = torch.empty(A.n, dtype=torch.float64, device="cuda")
         Hg.vcycle(dev(r), z)

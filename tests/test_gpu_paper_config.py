@@ -3,9 +3,11 @@ three composed pairwise steps (aggregates of at most 8), coarsest size at most
 40 * nd solved by 20 l1-Jacobi sweeps, 4 + 4 sweeps, unit right-hand side.
 Pins from the paper's text (tests/golden/paper_hierarchy.json): 4 levels at
 130^3 on one node, 5 levels at 300^3, operator complexity about 1.14; the
-whole hierarchy is also bit-exact with the oracle's at 130^3, and at 300^3
-(the size bench.py runs, 27 M rows) the solve from the unit right-hand side
-meets 1e-6 on the true residual."""
+whole hierarchy is also bit-exact with the oracle's at 130^3; at 300^3 (the
+size bench.py runs, 27 M rows) every level hashes to the oracle's stored
+digests (tests/golden/oracle_paper300.json, written by the oracle alone), the
+PCG from the unit right-hand side takes the oracle's iterations +-1 and meets
+1e-6 on the true residual."""
 import json
 import os
 
@@ -15,10 +17,12 @@ import pytest
 import oracle
 import workloads as W
 
-from gpu_helpers import assert_same_hierarchy, dev, gpu_hierarchy, require_gpu, say, torch
+from gpu_helpers import (assert_level_digests, assert_same_hierarchy, dev, gpu_hierarchy, require_gpu,
+                         say, torch)
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_hierarchy.json")
+ORACLE300 = os.path.join(os.path.dirname(__file__), "golden", "oracle_paper300.json")
 
 
 @pytest.fixture(autouse=True)
@@ -63,10 +67,14 @@ def test_paper_hierarchy_300_on_gpu():
     say("  levels %s opc %.4f" % (inf["n"], inf["opc"]))
     assert inf["levels"] == g["strong_scaling_300"]["levels"]
     assert abs(inf["opc"] - g["operator_complexity"]["value"]) <= g["operator_complexity"]["tolerance"]
+    o = json.load(open(ORACLE300))
+    assert [[n, z] for n, z in zip(inf["n"], inf["nnz"])] == o["levels"]
+    assert_level_digests(Hg, o["level_sha256"])
     b = np.ones(A.n)
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     st, it, rel = Hg.solve(dev(b), x)
     xh = x.cpu().numpy()
     true_rel = float(np.linalg.norm(b - A.scipy() @ xh) / np.linalg.norm(b))
-    say("  iterations %d relres %.2e true %.2e" % (it, rel, true_rel))
+    say("  iterations %d (oracle %d) relres %.2e true %.2e" % (it, o["iterations"], rel, true_rel))
     assert st == 0 and rel <= 1e-6 and true_rel <= 1e-6 * 1.01
+    assert abs(it - o["iterations"]) <= 1

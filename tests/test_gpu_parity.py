@@ -35,6 +35,9 @@ CASES = {
     "lognormal7_20_relax": (lambda: W.lognormal7(20, 7, ell=4.0), dict(smooth_vec=1, smooth_sweeps=20)),
     "poisson16_pre1_post2": (lambda: W.poisson7(16), dict(pre_sweeps=1, post_sweeps=2, aggr_steps=1)),
     "poisson12_maxlev2": (lambda: W.poisson7(12), dict(max_levels=2)),
+    # coarsest level of 2000 rows: above the direct-solve limit, so solved by
+    # sweeps (in binary64 also inside the binary32 cycle)
+    "poisson20_maxlev2": (lambda: W.poisson7(20), dict(max_levels=2)),
     "poisson4_single_level": (lambda: W.poisson7(4), {}),
     "poisson1_n1": (lambda: W.poisson7(1), {}),
     # rows past 70304 shuffled: slot groups spanning more than 16 bits of
@@ -217,7 +220,7 @@ def test_host_csr_input_equals_device_input():
 
 
 MIXED_CASES = ["poisson32", "poisson33_ragged", "diffusion27_14_relax", "lognormal7_20_relax",
-               "poisson17_s3_jacobi"]
+               "poisson17_s3_jacobi", "poisson20_maxlev2"]
 
 
 @pytest.mark.parametrize("case", MIXED_CASES)

@@ -48,11 +48,15 @@ def _smoother_from_zero(A, D, nu):
     return S
 
 
-def _dense_B(H, pre, post):
-    """B^k recursively: pre-smooth, coarse correction, post-smooth (Sec. 3.1)."""
+def _dense_B(H, pre, post, coarse_sweeps=0):
+    """B^k recursively: pre-smooth, coarse correction, post-smooth (Sec. 3.1);
+    at the coarsest level A^-1, or coarse_sweeps l1-Jacobi sweeps from zero."""
     levels = [H.level(k) for k in range(H.nlevels)]
     mats = [W.CSR(L["n"], L["row_ptr"], L["col"], L["val"]).scipy().toarray() for L in levels]
-    B = np.linalg.inv(mats[-1])
+    if coarse_sweeps:
+        B = _smoother_from_zero(mats[-1], np.diag(levels[-1]["dinv"]), coarse_sweeps)
+    else:
+        B = np.linalg.inv(mats[-1])
     for k in range(H.nlevels - 2, -1, -1):
         A = mats[k]
         D = np.diag(levels[k]["dinv"])
@@ -122,6 +126,25 @@ def test_binary32_vcycle_within_rounding_of_dense_operator(maker, steps, pre, po
         # scaling by a power of two commutes with every binary32 rounding
         s = 2.0 ** -5
         assert np.array_equal(H.vcycle_f32(r * s), H.vcycle_f32(r) * s)
+
+
+@pytest.mark.parametrize("maker", ["poisson", "diffusion27"])
+def test_binary32_vcycle_with_sweeps_at_the_coarsest_level(maker):
+    """Coarsest level solved by 20 l1-Jacobi sweeps (the paper's setting):
+    the binary32 cycle against the dense binary64 operator whose coarsest
+    block is the 20-sweep polynomial, same 64 u bound; the binary64 cycle
+    equals that operator to 1e-12."""
+    A = {"poisson": lambda: W.poisson7(6), "diffusion27": lambda: W.diffusion27(5, 3)}[maker]()
+    H = oracle.Hierarchy(A, oracle.AMGParams(aggr_steps=2, coarse_max=12, coarse_solver=1,
+                                             coarse_sweeps=20))
+    assert H.nlevels >= 3 and not H.coarse_dense
+    B, _, _ = _dense_B(H, 4, 4, coarse_sweeps=20)
+    for seed in (77, 78):
+        r = W.uniform_pm1(seed, A.n)
+        ref = B @ r
+        assert np.max(np.abs(H.vcycle(r) - ref)) <= 1e-12 * np.max(np.abs(ref))
+        err = np.max(np.abs(H.vcycle_f32(r) - ref)) / np.max(np.abs(ref))
+        assert 1e-9 < err <= 64 * U32
 
 
 @pytest.mark.parametrize("maker,N", [("poisson", 16), ("diffusion27", 10), ("lognormal7", 12)])
