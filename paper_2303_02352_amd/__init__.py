@@ -346,8 +346,9 @@ class Batch:
         self.device = _device_of(systems[0][2])
 
     def _block(self, a, name, nrhs):
-        if int(nrhs) not in (1, 2, 4, 8, 16):
-            raise ValueError("nrhs must be 1, 2, 4, 8 or 16")
+        # (an unsupported nrhs is the library's to refuse: AMG_ERR_UNSUPPORTED)
+        if int(nrhs) < 1:
+            raise ValueError("nrhs must be positive")
         return _arr(a, name, "float64", sum(self.sizes) * int(nrhs), ("cuda", self.device))
 
     def close(self):

@@ -113,7 +113,7 @@ def test_batch_refuses_bad_blocks():
     with pytest.raises(ValueError):
         B.solve(ok, _FakeCuda(np.zeros(91 * 4 - 1)), 4)
     with pytest.raises(ValueError):
-        B.solve(ok, ok, 3)                      # nrhs not a supported width
+        B.solve(ok, ok, 0)
     with pytest.raises(ValueError):
         B.vcycle(ok, np.zeros(91 * 4), 4)       # host output
     with pytest.raises(ValueError):
