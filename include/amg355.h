@@ -162,6 +162,26 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out);
 int amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
                   int32_t *iters_out, double *relres_out);
 
+/* The same solve as amg_pcg_solve, for callers that cannot allocate memory
+ * during a solve (tight serving loops, harnesses that forbid allocation): it
+ * calls no hipMalloc, hipFree, graph instantiation or event creation.  The
+ * PCG scalars and the partial sums of the fine-level reductions live in a
+ * static device array of 4 MiB, one per device, held until the process ends
+ * (its address is looked up once per device by amg_setup); everything else
+ * is the hierarchy's, allocated by amg_setup.  Each iteration's kernels are
+ * launched one by one (no graph), and the host waits by polling the scalars
+ * the GPU copies to the hierarchy's pinned memory.  Results are bit-identical
+ * to amg_pcg_solve's.
+ * Limit: n_0 <= amg_pcg_solve_noalloc_max_rows() (89,473,024 rows); a larger
+ * hierarchy gives AMG_ERR_INVALID before any work is queued.
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (from different host
+ * threads, or on streams that run concurrently) race and give wrong results.
+ * Arguments, statuses and synchronisation as amg_pcg_solve. */
+int amg_pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol,
+                          int32_t maxit, int32_t *iters_out, double *relres_out);
+int64_t amg_pcg_solve_noalloc_max_rows(void);
+
 /* Release everything held by h.  NULL-safe.  Synchronises the stream first. */
 void amg_destroy(amg_hierarchy *h);
 

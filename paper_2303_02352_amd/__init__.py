@@ -62,6 +62,9 @@ EXPORTS = {
     "amg_setup": (C.c_int, [C.POINTER(amg_csr), C.POINTER(amg_params), C.POINTER(C.c_void_p)]),
     "amg_pcg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                 C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "amg_pcg_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "amg_pcg_solve_noalloc_max_rows": (C.c_int64, []),
     "amg_destroy": (None, [C.c_void_p]),
     "amg_strerror": (C.c_char_p, [C.c_int]),
     "amg_last_error": (C.c_char_p, []),
@@ -261,6 +264,18 @@ class Hierarchy:
         st = load().amg_pcg_solve(self.h, pb, px, float(rtol), int(maxit), C.byref(it), C.byref(rel))
         if check and st < 0:
             raise AMGError(st, "amg_pcg_solve")
+        return st, it.value, rel.value
+
+    def solve_noalloc(self, b, x, rtol=1e-6, maxit=1000, check=True):
+        """amg_pcg_solve_noalloc: the same solve with its PCG state in the
+        library's static per-device scratch (no allocation during the call).
+        Returns (status, iters, relres)."""
+        it, rel = C.c_int32(), C.c_double()
+        pb, px = self._vec(b, "b"), self._vec(x, "x")
+        st = load().amg_pcg_solve_noalloc(self.h, pb, px, float(rtol), int(maxit), C.byref(it),
+                                          C.byref(rel))
+        if check and st < 0:
+            raise AMGError(st, "amg_pcg_solve_noalloc")
         return st, it.value, rel.value
 
     def info(self) -> dict:

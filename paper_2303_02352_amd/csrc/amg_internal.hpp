@@ -296,6 +296,7 @@ constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kSlice = 64;         // SELL slice height = one wavefront of rows
 constexpr int kBlock = 256;        // rows per workgroup in row-parallel kernels
 constexpr int kXcd = 8;            // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kMaxDevices = 64;    // devices a process may use the library on
 constexpr int kDenseMax = 1024;    // largest coarsest level factored densely
 constexpr double kStagnation = 0.95;
 constexpr int kTailRows = 1024;    // levels up to this size run in the coarse-tail kernel
@@ -425,6 +426,7 @@ struct amg_hierarchy {
   hipStream_t stream = nullptr;
   bool own_stream = false;     // stream from acquire_private_stream (on stream_dev)
   int stream_dev = 0;
+  int dev = 0;                 // device current at amg_setup (holds every buffer)
   std::vector<amg::Level> L;
   int coarse_dense = 0;
   amg::dvec<double> Ainv;      // inverse of the coarsest matrix, column-major
@@ -462,6 +464,13 @@ void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y);
 void enqueue_sweep(amg_hierarchy *h, int k, const double *r, const double *x, double *xn);
 int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,
               double *relres);
+// amg_pcg_solve_noalloc: the same solve with its PCG state in a static
+// per-device scratch array; noalloc_scratch(dev) looks up (once per device)
+// and returns that array's device address.
+int pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit,
+                      int *iters, double *relres);
+void *noalloc_scratch(int dev);
+int64_t noalloc_max_rows();
 void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, double *bytes);
 void destroy_graph(amg_hierarchy *h);
 

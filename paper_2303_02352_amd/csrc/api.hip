@@ -170,6 +170,9 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
     h->own_stream = true;
   }
   st = guarded([&] {
+    AMG_HIP(hipGetDevice(&h->dev));
+    // device address of the allocation-free solve's scratch, once per device
+    (void)amg::noalloc_scratch(h->dev);
     amg::keep_pool_memory();
     amg::SetupStream on(h->stream, !h->own_stream);
     amg::PoolScope pool(h->stream);
@@ -203,6 +206,25 @@ int amg_pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int
     return st;
   });
 }
+
+int amg_pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit,
+                          int32_t *iters_out, double *relres_out) {
+  if (!h || !b || !x || !iters_out || !relres_out) return set_error(AMG_ERR_INVALID, "NULL argument");
+  if (!(rtol > 0.0) || !std::isfinite(rtol) || maxit < 1)
+    return set_error(AMG_ERR_INVALID, "rtol must be > 0 and maxit >= 1");
+  return guarded([&] {
+    int it = 0;
+    double rel = 0.0;
+    int st = amg::pcg_solve_noalloc(h, b, x, rtol, maxit, &it, &rel);
+    *iters_out = it;
+    *relres_out = rel;
+    if (st == AMG_ERR_NOT_SPD) g_last_error = "PCG breakdown: rho <= 0 (A or B not s.p.d.)";
+    if (st == AMG_ERR_NONFINITE) g_last_error = "non-finite value in the iteration";
+    return st;
+  });
+}
+
+int64_t amg_pcg_solve_noalloc_max_rows(void) { return amg::noalloc_max_rows(); }
 
 void amg_destroy(amg_hierarchy *h) {
   if (!h) return;

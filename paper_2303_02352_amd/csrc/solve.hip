@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "amg_internal.hpp"
@@ -1226,31 +1228,41 @@ FirstOut first_out_for(amg_hierarchy *h, double *z) {
 int nb_dot(int n) { return std::max(1, ceil_div(n, kBlock * kRowsDot)); }
 int nb_upd(int n) { return std::max(1, ceil_div(n, kBlock * kRowsUpd)); }
 
-void launch_spmv_dots(amg_hierarchy *h, const int *skip) {
+// Device state of one PCG solve: the scalar block (with the `done` flag the
+// iteration's kernels test) and 3 nb_dot(n) partial sums of the fine-level
+// reductions.  The hierarchy's own buffers, or the allocation-free solve's
+// static scratch.
+struct PcgState {
+  Scalars *sc;
+  double *part;
+};
+
+PcgState own_state(amg_hierarchy *h) { return PcgState{h->sc.p, h->partials.p}; }
+
+void launch_spmv_dots(amg_hierarchy *h, const int *skip, double *part) {
   const Level &L0 = h->L[0];
   const int n = L0.A.n, nbd = nb_dot(n);
   if (streamed<double>(L0))
     hipLaunchKernelGGL(k_pcg_spmv_dots<true>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
-                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, part);
   else
     hipLaunchKernelGGL(k_pcg_spmv_dots<false>, dim3(nbd), dim3(kBlock), 0, h->stream, skip, n,
-                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, h->partials.p);
+                       sell_ref(L0.S), val_ref<double>(L0.S), h->w.p, h->r.p, h->q.p, h->v.p, part);
 }
 
-void enqueue_iteration(amg_hierarchy *h) {
+void enqueue_iteration(amg_hierarchy *h, PcgState ps) {
   hipStream_t s = h->stream;
   const Level &L0 = h->L[0];
   const int n = L0.A.n, nbd = nb_dot(n), nbu = nb_upd(n);
-  const int *skip = &h->sc.p->done;
+  const int *skip = &ps.sc->done;
   const FirstOut fo = first_out_for(h, h->w.p);
   vcycle_any(h, skip, h->r.p, h->w.p, /*first_done=*/true);
-  launch_spmv_dots(h, skip);
-  hipLaunchKernelGGL(k_pcg_dots_finish, dim3(1), dim3(kFinish), 0, s, skip, nbd, h->partials.p,
-                     h->sc.p);
+  launch_spmv_dots(h, skip, ps.part);
+  hipLaunchKernelGGL(k_pcg_dots_finish, dim3(1), dim3(kFinish), 0, s, skip, nbd, ps.part, ps.sc);
   hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, skip, n, h->w.p, h->v.p, h->d.p,
-                     h->u.p, h->q.p, h->r.p, h->sc.p, h->partials.p, fo);
-  hipLaunchKernelGGL(k_pcg_norm_finish, dim3(1), dim3(kFinish), 0, s, skip, nbu, h->partials.p,
-                     h->sc.p, h->sc_host_dev);
+                     h->u.p, h->q.p, h->r.p, ps.sc, ps.part, fo);
+  hipLaunchKernelGGL(k_pcg_norm_finish, dim3(1), dim3(kFinish), 0, s, skip, nbu, ps.part, ps.sc,
+                     h->sc_host_dev);
   AMG_LAUNCH_CHECK();
 }
 
@@ -1368,8 +1380,13 @@ constexpr int kAhead = AMG_QUEUE_AHEAD;
 // scalars, vector updates + ||r||^2, convergence test, copy of the scalars
 // to pinned host memory].  The host keeps one further iteration queued and
 // waits on the older one; a queued iteration after convergence does nothing.
-int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,
-              double *relres) {
+//
+// alloc_free: the iteration's kernels are launched one by one (no graph is
+// instantiated) and the host waits by polling the scalars the last kernel of
+// each iteration writes to pinned host memory (no events are created); the
+// stream draining ends every wait, so it cannot outlast the queued work.
+int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, double *x, double rtol,
+            int maxit, int *iters, double *relres) {
   hipStream_t s = h->stream;
   const Level &L0 = h->L[0];
   const int n = L0.A.n, nb = nb_dot(n);
@@ -1378,24 +1395,46 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->q.p);
   if (streamed<double>(L0))
     hipLaunchKernelGGL(k_pcg_init<true>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
-                       b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
+                       b, h->u.p, h->r.p, ps.part, first_out_for(h, h->w.p));
   else
     hipLaunchKernelGGL(k_pcg_init<false>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
-                       b, h->u.p, h->r.p, h->partials.p, first_out_for(h, h->w.p));
-  hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, h->partials.p, h->sc.p, rtol,
-                     maxit);
+                       b, h->u.p, h->r.p, ps.part, first_out_for(h, h->w.p));
+  hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, ps.part, ps.sc, rtol, maxit);
   AMG_LAUNCH_CHECK();
-  AMG_HIP(hipMemcpyAsync(h->sc_host, h->sc.p, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  AMG_HIP(hipMemcpyAsync(h->sc_host, ps.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
   Scalars st = *h->sc_host;
-  if (!st.done) {
+  if (!st.done && alloc_free) {
+    const volatile Scalars *mirror = h->sc_host;
+    // true once iteration j has ended (or the solve has), read from the mirror
+    auto ended = [&](int j) { return mirror->done != 0 || mirror->it >= j; };
+    int launched = 0;
+    for (int k = 0; k <= kAhead && launched < maxit; ++k) {
+      enqueue_iteration(h, ps);
+      ++launched;
+    }
+    for (int j = 1;; ++j) {
+      while (!ended(j)) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipSuccess) break;            // drained: the mirror holds the final state
+        if (q != hipErrorNotReady) AMG_HIP(q);
+      }
+      if (mirror->done || j >= maxit) break;
+      if (launched < maxit) {
+        enqueue_iteration(h, ps);
+        ++launched;
+      }
+    }
+    AMG_HIP(hipStreamSynchronize(s));
+    st = *h->sc_host;
+  } else if (!st.done) {
     if (h->use_graph && !h->graph_exec) {
-      capture_graph(h->stream, &h->graph, [&] { enqueue_iteration(h); });
+      capture_graph(h->stream, &h->graph, [&] { enqueue_iteration(h, ps); });
       AMG_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
     }
     auto launch = [&]() {
       if (h->graph_exec) AMG_HIP(hipGraphLaunch(h->graph_exec, s));
-      else enqueue_iteration(h);
+      else enqueue_iteration(h, ps);
     };
     // iteration k (from 1) records ev[k % (kAhead + 1)]; before waiting on
     // iteration j at most j + kAhead have been launched, so its event is intact
@@ -1427,6 +1466,65 @@ int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int max
   return st.conv ? AMG_OK : AMG_NOT_CONVERGED;
 }
 
+int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,
+              double *relres) {
+  return pcg_run(h, own_state(h), false, b, x, rtol, maxit, iters, relres);
+}
+
+// ------------------------------------------------ allocation-free solve
+// The PCG state of amg_pcg_solve_noalloc lives in this file-scope array, one
+// copy per device, held until the process ends: the scalar block in the
+// first 256 bytes, then the partial sums.  Host code never passes the
+// array's name to a kernel; it uses the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+constexpr size_t kNoAllocBytes = size_t(4) << 20;
+constexpr size_t kNoAllocHead = 256;
+static_assert(sizeof(Scalars) <= kNoAllocHead, "scalar block exceeds its slot");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void *noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) fail(AMG_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    AMG_HIP(hipGetDevice(&cur));
+    if (cur != dev) AMG_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) AMG_HIP(hipSetDevice(cur));
+    AMG_HIP(e);
+    if (!p) fail(AMG_ERR_DEVICE, "no device address for the solve scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int64_t noalloc_max_rows() {
+  const int64_t parts = static_cast<int64_t>((kNoAllocBytes - kNoAllocHead) / (3 * sizeof(double)));
+  return parts * kBlock * kRowsDot;
+}
+
+int pcg_solve_noalloc(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit,
+                      int *iters, double *relres) {
+  const int n = h->L[0].A.n;
+  if (static_cast<int64_t>(n) > noalloc_max_rows())
+    fail(AMG_ERR_INVALID, "amg_pcg_solve_noalloc: n = " + std::to_string(n) + " exceeds its scratch (" +
+                              std::to_string(noalloc_max_rows()) + " rows)");
+  unsigned char *base = static_cast<unsigned char *>(noalloc_scratch(h->dev));
+  PcgState ps{reinterpret_cast<Scalars *>(base), reinterpret_cast<double *>(base + kNoAllocHead)};
+  // the scalar block starts from zero (k_pcg_init_finish then sets every
+  // field it reads); the partial sums are written before they are read
+  hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(kBlock), 0, h->stream, nullptr,
+                     static_cast<int>(kNoAllocHead / sizeof(double)), reinterpret_cast<double *>(base));
+  AMG_LAUNCH_CHECK();
+  return pcg_run(h, ps, true, b, x, rtol, maxit, iters, relres);
+}
+
 // ------------------------------------------------------- kernel timing
 void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, double *bytes) {
   hipStream_t s = h->stream;
@@ -1442,7 +1540,7 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
   auto launch = [&]() {
     switch (kernel) {
       case 0:
-        if (k == 0) launch_spmv_dots(h, nullptr);
+        if (k == 0) launch_spmv_dots(h, nullptr, h->partials.p);
         else launch_spmv(L, L.x.p, L.t.p, s);
         break;
       case 1:
