@@ -58,7 +58,9 @@ def build_timing(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [(name, C.c_int32) for name in (
         "aggr_steps", "max_levels", "coarse_max", "coarse_solver", "coarse_sweeps",
-        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond")]
+        "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond", "n_parts",
+        "cycle_type", "relax_type", "coarse_relax", "max_hrc", "bootstrap_type", "bootstrap_its",
+        "bootstrap_seed")] + [("bootstrap_rate", C.c_double)]
 
 
 @dataclass
@@ -76,9 +78,19 @@ class AMGParams:
     smooth_vec: int = 0
     smooth_sweeps: int = 20
     precond: int = 1
+    n_parts: int = 1            # decoupled aggregation over this many row blocks (Sec. 4.1)
+    cycle_type: int = 0         # 0 V, 1 H, 2 W
+    relax_type: int = 4         # 0 Jacobi, 1 forward/backward GS, 3 symmetrized GS, 4 l1-Jacobi
+    coarse_relax: int = 4       # the same codes, for coarse_solver = 1
+    max_hrc: int = 1            # bootstrap: most hierarchies in the composite
+    bootstrap_type: int = 0     # 0 multiplicative, 1 symmetrized multiplicative, 2 additive
+    bootstrap_its: int = 15     # composite iterations on A x = 0 per rate estimate
+    bootstrap_seed: int = 1
+    bootstrap_rate: float = 0.8  # desired convergence rate of the composite
 
     def c(self) -> Params:
-        return Params(*[int(getattr(self, f.name)) for f in fields(self)])
+        return Params(*[float(getattr(self, f.name)) if f.name == "bootstrap_rate"
+                        else int(getattr(self, f.name)) for f in fields(self)])
 
 
 _lib = None
@@ -130,8 +142,10 @@ def _register(L):
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.orc_pcg.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32,
                               C.POINTER(C.c_int32), C.POINTER(C.c_double)]
-        L.orc_pairwise_step.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p,
-                                        _f64p, C.POINTER(C.c_int32),
+        L.orc_row_blocks.argtypes = [C.c_int32, C.c_int32, _i32p]
+        L.orc_export_part.argtypes = [C.c_void_p, C.c_int, _i32p]
+        L.orc_pairwise_step.argtypes = [C.c_int32, _i32p, _i32p, _f64p, _f64p, C.c_void_p, _i32p,
+                                        _i32p, _f64p, C.POINTER(C.c_int32),
                                         C.POINTER(C.POINTER(C.c_double)),
                                         C.POINTER(C.POINTER(C.c_int32)),
                                         C.POINTER(C.POINTER(C.c_int32)),
@@ -197,10 +211,20 @@ def chol_solve(L, r):
     return x
 
 
-def pairwise_step(A, w):
-    """One pairwise coarsening step: dict with mate, agg, pval, nc, wc and the coarse CSR."""
+def row_blocks(n, n_parts):
+    """Row block of each of n rows split into n_parts consecutive blocks (Sec. 4.1)."""
+    part = np.empty(n, np.int32)
+    assert lib().orc_row_blocks(int(n), int(n_parts), part) == OK
+    return part
+
+
+def pairwise_step(A, w, part=None):
+    """One pairwise coarsening step: dict with mate, agg, pval, nc, wc and the coarse CSR.
+    part: row block of each row (decoupled aggregation), or None."""
     L = lib()
     n = A.n
+    part = None if part is None else np.ascontiguousarray(part, np.int32)
+    pp = None if part is None else part.ctypes.data_as(C.c_void_p)
     mate = np.empty(n, np.int32)
     agg = np.empty(n, np.int32)
     pval = np.empty(n)
@@ -210,7 +234,7 @@ def pairwise_step(A, w):
     cci = C.POINTER(C.c_int32)()
     cv = C.POINTER(C.c_double)()
     cnnz = C.c_int64()
-    st = L.orc_pairwise_step(*_csr_args(A), np.ascontiguousarray(w, np.float64), mate, agg, pval,
+    st = L.orc_pairwise_step(*_csr_args(A), np.ascontiguousarray(w, np.float64), pp, mate, agg, pval,
                              C.byref(nc), C.byref(wc), C.byref(crp), C.byref(cci), C.byref(cv),
                              C.byref(cnnz))
     assert st == OK, st
@@ -280,6 +304,13 @@ class Hierarchy:
         return dict(n=n, nnz=z, row_ptr=rp, col=ci[:z], val=v[:z], w=w, dinv=dinv,
                     agg=agg if k < self.nlevels - 1 else None,
                     pval=pval if k < self.nlevels - 1 else None)
+
+    def part(self, k):
+        """Row block of each row of level k (decoupled aggregation)."""
+        n, _ = self.level_size(k)
+        out = np.empty(n, np.int32)
+        assert self._L.orc_export_part(self.h, k, out) == OK
+        return out
 
     def coarse_factor(self):
         n, _ = self.level_size(self.nlevels - 1)

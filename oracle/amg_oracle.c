@@ -63,6 +63,16 @@ typedef struct {
   int32_t smooth_vec;    /* 0 ones, 1 relaxation from ones, 2 caller-given */
   int32_t smooth_sweeps; /* relaxation sweeps for smooth_vec 1 */
   int32_t precond;       /* 1 AMG V-cycle, 0 identity (plain CG) */
+  int32_t n_parts;       /* decoupled aggregation: row blocks matched separately (>= 1) */
+  int32_t cycle_type;    /* 0 V-cycle, 1 H-cycle, 2 W-cycle */
+  int32_t relax_type;    /* smoother: 0 Jacobi, 1 forward/backward Gauss-Seidel,
+                            3 symmetrized Gauss-Seidel, 4 l1-Jacobi */
+  int32_t coarse_relax;  /* the same codes, for coarse_solver 1 */
+  int32_t max_hrc;       /* bootstrap: most hierarchies in the composite (>= 1) */
+  int32_t bootstrap_type;/* 0 multiplicative, 1 symmetrized multiplicative, 2 additive */
+  int32_t bootstrap_its; /* iterations of the composite on A x = 0 per rate estimate */
+  int32_t bootstrap_seed;/* seed of the random start vectors */
+  double bootstrap_rate; /* desired convergence rate of the composite */
 } orc_params;
 
 typedef struct {
@@ -77,6 +87,7 @@ typedef struct {
   orc_params p;
   int nlev;
   csr_t A[ORC_MAXLEV];
+  int32_t *part[ORC_MAXLEV]; /* row block (task) of each row, Sec. 4.1 */
   double *dinv[ORC_MAXLEV];
   double *w[ORC_MAXLEV];     /* smooth vector of each level */
   int32_t *agg[ORC_MAXLEV];  /* level k row -> level k+1 row */
@@ -281,8 +292,10 @@ static int edge_cmp_desc(const void *pa, const void *pb) {
 }
 
 /* Sequential greedy: scan eligible edges by decreasing key, match when both
- * ends are free.  mate[i] = partner or -1. */
-static int match_greedy(const csr_t *A, const double *w, int32_t *mate) {
+ * ends are free.  mate[i] = partner or -1.  With part != NULL (decoupled
+ * aggregation, Sec. 4.1) an edge whose ends lie in different row blocks is
+ * not eligible: each block is matched as its own local subgraph. */
+static int match_greedy(const csr_t *A, const double *w, const int32_t *part, int32_t *mate) {
   double *d = diag_of(A);
   if (!d) return ORC_NOMEM;
   int64_t m = 0;
@@ -296,6 +309,7 @@ static int match_greedy(const csr_t *A, const double *w, int32_t *mate) {
     for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) {
       int32_t j = A->ci[k];
       if (j <= i || A->v[k] == 0.0) continue;
+      if (part && part[i] != part[j]) continue;
       double wt = edge_weight(A->v[k], d[i], d[j], w[i], w[j]);
       if (!(wt > 0.0)) continue;
       E[e].w = wt; E[e].hi = j; E[e].lo = i; e++;
@@ -315,7 +329,27 @@ static int match_greedy(const csr_t *A, const double *w, int32_t *mate) {
 int orc_match_greedy(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
                      const double *w, int32_t *mate) {
   csr_t A = {n, rp[n], (int32_t *)rp, (int32_t *)ci, (double *)v};
-  return match_greedy(&A, w, mate);
+  return match_greedy(&A, w, NULL, mate);
+}
+
+/* ------------------------------------------------- decoupled aggregation
+ * Sec. 4.1: every task owns a block of consecutive rows and matches only the
+ * subgraph of its own rows.  Block p of n rows split into np blocks is
+ * [floor(p n / np), floor((p+1) n / np)).  An aggregate then lies inside one
+ * block, and the coarse row it becomes belongs to that block; since
+ * aggregates are numbered by their smallest row, the coarse blocks are again
+ * consecutive ranges. */
+static void row_blocks(int32_t n, int32_t np, int32_t *part) {
+  for (int32_t p = 0; p < np; p++) {
+    int64_t a = (int64_t)p * n / np, b = (int64_t)(p + 1) * n / np;
+    for (int64_t i = a; i < b; i++) part[i] = p;
+  }
+}
+
+int orc_row_blocks(int32_t n, int32_t np, int32_t *part) {
+  if (n < 1 || np < 1) return ORC_INVALID;
+  row_blocks(n, np, part);
+  return ORC_OK;
 }
 
 /* Sequential Suitor (Manne and Halappanavar): each vertex proposes to its
@@ -579,7 +613,11 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
   if (*status != ORC_OK) return NULL;
   if (par->aggr_steps < 1 || par->max_levels < 1 || par->coarse_max < 1 ||
       par->pre_sweeps < 0 || par->post_sweeps < 0 || par->coarse_sweeps < 1 ||
-      par->smooth_sweeps < 0) {
+      par->smooth_sweeps < 0 || par->n_parts < 1) {
+    *status = ORC_INVALID; return NULL;
+  }
+  /* cycle and smoother variants and the bootstrap composite: not built yet */
+  if (par->cycle_type != 0 || par->relax_type != 4 || par->coarse_relax != 4 || par->max_hrc != 1) {
     *status = ORC_INVALID; return NULL;
   }
   orc_h *h = (orc_h *)calloc(1, sizeof(orc_h));
@@ -596,6 +634,9 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
   l1_dinv(&h->A[0], h->dinv[0]);
   *status = smooth_vector(par, &h->A[0], h->dinv[0], w_given, h->w[0]);
   if (*status != ORC_OK) { orc_free(h); return NULL; }
+  h->part[0] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!h->part[0]) { orc_free(h); *status = ORC_NOMEM; return NULL; }
+  row_blocks(n, par->n_parts, h->part[0]);
 
   int maxlev = par->max_levels < ORC_MAXLEV ? par->max_levels : ORC_MAXLEV;
   while (par->precond && h->nlev < maxlev && h->A[h->nlev - 1].n > par->coarse_max) {
@@ -603,6 +644,7 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
     int32_t nk = h->A[k].n;
     csr_t cur = h->A[k];       /* borrowed for step 0 */
     double *wcur = h->w[k];
+    int32_t *pcur = h->part[k];
     int32_t *aggt = (int32_t *)malloc(sizeof(int32_t) * (size_t)nk);
     double *pt = (double *)malloc(sizeof(double) * (size_t)nk);
     if (!aggt || !pt) { free(aggt); free(pt); orc_free(h); *status = ORC_NOMEM; return NULL; }
@@ -615,39 +657,42 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
       int32_t *a1 = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
       double *p1 = (double *)malloc(sizeof(double) * (size_t)m);
       if (!mate || !a1 || !p1) { *status = ORC_NOMEM; }
-      else *status = match_greedy(&cur, wcur, mate);
+      else *status = match_greedy(&cur, wcur, pcur, mate);
       if (*status != ORC_OK) {
         free(mate); free(a1); free(p1); free(aggt); free(pt);
-        if (owned) { csr_free(&cur); free(wcur); }
+        if (owned) { csr_free(&cur); free(wcur); free(pcur); }
         orc_free(h); return NULL;
       }
       int32_t mc = aggregate_ids(m, mate, a1);
       pair_pvals(m, mate, wcur, p1);
       double *wc = (double *)malloc(sizeof(double) * (size_t)mc);
+      int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(mc > 0 ? mc : 1));
       csr_t Ac;
       memset(&Ac, 0, sizeof(Ac));
-      *status = wc ? galerkin(&cur, mc, a1, p1, &Ac) : ORC_NOMEM;
+      *status = (wc && pc) ? galerkin(&cur, mc, a1, p1, &Ac) : ORC_NOMEM;
       if (*status != ORC_OK) {
-        free(mate); free(a1); free(p1); free(wc); free(aggt); free(pt);
-        if (owned) { csr_free(&cur); free(wcur); }
+        free(mate); free(a1); free(p1); free(wc); free(pc); free(aggt); free(pt);
+        if (owned) { csr_free(&cur); free(wcur); free(pcur); }
         orc_free(h); return NULL;
       }
       restrict_fold(m, mc, a1, p1, wcur, wc);
+      /* the coarse row of an aggregate stays in its members' block */
+      for (int32_t i = 0; i < m; i++) pc[a1[i]] = pcur[i];
       for (int32_t i = 0; i < nk; i++) {
         pt[i] = pt[i] * p1[aggt[i]];
         aggt[i] = a1[aggt[i]];
       }
-      if (owned) { csr_free(&cur); free(wcur); }
-      cur = Ac; wcur = wc; owned = 1;
+      if (owned) { csr_free(&cur); free(wcur); free(pcur); }
+      cur = Ac; wcur = wc; pcur = pc; owned = 1;
       free(mate); free(a1); free(p1);
     }
     if (!owned || (double)cur.n > ORC_STAGNATION * (double)nk) {
-      if (owned) { csr_free(&cur); free(wcur); }
+      if (owned) { csr_free(&cur); free(wcur); free(pcur); }
       free(aggt); free(pt);
       break;
     }
     h->agg[k] = aggt; h->pval[k] = pt;
-    h->A[k + 1] = cur; h->w[k + 1] = wcur;
+    h->A[k + 1] = cur; h->w[k + 1] = wcur; h->part[k + 1] = pcur;
     h->dinv[k + 1] = (double *)malloc(sizeof(double) * (size_t)cur.n);
     if (!h->dinv[k + 1]) { h->nlev = k + 2; orc_free(h); *status = ORC_NOMEM; return NULL; }
     l1_dinv(&h->A[k + 1], h->dinv[k + 1]);
@@ -696,7 +741,7 @@ void orc_free(orc_h *h) {
   if (!h) return;
   for (int k = 0; k < ORC_MAXLEV; k++) {
     csr_free(&h->A[k]);
-    free(h->dinv[k]); free(h->w[k]); free(h->agg[k]); free(h->pval[k]);
+    free(h->dinv[k]); free(h->w[k]); free(h->agg[k]); free(h->pval[k]); free(h->part[k]);
     free(h->vx[k]); free(h->vt[k]); free(h->vr[k]); free(h->vres[k]); free(h->ve[k]);
     free(h->fv[k]); free(h->fdinv[k]); free(h->fpval[k]);
     free(h->fx[k]); free(h->ft[k]); free(h->fr[k]); free(h->fres[k]); free(h->fe[k]);
@@ -1029,11 +1074,11 @@ int orc_export_coarse_factor(const orc_h *h, double *L) {
  * aggregates, P values, coarse vector and coarse matrix (caller frees via
  * orc_free_csr_arrays). */
 int orc_pairwise_step(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-                      const double *w, int32_t *mate, int32_t *agg, double *pval,
-                      int32_t *nc_out, double **wc_out, int32_t **crp, int32_t **cci,
-                      double **cv, int64_t *cnnz) {
+                      const double *w, const int32_t *part, int32_t *mate, int32_t *agg,
+                      double *pval, int32_t *nc_out, double **wc_out, int32_t **crp,
+                      int32_t **cci, double **cv, int64_t *cnnz) {
   csr_t A = {n, rp[n], (int32_t *)rp, (int32_t *)ci, (double *)v};
-  int st = match_greedy(&A, w, mate);
+  int st = match_greedy(&A, w, part, mate);
   if (st != ORC_OK) return st;
   int32_t nc = aggregate_ids(n, mate, agg);
   pair_pvals(n, mate, w, pval);
@@ -1044,6 +1089,13 @@ int orc_pairwise_step(int32_t n, const int32_t *rp, const int32_t *ci, const dou
   if (st != ORC_OK) { free(wc); return st; }
   restrict_fold(n, nc, agg, pval, w, wc);
   *nc_out = nc; *wc_out = wc; *crp = Ac.rp; *cci = Ac.ci; *cv = Ac.v; *cnnz = Ac.nnz;
+  return ORC_OK;
+}
+
+/* Row block of every row of level k (decoupled aggregation). */
+int orc_export_part(const orc_h *h, int k, int32_t *part) {
+  if (!h || k < 0 || k >= h->nlev) return ORC_INVALID;
+  memcpy(part, h->part[k], sizeof(int32_t) * (size_t)h->A[k].n);
   return ORC_OK;
 }
 
