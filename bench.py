@@ -239,24 +239,72 @@ def paper_leg(amd, torch, W, np, dev, nd=300):
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     rp, ci, va = d(A.row_ptr), d(A.col), d(A.val)
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
-    out = None
-    for rep in range(2):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        H = amd.Hierarchy(rp, ci, va, aggr_steps=3, coarse_max=40 * nd, coarse_solver=amd.AMG_COARSE_JACOBI,
-                          coarse_sweeps=20)
-        t1 = time.perf_counter()
-        x = torch.zeros(A.n, dtype=torch.float64, device=dev)
-        st, it, rel = H.solve(b, x, rtol=RTOL, maxit=MAXIT)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        inf = H.info()
-        out = dict(nd=nd, rows=A.n, nnz=A.nnz, status=st, iters=it, relres=rel, setup_s=t1 - t0,
-                   solve_s=t2 - t1, titer_ms=(t2 - t1) / max(1, it) * 1e3, levels=inf["n"],
-                   opc=inf["opc"], paper_context=dict(levels=5, opc=1.14, solve_s_one_p100=5.14))
-        H.close()
+
+    def run(n_parts, reps):
+        rec = None
+        for rep in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = amd.Hierarchy(rp, ci, va, aggr_steps=3, coarse_max=40 * nd,
+                              coarse_solver=amd.AMG_COARSE_JACOBI, coarse_sweeps=20, n_parts=n_parts)
+            t1 = time.perf_counter()
+            x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            st, it, rel = H.solve(b, x, rtol=RTOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            inf = H.info()
+            rec = dict(n_parts=n_parts, status=st, iters=it, relres=rel, setup_s=t1 - t0,
+                       solve_s=t2 - t1, titer_ms=(t2 - t1) / max(1, it) * 1e3, levels=inf["n"],
+                       opc=inf["opc"])
+            H.close()
+        return rec
+
+    out = dict(nd=nd, rows=A.n, nnz=A.nnz, **run(1, 2),
+               paper_context=dict(levels=5, opc=1.14, solve_s_one_p100=5.14))
+    # Decoupled aggregation (Sec. 4.1) as the paper's strong-scaling runs set
+    # it up: the same 300^3 system split into 2..16 row blocks, each matched
+    # on its own subgraph (one GPU runs all blocks).  The paper reports 5
+    # levels for every task count and OPC about 1.14.
+    out["decoupled_strong"] = [run(q, 1) for q in (2, 4, 8, 16)]
     del rp, ci, va
     return out
+
+
+def decoupled_weak_leg(amd, torch, W, np, dev, nd=130, tasks=(1, 2, 4, 8)):
+    """Weak scaling of decoupled aggregation as the paper ran it (Sec. 5.2):
+    a 130^3 share per task, here P tasks' shares stacked along z (a
+    130 x 130 x 130 P box, P row blocks = P cubes) solved on one GPU in the
+    paper configuration (s = 3, coarsest <= 40 * 130 rows by 20 sweeps,
+    f = 1).  The paper reports 4 levels on 1 task, 5 on 2-16, and about 36 %
+    more iterations from 1 to 100 tasks."""
+    recs = []
+    for P in tasks:
+        A = W.poisson7_box(nd, nd, nd * P)
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        rp, ci, va = d(A.row_ptr), d(A.col), d(A.val)
+        b = torch.ones(A.n, dtype=torch.float64, device=dev)
+        del A
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = amd.Hierarchy(rp, ci, va, aggr_steps=3, coarse_max=40 * nd,
+                              coarse_solver=amd.AMG_COARSE_JACOBI, coarse_sweeps=20, n_parts=P)
+            t1 = time.perf_counter()
+            x = torch.zeros(b.numel(), dtype=torch.float64, device=dev)
+            st, it, rel = H.solve(b, x, rtol=RTOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            inf = H.info()
+            rec = dict(tasks=P, rows=b.numel(), status=st, iters=it, relres=rel, setup_s=t1 - t0,
+                       solve_s=t2 - t1, titer_ms=(t2 - t1) / max(1, it) * 1e3, levels=inf["n"],
+                       opc=inf["opc"])
+            H.close()
+        recs.append(rec)
+        log("weak", json.dumps(rec))
+        del rp, ci, va, b, x
+        torch.cuda.empty_cache()
+    return dict(per_task="130^3", runs=recs,
+                paper_context=dict(levels={"1": 4, "2-16": 5, "32-100": 6}, iteration_growth_1_to_100=0.36))
 
 
 def sweep_kernel_name(info):
@@ -278,7 +326,8 @@ def main():
     ap.add_argument("--values", choices=["auto", "plain"], default="auto",
                     help="matrix values of the solve kernels: coded where a level has at most "
                          "256 distinct values (auto), or plain binary64 arrays")
-    ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160"],
+    ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160",
+                                       "decoupled_weak"],
                     help="only: run one form's leg and print its record (for profiling)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only: build the 160^3 hierarchy, launch the fine-level sweep "
@@ -298,7 +347,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.only and args.only != "mixed160":
-        leg = dict(batched=batched_leg, mixed27=mixed27_leg, learned=learned_leg, paper=paper_leg)[args.only]
+        leg = dict(batched=batched_leg, mixed27=mixed27_leg, learned=learned_leg, paper=paper_leg,
+                   decoupled_weak=decoupled_weak_leg)[args.only]
         log("only", args.only)
         print(json.dumps({"form": args.only, "record": leg(amd, torch, W, np, dev)}), flush=True)
         return

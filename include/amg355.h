@@ -64,6 +64,19 @@ extern "C" {
 #define AMG_VALUES_AUTO 1         /* a level whose stored values take at most 256 distinct
                                      bit patterns keeps one byte per entry, an index into a
                                      per-level table of those values; other levels plain */
+/* cycle_type (Appendix A option set) */
+#define AMG_CYCLE_V 0             /* one coarse-grid correction per level (Alg. 2) */
+#define AMG_CYCLE_H 1             /* two corrections on odd levels, one on even levels */
+#define AMG_CYCLE_W 2             /* two coarse-grid corrections on every level */
+/* relax_type / coarse_relax (Appendix A codes) */
+#define AMG_RELAX_JACOBI 0        /* x <- x + (r - A x) / a_ii */
+#define AMG_RELAX_GS 1            /* forward Gauss-Seidel before, backward after the correction */
+#define AMG_RELAX_SYM_GS 3        /* each sweep a forward then a backward Gauss-Seidel pass */
+#define AMG_RELAX_L1_JACOBI 4     /* x <- x + (r - A x) / sum_j |a_ij|  (Sec. 3.1) */
+/* bootstrap_type: composition rule of the hierarchies of a bootstrap composite */
+#define AMG_BOOTSTRAP_MULT 0      /* B_1, then B_2 on the remaining residual, ... */
+#define AMG_BOOTSTRAP_SYMMULT 1   /* B_1 ... B_m, then B_{m-1} ... B_1 */
+#define AMG_BOOTSTRAP_ADD 2       /* B_1 + ... + B_m */
 
 /* Square sparse matrix in CSR form.
  *   row_ptr: n+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
@@ -87,7 +100,10 @@ typedef struct {
  *   aggr_steps 2 (aggregates of at most 4), max_levels 40, coarse_max 100,
  *   coarse_solver CHOLESKY, coarse_sweeps 20, pre/post sweeps 4/4,
  *   smooth_vec ONES, smooth_sweeps 20, precond 1, precision DOUBLE,
- *   value_coding AUTO, smooth_vector NULL, stream NULL.
+ *   value_coding AUTO, n_parts 1, cycle_type V, relax_type and coarse_relax
+ *   L1_JACOBI, max_hrc 1, bootstrap_type MULT, bootstrap_its 15,
+ *   bootstrap_seed 1, bootstrap_rate 0.8, smooth_vector NULL, model_params
+ *   NULL, stream NULL.
  * The paper's own runs (Sec. 5, Appendix A) use aggr_steps 3, coarse_max
  * 40*nd, coarse_solver JACOBI with 20 sweeps. */
 typedef struct {
@@ -103,7 +119,22 @@ typedef struct {
   int32_t precond;         /* 1: AMG V-cycle; 0: B = I, plain CG (Appendix A) */
   int32_t precision;       /* AMG_PREC_* */
   int32_t value_coding;    /* AMG_VALUES_* */
+  int32_t n_parts;         /* 1 .. 2^24: decoupled aggregation (Sec. 4.1): the rows of every
+                              level are split into n_parts blocks of consecutive rows (block p
+                              = [floor(p n / n_parts), floor((p+1) n / n_parts)) on the fine
+                              level; a coarse row belongs to the block of its aggregate) and
+                              each block is matched on its own subgraph: edges between blocks
+                              are never matched, so P is block diagonal.  1 = one block. */
+  int32_t cycle_type;      /* AMG_CYCLE_* */
+  int32_t relax_type;      /* AMG_RELAX_*: pre- and post-smoother */
+  int32_t coarse_relax;    /* AMG_RELAX_*: the coarsest-level sweeps when they are used */
+  int32_t max_hrc;         /* 1 .. 16: bootstrap composite of at most max_hrc hierarchies */
+  int32_t bootstrap_type;  /* AMG_BOOTSTRAP_* */
+  int32_t bootstrap_its;   /* >= 1: composite iterations on A x = 0 per rate estimate */
+  int32_t bootstrap_seed;  /* seed of the bootstrap's random start vectors */
+  double bootstrap_rate;   /* (0, 1]: desired convergence rate of the composite */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
+  const float *model_params;   /* AMG_SMOOTH_LEARNED: AMG_MPNN_NPARAMS floats in host memory */
   void *stream;            /* hipStream_t on which the solve-phase work is ordered; NULL =
                               a blocking stream the library keeps for this hierarchy alone
                               (reused after amg_destroy).  A caller's stream must stay

@@ -24,6 +24,9 @@ AMG_COARSE_CHOLESKY, AMG_COARSE_JACOBI = 0, 1
 AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN = 0, 1, 2
 AMG_PREC_DOUBLE, AMG_PREC_MIXED = 0, 1
 AMG_VALUES_PLAIN, AMG_VALUES_AUTO = 0, 1
+AMG_CYCLE_V, AMG_CYCLE_H, AMG_CYCLE_W = 0, 1, 2
+AMG_RELAX_JACOBI, AMG_RELAX_GS, AMG_RELAX_SYM_GS, AMG_RELAX_L1_JACOBI = 0, 1, 3, 4
+AMG_BOOTSTRAP_MULT, AMG_BOOTSTRAP_SYMMULT, AMG_BOOTSTRAP_ADD = 0, 1, 2
 AMG_MAX_LEVELS = 64
 KERNEL_SPMV, KERNEL_SWEEP, KERNEL_RESTRICT, KERNEL_PROLONG, KERNEL_UPDATE, KERNEL_CORR_SWEEP = 0, 1, 2, 3, 4, 5
 
@@ -37,8 +40,10 @@ class amg_params(C.Structure):
     _fields_ = [(f, C.c_int32) for f in (
         "aggr_steps", "max_levels", "coarse_max", "coarse_solver", "coarse_sweeps",
         "pre_sweeps", "post_sweeps", "smooth_vec", "smooth_sweeps", "precond", "precision",
-        "value_coding")] + [
-        ("smooth_vector", C.c_void_p), ("stream", C.c_void_p)]
+        "value_coding", "n_parts", "cycle_type", "relax_type", "coarse_relax", "max_hrc",
+        "bootstrap_type", "bootstrap_its", "bootstrap_seed")] + [
+        ("bootstrap_rate", C.c_double), ("smooth_vector", C.c_void_p),
+        ("model_params", C.c_void_p), ("stream", C.c_void_p)]
 
 
 class amg_info_t(C.Structure):
@@ -178,7 +183,10 @@ def _where(sp):
 def default_params(**overrides) -> amg_params:
     p = amg_params()
     load().amg_params_default(C.byref(p))
+    names = {f[0] for f in amg_params._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise TypeError("unknown amg_params field %r" % k)
         setattr(p, k, v)
     return p
 

@@ -476,6 +476,7 @@ void destroy_graph(amg_hierarchy *h);
 
 // --------------------------------------------------- C ABI error plumbing
 int api_set_error(int code, const std::string &msg);
+int api_check_params(const amg_params *p);        // AMG_OK or the status (message set)
 int api_guarded(const std::function<int()> &f);   // maps amg::Error to a status
 const std::string &api_last_error();
 

@@ -50,12 +50,29 @@ int check_params(const amg_params *p) {
   if (p->value_coding != AMG_VALUES_PLAIN && p->value_coding != AMG_VALUES_AUTO)
     return set_error(AMG_ERR_INVALID, "unknown value_coding");
   if (p->precond != 0 && p->precond != 1) return set_error(AMG_ERR_INVALID, "precond must be 0 or 1");
+  if (p->n_parts < 1 || p->n_parts > (1 << 24)) return set_error(AMG_ERR_INVALID, "n_parts out of range");
+  if (p->cycle_type < AMG_CYCLE_V || p->cycle_type > AMG_CYCLE_W)
+    return set_error(AMG_ERR_INVALID, "unknown cycle_type");
+  auto relax_ok = [](int r) {
+    return r == AMG_RELAX_JACOBI || r == AMG_RELAX_GS || r == AMG_RELAX_SYM_GS || r == AMG_RELAX_L1_JACOBI;
+  };
+  if (!relax_ok(p->relax_type) || !relax_ok(p->coarse_relax))
+    return set_error(AMG_ERR_INVALID, "unknown relax_type or coarse_relax");
+  if (p->max_hrc < 1 || p->max_hrc > 16) return set_error(AMG_ERR_INVALID, "max_hrc out of range");
+  if (p->bootstrap_type < AMG_BOOTSTRAP_MULT || p->bootstrap_type > AMG_BOOTSTRAP_ADD)
+    return set_error(AMG_ERR_INVALID, "unknown bootstrap_type");
+  if (p->bootstrap_its < 1 || !(p->bootstrap_rate > 0.0 && p->bootstrap_rate <= 1.0))
+    return set_error(AMG_ERR_INVALID, "bootstrap_its or bootstrap_rate out of range");
+  if (p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI ||
+      p->coarse_relax != AMG_RELAX_L1_JACOBI || p->max_hrc != 1)
+    return set_error(AMG_ERR_UNSUPPORTED, "cycle, smoother and bootstrap variants are not built");
   return AMG_OK;
 }
 }  // namespace
 
 namespace amg {
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+int api_check_params(const amg_params *p) { return check_params(p); }
 int api_set_error(int code, const std::string &msg) { return set_error(code, msg); }
 int api_guarded(const std::function<int()> &f) { return guarded(f); }
 const std::string &api_last_error() { return g_last_error; }
@@ -140,7 +157,17 @@ int amg_params_default(amg_params *p) {
   p->precond = 1;
   p->precision = AMG_PREC_DOUBLE;
   p->value_coding = AMG_VALUES_AUTO;
+  p->n_parts = 1;
+  p->cycle_type = AMG_CYCLE_V;
+  p->relax_type = AMG_RELAX_L1_JACOBI;
+  p->coarse_relax = AMG_RELAX_L1_JACOBI;
+  p->max_hrc = 1;
+  p->bootstrap_type = AMG_BOOTSTRAP_MULT;
+  p->bootstrap_its = 15;
+  p->bootstrap_seed = 1;
+  p->bootstrap_rate = 0.8;
   p->smooth_vector = nullptr;
+  p->model_params = nullptr;
   p->stream = nullptr;
   return AMG_OK;
 }

@@ -1319,8 +1319,10 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   for (int s = 0; s < nsys; ++s)
     if (A[s].n <= 0 || A[s].nnz < A[s].n || !A[s].row_ptr || !A[s].col_idx || !A[s].val)
       return amg::api_set_error(AMG_ERR_INVALID, "bad CSR header in the batch");
-  amg_params dflt;
-  amg_params_default(&dflt);
+  const int pst = amg::api_check_params(p);
+  if (pst != AMG_OK) return pst;
+  if (p->max_hrc != 1 || p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI)
+    return amg::api_set_error(AMG_ERR_UNSUPPORTED, "the batched solve runs the l1-Jacobi V-cycle of one hierarchy");
   amg_batch *bt = new (std::nothrow) amg_batch();
   if (!bt) return amg::api_set_error(AMG_ERR_NOMEM, "host allocation failed");
   bt->p = *p;

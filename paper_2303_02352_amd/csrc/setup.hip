@@ -271,15 +271,29 @@ __global__ void k_check_finite(int n, const double *x, int *flag) {
 // i = min(row, col) so both stored copies of an edge get the same bits:
 // num = ((2 a) w_lo) w_hi, den = (a_lolo w_lo) w_lo + (a_hihi w_hi) w_hi.
 // Eligible edges (a_ij != 0, w_hat > 0) keep their weight, others get -1.
+// Decoupled aggregation (Sec. 4.1): with row-block bounds `off` (nparts + 1
+// ascending offsets, off[0] = 0, off[nparts] = n) an edge is eligible only
+// inside its row's block.
 __global__ void k_weights(int n, const int *rp, const int *ci, const double *v, const double *d,
-                          const double *w, double *wgt) {
+                          const double *w, double *wgt, const int *off, int nparts) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  int blo = 0, bhi = n;   // columns of row i's block
+  if (off) {
+    int lo = 0, hi = nparts;   // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    blo = off[lo];
+    bhi = off[lo + 1];
+  }
   for (int k = rp[i]; k < rp[i + 1]; ++k) {
     const int j = ci[k];
     const double a = v[k];
     double out = -1.0;
-    if (j != i && a != 0.0) {
+    if (j != i && a != 0.0 && j >= blo && j < bhi) {
       const int lo = j < i ? j : i, hi = j < i ? i : j;
       const double wl = w[lo], wh = w[hi];
       const double num = ((2.0 * a) * wl) * wh;
@@ -289,6 +303,17 @@ __global__ void k_weights(int n, const int *rp, const int *ci, const double *v, 
     }
     wgt[k] = out;
   }
+}
+
+// Row-block bounds of the coarse matrix of a pairwise step: the aggregate of
+// a block's first row is the block's first coarse row (aggregates lie inside
+// blocks and are numbered by their smallest row).
+__global__ void k_coarse_offsets(int nparts, const int *off, int n, const int *agg, int nc,
+                                 int *offc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > nparts) return;
+  const int o = off[p];
+  offc[p] = (o < n) ? agg[o] : nc;
 }
 
 // Strict total order on edges: weight, then max endpoint, then min endpoint.
@@ -1397,6 +1422,7 @@ struct PairStep {
   wsv<double> p;
   dvec<double> wc;             // these two become the next level
   DevCSR Ac;
+  dvec<int> offc;              // row-block bounds of Ac (decoupled aggregation only)
 };
 
 // Workspace bytes of one pairwise step on (n rows, nnz entries): matching
@@ -1406,8 +1432,10 @@ size_t pair_workspace_bytes(int64_t n, int64_t nnz) {
   return static_cast<size_t>(264 * n + 28 * nnz) + 64 * 256 + 4096;
 }
 
-void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &out, Timing &tm,
-                   Arena &ws) {
+// off: row-block bounds of A (nparts + 1 entries, device) for decoupled
+// aggregation, or nullptr for one block.
+void pairwise_step(const DevCSR &A, const double *w, const int *off, int nparts, hipStream_t s,
+                   PairStep &out, Timing &tm, Arena &ws) {
   const int n = A.n;
   const dim3 g = grid_for(n), b(kBlock);
   double t0 = now_ms();
@@ -1415,7 +1443,7 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   wsv<double> d(ws, n), wgt(ws, A.nnz);
   hipLaunchKernelGGL(k_diag, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p);
   AMG_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p);
+  hipLaunchKernelGGL(k_weights, g, b, 0, s, n, A.rp.p, A.ci.p, A.v.p, d.p, w, wgt.p, off, nparts);
   AMG_LAUNCH_CHECK();
   out.mate = wsv<int>(ws, n);
   wsv<int> cand(ws, n), rlist(ws, n), mbuf0(ws, n), mbuf1(ws, n);
@@ -1483,6 +1511,12 @@ void pairwise_step(const DevCSR &A, const double *w, hipStream_t s, PairStep &ou
   hipLaunchKernelGGL(k_pair_restrict_w, grid_for(nc), b, 0, s, nc, out.rep.p, out.mate.p, out.p.p,
                      w, out.wc.p);
   AMG_LAUNCH_CHECK();
+  if (off) {
+    out.offc.alloc(nparts + 1);
+    hipLaunchKernelGGL(k_coarse_offsets, grid_for(nparts + 1), b, 0, s, nparts, off, n, out.agg.p, nc,
+                       out.offc.p);
+    AMG_LAUNCH_CHECK();
+  }
   AMG_HIP(hipStreamSynchronize(s));
   double t1 = now_ms();
   tm.match_ms += t1 - t0;
@@ -1651,6 +1685,16 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   h->tm.smooth_ms = now_ms() - t_w;
 
   Arena ws;   // setup temporaries of the pairwise steps (largest first)
+  // decoupled aggregation: row-block bounds of the current level (Sec. 4.1)
+  const int nparts = P.n_parts;
+  dvec<int> off_level;
+  if (nparts > 1) {
+    std::vector<int> off(nparts + 1);
+    for (int q = 0; q <= nparts; ++q) off[q] = static_cast<int>(static_cast<int64_t>(q) * n / nparts);
+    off_level.alloc(nparts + 1);
+    AMG_HIP(hipMemcpyAsync(off_level.p, off.data(), sizeof(int) * (nparts + 1), hipMemcpyHostToDevice, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
   const int maxlev = std::min(P.max_levels, AMG_MAX_LEVELS);
   while (P.precond && static_cast<int>(h->L.size()) < maxlev && h->L.back().A.n > P.coarse_max) {
     const int k = static_cast<int>(h->L.size()) - 1;
@@ -1664,9 +1708,10 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     for (int step = 0; step < P.aggr_steps; ++step) {
       const DevCSR &Acur = owned ? cur.Ac : h->L[k].A;
       const double *wcur = owned ? cur.wc.p : h->L[k].w.p;
+      const int *offcur = nparts > 1 ? (owned ? cur.offc.p : off_level.p) : nullptr;
       if (step > 0 && Acur.n <= P.coarse_max) break;
       PairStep nxt;
-      pairwise_step(Acur, wcur, s, nxt, h->tm, ws);
+      pairwise_step(Acur, wcur, offcur, nparts, s, nxt, h->tm, ws);
       hipLaunchKernelGGL(k_compose, grid_for(nk), dim3(kBlock), 0, s, nk, agg.p, pv.p, nxt.agg.p,
                          nxt.p.p);
       AMG_LAUNCH_CHECK();
@@ -1686,6 +1731,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
                          Lk.pval.p, Lk.pvalf.p);
       AMG_LAUNCH_CHECK();
     }
+    if (nparts > 1) off_level = std::move(cur.offc);
     Level next;
     next.A = std::move(cur.Ac);
     next.w = std::move(cur.wc);

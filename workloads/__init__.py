@@ -109,8 +109,16 @@ def poisson7(N: int) -> CSR:
     neighbour (the 1/h^2 factor is dropped: CG iterates do not change under
     A -> cA).  nnz = 7N^3 - 6N^2.
     """
-    n = N ** 3
-    idx, x, y, z = _grid(N)
+    return poisson7_box(N, N, N)
+
+
+def poisson7_box(Nx: int, Ny: int, Nz: int) -> CSR:
+    """The same stencil on an Nx x Ny x Nz box, id = x + Nx y + Nx Ny z.  With
+    Nz = P * Nx the consecutive row blocks of P tasks are Nx x Ny x Nx cubes
+    (the per-task share of a weak-scaling run)."""
+    n = Nx * Ny * Nz
+    idx = np.arange(n, dtype=np.int64)
+    x, y, z = idx % Nx, (idx // Nx) % Ny, idx // (Nx * Ny)
     offs = _offsets_3d([(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0),
                         (1, 0, 0), (0, 1, 0), (0, 0, 1)])
     cols = np.empty((n, 7), dtype=np.int64)
@@ -118,8 +126,8 @@ def poisson7(N: int) -> CSR:
     valid = np.empty((n, 7), dtype=bool)
     for s, (dx, dy, dz) in enumerate(offs):
         xx, yy, zz = x + dx, y + dy, z + dz
-        valid[:, s] = (xx >= 0) & (xx < N) & (yy >= 0) & (yy < N) & (zz >= 0) & (zz < N)
-        cols[:, s] = idx + dx + N * dy + N * N * dz
+        valid[:, s] = (xx >= 0) & (xx < Nx) & (yy >= 0) & (yy < Ny) & (zz >= 0) & (zz < Nz)
+        cols[:, s] = idx + dx + Nx * dy + Nx * Ny * dz
         vals[:, s] = 6.0 if (dx, dy, dz) == (0, 0, 0) else -1.0
     return _assemble(n, cols, vals, valid)
 
