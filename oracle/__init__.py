@@ -152,6 +152,11 @@ def _register(L):
                                         C.POINTER(C.POINTER(C.c_double)),
                                         C.POINTER(C.c_int64)]
         L.orc_free_ptr.argtypes = [C.c_void_p]
+        L.orc_nhrc.argtypes = [C.c_void_p]
+        L.orc_vcycle_single.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.orc_rates.argtypes = [C.c_void_p, _f64p]
+        L.orc_component.restype = C.c_void_p
+        L.orc_component.argtypes = [C.c_void_p, C.c_int]
     return L
 
 
@@ -267,9 +272,29 @@ class Hierarchy:
             raise OracleError(self.status)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and not getattr(self, "_view", False):
             self._L.orc_free(self.h)
             self.h = None
+
+    @property
+    def nhrc(self) -> int:
+        """Hierarchies in the bootstrap composite (1 without bootstrap)."""
+        return self._L.orc_nhrc(self.h)
+
+    def rates(self):
+        """Estimated convergence rates: [j-1] = composite of the first j hierarchies."""
+        out = np.empty(16)
+        k = self._L.orc_rates(self.h, out)
+        return out[:k].copy()
+
+    def component(self, j):
+        """Hierarchy j (0-based) of the composite as a non-owning view."""
+        v = object.__new__(Hierarchy)
+        v._L, v.params, v.n, v.status, v._w = self._L, self.params, self.n, OK, None
+        v.h = self._L.orc_component(self.h, int(j))
+        assert v.h, "no component %d" % j
+        v._view, v._owner = True, self
+        return v
 
     @property
     def nlevels(self) -> int:
@@ -324,9 +349,12 @@ class Hierarchy:
         assert self._L.orc_export_coarse_inverse(self.h, Ai) == OK
         return Ai
 
-    def vcycle(self, r):
+    def vcycle(self, r, single=False):
+        """z = B r: the preconditioner (the bootstrap composite when there is
+        one); single=True applies this hierarchy's own V-cycle only."""
         z = np.empty(self.n)
-        assert self._L.orc_vcycle(self.h, np.ascontiguousarray(r, np.float64), z) == OK
+        f = self._L.orc_vcycle_single if single else self._L.orc_vcycle
+        assert f(self.h, np.ascontiguousarray(r, np.float64), z) == OK
         return z
 
     def vcycle_f32(self, r):

@@ -83,7 +83,10 @@ typedef struct {
   double *v;
 } csr_t;
 
-typedef struct {
+#define ORC_MAXHRC 16
+
+typedef struct orc_h orc_h;
+struct orc_h {
   orc_params p;
   int nlev;
   csr_t A[ORC_MAXLEV];
@@ -101,7 +104,13 @@ typedef struct {
   float *fv[ORC_MAXLEV], *fdinv[ORC_MAXLEV], *fpval[ORC_MAXLEV];
   float *fx[ORC_MAXLEV], *ft[ORC_MAXLEV], *fr[ORC_MAXLEV], *fres[ORC_MAXLEV], *fe[ORC_MAXLEV];
   int have_f32;
-} orc_h;
+  /* bootstrap composite: hierarchies 2..nhrc (hierarchy 1 is this one) and
+   * the rate estimates (rate[j-1]: composite of the first j hierarchies) */
+  int nhrc;
+  orc_h *hrc[ORC_MAXHRC];
+  double rate[ORC_MAXHRC];
+  int nrate;
+};
 
 /* ------------------------------------------------------------------ utils */
 
@@ -607,8 +616,8 @@ static int smooth_vector(const orc_params *p, const csr_t *A, const double *dinv
  * matrix is the last pairwise A_c (equal to the composite Galerkin product
  * in exact arithmetic).  Coarsening stops at n <= coarse_max, at max_levels,
  * or when a level shrinks by less than 5%. */
-orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-                 const orc_params *par, const double *w_given, int *status) {
+static orc_h *build_single(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                           const orc_params *par, const double *w_given, int *status) {
   *status = orc_validate(n, rp, ci, v);
   if (*status != ORC_OK) return NULL;
   if (par->aggr_steps < 1 || par->max_levels < 1 || par->coarse_max < 1 ||
@@ -616,8 +625,13 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
       par->smooth_sweeps < 0 || par->n_parts < 1) {
     *status = ORC_INVALID; return NULL;
   }
-  /* cycle and smoother variants and the bootstrap composite: not built yet */
-  if (par->cycle_type != 0 || par->relax_type != 4 || par->coarse_relax != 4 || par->max_hrc != 1) {
+  if (par->max_hrc < 1 || par->max_hrc > ORC_MAXHRC || par->bootstrap_type < 0 ||
+      par->bootstrap_type > 2 || par->bootstrap_its < 1 ||
+      !(par->bootstrap_rate > 0.0 && par->bootstrap_rate <= 1.0)) {
+    *status = ORC_INVALID; return NULL;
+  }
+  /* cycle and smoother variants: not built yet */
+  if (par->cycle_type != 0 || par->relax_type != 4 || par->coarse_relax != 4) {
     *status = ORC_INVALID; return NULL;
   }
   orc_h *h = (orc_h *)calloc(1, sizeof(orc_h));
@@ -739,6 +753,7 @@ orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *
 
 void orc_free(orc_h *h) {
   if (!h) return;
+  for (int j = 0; j < ORC_MAXHRC; j++) orc_free(h->hrc[j]);
   for (int k = 0; k < ORC_MAXLEV; k++) {
     csr_free(&h->A[k]);
     free(h->dinv[k]); free(h->w[k]); free(h->agg[k]); free(h->pval[k]); free(h->part[k]);
@@ -814,11 +829,19 @@ static void vcycle(orc_h *h, int k, const double *r, double *z) {
   memcpy(z, x, sizeof(double) * (size_t)n);
 }
 
-int orc_vcycle(orc_h *h, const double *r, double *z) {
-  if (!h) return ORC_INVALID;
+/* One hierarchy's preconditioner z = B r (binary64). */
+static int single_apply(orc_h *h, const double *r, double *z) {
   if (!h->p.precond) { memcpy(z, r, sizeof(double) * (size_t)h->A[0].n); return ORC_OK; }
   vcycle(h, 0, r, z);
   return ORC_OK;
+}
+
+static int single_apply_f32(orc_h *h, const double *r, double *z);
+static int composite_apply(orc_h *h, int m, int mixed, const double *r, double *z);
+
+int orc_vcycle(orc_h *h, const double *r, double *z) {
+  if (!h) return ORC_INVALID;
+  return composite_apply(h, h->nhrc, 0, r, z);
 }
 
 /* ------------------------------------------------- binary32 V-cycle
@@ -920,8 +943,12 @@ static void vcycle_f(orc_h *h, int k, const float *r, float *z) {
 /* z = B_32 r with r, z binary64 (single-level hierarchies use the binary64 solve). */
 int orc_vcycle_f32(orc_h *h, const double *r, double *z) {
   if (!h) return ORC_INVALID;
+  return composite_apply(h, h->nhrc, 1, r, z);
+}
+
+static int single_apply_f32(orc_h *h, const double *r, double *z) {
   int32_t n = h->A[0].n;
-  if (!h->p.precond || h->nlev == 1) return orc_vcycle(h, r, z);
+  if (!h->p.precond || h->nlev == 1) return single_apply(h, r, z);
   if (!h->have_f32 && build_f32(h) != ORC_OK) return ORC_NOMEM;
   float *rf = (float *)malloc(sizeof(float) * (size_t)n);
   float *zf = (float *)malloc(sizeof(float) * (size_t)n);
@@ -931,6 +958,165 @@ int orc_vcycle_f32(orc_h *h, const double *r, double *z) {
   for (int32_t i = 0; i < n; i++) z[i] = (double)zf[i];
   free(rf); free(zf);
   return ORC_OK;
+}
+
+/* ------------------------------------------------- bootstrap composite
+ * Appendix A lists a bootstrap AMG with up to max_hrc hierarchies combined by
+ * a composition rule, built until the composite reaches a desired
+ * convergence rate (the bootstrap of the cited BootCMatch papers).  With
+ * B_1 .. B_m the hierarchies' preconditioners (each one V-cycle) and the
+ * residual r:
+ *   multiplicative (0):  z = B_1 r;  z += B_j (r - A z) for j = 2 .. m,
+ *       so the error propagates by E = (I - B_m A) ... (I - B_1 A);
+ *   symmetrized (1):     the same for j = 1 .. m, then for j = m-1 .. 1,
+ *       E = (I - B_1 A) ... (I - B_m A) ... (I - B_1 A), an s.p.d. B;
+ *   additive (2):        z = (B_1 r + ... + B_m r) / m (left fold, then the
+ *       division): the average, so that the composite's stationary
+ *       iteration converges whenever every B_j's does (a plain sum
+ *       overcorrects by about a factor m; flexible CG itself is invariant
+ *       under scaling B).
+ * m = 1 is the plain preconditioner for every rule.  The outer product,
+ * residuals and sums are binary64 also in the mixed-precision form (each
+ * B_j is then the binary32 cycle). */
+static int composite_apply(orc_h *h, int m, int mixed, const double *r, double *z) {
+  orc_h *c0 = h;
+  int32_t n = h->A[0].n;
+  int st = mixed ? single_apply_f32(c0, r, z) : single_apply(c0, r, z);
+  if (st != ORC_OK || m <= 1) return st;
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  double *e = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!t || !e) { free(t); free(e); return ORC_NOMEM; }
+  int nsteps = (h->p.bootstrap_type == 1) ? 2 * m - 1 : m;
+  for (int q = 1; q < nsteps && st == ORC_OK; q++) {
+    int j = (q < m) ? q : 2 * m - 2 - q;       /* 0-based hierarchy of step q */
+    orc_h *cj = (j == 0) ? h : h->hrc[j - 1];
+    if (h->p.bootstrap_type == 2) {
+      st = mixed ? single_apply_f32(cj, r, e) : single_apply(cj, r, e);
+    } else {
+      spmv(&h->A[0], z, t);
+      for (int32_t i = 0; i < n; i++) t[i] = r[i] - t[i];
+      st = mixed ? single_apply_f32(cj, t, e) : single_apply(cj, t, e);
+    }
+    for (int32_t i = 0; i < n; i++) z[i] = z[i] + e[i];
+  }
+  if (h->p.bootstrap_type == 2)
+    for (int32_t i = 0; i < n; i++) z[i] = z[i] / (double)m;
+  free(t); free(e);
+  return st;
+}
+
+/* SplitMix64 (Steele, Lea and Flood 2014): the first output of a generator
+ * whose state is c. */
+static uint64_t splitmix64(uint64_t c) {
+  uint64_t z = c + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Start vector of the rate estimate before hierarchy j + 1 is built:
+ * x_i = 2 u - 1, u = (splitmix64(((16 seed + j) << 32) + i) >> 11) 2^-53. */
+static void bootstrap_start(int32_t n, int32_t seed, int j, double *x) {
+  uint64_t base = ((uint64_t)(uint32_t)(16 * seed + j)) << 32;
+  for (int32_t i = 0; i < n; i++) {
+    double u = (double)(splitmix64(base + (uint64_t)i) >> 11) * 0x1.0p-53;
+    x[i] = 2.0 * u - 1.0;
+  }
+}
+
+static double a_norm(const csr_t *A, const double *x, double *t) {
+  spmv(A, x, t);
+  return sqrt(dot(A->n, x, t));
+}
+
+/* Convergence-rate estimate of the composite of the first m hierarchies:
+ * bootstrap_its steps of x <- x + B (0 - A x) on A x = 0 from the start
+ * vector, rate = (||x_its||_A / ||x_0||_A)^(1 / its).  x holds x_its on
+ * return. */
+static int estimate_rate(orc_h *h, int m, double *x, double *rate) {
+  const csr_t *A = &h->A[0];
+  int32_t n = A->n;
+  double *t = (double *)malloc(sizeof(double) * (size_t)n);
+  double *e = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!t || !e) { free(t); free(e); return ORC_NOMEM; }
+  bootstrap_start(n, h->p.bootstrap_seed, m, x);
+  double n0 = a_norm(A, x, t);
+  int st = ORC_OK;
+  for (int it = 0; it < h->p.bootstrap_its && st == ORC_OK; it++) {
+    spmv(A, x, t);
+    for (int32_t i = 0; i < n; i++) t[i] = 0.0 - t[i];
+    st = composite_apply(h, m, 0, t, e);
+    for (int32_t i = 0; i < n; i++) x[i] = x[i] + e[i];
+  }
+  double nf = a_norm(A, x, t);
+  *rate = pow(nf / n0, 1.0 / (double)h->p.bootstrap_its);
+  free(t); free(e);
+  return st;
+}
+
+/* Bootstrap setup: hierarchy 1 from the configured smooth vector; then, while
+ * fewer than max_hrc hierarchies exist and the composite's estimated rate is
+ * above bootstrap_rate, the estimate's final iterate (the error the
+ * composite reduces slowest), scaled by its largest magnitude, is the smooth
+ * vector of a new hierarchy with the same parameters.  The rate of the final
+ * composite is estimated as well (rate[nhrc - 1]). */
+orc_h *orc_setup(int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                 const orc_params *par, const double *w_given, int *status) {
+  orc_h *h = build_single(n, rp, ci, v, par, w_given, status);
+  if (!h) return NULL;
+  h->nhrc = 1;
+  if (par->max_hrc <= 1 || !par->precond) return h;
+  double *x = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!x) { orc_free(h); *status = ORC_NOMEM; return NULL; }
+  orc_params pc = *par;
+  pc.max_hrc = 1;
+  pc.smooth_vec = 2;
+  for (;;) {
+    double rate;
+    *status = estimate_rate(h, h->nhrc, x, &rate);
+    if (*status != ORC_OK) break;
+    h->rate[h->nrate++] = rate;
+    if (rate <= par->bootstrap_rate || h->nhrc >= par->max_hrc) break;
+    double mx = 0.0;
+    int finite = 1;
+    for (int32_t i = 0; i < n; i++) {
+      if (!isfinite(x[i])) finite = 0;
+      else if (fabs(x[i]) > mx) mx = fabs(x[i]);
+    }
+    if (!finite || !(mx > 0.0)) break;
+    for (int32_t i = 0; i < n; i++) x[i] = x[i] / mx;
+    orc_h *c = build_single(n, rp, ci, v, &pc, x, status);
+    if (!c) break;
+    c->nhrc = 1;
+    h->hrc[h->nhrc - 1] = c;
+    h->nhrc++;
+  }
+  free(x);
+  if (*status != ORC_OK) { orc_free(h); return NULL; }
+  return h;
+}
+
+int orc_nhrc(const orc_h *h) { return h ? h->nhrc : 0; }
+
+/* The preconditioner of hierarchy h alone (its V-cycle), also when h heads a
+ * composite. */
+int orc_vcycle_single(orc_h *h, const double *r, double *z) {
+  if (!h) return ORC_INVALID;
+  return single_apply(h, r, z);
+}
+
+/* Rate estimates: out[j-1] = estimated rate of the composite of the first j
+ * hierarchies; returns how many were taken. */
+int orc_rates(const orc_h *h, double *out) {
+  if (!h) return 0;
+  for (int j = 0; j < h->nrate; j++) out[j] = h->rate[j];
+  return h->nrate;
+}
+
+/* Hierarchy j (0-based) of the composite, owned by h. */
+orc_h *orc_component(orc_h *h, int j) {
+  if (!h || j < 0 || j >= h->nhrc) return NULL;
+  return j == 0 ? h : h->hrc[j - 1];
 }
 
 /* ------------------------------------------------------------- flexible CG
