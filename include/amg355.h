@@ -151,6 +151,7 @@ typedef struct {
 typedef struct amg_hierarchy amg_hierarchy;   /* opaque, owned by the library */
 
 #define AMG_MAX_LEVELS 64
+#define AMG_MAX_HRC 16
 typedef struct {
   int32_t levels;
   int32_t n[AMG_MAX_LEVELS];
@@ -164,6 +165,10 @@ typedef struct {
   int64_t device_bytes;         /* device memory held by the hierarchy */
   int32_t dict_size[AMG_MAX_LEVELS]; /* distinct values of a coded level's table, 0 = plain */
   double setup_smooth_ms;       /* part spent on the fine smooth vector (relaxation or copy) */
+  int32_t nhrc;                 /* hierarchies in the bootstrap composite (1 without) */
+  int32_t nrates;               /* rate estimates taken by the bootstrap */
+  double rates[AMG_MAX_HRC];    /* rates[j-1]: estimated rate of the first j hierarchies */
+  double setup_bootstrap_ms;    /* part spent on rate estimates and further hierarchies */
 } amg_info_t;
 
 /* Fill *p with the defaults above.  Returns AMG_OK or AMG_ERR_INVALID (p NULL). */
@@ -225,6 +230,14 @@ const char *amg_last_error(void);
 /* Sizes, operator complexity and setup timings. */
 int amg_info(const amg_hierarchy *h, amg_info_t *out);
 
+/* Hierarchy j (0-based) of a bootstrap composite, j = 0 being h itself:
+ * a borrowed handle, owned by h and valid until amg_destroy(h), for
+ * amg_info, amg_export_level, amg_vcycle (which then applies that
+ * hierarchy's own V-cycle), amg_spmv and amg_sweep, all ordered on h's
+ * stream; never pass it to amg_destroy.  NULL (and INVALID as the last
+ * error) when j is out of range. */
+amg_hierarchy *amg_component(amg_hierarchy *h, int32_t j);
+
 /* Introspection for parity tests: copy level k to HOST buffers (any may be
  * NULL).  row_ptr n_k+1, col_idx/val nnz_k (canonical CSR, columns
  * ascending), dinv n_k (1 / l1 row sum), w n_k (smooth vector), and for
@@ -233,7 +246,8 @@ int amg_info(const amg_hierarchy *h, amg_info_t *out);
 int amg_export_level(const amg_hierarchy *h, int32_t k, int32_t *row_ptr, int32_t *col_idx,
                      double *val, double *dinv, double *w, int32_t *agg, double *pval);
 
-/* z = B r: one V-cycle of Alg. 2 (B = I when precond = 0).  r, z: device
+/* z = B r: one V-cycle of Alg. 2 (B = I when precond = 0); with a bootstrap
+ * composite, its composition of the hierarchies' V-cycles.  r, z: device
  * pointers to n_0 doubles, may not alias.  Enqueued on the stream; returns
  * without synchronising. */
 int amg_vcycle(amg_hierarchy *h, const double *r, double *z);

@@ -52,7 +52,9 @@ class amg_info_t(C.Structure):
                 ("coarse_dense", C.c_int32), ("matching_rounds", C.c_int32),
                 ("setup_ms", C.c_double), ("setup_match_ms", C.c_double),
                 ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64),
-                ("dict_size", C.c_int32 * AMG_MAX_LEVELS), ("setup_smooth_ms", C.c_double)]
+                ("dict_size", C.c_int32 * AMG_MAX_LEVELS), ("setup_smooth_ms", C.c_double),
+                ("nhrc", C.c_int32), ("nrates", C.c_int32), ("rates", C.c_double * 16),
+                ("setup_bootstrap_ms", C.c_double)]
 
 
 class amg_batch_info_t(C.Structure):
@@ -75,6 +77,7 @@ EXPORTS = {
     "amg_last_error": (C.c_char_p, []),
     "amg_info": (C.c_int, [C.c_void_p, C.POINTER(amg_info_t)]),
     "amg_export_level": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 7),
+    "amg_component": (C.c_void_p, [C.c_void_p, C.c_int32]),
     "amg_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "amg_spmv": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "amg_sweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -255,6 +258,8 @@ class Hierarchy:
         return int(k)
 
     def close(self):
+        if getattr(self, "_borrowed", False):
+            return
         if getattr(self, "h", None) and self.h.value:
             load().amg_destroy(self.h)
             self.h = C.c_void_p()
@@ -296,7 +301,23 @@ class Hierarchy:
                     coarse_dense=bool(inf.coarse_dense), matching_rounds=inf.matching_rounds,
                     setup_ms=inf.setup_ms, setup_match_ms=inf.setup_match_ms,
                     setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes,
-                    dict_size=list(inf.dict_size[:L]), setup_smooth_ms=inf.setup_smooth_ms)
+                    dict_size=list(inf.dict_size[:L]), setup_smooth_ms=inf.setup_smooth_ms,
+                    nhrc=inf.nhrc, rates=list(inf.rates[:inf.nrates]),
+                    setup_bootstrap_ms=inf.setup_bootstrap_ms)
+
+    def component(self, j):
+        """Hierarchy j of the bootstrap composite (0 = this one) as a borrowed
+        view for info / export_level / vcycle / spmv / sweep; it is never
+        destroyed on its own and keeps this hierarchy alive."""
+        ph = load().amg_component(self.h, int(j))
+        if not ph:
+            raise AMGError(AMG_ERR_INVALID, "amg_component")
+        v = object.__new__(Hierarchy)
+        v.h = C.c_void_p(ph)
+        v.n, v.nnz, v.params, v.device, v._owner = self.n, self.nnz, self.params, self.device, self
+        v._borrowed = True
+        v.sizes = v.info()["n"]
+        return v
 
     def export_level(self, k) -> dict:
         inf = self.info()

@@ -415,7 +415,7 @@ struct TailDesc {
 };
 
 struct Timing {
-  double setup_ms = 0, match_ms = 0, rap_ms = 0, smooth_ms = 0;
+  double setup_ms = 0, match_ms = 0, rap_ms = 0, smooth_ms = 0, bootstrap_ms = 0;
   int rounds = 0;
 };
 
@@ -445,6 +445,11 @@ struct amg_hierarchy {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int use_graph = 1;
+  // bootstrap composite: hierarchies 2..m (owned; they run on this
+  // hierarchy's stream), the rate estimates, and two fine-level work vectors
+  std::vector<amg_hierarchy *> comp;
+  std::vector<double> rates;
+  amg::dvec<double> ct, ce;
 };
 
 namespace amg {
@@ -459,7 +464,12 @@ double wall_ms();
 
 // -------------------------------------------------------- solve interface
 void alloc_solve_buffers(amg_hierarchy *h);
-void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z);
+void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z);          // the preconditioner
+void enqueue_vcycle_single(amg_hierarchy *h, const double *r, double *z);   // h's own V-cycle
+// the first m hierarchies' composite with binary64 cycles (bootstrap estimates)
+void enqueue_composite(amg_hierarchy *h, int m, const double *r, double *z);
+void bootstrap_build(amg_hierarchy *h);   // adds hierarchies per max_hrc / bootstrap_rate
+void destroy_components(amg_hierarchy *h);
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y);
 void enqueue_sweep(amg_hierarchy *h, int k, const double *r, const double *x, double *xn);
 int pcg_solve(amg_hierarchy *h, const double *b, double *x, double rtol, int maxit, int *iters,

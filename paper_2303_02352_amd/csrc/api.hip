@@ -3,6 +3,7 @@
 // across the boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -64,8 +65,8 @@ int check_params(const amg_params *p) {
   if (p->bootstrap_its < 1 || !(p->bootstrap_rate > 0.0 && p->bootstrap_rate <= 1.0))
     return set_error(AMG_ERR_INVALID, "bootstrap_its or bootstrap_rate out of range");
   if (p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI ||
-      p->coarse_relax != AMG_RELAX_L1_JACOBI || p->max_hrc != 1)
-    return set_error(AMG_ERR_UNSUPPORTED, "cycle, smoother and bootstrap variants are not built");
+      p->coarse_relax != AMG_RELAX_L1_JACOBI)
+    return set_error(AMG_ERR_UNSUPPORTED, "cycle and smoother variants are not built");
   return AMG_OK;
 }
 }  // namespace
@@ -204,8 +205,10 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
     amg::SetupStream on(h->stream, !h->own_stream);
     amg::PoolScope pool(h->stream);
     amg::build_hierarchy(h, A);
+    amg::bootstrap_build(h);
     return AMG_OK;
   });
+  for (amg_hierarchy *c : h->comp) c->stream = h->stream;
   h->p.smooth_vector = nullptr;
   if (st != AMG_OK) {
     std::string msg = g_last_error;
@@ -264,6 +267,7 @@ void amg_destroy(amg_hierarchy *h) {
   hipStream_t s = h->stream;
   {
     amg::FreeOn on(amg::library_stream());   // h->stream is idle and may be the caller's
+    amg::destroy_components(h);
     delete h;   // frees all device buffers
   }
   if (own) amg::release_private_stream(dev, s);
@@ -304,7 +308,21 @@ int amg_info(const amg_hierarchy *h, amg_info_t *out) {
   out->setup_rap_ms = h->tm.rap_ms;
   out->setup_smooth_ms = h->tm.smooth_ms;
   out->device_bytes = amg::device_bytes(h);
+  for (const amg_hierarchy *c : h->comp) out->device_bytes += amg::device_bytes(c) + c->ct.bytes() + c->ce.bytes();
+  out->device_bytes += h->ct.bytes() + h->ce.bytes();
+  out->nhrc = 1 + static_cast<int32_t>(h->comp.size());
+  out->nrates = static_cast<int32_t>(std::min<size_t>(h->rates.size(), AMG_MAX_HRC));
+  for (int j = 0; j < out->nrates; ++j) out->rates[j] = h->rates[j];
+  out->setup_bootstrap_ms = h->tm.bootstrap_ms;
   return AMG_OK;
+}
+
+amg_hierarchy *amg_component(amg_hierarchy *h, int32_t j) {
+  if (!h || j < 0 || j > static_cast<int32_t>(h->comp.size())) {
+    set_error(AMG_ERR_INVALID, "no such hierarchy in the composite");
+    return nullptr;
+  }
+  return j == 0 ? h : h->comp[j - 1];
 }
 
 int amg_export_level(const amg_hierarchy *h, int32_t k, int32_t *row_ptr, int32_t *col_idx,

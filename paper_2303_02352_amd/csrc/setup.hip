@@ -1611,6 +1611,153 @@ int device_read_int(const int *p, hipStream_t s) { return read_int(p, s); }
 void finalize_level(Level &Lv, hipStream_t s, bool want_float) { finish_level(Lv, s, want_float, false); }
 double wall_ms() { return now_ms(); }
 
+// ================================================= bootstrap composite
+// Appendix A's bootstrap AMG: while the composite of the hierarchies built so
+// far has fewer than max_hrc members and its estimated convergence rate is
+// above bootstrap_rate, the iterate that estimate ends with (the error the
+// composite reduces slowest), scaled by its largest magnitude, becomes the
+// smooth vector of one more hierarchy with the same parameters.  Estimate:
+// bootstrap_its steps x <- x + B (0 - A x) on A x = 0 from a SplitMix64 start
+// vector, rate = (||x_its||_A / ||x_0||_A)^(1 / its).
+
+// SplitMix64 (Steele, Lea and Flood 2014): first output for state c.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long c) {
+  unsigned long long z = c + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// x_i = 2 u - 1, u = (splitmix64(((16 seed + j) << 32) + i) >> 11) 2^-53
+__global__ void k_bootstrap_start(int n, unsigned seed16j, double *x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const unsigned long long c = (static_cast<unsigned long long>(seed16j) << 32) + static_cast<unsigned>(i);
+  const double u = static_cast<double>(splitmix64(c) >> 11) * 0x1.0p-53;
+  x[i] = 2.0 * u - 1.0;
+}
+
+__global__ void k_neg_from_zero(int n, double *t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = 0.0 - t[i];
+}
+
+__global__ void k_accumulate(int n, double *x, const double *e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = x[i] + e[i];
+}
+
+constexpr int kDotBlocks = 1024;
+
+// Partial sums of x . y, one per workgroup (grid-stride), folded by k_dot_finish.
+__global__ void __launch_bounds__(kBlock) k_dot_part(int n, const double *x, const double *y, double *part) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) acc = acc + x[i] * y[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot_finish(int np, const double *part, double *out) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < np; q += kBlock) acc = acc + part[q];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+namespace {
+double device_dot(int n, const double *x, const double *y, double *part, double *res, hipStream_t s) {
+  const int nb = std::max(1, std::min(kDotBlocks, ceil_div(n, kBlock)));
+  hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(kBlock), 0, s, n, x, y, part);
+  hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(kBlock), 0, s, nb, part, res);
+  AMG_LAUNCH_CHECK();
+  double v = 0.0;
+  read_small(&v, res, sizeof(double), s);
+  return v;
+}
+}  // namespace
+
+void destroy_components(amg_hierarchy *h) {
+  for (amg_hierarchy *c : h->comp) {
+    destroy_graph(c);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    c->sc_host = nullptr;
+    delete c;
+  }
+  h->comp.clear();
+}
+
+void bootstrap_build(amg_hierarchy *h) {
+  const amg_params &P = h->p;
+  if (P.max_hrc <= 1 || !P.precond) return;
+  hipStream_t s = h->stream;
+  const double t0 = now_ms();
+  const int n = h->L[0].A.n;
+  h->ct.alloc(n);
+  h->ce.alloc(n);
+  dvec<double> x(n), t(n), e(n), part(kDotBlocks), res(1);
+  dvec<unsigned long long> mx(1);
+  dvec<int> nf(1);
+  // the components are built from the fine matrix the head already holds
+  const DevCSR &A0 = h->L[0].A;
+  amg_csr Adev{n, A0.nnz, A0.rp.p, A0.ci.p, A0.v.p, 1};
+  const dim3 g = grid_for(n), b(kBlock);
+  auto a_norm = [&](const double *v) {
+    enqueue_spmv(h, 0, v, t.p);
+    return sqrt(device_dot(n, v, t.p, part.p, res.p, s));
+  };
+  for (;;) {
+    const int m = 1 + static_cast<int>(h->comp.size());
+    hipLaunchKernelGGL(k_bootstrap_start, g, b, 0, s, n, static_cast<unsigned>(16 * P.bootstrap_seed + m), x.p);
+    AMG_LAUNCH_CHECK();
+    const double n0 = a_norm(x.p);
+    for (int it = 0; it < P.bootstrap_its; ++it) {
+      enqueue_spmv(h, 0, x.p, t.p);
+      hipLaunchKernelGGL(k_neg_from_zero, g, b, 0, s, n, t.p);
+      enqueue_composite(h, m, t.p, e.p);
+      hipLaunchKernelGGL(k_accumulate, g, b, 0, s, n, x.p, e.p);
+      AMG_LAUNCH_CHECK();
+    }
+    const double nfin = a_norm(x.p);
+    const double rate = pow(nfin / n0, 1.0 / static_cast<double>(P.bootstrap_its));
+    h->rates.push_back(rate);
+    if (rate <= P.bootstrap_rate || m >= P.max_hrc) break;
+    AMG_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
+    AMG_HIP(hipMemsetAsync(nf.p, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_absmax, dim3(std::min(1024, ceil_div(n, kBlock))), b, 0, s, n, x.p, mx.p, nf.p);
+    AMG_LAUNCH_CHECK();
+    unsigned long long mbits = 0;
+    read_small(&mbits, mx.p, sizeof(mbits), s);
+    if (read_int(nf.p, s) || mbits == 0) break;   // non-finite or zero: no new vector
+    hipLaunchKernelGGL(k_scale_by_max, g, b, 0, s, n, x.p, mx.p);
+    AMG_LAUNCH_CHECK();
+    amg_hierarchy *c = new amg_hierarchy();
+    h->comp.push_back(c);
+    c->p = P;
+    c->p.smooth_vec = AMG_SMOOTH_GIVEN;
+    c->p.smooth_vector = x.p;
+    c->p.max_hrc = 1;
+    c->stream = s;
+    c->dev = h->dev;
+    build_hierarchy(c, &Adev);
+    c->p.smooth_vector = nullptr;
+  }
+  AMG_HIP(hipStreamSynchronize(s));
+  h->tm.bootstrap_ms = now_ms() - t0;
+  h->tm.setup_ms += h->tm.bootstrap_ms;
+}
+
 // ===================================================== hierarchy builder
 void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   hipStream_t s = h->stream;

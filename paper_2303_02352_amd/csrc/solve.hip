@@ -1197,15 +1197,74 @@ void vcycle_mixed(amg_hierarchy *h, const int *skip, const double *r, double *z,
 
 // first_done: the residual kernel already wrote the first smoothing iterate
 // (the outputs described by first_out_for).
+// binary64: the binary64 cycle also in a mixed-precision hierarchy (the
+// bootstrap's rate estimates belong to the setup, which is binary64).
 void vcycle_any(amg_hierarchy *h, const int *skip, const double *r, double *z,
-                bool first_done = false) {
+                bool first_done = false, bool binary64 = false) {
   const int n = h->L[0].A.n;
   if (!h->p.precond) {
     AMG_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
     return;
   }
-  if (h->p.precision == AMG_PREC_MIXED) vcycle_mixed(h, skip, r, z, first_done);
+  if (h->p.precision == AMG_PREC_MIXED && !binary64) vcycle_mixed(h, skip, r, z, first_done);
   else vcycle_level<double>(h, skip, 0, r, z, first_done);
+  AMG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------- bootstrap composite
+// Appendix A's bootstrap composite of hierarchies h (the first) and
+// h->comp[0..]: multiplicative z = B_1 r, z += B_j (r - A z) for j = 2..m;
+// symmetrized the same for j = 1..m and then j = m-1..1; additive
+// z = (B_1 r + ... + B_m r) / m.  Residuals, sums and the division are
+// binary64 in both precisions.
+__global__ void k_sub_from(const int *skip, int n, const double *__restrict__ r, double *__restrict__ t) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = r[i] - t[i];
+}
+
+__global__ void k_add_to(const int *skip, int n, double *__restrict__ z, const double *__restrict__ e) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = z[i] + e[i];
+}
+
+__global__ void k_div_by(const int *skip, int n, double *z, double m) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = z[i] / m;
+}
+
+// z = B r for the composite of the first m hierarchies (m < 0: all of them);
+// first_done as for vcycle_any (first hierarchy only).
+void precond_apply(amg_hierarchy *h, const int *skip, const double *r, double *z, bool first_done,
+                   int m = -1, bool binary64 = false) {
+  const int total = 1 + static_cast<int>(h->comp.size());
+  if (m < 0 || m > total) m = total;
+  vcycle_any(h, skip, r, z, first_done, binary64);
+  if (m <= 1 || !h->p.precond) return;
+  hipStream_t s = h->stream;
+  const int n = h->L[0].A.n;
+  const int type = h->p.bootstrap_type;
+  const int steps = (type == AMG_BOOTSTRAP_SYMMULT) ? 2 * m - 1 : m;
+  for (int q = 1; q < steps; ++q) {
+    const int j = (q < m) ? q : 2 * m - 2 - q;
+    amg_hierarchy *c = (j == 0) ? h : h->comp[j - 1];
+    // run on the head's stream (a capture stream while the head captures)
+    const hipStream_t own = c->stream;
+    c->stream = s;
+    if (type == AMG_BOOTSTRAP_ADD) {
+      vcycle_any(c, skip, r, h->ce.p, false, binary64);
+    } else {
+      launch_spmv(h->L[0], z, h->ct.p, s);
+      hipLaunchKernelGGL(k_sub_from, grid_for(n), dim3(kBlock), 0, s, skip, n, r, h->ct.p);
+      vcycle_any(c, skip, h->ct.p, h->ce.p, false, binary64);
+    }
+    c->stream = own;
+    hipLaunchKernelGGL(k_add_to, grid_for(n), dim3(kBlock), 0, s, skip, n, z, h->ce.p);
+  }
+  if (type == AMG_BOOTSTRAP_ADD)
+    hipLaunchKernelGGL(k_div_by, grid_for(n), dim3(kBlock), 0, s, skip, n, z, static_cast<double>(m));
   AMG_LAUNCH_CHECK();
 }
 
@@ -1256,7 +1315,7 @@ void enqueue_iteration(amg_hierarchy *h, PcgState ps) {
   const int n = L0.A.n, nbd = nb_dot(n), nbu = nb_upd(n);
   const int *skip = &ps.sc->done;
   const FirstOut fo = first_out_for(h, h->w.p);
-  vcycle_any(h, skip, h->r.p, h->w.p, /*first_done=*/true);
+  precond_apply(h, skip, h->r.p, h->w.p, /*first_done=*/true);
   launch_spmv_dots(h, skip, ps.part);
   hipLaunchKernelGGL(k_pcg_dots_finish, dim3(1), dim3(kFinish), 0, s, skip, nbd, ps.part, ps.sc);
   hipLaunchKernelGGL(k_pcg_update, dim3(nbu), dim3(kBlock), 0, s, skip, n, h->w.p, h->v.p, h->d.p,
@@ -1351,7 +1410,13 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   }
 }
 
-void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z) { vcycle_any(h, nullptr, r, z); }
+void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z) { precond_apply(h, nullptr, r, z, false); }
+
+void enqueue_vcycle_single(amg_hierarchy *h, const double *r, double *z) { vcycle_any(h, nullptr, r, z); }
+
+void enqueue_composite(amg_hierarchy *h, int m, const double *r, double *z) {
+  precond_apply(h, nullptr, r, z, false, m, /*binary64=*/true);
+}
 
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y) {
   launch_spmv(h->L[k], x, y, h->stream);
