@@ -100,6 +100,8 @@ struct orc_h {
   double *Ainv;              /* inverse of the coarsest matrix, row-major */
   /* V-cycle work vectors per level */
   double *vx[ORC_MAXLEV], *vt[ORC_MAXLEV], *vr[ORC_MAXLEV], *vres[ORC_MAXLEV], *ve[ORC_MAXLEV];
+  double *vw[ORC_MAXLEV], *vz[ORC_MAXLEV];  /* second coarse correction (H/W cycles) */
+  double *djac[ORC_MAXLEV];  /* 1 / a_ii (Jacobi and Gauss-Seidel smoothers) */
   /* binary32 copies for the mixed-precision V-cycle (built on first use) */
   float *fv[ORC_MAXLEV], *fdinv[ORC_MAXLEV], *fpval[ORC_MAXLEV];
   float *fx[ORC_MAXLEV], *ft[ORC_MAXLEV], *fr[ORC_MAXLEV], *fres[ORC_MAXLEV], *fe[ORC_MAXLEV];
@@ -630,9 +632,10 @@ static orc_h *build_single(int32_t n, const int32_t *rp, const int32_t *ci, cons
       !(par->bootstrap_rate > 0.0 && par->bootstrap_rate <= 1.0)) {
     *status = ORC_INVALID; return NULL;
   }
-  /* cycle and smoother variants: not built yet */
-  if (par->cycle_type != 0 || par->relax_type != 4 || par->coarse_relax != 4) {
-    *status = ORC_INVALID; return NULL;
+  if (par->cycle_type < 0 || par->cycle_type > 2) { *status = ORC_INVALID; return NULL; }
+  for (int q = 0; q < 2; q++) {
+    int t = q ? par->coarse_relax : par->relax_type;
+    if (t != 0 && t != 1 && t != 3 && t != 4) { *status = ORC_INVALID; return NULL; }
   }
   orc_h *h = (orc_h *)calloc(1, sizeof(orc_h));
   if (!h) { *status = ORC_NOMEM; return NULL; }
@@ -743,8 +746,19 @@ static orc_h *build_single(int32_t n, const int32_t *rp, const int32_t *ci, cons
     h->vx[k] = (double *)malloc(nb); h->vt[k] = (double *)malloc(nb);
     h->vr[k] = (double *)malloc(nb); h->vres[k] = (double *)malloc(nb);
     h->ve[k] = (double *)malloc(nb);
-    if (!h->vx[k] || !h->vt[k] || !h->vr[k] || !h->vres[k] || !h->ve[k]) {
+    h->vw[k] = (double *)malloc(nb); h->vz[k] = (double *)malloc(nb);
+    h->djac[k] = (double *)malloc(nb);
+    if (!h->vx[k] || !h->vt[k] || !h->vr[k] || !h->vres[k] || !h->ve[k] || !h->vw[k] || !h->vz[k] ||
+        !h->djac[k]) {
       orc_free(h); *status = ORC_NOMEM; return NULL;
+    }
+    /* Jacobi / Gauss-Seidel diagonal: 1 / a_ii */
+    const csr_t *Ak = &h->A[k];
+    for (int32_t i = 0; i < Ak->n; i++) {
+      double d = 0.0;
+      for (int32_t t = Ak->rp[i]; t < Ak->rp[i + 1]; t++)
+        if (Ak->ci[t] == i) d = Ak->v[t];
+      h->djac[k][i] = 1.0 / d;
     }
   }
   *status = ORC_OK;
@@ -758,6 +772,7 @@ void orc_free(orc_h *h) {
     csr_free(&h->A[k]);
     free(h->dinv[k]); free(h->w[k]); free(h->agg[k]); free(h->pval[k]); free(h->part[k]);
     free(h->vx[k]); free(h->vt[k]); free(h->vr[k]); free(h->vres[k]); free(h->ve[k]);
+    free(h->vw[k]); free(h->vz[k]); free(h->djac[k]);
     free(h->fv[k]); free(h->fdinv[k]); free(h->fpval[k]);
     free(h->fx[k]); free(h->ft[k]); free(h->fr[k]); free(h->fres[k]); free(h->fe[k]);
   }
@@ -797,19 +812,87 @@ static void coarse_direct(const orc_h *h, const double *r, double *z) {
   }
 }
 
+/* ---------------------------------------------- smoothers (Appendix A)
+ * relax_type / coarse_relax codes:
+ *   4 l1-Jacobi  x <- x + M^-1 (r - A x), M_ii = sum_j |a_ij| (Sec. 3.1);
+ *   0 Jacobi     the same with a_ii;
+ *   1 FGS/BGS    Gauss-Seidel: forward (rows ascending) before the coarse
+ *                correction, backward (rows descending) after it, so that
+ *                the cycle stays symmetric;
+ *   3 symmetrized Gauss-Seidel: every sweep a forward then a backward pass.
+ * A Gauss-Seidel pass updates row by row in place,
+ *   x_i <- x_i + (r_i - sum_j a_ij x_j) / a_ii,
+ * the row folded in CSR order over the current x.  Smoothing from zero:
+ * the Jacobi types start with x = dinv r and do nsw - 1 further sweeps; the
+ * Gauss-Seidel types start from x = 0 and do nsw sweeps. */
+static void gs_pass(const csr_t *A, const double *dj, const double *r, double *x, int forward) {
+  int32_t n = A->n;
+  for (int32_t q = 0; q < n; q++) {
+    int32_t i = forward ? q : n - 1 - q;
+    double s = 0.0;
+    for (int32_t k = A->rp[i]; k < A->rp[i + 1]; k++) s = s + A->v[k] * x[A->ci[k]];
+    x[i] = x[i] + dj[i] * (r[i] - s);
+  }
+}
+
+/* nsw sweeps of smoother `type` on A_k x = r continuing from x; pass = +1
+ * pre-smoothing, -1 post-smoothing, 0 coarsest level (for FGS/BGS: forward
+ * and backward passes alternate there, starting forward). */
+static void smooth_more(orc_h *h, int k, int type, int pass, const double *r, int nsw, double *x) {
+  const csr_t *A = &h->A[k];
+  double *t = h->vt[k];
+  for (int q = 0; q < nsw; q++) {
+    if (type == 4 || type == 0) {
+      sweep(A, type == 4 ? h->dinv[k] : h->djac[k], r, x, t);
+      memcpy(x, t, sizeof(double) * (size_t)A->n);
+    } else if (type == 1) {
+      int fwd = (pass > 0) || (pass == 0 && q % 2 == 0);
+      gs_pass(A, h->djac[k], r, x, fwd);
+    } else {
+      gs_pass(A, h->djac[k], r, x, 1);
+      gs_pass(A, h->djac[k], r, x, 0);
+    }
+  }
+}
+
+static void smooth_zero(orc_h *h, int k, int type, int pass, const double *r, int nsw, double *x) {
+  int32_t n = h->A[k].n;
+  if (nsw <= 0) { for (int32_t i = 0; i < n; i++) x[i] = 0.0; return; }
+  if (type == 4 || type == 0) {
+    const double *d = (type == 4) ? h->dinv[k] : h->djac[k];
+    ORC_ROWS
+    for (int32_t i = 0; i < n; i++) x[i] = d[i] * r[i];
+    smooth_more(h, k, type, pass, r, nsw - 1, x);
+  } else {
+    for (int32_t i = 0; i < n; i++) x[i] = 0.0;
+    smooth_more(h, k, type, pass, r, nsw, x);
+  }
+}
+
+/* Coarse-grid corrections per visit of level k (Appendix A cycle_type):
+ * V-cycle 1; W-cycle 2 on every level; H-cycle (reading: the hybrid that
+ * alternates them) 2 on odd levels and 1 on even ones.  With 2 the coarse
+ * system is approximated by two cycles from zero: e = C(r_c), then
+ * e += C(r_c - A_{k+1} e). */
+static int corrections(const orc_h *h, int k) {
+  if (h->p.cycle_type == 2) return 2;
+  if (h->p.cycle_type == 1) return (k % 2 == 1) ? 2 : 1;
+  return 1;
+}
+
 static void vcycle(orc_h *h, int k, const double *r, double *z) {
   const csr_t *A = &h->A[k];
   int32_t n = A->n;
-  double *x = h->vx[k], *t = h->vt[k];
+  double *x = h->vx[k];
   if (k == h->nlev - 1) {
     if (h->coarse_dense) coarse_direct(h, r, z);
     else {
-      smooth_from_zero(A, h->dinv[k], r, h->p.coarse_sweeps, x, t);
+      smooth_zero(h, k, h->p.coarse_relax, 0, r, h->p.coarse_sweeps, x);
       memcpy(z, x, sizeof(double) * (size_t)n);
     }
     return;
   }
-  smooth_from_zero(A, h->dinv[k], r, h->p.pre_sweeps, x, t);
+  smooth_zero(h, k, h->p.relax_type, 1, r, h->p.pre_sweeps, x);
   /* residual and restriction: r_c[I] = sum_{i in I, ascending} p_i (r - A x)_i */
   double *res = h->vres[k];
   spmv(A, x, res);
@@ -820,12 +903,16 @@ static void vcycle(orc_h *h, int k, const double *r, double *z) {
   restrict_fold(n, nc, h->agg[k], h->pval[k], res, rc);
   double *ec = h->ve[k + 1];
   vcycle(h, k + 1, rc, ec);
+  for (int g = 1; g < corrections(h, k); g++) {
+    double *tc = h->vw[k + 1], *e2 = h->vz[k + 1];
+    spmv(&h->A[k + 1], ec, tc);
+    for (int32_t I = 0; I < nc; I++) tc[I] = rc[I] - tc[I];
+    vcycle(h, k + 1, tc, e2);
+    for (int32_t I = 0; I < nc; I++) ec[I] = ec[I] + e2[I];
+  }
   ORC_ROWS
   for (int32_t i = 0; i < n; i++) x[i] = x[i] + h->pval[k][i] * ec[h->agg[k][i]];
-  for (int s = 0; s < h->p.post_sweeps; s++) {
-    sweep(A, h->dinv[k], r, x, t);
-    memcpy(x, t, sizeof(double) * (size_t)n);
-  }
+  smooth_more(h, k, h->p.relax_type, -1, r, h->p.post_sweeps, x);
   memcpy(z, x, sizeof(double) * (size_t)n);
 }
 
@@ -949,6 +1036,8 @@ int orc_vcycle_f32(orc_h *h, const double *r, double *z) {
 static int single_apply_f32(orc_h *h, const double *r, double *z) {
   int32_t n = h->A[0].n;
   if (!h->p.precond || h->nlev == 1) return single_apply(h, r, z);
+  /* the binary32 cycle is the l1-Jacobi V-cycle */
+  if (h->p.cycle_type != 0 || h->p.relax_type != 4 || h->p.coarse_relax != 4) return ORC_INVALID;
   if (!h->have_f32 && build_f32(h) != ORC_OK) return ORC_NOMEM;
   float *rf = (float *)malloc(sizeof(float) * (size_t)n);
   float *zf = (float *)malloc(sizeof(float) * (size_t)n);
