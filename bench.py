@@ -227,6 +227,38 @@ def bootstrap_leg(amd, torch, W, np, dev):
                 bootstrap_rate=0.05, bootstrap_its=15, runs=runs)
 
 
+def cycles_leg(amd, torch, W, np, dev, N=160):
+    """Cycle and smoother options of Appendix A on the 160^3 Poisson system
+    (FP64, same right-hand side as the headline): V/H/W cycles with the
+    l1-Jacobi smoother, and the V- and W-cycle with Jacobi, forward/backward
+    Gauss-Seidel and symmetrized Gauss-Seidel.  Gauss-Seidel passes are level
+    schedules (one launch per wavefront of the dependency graph on the fine
+    levels: 478 at 160^3), the sequential smoother the paper avoids on GPUs."""
+    A = W.poisson7(N)
+    xs, b = W.manufactured_rhs(A, SEED)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    rp, ci, va, bd = d(A.row_ptr), d(A.col), d(A.val), d(b)
+    names = {0: "Jacobi", 1: "FGS/BGS", 3: "symmetrized GS", 4: "l1-Jacobi"}
+    runs = []
+    for cyc, rel in ((0, 4), (1, 4), (2, 4), (0, 0), (0, 1), (0, 3), (2, 1), (2, 3)):
+        rec = None
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = amd.Hierarchy(rp, ci, va, cycle_type=cyc, relax_type=rel)
+            t1 = time.perf_counter()
+            x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            st, it, rr = H.solve(bd, x, rtol=RTOL, maxit=MAXIT)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec = dict(cycle="VHW"[cyc], smoother=names[rel], status=st, iters=it, relres=rr,
+                       setup_s=t1 - t0, solve_s=t2 - t1, titer_ms=(t2 - t1) / max(1, it) * 1e3)
+            H.close()
+        runs.append(rec)
+        log("cycles", json.dumps(rec))
+    return dict(workload="3D Poisson 7-point 160^3, FP64, b = A x* seed 2", runs=runs)
+
+
 def mixed27_leg(amd, torch, W, np, dev):
     """27-point diffusion 128^3, kappa log-uniform in [1e-3, 1e3] (seed 3),
     x* seed 4, relaxation smooth vector: FP64 V-cycle versus binary32 V-cycle
@@ -363,7 +395,7 @@ def main():
                     help="matrix values of the solve kernels: coded where a level has at most "
                          "256 distinct values (auto), or plain binary64 arrays")
     ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160",
-                                       "decoupled_weak", "bootstrap"],
+                                       "decoupled_weak", "bootstrap", "cycles"],
                     help="only: run one form's leg and print its record (for profiling)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only: build the 160^3 hierarchy, launch the fine-level sweep "
@@ -384,7 +416,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.only and args.only != "mixed160":
         leg = dict(batched=batched_leg, mixed27=mixed27_leg, learned=learned_leg, paper=paper_leg,
-                   decoupled_weak=decoupled_weak_leg, bootstrap=bootstrap_leg)[args.only]
+                   decoupled_weak=decoupled_weak_leg, bootstrap=bootstrap_leg,
+                   cycles=cycles_leg)[args.only]
         log("only", args.only)
         print(json.dumps({"form": args.only, "record": leg(amd, torch, W, np, dev)}), flush=True)
         return
@@ -537,6 +570,8 @@ def main():
     if not args.no_forms:
         log("bootstrap composite")
         forms["bootstrap"] = bootstrap_leg(amd, torch, W, np, dev)
+        log("cycle and smoother options")
+        forms["cycles"] = cycles_leg(amd, torch, W, np, dev)
 
     if not args.no_forms and not args.no_paper:
         log("paper configuration 300^3")

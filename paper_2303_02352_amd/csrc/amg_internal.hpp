@@ -392,6 +392,11 @@ struct Level {
   // V-cycle work vectors
   dvec<double> r, x, t;
   dvec<float> rf, xf, tf;
+  // general cycle (H/W cycles, Jacobi / Gauss-Seidel smoothers): 1 / a_ii,
+  // the second coarse correction's vectors, the Gauss-Seidel level schedule
+  dvec<double> djac, ge, gw, gz;
+  dvec<int> gs_rows, gs_ptr_d;
+  std::vector<int> gs_ptr;
 };
 
 struct Scalars {        // PCG state living in device memory

@@ -64,9 +64,9 @@ int check_params(const amg_params *p) {
     return set_error(AMG_ERR_INVALID, "unknown bootstrap_type");
   if (p->bootstrap_its < 1 || !(p->bootstrap_rate > 0.0 && p->bootstrap_rate <= 1.0))
     return set_error(AMG_ERR_INVALID, "bootstrap_its or bootstrap_rate out of range");
-  if (p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI ||
-      p->coarse_relax != AMG_RELAX_L1_JACOBI)
-    return set_error(AMG_ERR_UNSUPPORTED, "cycle and smoother variants are not built");
+  if ((p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI ||
+       p->coarse_relax != AMG_RELAX_L1_JACOBI) && p->precision != AMG_PREC_DOUBLE)
+    return set_error(AMG_ERR_UNSUPPORTED, "the binary32 cycle is the l1-Jacobi V-cycle");
   return AMG_OK;
 }
 }  // namespace
@@ -88,6 +88,7 @@ int64_t device_bytes(const amg_hierarchy *h) {
     b += L.dinv.bytes() + L.w.bytes() + L.dinvf.bytes() + L.agg.bytes() + L.pval.bytes();
     b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
     b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();
+    b += L.djac.bytes() + L.ge.bytes() + L.gw.bytes() + L.gz.bytes() + L.gs_rows.bytes() + L.gs_ptr_d.bytes();
   }
   b += h->Ainv.bytes() + h->tail_desc_d.bytes() + h->tail_desc_f.bytes();
   b += h->u.bytes() + h->r.bytes() + h->w.bytes() + h->v.bytes() + h->d.bytes() + h->q.bytes();

@@ -1321,7 +1321,8 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
       return amg::api_set_error(AMG_ERR_INVALID, "bad CSR header in the batch");
   const int pst = amg::api_check_params(p);
   if (pst != AMG_OK) return pst;
-  if (p->max_hrc != 1 || p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI)
+  if (p->max_hrc != 1 || p->cycle_type != AMG_CYCLE_V || p->relax_type != AMG_RELAX_L1_JACOBI ||
+      p->coarse_relax != AMG_RELAX_L1_JACOBI)
     return amg::api_set_error(AMG_ERR_UNSUPPORTED, "the batched solve runs the l1-Jacobi V-cycle of one hierarchy");
   amg_batch *bt = new (std::nothrow) amg_batch();
   if (!bt) return amg::api_set_error(AMG_ERR_NOMEM, "host allocation failed");

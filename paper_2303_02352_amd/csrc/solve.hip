@@ -1177,6 +1177,307 @@ bool vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
   return wide != nullptr && P.post_sweeps >= 2;
 }
 
+// ---------------------------------- general cycle (Appendix A options)
+// H- and W-cycles and the Jacobi / Gauss-Seidel smoothers, in binary64.
+// Coarse-grid corrections per visit of level k: 1 (V), 2 (W), 2 on odd
+// levels and 1 on even ones (H); with two, the coarse system is
+// approximated by two cycles from zero: e = C(r_c), e += C(r_c - A_c e).
+// Smoothers: l1-Jacobi and Jacobi sweep x <- x + dinv (r - A x) with dinv =
+// 1 / sum_j |a_ij| or 1 / a_ii (from zero: x = dinv r, then nu - 1 sweeps);
+// Gauss-Seidel passes update x_i <- x_i + (r_i - sum_j a_ij x_j) / a_ii in
+// place, row by row (from zero: x = 0, then nu passes); FGS/BGS runs forward
+// passes before the correction and backward ones after it (alternating,
+// forward first, on the coarsest level); symmetrized GS a forward and a
+// backward pass per sweep.  Rows are folded in CSR order.
+//
+// A Gauss-Seidel pass runs as a level schedule: level(i) = 1 + the largest
+// level of a stored neighbour j < i (0 without one).  Rows of one level have
+// no stored entry between them, so they update concurrently; a forward
+// pass takes the levels in ascending order, a backward pass in descending
+// order (a neighbour j > i of row i always has a higher level), which gives
+// exactly the sequential pass.
+__global__ void k_sub_from(const int *skip, int n, const double *__restrict__ r, double *__restrict__ t) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = r[i] - t[i];
+}
+
+__global__ void k_add_to(const int *skip, int n, double *__restrict__ z, const double *__restrict__ e) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = z[i] + e[i];
+}
+
+__global__ void k_div_by(const int *skip, int n, double *z, double m) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = z[i] / m;
+}
+
+__global__ void k_copy(const int *skip, int n, const double *__restrict__ a, double *__restrict__ b) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+// xn = x + dinv (r - A x) over the canonical CSR rows.
+__global__ void __launch_bounds__(kBlock) k_csr_sweep(const int *skip, int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const double *__restrict__ v,
+                                                      const double *__restrict__ dinv,
+                                                      const double *__restrict__ r,
+                                                      const double *__restrict__ x, double *__restrict__ xn) {
+  AMG_SKIP_IF_DONE();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) acc = acc + v[k] * x[ci[k]];
+  xn[i] = x[i] + dinv[i] * (r[i] - acc);
+}
+
+__device__ __forceinline__ void gs_row(int i, const int *__restrict__ rp, const int *__restrict__ ci,
+                                       const double *__restrict__ v, const double *__restrict__ dj,
+                                       const double *__restrict__ r, double *x) {
+  double acc = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) acc = acc + v[k] * x[ci[k]];
+  x[i] = x[i] + dj[i] * (r[i] - acc);
+}
+
+// One level of a Gauss-Seidel pass: rows[0 .. cnt) are independent.
+__global__ void __launch_bounds__(kBlock) k_gs_level(const int *skip, int cnt, const int *__restrict__ rows,
+                                                     const int *__restrict__ rp, const int *__restrict__ ci,
+                                                     const double *__restrict__ v,
+                                                     const double *__restrict__ dj,
+                                                     const double *__restrict__ r, double *x) {
+  AMG_SKIP_IF_DONE();
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < cnt) gs_row(rows[q], rp, ci, v, dj, r, x);
+}
+
+// A whole Gauss-Seidel pass in one workgroup (small levels): the levels in
+// order with a workgroup barrier between them.
+constexpr int kGsSmallRows = 65536;
+constexpr int kGsThreads = 1024;
+__global__ void __launch_bounds__(kGsThreads) k_gs_pass_small(const int *skip, int nlev,
+                                                              const int *__restrict__ ptr,
+                                                              const int *__restrict__ rows,
+                                                              const int *__restrict__ rp,
+                                                              const int *__restrict__ ci,
+                                                              const double *__restrict__ v,
+                                                              const double *__restrict__ dj,
+                                                              const double *__restrict__ r, double *x,
+                                                              int forward) {
+  AMG_SKIP_IF_DONE();
+  for (int l0 = 0; l0 < nlev; ++l0) {
+    const int l = forward ? l0 : nlev - 1 - l0;
+    for (int q = ptr[l] + static_cast<int>(threadIdx.x); q < ptr[l + 1]; q += kGsThreads)
+      gs_row(rows[q], rp, ci, v, dj, r, x);
+    __syncthreads();
+  }
+}
+
+// Level schedule, fixed point of level(i) = max over stored j < i of
+// level(j) + 1: updated in place (relaxed atomic accesses) until a pass
+// changes nothing; the fixed point is unique whatever order rows are seen in.
+__global__ void __launch_bounds__(kBlock) k_gs_levels(int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci, int *lev, int *changed) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int m = 0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k) {
+    const int j = ci[k];
+    if (j < i) m = max(m, __hip_atomic_load(lev + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
+  }
+  if (m > __hip_atomic_load(lev + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    __hip_atomic_store(lev + i, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicOr(changed, 1);
+  }
+}
+
+__global__ void k_gs_count(int n, const int *__restrict__ lev, int *cnt, int *maxlev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(cnt + lev[i], 1);
+  atomicMax(maxlev, lev[i]);
+}
+
+// rows grouped by level (the order inside a level is free: its rows are independent)
+__global__ void k_gs_place(int n, const int *__restrict__ lev, const int *__restrict__ ptr, int *fill,
+                           int *rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int l = lev[i];
+  rows[ptr[l] + atomicAdd(fill + l, 1)] = i;
+}
+
+__global__ void k_jacobi_diag(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                              const double *__restrict__ v, double *dj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int k = rp[i]; k < rp[i + 1]; ++k)
+    if (ci[k] == i) d = v[k];
+  dj[i] = 1.0 / d;
+}
+
+bool general_cycle(const amg_hierarchy *h) {
+  const amg_params &P = h->p;
+  return P.precond && (P.cycle_type != AMG_CYCLE_V || P.relax_type != AMG_RELAX_L1_JACOBI ||
+                       P.coarse_relax != AMG_RELAX_L1_JACOBI);
+}
+
+int corrections(const amg_hierarchy *h, int k) {
+  if (h->p.cycle_type == AMG_CYCLE_W) return 2;
+  if (h->p.cycle_type == AMG_CYCLE_H) return (k % 2 == 1) ? 2 : 1;
+  return 1;
+}
+
+void gs_pass(amg_hierarchy *h, const int *skip, Level &L, const double *r, double *x, bool forward) {
+  hipStream_t s = h->stream;
+  const int n = L.A.n;
+  const int nlev = static_cast<int>(L.gs_ptr.size()) - 1;
+  if (n <= kGsSmallRows) {
+    hipLaunchKernelGGL(k_gs_pass_small, dim3(1), dim3(kGsThreads), 0, s, skip, nlev, L.gs_ptr_d.p,
+                       L.gs_rows.p, L.A.rp.p, L.A.ci.p, L.A.v.p, L.djac.p, r, x, forward ? 1 : 0);
+    return;
+  }
+  for (int l0 = 0; l0 < nlev; ++l0) {
+    const int l = forward ? l0 : nlev - 1 - l0;
+    const int cnt = L.gs_ptr[l + 1] - L.gs_ptr[l];
+    hipLaunchKernelGGL(k_gs_level, grid_for(cnt), dim3(kBlock), 0, s, skip, cnt,
+                       L.gs_rows.p + L.gs_ptr[l], L.A.rp.p, L.A.ci.p, L.A.v.p, L.djac.p, r, x);
+  }
+}
+
+// nsw further sweeps of smoother `type` on level k, in place on x; pass: +1
+// pre-smoothing, -1 post-smoothing, 0 the coarsest level.
+void smooth_more_g(amg_hierarchy *h, const int *skip, int k, int type, int pass, const double *r, int nsw,
+                   double *x) {
+  hipStream_t s = h->stream;
+  Level &L = h->L[k];
+  const int n = L.A.n;
+  if (type == AMG_RELAX_L1_JACOBI || type == AMG_RELAX_JACOBI) {
+    const double *d = (type == AMG_RELAX_L1_JACOBI) ? L.dinv.p : L.djac.p;
+    double *a = x, *b = L.t.p;
+    for (int q = 0; q < nsw; ++q) {
+      hipLaunchKernelGGL(k_csr_sweep, grid_for(n), dim3(kBlock), 0, s, skip, n, L.A.rp.p, L.A.ci.p, L.A.v.p,
+                         d, r, a, b);
+      std::swap(a, b);
+    }
+    if (a != x) hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kBlock), 0, s, skip, n, a, x);
+    return;
+  }
+  for (int q = 0; q < nsw; ++q) {
+    if (type == AMG_RELAX_GS) {
+      gs_pass(h, skip, L, r, x, pass > 0 || (pass == 0 && q % 2 == 0));
+    } else {
+      gs_pass(h, skip, L, r, x, true);
+      gs_pass(h, skip, L, r, x, false);
+    }
+  }
+}
+
+void smooth_zero_g(amg_hierarchy *h, const int *skip, int k, int type, int pass, const double *r, int nsw,
+                   double *x) {
+  hipStream_t s = h->stream;
+  Level &L = h->L[k];
+  const int n = L.A.n;
+  if (nsw <= 0 || type == AMG_RELAX_GS || type == AMG_RELAX_SYM_GS) {
+    hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, skip, n, x);
+    if (nsw > 0) smooth_more_g(h, skip, k, type, pass, r, nsw, x);
+    return;
+  }
+  const double *d = (type == AMG_RELAX_L1_JACOBI) ? L.dinv.p : L.djac.p;
+  hipLaunchKernelGGL(k_sweep_first<double>, grid_for(n), dim3(kBlock), 0, s, skip, n, d, r, x);
+  smooth_more_g(h, skip, k, type, pass, r, nsw - 1, x);
+}
+
+void cycle_general(amg_hierarchy *h, const int *skip, int k, const double *rhs, double *out) {
+  hipStream_t s = h->stream;
+  Level &L = h->L[k];
+  const int n = L.A.n;
+  const int nl = static_cast<int>(h->L.size());
+  const amg_params &P = h->p;
+  if (k == nl - 1) {
+    if (h->coarse_dense) {   // the coarse-tail kernel holding only this level: z = A^-1 r
+      auto kern = (h->tail_w <= 8) ? k_vcycle_tail<double, 8> : k_vcycle_tail<double, 16>;
+      hipLaunchKernelGGL(kern, dim3(1), dim3(kTailThreads), 0, s, skip, 1, tail_desc<double>(h), h->Ainv.p,
+                         h->coarse_dense, P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out);
+    } else {
+      smooth_zero_g(h, skip, k, P.coarse_relax, 0, rhs, P.coarse_sweeps, L.x.p);
+      hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kBlock), 0, s, skip, n, L.x.p, out);
+    }
+    return;
+  }
+  smooth_zero_g(h, skip, k, P.relax_type, 1, rhs, P.pre_sweeps, L.x.p);
+  launch_resid<double>(skip, L, rhs, L.x.p, L.t.p, s);
+  Level &C = h->L[k + 1];
+  const int nc = L.nc;
+  hipLaunchKernelGGL(k_agg_sum<double>, grid_for(nc), dim3(kBlock), 0, s, skip, nc, L.mptr.p, L.mem.p, L.t.p,
+                     C.r.p, nullptr, nullptr);
+  cycle_general(h, skip, k + 1, C.r.p, C.ge.p);
+  for (int g = 1; g < corrections(h, k); ++g) {
+    launch_spmv(C, C.ge.p, C.gw.p, s);
+    hipLaunchKernelGGL(k_sub_from, grid_for(nc), dim3(kBlock), 0, s, skip, nc, C.r.p, C.gw.p);
+    cycle_general(h, skip, k + 1, C.gw.p, C.gz.p);
+    hipLaunchKernelGGL(k_add_to, grid_for(nc), dim3(kBlock), 0, s, skip, nc, C.ge.p, C.gz.p);
+  }
+  hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, L.pval.p, C.ge.p,
+                     L.x.p);
+  smooth_more_g(h, skip, k, P.relax_type, -1, rhs, P.post_sweeps, L.x.p);
+  hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kBlock), 0, s, skip, n, L.x.p, out);
+  AMG_LAUNCH_CHECK();
+}
+
+// Setup of the general cycle's data: 1 / a_ii, Gauss-Seidel level schedules
+// and the coarse-correction vectors.
+void prepare_general(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  const amg_params &P = h->p;
+  const int nl = static_cast<int>(h->L.size());
+  const bool gs_smooth = P.relax_type == AMG_RELAX_GS || P.relax_type == AMG_RELAX_SYM_GS;
+  const bool gs_coarse = !h->coarse_dense && (P.coarse_relax == AMG_RELAX_GS || P.coarse_relax == AMG_RELAX_SYM_GS);
+  for (int k = 0; k < nl; ++k) {
+    Level &L = h->L[k];
+    const int n = L.A.n;
+    L.djac.alloc(n);
+    hipLaunchKernelGGL(k_jacobi_diag, grid_for(n), dim3(kBlock), 0, s, n, L.A.rp.p, L.A.ci.p, L.A.v.p, L.djac.p);
+    AMG_LAUNCH_CHECK();
+    if (k > 0) { L.ge.alloc(n); L.gw.alloc(n); L.gz.alloc(n); }
+    const bool want_gs = (k < nl - 1) ? gs_smooth : gs_coarse;
+    if (!want_gs) continue;
+    dvec<int> lev(n), changed(1), cnt(n + 1), maxlev(1), fill(n + 1);
+    hipLaunchKernelGGL(k_zero<int>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, lev.p);
+    for (int it = 0;; ++it) {
+      if (it > n + 1) fail(AMG_ERR_DEVICE, "Gauss-Seidel level schedule did not settle");
+      hipLaunchKernelGGL(k_zero<int>, dim3(1), dim3(kBlock), 0, s, nullptr, 1, changed.p);
+      hipLaunchKernelGGL(k_gs_levels, grid_for(n), dim3(kBlock), 0, s, n, L.A.rp.p, L.A.ci.p, lev.p, changed.p);
+      AMG_LAUNCH_CHECK();
+      int c = 0;
+      AMG_HIP(hipMemcpyAsync(&c, changed.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      AMG_HIP(hipStreamSynchronize(s));
+      if (!c) break;
+    }
+    hipLaunchKernelGGL(k_zero<int>, grid_for(n + 1), dim3(kBlock), 0, s, nullptr, n + 1, cnt.p);
+    hipLaunchKernelGGL(k_zero<int>, grid_for(n + 1), dim3(kBlock), 0, s, nullptr, n + 1, fill.p);
+    hipLaunchKernelGGL(k_zero<int>, dim3(1), dim3(kBlock), 0, s, nullptr, 1, maxlev.p);
+    hipLaunchKernelGGL(k_gs_count, grid_for(n), dim3(kBlock), 0, s, n, lev.p, cnt.p, maxlev.p);
+    AMG_LAUNCH_CHECK();
+    int ml = 0;
+    AMG_HIP(hipMemcpyAsync(&ml, maxlev.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    const int nlev = ml + 1;
+    L.gs_ptr_d.alloc(nlev + 1);
+    device_exclusive_scan(cnt.p, L.gs_ptr_d.p, nlev, s);
+    L.gs_rows.alloc(n);
+    hipLaunchKernelGGL(k_gs_place, grid_for(n), dim3(kBlock), 0, s, n, lev.p, L.gs_ptr_d.p, fill.p, L.gs_rows.p);
+    AMG_LAUNCH_CHECK();
+    L.gs_ptr.resize(nlev + 1);
+    AMG_HIP(hipMemcpyAsync(L.gs_ptr.data(), L.gs_ptr_d.p, sizeof(int) * (nlev + 1), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
+}
+
 // Mixed precision: the residual is rounded to binary32 on entry (fused with
 // the first sweep), the cycle runs in binary32 except for the coarsest solve
 // (binary64 inside its kernel), and the result is widened to binary64.
@@ -1206,7 +1507,8 @@ void vcycle_any(amg_hierarchy *h, const int *skip, const double *r, double *z,
     AMG_HIP(hipMemcpyAsync(z, r, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
     return;
   }
-  if (h->p.precision == AMG_PREC_MIXED && !binary64) vcycle_mixed(h, skip, r, z, first_done);
+  if (general_cycle(h)) cycle_general(h, skip, 0, r, z);
+  else if (h->p.precision == AMG_PREC_MIXED && !binary64) vcycle_mixed(h, skip, r, z, first_done);
   else vcycle_level<double>(h, skip, 0, r, z, first_done);
   AMG_LAUNCH_CHECK();
 }
@@ -1217,24 +1519,6 @@ void vcycle_any(amg_hierarchy *h, const int *skip, const double *r, double *z,
 // symmetrized the same for j = 1..m and then j = m-1..1; additive
 // z = (B_1 r + ... + B_m r) / m.  Residuals, sums and the division are
 // binary64 in both precisions.
-__global__ void k_sub_from(const int *skip, int n, const double *__restrict__ r, double *__restrict__ t) {
-  AMG_SKIP_IF_DONE();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) t[i] = r[i] - t[i];
-}
-
-__global__ void k_add_to(const int *skip, int n, double *__restrict__ z, const double *__restrict__ e) {
-  AMG_SKIP_IF_DONE();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] = z[i] + e[i];
-}
-
-__global__ void k_div_by(const int *skip, int n, double *z, double m) {
-  AMG_SKIP_IF_DONE();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z[i] = z[i] / m;
-}
-
 // z = B r for the composite of the first m hierarchies (m < 0: all of them);
 // first_done as for vcycle_any (first hierarchy only).
 void precond_apply(amg_hierarchy *h, const int *skip, const double *r, double *z, bool first_done,
@@ -1271,7 +1555,7 @@ void precond_apply(amg_hierarchy *h, const int *skip, const double *r, double *z
 // What the PCG residual kernels write for the next V-cycle whose output is z.
 FirstOut first_out_for(amg_hierarchy *h, double *z) {
   FirstOut fo{nullptr, nullptr, nullptr, nullptr, nullptr};
-  if (!h->p.precond) return fo;
+  if (!h->p.precond || general_cycle(h)) return fo;
   Level &L = h->L[0];
   if (h->p.precision == AMG_PREC_MIXED && h->L.size() > 1) {
     fo.rf = L.rf.p;
@@ -1380,13 +1664,19 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   h->tail_start = nl;
   int used = 0;
   // (the binary32 cycle solves a coarsest level without a direct solve by
-  // binary64 sweeps, which the tail kernel does not provide)
-  const bool tail_ok = !(mixed && h->p.precond && !h->coarse_dense && nl > 1);
+  // binary64 sweeps, which the tail kernel does not provide; the general
+  // cycle uses it for the direct coarsest solve only)
+  const bool general = general_cycle(h);
+  const bool tail_ok = !(mixed && h->p.precond && !h->coarse_dense && nl > 1) && !general;
   for (int k = nl - 1; tail_ok && k >= 0; --k) {
     const int nk = h->L[k].A.n;
     if (nk > kTailRows || used + 4 * nk > kTailLds) break;
     used += 4 * nk;
     h->tail_start = k;
+  }
+  if (general && h->coarse_dense) {
+    h->tail_start = nl - 1;
+    used = 4 * h->L[nl - 1].A.n;
   }
   if (h->coarse_dense && h->tail_start > nl - 1) fail(AMG_ERR_DEVICE, "dense coarsest level outside the tail");
   // widest slice of the tail levels: rows up to 8 slots stay in registers
@@ -1401,6 +1691,7 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   }
   upload_tail<double>(h, h->tail_desc_d, false);
   if (mixed) upload_tail<float>(h, h->tail_desc_f, true);
+  if (general) prepare_general(h);
   h->sc.alloc(1);
   AMG_HIP(hipMemsetAsync(h->sc.p, 0, sizeof(Scalars), h->stream));
   if (!h->sc_host) {
