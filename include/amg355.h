@@ -46,6 +46,9 @@ extern "C" {
 #define AMG_ERR_NOMEM (-4)        /* device allocation failed */
 #define AMG_ERR_DEVICE (-5)       /* any other HIP runtime error */
 #define AMG_ERR_UNSUPPORTED (-6)  /* a parameter combination the library does not provide */
+#define AMG_ERR_MODEL (-7)        /* the learned smooth vector was unusable (non-finite or
+                                     non-positive): reported in amg_info_t.smooth_status while
+                                     amg_setup falls back to AMG_SMOOTH_RELAX and succeeds */
 
 /* coarse_solver */
 #define AMG_COARSE_CHOLESKY 0     /* dense FP64 Cholesky (coarsest n <= 1024, else Jacobi sweeps) */
@@ -54,6 +57,9 @@ extern "C" {
 #define AMG_SMOOTH_ONES 0         /* w = 1 */
 #define AMG_SMOOTH_RELAX 1        /* smooth_sweeps l1-Jacobi sweeps on A w = 0 from w = 1, w /= max|w| */
 #define AMG_SMOOTH_GIVEN 2        /* w supplied in amg_params.smooth_vector (e.g. a learned surrogate) */
+#define AMG_SMOOTH_LEARNED 3      /* w predicted by the message-passing network (amg_mpnn below)
+                                     with amg_params.model_params; relaxation (smooth_sweeps)
+                                     when the prediction is unusable */
 /* precision */
 #define AMG_PREC_DOUBLE 0         /* everything in binary64 */
 #define AMG_PREC_MIXED 1          /* V-cycle below the coarsest level in binary32; PCG,
@@ -169,6 +175,7 @@ typedef struct {
   int32_t nrates;               /* rate estimates taken by the bootstrap */
   double rates[AMG_MAX_HRC];    /* rates[j-1]: estimated rate of the first j hierarchies */
   double setup_bootstrap_ms;    /* part spent on rate estimates and further hierarchies */
+  int32_t smooth_status;        /* AMG_OK, or AMG_ERR_MODEL when LEARNED fell back to RELAX */
 } amg_info_t;
 
 /* Fill *p with the defaults above.  Returns AMG_OK or AMG_ERR_INVALID (p NULL). */

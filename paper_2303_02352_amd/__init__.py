@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libamg355.so")
 
 AMG_OK, AMG_NOT_CONVERGED = 0, 1
 AMG_ERR_INVALID, AMG_ERR_NOT_SPD, AMG_ERR_NONFINITE = -1, -2, -3
-AMG_ERR_NOMEM, AMG_ERR_DEVICE, AMG_ERR_UNSUPPORTED = -4, -5, -6
+AMG_ERR_NOMEM, AMG_ERR_DEVICE, AMG_ERR_UNSUPPORTED, AMG_ERR_MODEL = -4, -5, -6, -7
 AMG_COARSE_CHOLESKY, AMG_COARSE_JACOBI = 0, 1
-AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN = 0, 1, 2
+AMG_SMOOTH_ONES, AMG_SMOOTH_RELAX, AMG_SMOOTH_GIVEN, AMG_SMOOTH_LEARNED = 0, 1, 2, 3
 AMG_PREC_DOUBLE, AMG_PREC_MIXED = 0, 1
 AMG_VALUES_PLAIN, AMG_VALUES_AUTO = 0, 1
 AMG_CYCLE_V, AMG_CYCLE_H, AMG_CYCLE_W = 0, 1, 2
@@ -54,7 +54,7 @@ class amg_info_t(C.Structure):
                 ("setup_rap_ms", C.c_double), ("device_bytes", C.c_int64),
                 ("dict_size", C.c_int32 * AMG_MAX_LEVELS), ("setup_smooth_ms", C.c_double),
                 ("nhrc", C.c_int32), ("nrates", C.c_int32), ("rates", C.c_double * 16),
-                ("setup_bootstrap_ms", C.c_double)]
+                ("setup_bootstrap_ms", C.c_double), ("smooth_status", C.c_int32)]
 
 
 class amg_batch_info_t(C.Structure):
@@ -231,17 +231,26 @@ class Hierarchy:
     ``smooth_vector`` is an array of n doubles in the CSR's memory space.
     """
 
-    def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, **params):
+    def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, model_params=None, **params):
         L = load()
         A, self.n, self.nnz = _csr_args(row_ptr, col, val)
         p = default_params(**params)
         if smooth_vector is not None:
             p.smooth_vec = AMG_SMOOTH_GIVEN
             p.smooth_vector = _arr(smooth_vector, "smooth_vector", "float64", self.n, _space(val))
+        theta = None
+        if model_params is not None:
+            theta = np.ascontiguousarray(model_params, dtype=np.float32)
+            if theta.shape != (AMG_MPNN_NPARAMS,):
+                raise ValueError("model_params: shape %s, expected (%d,)" % (theta.shape, AMG_MPNN_NPARAMS))
+            p.smooth_vec = AMG_SMOOTH_LEARNED
+            p.model_params = theta.ctypes.data
         p.stream = stream if stream is not None else (current_stream() if A.on_device else None)
         self.params = p
         h = C.c_void_p()
         st = L.amg_setup(C.byref(A), C.byref(p), C.byref(h))
+        p.smooth_vector = None   # read during amg_setup only
+        p.model_params = None
         if st != AMG_OK:
             raise AMGError(st, "amg_setup")
         self.h = h
@@ -303,7 +312,7 @@ class Hierarchy:
                     setup_rap_ms=inf.setup_rap_ms, device_bytes=inf.device_bytes,
                     dict_size=list(inf.dict_size[:L]), setup_smooth_ms=inf.setup_smooth_ms,
                     nhrc=inf.nhrc, rates=list(inf.rates[:inf.nrates]),
-                    setup_bootstrap_ms=inf.setup_bootstrap_ms)
+                    setup_bootstrap_ms=inf.setup_bootstrap_ms, smooth_status=inf.smooth_status)
 
     def component(self, j):
         """Hierarchy j of the bootstrap composite (0 = this one) as a borrowed

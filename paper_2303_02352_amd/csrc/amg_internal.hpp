@@ -452,6 +452,7 @@ struct amg_hierarchy {
   int use_graph = 1;
   // bootstrap composite: hierarchies 2..m (owned; they run on this
   // hierarchy's stream), the rate estimates, and two fine-level work vectors
+  int smooth_status = AMG_OK;  // AMG_ERR_MODEL: the learned vector was unusable
   std::vector<amg_hierarchy *> comp;
   std::vector<double> rates;
   amg::dvec<double> ct, ce;

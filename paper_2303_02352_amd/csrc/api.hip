@@ -42,10 +42,12 @@ int check_params(const amg_params *p) {
     return set_error(AMG_ERR_INVALID, "parameter out of range");
   if (p->coarse_solver != AMG_COARSE_CHOLESKY && p->coarse_solver != AMG_COARSE_JACOBI)
     return set_error(AMG_ERR_INVALID, "unknown coarse_solver");
-  if (p->smooth_vec < AMG_SMOOTH_ONES || p->smooth_vec > AMG_SMOOTH_GIVEN)
+  if (p->smooth_vec < AMG_SMOOTH_ONES || p->smooth_vec > AMG_SMOOTH_LEARNED)
     return set_error(AMG_ERR_INVALID, "unknown smooth_vec");
   if (p->smooth_vec == AMG_SMOOTH_GIVEN && !p->smooth_vector)
     return set_error(AMG_ERR_INVALID, "smooth_vec = GIVEN needs smooth_vector");
+  if (p->smooth_vec == AMG_SMOOTH_LEARNED && !p->model_params)
+    return set_error(AMG_ERR_INVALID, "smooth_vec = LEARNED needs model_params");
   if (p->precision != AMG_PREC_DOUBLE && p->precision != AMG_PREC_MIXED)
     return set_error(AMG_ERR_INVALID, "unknown precision");
   if (p->value_coding != AMG_VALUES_PLAIN && p->value_coding != AMG_VALUES_AUTO)
@@ -211,6 +213,7 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
   });
   for (amg_hierarchy *c : h->comp) c->stream = h->stream;
   h->p.smooth_vector = nullptr;
+  h->p.model_params = nullptr;
   if (st != AMG_OK) {
     std::string msg = g_last_error;
     amg_destroy(h);
@@ -284,6 +287,7 @@ const char *amg_strerror(int code) {
     case AMG_ERR_NOMEM: return "out of memory";
     case AMG_ERR_DEVICE: return "HIP device error";
     case AMG_ERR_UNSUPPORTED: return "unsupported parameter combination";
+    case AMG_ERR_MODEL: return "learned smooth vector unusable (relaxation used instead)";
     default: return "unknown status";
   }
 }
@@ -315,6 +319,7 @@ int amg_info(const amg_hierarchy *h, amg_info_t *out) {
   out->nrates = static_cast<int32_t>(std::min<size_t>(h->rates.size(), AMG_MAX_HRC));
   for (int j = 0; j < out->nrates; ++j) out->rates[j] = h->rates[j];
   out->setup_bootstrap_ms = h->tm.bootstrap_ms;
+  out->smooth_status = h->smooth_status;
   return AMG_OK;
 }
 

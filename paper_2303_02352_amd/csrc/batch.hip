@@ -1055,6 +1055,7 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
     for (std::thread &th : pool) th.join();
   }
   if (first.code != AMG_OK) fail(first.code, first.msg);
+  bt->p.model_params = nullptr;
   // deepest systems first (stable): active systems on any level form a prefix
   std::vector<int> order(nsys);
   std::iota(order.begin(), order.end(), 0);
@@ -1327,7 +1328,7 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   amg_batch *bt = new (std::nothrow) amg_batch();
   if (!bt) return amg::api_set_error(AMG_ERR_NOMEM, "host allocation failed");
   bt->p = *p;
-  bt->p.smooth_vector = nullptr;
+  bt->p.smooth_vector = nullptr;   // (model_params stays valid while amg_batch_setup runs)
   if (p->stream) {
     bt->stream = static_cast<hipStream_t>(p->stream);
   } else {

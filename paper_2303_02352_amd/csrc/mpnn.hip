@@ -400,7 +400,8 @@ __global__ void k_pack_weights(const float *__restrict__ theta, bf16 *__restrict
 struct amg_mpnn {
   hipStream_t stream = nullptr;
   int own_stream = 0;
-  int cap = 0;                      // rows the work buffers hold
+  int cap = 0;                      // rows the forward buffers hold
+  int cap_train = 0;                // rows the backward buffers hold
   int step = 0;
   amg::dvec<float> theta, m1, m2, grad;
   amg::dvec<unsigned short> Wt1, Wt2;
@@ -412,16 +413,25 @@ struct amg_mpnn {
 namespace amg {
 namespace {
 
+// Forward buffers (features, activations, prediction) for n rows; the
+// backward pass's buffers only when training.
 void mpnn_reserve(amg_mpnn *m, int n) {
   if (n <= m->cap) return;
   const size_t N = static_cast<size_t>(n);
   m->X0.alloc(N * kF0); m->N0.alloc(N * kF0);
   m->h1.alloc(N * kHid); m->N1.alloc(N * kHid); m->h2.alloc(N * kHid);
-  m->s.alloc(N); m->y.alloc(N); m->dy.alloc(N); m->w1.alloc(N);
+  m->s.alloc(N); m->y.alloc(N); m->w1.alloc(N);
+  m->cap = n;
+}
+
+void mpnn_reserve_train(amg_mpnn *m, int n) {
+  if (n <= m->cap_train) return;
+  const size_t N = static_cast<size_t>(n);
+  m->dy.alloc(N);
   m->G2.alloc(N * kHid); m->dself.alloc(N * kHid); m->dneigh.alloc(N * kHid); m->G1.alloc(N * kHid);
   const size_t nb = (N + kRowsDW - 1) / kRowsDW;
   m->part.alloc(std::max<size_t>(nb * (64 + 3) * kHid, (N + kBlock - 1) / kBlock));
-  m->cap = n;
+  m->cap_train = n;
 }
 
 void check_csr(const amg_csr *A) {
@@ -453,6 +463,7 @@ void mpnn_forward(amg_mpnn *m, const amg_csr *A, double *w_out) {
 float mpnn_train(amg_mpnn *m, const amg_csr *A, const double *wt, float lr, float *grad_host) {
   hipStream_t s = m->stream;
   const int n = A->n;
+  mpnn_reserve_train(m, n);
   mpnn_forward(m, A, nullptr);
   const int *rp = A->row_ptr, *ci = A->col_idx;
   const double *v = A->val;

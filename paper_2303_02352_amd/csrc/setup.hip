@@ -266,6 +266,12 @@ __global__ void k_check_finite(int n, const double *x, int *flag) {
   if (i < n && !isfinite(x[i])) atomicOr(flag, 1);
 }
 
+// flag unless every entry is finite and positive (a usable learned vector)
+__global__ void k_check_usable(int n, const double *x, int *flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(isfinite(x[i]) && x[i] > 0.0)) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------- matching weights
 // w_hat = 1 - 2 a_ij w_i w_j / (a_ii w_i^2 + a_jj w_j^2), evaluated with
 // i = min(row, col) so both stored copies of an edge get the same bits:
@@ -1796,6 +1802,33 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   AMG_HIP(hipStreamSynchronize(s));
   const double t_w = now_ms();
   L0.w.alloc(n);
+  // The learned vector (the network's prediction from the fine matrix) is
+  // used when every entry is finite and positive; otherwise the setup falls
+  // back to relaxation and records AMG_ERR_MODEL in amg_info.smooth_status.
+  bool relax = (P.smooth_vec == AMG_SMOOTH_RELAX);
+  h->smooth_status = AMG_OK;
+  if (P.smooth_vec == AMG_SMOOTH_LEARNED) {
+    amg_mpnn *m = nullptr;
+    int st = amg_mpnn_create(P.model_params, s, &m);
+    if (st == AMG_OK) {
+      const amg_csr Adev{n, L0.A.nnz, L0.A.rp.p, L0.A.ci.p, L0.A.v.p, 1};
+      st = amg_mpnn_predict(m, &Adev, L0.w.p, nullptr);
+    }
+    amg_mpnn_destroy(m);
+    if (st == AMG_OK) {
+      dvec<int> flag(1);
+      AMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+      hipLaunchKernelGGL(k_check_usable, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, flag.p);
+      AMG_LAUNCH_CHECK();
+      if (read_int(flag.p, s)) st = AMG_ERR_MODEL;
+    } else if (st == AMG_ERR_NOMEM || st == AMG_ERR_DEVICE) {
+      fail(st, "learned smooth vector: " + api_last_error());
+    }
+    if (st != AMG_OK) {
+      h->smooth_status = AMG_ERR_MODEL;
+      relax = true;
+    }
+  }
   if (P.smooth_vec == AMG_SMOOTH_GIVEN) {
     AMG_HIP(hipMemcpyAsync(L0.w.p, P.smooth_vector, sizeof(double) * n, kind, s));
     dvec<int> flag(1);
@@ -1803,10 +1836,10 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
     hipLaunchKernelGGL(k_check_finite, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, flag.p);
     AMG_LAUNCH_CHECK();
     if (read_int(flag.p, s)) fail(AMG_ERR_NONFINITE, "non-finite smooth vector");
-  } else {
+  } else if (P.smooth_vec != AMG_SMOOTH_LEARNED || relax) {
     hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kBlock), 0, s, n, L0.w.p, 1.0);
     AMG_LAUNCH_CHECK();
-    if (P.smooth_vec == AMG_SMOOTH_RELAX) {
+    if (relax) {
       dvec<double> t(n), zero(n);
       AMG_HIP(hipMemsetAsync(zero.p, 0, sizeof(double) * n, s));
       for (int it = 0; it < P.smooth_sweeps; ++it) {

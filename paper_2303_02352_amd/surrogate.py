@@ -5,7 +5,10 @@ matching weights of the coarsening (Sec. 3.1 leaves the smooth vector's source
 open).  Training targets are the method's own relaxation vectors: 20 l1-Jacobi
 sweeps on A w = 0 from ones (AMG_SMOOTH_RELAX), computed by the library.
 All arithmetic runs in the library's HIP kernels; this module only moves
-arrays and loops over training steps.
+arrays and loops over training steps.  A trained parameter set is used by
+passing it to amg_setup (``Hierarchy(..., model_params=params)``,
+AMG_SMOOTH_LEARNED): the library predicts the vector, checks it and falls
+back to relaxation by itself.
 
 Command line (writes the model file used by bench.py):
     python -m paper_2303_02352_amd.surrogate --out paper_2303_02352_amd/models/mpnn_lognormal.json
@@ -64,16 +67,6 @@ def train(net, data, steps, lr, log_every=50, lr_final=None):
     return hist
 
 
-def learned_smooth_vector(net, csr, torch):
-    """Predicted smooth vector (device float64) or None when it is unusable
-    (non-finite or non-positive): the caller then falls back to relaxation."""
-    rp, ci, va = csr
-    w = torch.empty(int(rp.shape[0]) - 1, dtype=torch.float64, device="cuda")
-    net.predict(rp, ci, va, w_out=w)
-    ok = bool(torch.isfinite(w).all().item()) and bool((w > 0).all().item())
-    return w if ok else None
-
-
 def save(path, params, meta):
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as f:
@@ -96,6 +89,8 @@ def main():
     ap.add_argument("--small", type=int, default=16, help="training fields at 64^3")
     ap.add_argument("--large", type=int, default=2, help="training fields at 128^3")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--relax-sweeps", type=int, default=RELAX_SWEEPS,
+                    help="relaxation sweeps of the training targets")
     args = ap.parse_args()
     t0 = time.time()
     data, seeds = [], []
@@ -106,7 +101,7 @@ def main():
     for N, sd in seeds:
         A = W.lognormal7(N, sd)
         csr = device_csr(A, torch)
-        data.append(csr + (relax_target(csr, torch),))
+        data.append(csr + (relax_target(csr, torch, args.relax_sweeps),))
         print("[surrogate] field %d^3 seed %d ready" % (N, sd), flush=True)
     t1 = time.time()
     net = amd.SmoothVectorNet(init_params(args.seed))
@@ -114,9 +109,10 @@ def main():
     torch.cuda.synchronize()
     t2 = time.time()
     meta = dict(fields=seeds, steps=args.steps, lr=args.lr, lr_final=args.lr_final,
-                relax_sweeps=RELAX_SWEEPS, sigma2=2.0, ell=8.0, final_loss=hist[-1],
+                relax_sweeps=args.relax_sweeps, sigma2=2.0, ell=8.0, final_loss=hist[-1],
                 first_loss=hist[0], data_s=t1 - t0, train_s=t2 - t1,
-                note="targets: 20 l1-Jacobi sweeps on A w = 0 from ones; loss: MSE of log w")
+                note="targets: %d l1-Jacobi sweeps on A w = 0 from ones; loss: MSE of log w"
+                     % args.relax_sweeps)
     save(args.out, net.params(), meta)
     print(json.dumps(meta), flush=True)
 

@@ -118,9 +118,11 @@ def test_training_lowers_loss_and_vector_drives_hierarchy():
     assert np.mean(hist[-10:]) < 0.5 * np.mean(hist[:10])
     A = W.lognormal7(16, 32, ell=4.0)
     csr = surrogate.device_csr(A, torch)
-    w = surrogate.learned_smooth_vector(net, csr, torch)
-    assert w is not None
-    H = amd.Hierarchy(*csr, smooth_vector=w)
+    w = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    net.predict(*csr, w_out=w)
+    assert bool(torch.isfinite(w).all()) and bool((w > 0).all())
+    H = amd.Hierarchy(*csr, model_params=net.params())
+    assert H.info()["smooth_status"] == amd.AMG_OK
     xs, b = W.manufactured_rhs(A, 1)
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     st, it, rel = H.solve(dev(b), x)
@@ -128,3 +130,49 @@ def test_training_lowers_loss_and_vector_drives_hierarchy():
     # the learned vector goes through the same setup as any other: oracle parity
     Ho = oracle.Hierarchy(A, oracle.AMGParams(smooth_vec=2), w=host(w))
     assert H.info()["n"] == [s[0] for s in Ho.sizes()]
+
+
+def _levels_equal(H1, H2):
+    assert H1.info()["n"] == H2.info()["n"]
+    for k in range(H1.info()["levels"]):
+        a, b = H1.export_level(k), H2.export_level(k)
+        for f in ("row_ptr", "col", "agg"):
+            assert (a[f] is None and b[f] is None) or np.array_equal(a[f], b[f]), (k, f)
+        for f in ("val", "w", "pval", "dinv"):
+            if a[f] is not None:
+                assert np.array_equal(a[f].view(np.uint64), b[f].view(np.uint64)), (k, f)
+
+
+def test_learned_mode_through_the_c_abi():
+    """AMG_SMOOTH_LEARNED in amg_setup: the same hierarchy as AMG_SMOOTH_GIVEN
+    with the network's prediction, and smooth_status OK."""
+    import paper_2303_02352_amd as amd
+    from paper_2303_02352_amd import surrogate
+    A = W.lognormal7(24, 7, ell=4.0)
+    rp, ci, va = dev(A.row_ptr), dev(A.col), dev(A.val)
+    params, meta = surrogate.load_params()
+    net = amd.SmoothVectorNet(params)
+    w = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    net.predict(rp, ci, va, w_out=w)
+    Hg = amd.Hierarchy(rp, ci, va, smooth_vector=w)
+    Hl = amd.Hierarchy(rp, ci, va, model_params=params)
+    assert Hl.info()["smooth_status"] == amd.AMG_OK
+    _levels_equal(Hl, Hg)
+
+
+@pytest.mark.parametrize("bias", [1e30, -1e30])
+def test_learned_mode_falls_back_to_relaxation(bias):
+    """A parameter set whose prediction overflows (w = inf) or underflows
+    (w = 0): amg_setup succeeds with the relaxation vector and reports
+    AMG_ERR_MODEL in smooth_status; the hierarchy is the RELAX one bit for bit."""
+    import paper_2303_02352_amd as amd
+    A = W.lognormal7(16, 5, ell=4.0)
+    rp, ci, va = dev(A.row_ptr), dev(A.col), dev(A.val)
+    theta = np.zeros(amd.AMG_MPNN_NPARAMS, np.float32)
+    theta[-1] = bias
+    Hl = amd.Hierarchy(rp, ci, va, model_params=theta, smooth_sweeps=20)
+    Hr = amd.Hierarchy(rp, ci, va, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20)
+    inf = Hl.info()
+    say("fallback bias %g: smooth_status %d" % (bias, inf["smooth_status"]))
+    assert inf["smooth_status"] == amd.AMG_ERR_MODEL
+    _levels_equal(Hl, Hr)

@@ -43,7 +43,12 @@ def test_bad_csr_header_is_invalid(n, nnz, arrays):
                                          ("coarse_sweeps", 0), ("pre_sweeps", -1), ("post_sweeps", -1),
                                          ("smooth_sweeps", -1), ("coarse_solver", 7), ("smooth_vec", 5),
                                          ("smooth_vec", amd.AMG_SMOOTH_GIVEN), ("precision", 3),
-                                         ("precond", 2), ("value_coding", 2), ("value_coding", -1)])
+                                         ("precond", 2), ("value_coding", 2), ("value_coding", -1),
+                                         ("smooth_vec", amd.AMG_SMOOTH_LEARNED), ("n_parts", 0),
+                                         ("n_parts", 2 ** 24 + 1), ("cycle_type", 3), ("relax_type", 2),
+                                         ("coarse_relax", 5), ("max_hrc", 0), ("max_hrc", 17),
+                                         ("bootstrap_type", 3), ("bootstrap_its", 0),
+                                         ("bootstrap_rate", 0.0), ("bootstrap_rate", 1.5)])
 def test_bad_parameter_is_invalid(field, value):
     A, keep = _csr(1, 1)
     p = amd.default_params()
@@ -57,6 +62,26 @@ def test_default_parameters():
     p = amd.default_params()
     assert (p.aggr_steps, p.max_levels, p.coarse_max, p.pre_sweeps, p.post_sweeps) == (2, 40, 100, 4, 4)
     assert p.value_coding == amd.AMG_VALUES_AUTO and p.precision == amd.AMG_PREC_DOUBLE
+    assert (p.n_parts, p.cycle_type, p.relax_type, p.coarse_relax) == (1, amd.AMG_CYCLE_V,
+                                                                      amd.AMG_RELAX_L1_JACOBI,
+                                                                      amd.AMG_RELAX_L1_JACOBI)
+    assert (p.max_hrc, p.bootstrap_type, p.bootstrap_its, p.bootstrap_seed) == (1, amd.AMG_BOOTSTRAP_MULT, 15, 1)
+    assert p.bootstrap_rate == 0.8 and not p.model_params and not p.smooth_vector
+
+
+def test_binary32_cycle_with_other_options_is_unsupported():
+    A, keep = _csr(1, 1)
+    for field, value in (("cycle_type", amd.AMG_CYCLE_W), ("relax_type", amd.AMG_RELAX_GS),
+                         ("coarse_relax", amd.AMG_RELAX_SYM_GS)):
+        p = amd.default_params(precision=amd.AMG_PREC_MIXED)
+        setattr(p, field, value)
+        st, h = _setup(A, p)
+        assert st == amd.AMG_ERR_UNSUPPORTED and not h.value, field
+
+
+def test_unknown_parameter_name_is_refused():
+    with pytest.raises(TypeError):
+        amd.default_params(n_part=2)
 
 
 def test_null_arguments():
@@ -73,7 +98,8 @@ def test_null_arguments():
 def test_status_strings_cover_every_code():
     L = amd.load()
     codes = [amd.AMG_OK, amd.AMG_NOT_CONVERGED, amd.AMG_ERR_INVALID, amd.AMG_ERR_NOT_SPD,
-             amd.AMG_ERR_NONFINITE, amd.AMG_ERR_NOMEM, amd.AMG_ERR_DEVICE, amd.AMG_ERR_UNSUPPORTED]
+             amd.AMG_ERR_NONFINITE, amd.AMG_ERR_NOMEM, amd.AMG_ERR_DEVICE, amd.AMG_ERR_UNSUPPORTED,
+             amd.AMG_ERR_MODEL]
     msgs = [L.amg_strerror(c).decode() for c in codes]
     assert all(msgs) and len(set(msgs)) == len(codes)
 
