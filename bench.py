@@ -391,6 +391,8 @@ def main():
     ap.add_argument("--only", choices=["batched", "mixed27", "learned", "paper", "mixed160",
                                        "decoupled_weak", "bootstrap", "cycles"],
                     help="only: run one form's leg and print its record (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="with --only: copy 1 GiB device to device after the leg (counter calibration)")
     ap.add_argument("--kernel-profile", action="store_true",
                     help="only: build the 160^3 hierarchy, launch the fine-level sweep "
                          "--kernel-reps times, then copy 1 GiB (counter calibration)")
@@ -413,7 +415,14 @@ def main():
                    decoupled_weak=decoupled_weak_leg, bootstrap=bootstrap_leg,
                    cycles=cycles_leg)[args.only]
         log("only", args.only)
-        print(json.dumps({"form": args.only, "record": leg(amd, torch, W, np, dev)}), flush=True)
+        rec = leg(amd, torch, W, np, dev)
+        if args.calibrate_copy:   # a 1 GiB device copy after the leg (counter calibration)
+            src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            rec["calibration_copy_bytes"] = src.numel() * 8
+        print(json.dumps({"form": args.only, "record": rec}), flush=True)
         return
     log("generating 160^3 Poisson")
     A = W.poisson7(N_EDGE)
