@@ -438,11 +438,17 @@ __global__ void __launch_bounds__(kBlock) k_bprolong(const int *skip, int n,
   }
 }
 
-// Terminal systems: z = A_c^-1 r, one workgroup per system, binary64 fold
-// over j ascending (column-major inverse), NR columns at once.
-// Systems of up to kBCoarseLds coarsest rows first copy the inverse and the
-// right-hand sides into LDS (same fold, same bits).
-constexpr int kBCoarseLds = 100;
+// Terminal systems: z = A_c^-1 r for all NR right-hand sides at once, one
+// workgroup per system: the dense n x n inverse (column-major) times the
+// n x NR block of right-hand sides, the one dense product of the method,
+// on the FP64 matrix cores.  Each wavefront computes 16-row tiles of z with
+// v_mfma_f64_16x16x4f64 over k in steps of 4: lane l supplies
+// A[i0 + l % 16][k0 + l / 16] and R[k0 + l / 16][l % 16] and receives
+// z[i0 + 4 q + l / 16][l % 16] in accumulator q (rows past n and columns
+// past NR are zero-padded and not stored).  The sums round in the matrix
+// core's order rather than the sequential fold's (relative difference of
+// the order of the binary64 unit).
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <class T, int NR>
 __global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *__restrict__ toff,
@@ -451,31 +457,26 @@ __global__ void __launch_bounds__(kBlock) k_bcoarse(const int *skip, const int *
                                                     const double *__restrict__ pool,
                                                     const T *__restrict__ rhs, T *__restrict__ out) {
   AMG_SKIP_IF_DONE();
-  __shared__ double sA[kBCoarseLds * kBCoarseLds];
-  __shared__ double sR[kBCoarseLds * NR];
   const int sys = blockIdx.x;
   const int off = toff[sys], n = tn[sys];
   const double *Ai = pool + tinv[sys];
-  if (n <= kBCoarseLds) {
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) sA[e] = Ai[e];
-    for (int e = threadIdx.x; e < n * NR; e += blockDim.x)
-      sR[e] = static_cast<double>(rhs[static_cast<int64_t>(off) * NR + e]);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * NR; e += blockDim.x) {
-      const int i = e / NR, c = e % NR;
-      double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc = acc + sA[j * n + i] * sR[j * NR + c];
-      out[static_cast<int64_t>(off + i) * NR + c] = static_cast<T>(acc);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int li = lane % 16, lk = lane / 16;
+  const int ntile = (n + 15) / 16;
+  for (int tile = wave; tile < ntile; tile += kBlock / kWave) {
+    const int i = tile * 16 + li;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int k = k0 + lk;
+      const double a = (i < n && k < n) ? Ai[static_cast<int64_t>(k) * n + i] : 0.0;
+      const double b = (k < n && li < NR) ? static_cast<double>(rhs[static_cast<int64_t>(off + k) * NR + li]) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
-    return;
-  }
-  for (int e = threadIdx.x; e < n * NR; e += blockDim.x) {
-    const int i = e / NR, c = e % NR;
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j)
-      acc = acc + Ai[static_cast<int64_t>(j) * n + i] *
-                      static_cast<double>(rhs[static_cast<int64_t>(off + j) * NR + c]);
-    out[static_cast<int64_t>(off + i) * NR + c] = static_cast<T>(acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = tile * 16 + 4 * q + lk;
+      if (row < n && li < NR) out[static_cast<int64_t>(off + row) * NR + li] = static_cast<T>(acc[q]);
+    }
   }
 }
 

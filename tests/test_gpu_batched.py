@@ -2,7 +2,9 @@
 
 Every (system, right-hand side) pair must behave as its own single-system
 solve: the batched V-cycle column equals the oracle's V-cycle of that system
-(binary64: <= 1e-12 relative, bit-exact expected; mixed: against the oracle's
+(binary64: <= 1e-12 relative; the coarsest block product runs on the FP64
+matrix cores, whose sums round in their own order, so the columns agree to
+the binary64 unit rather than bit for bit; mixed: against the oracle's
 binary32 cycle, <= 1e-6), and the batched PCG reaches rtol with the oracle's
 iteration count +-1 for every pair.  The batch mixes grid edges so that
 systems have different depths, one system is a single level, and one edge is
