@@ -298,6 +298,9 @@ typedef struct {
   int64_t nnz[AMG_MAX_LEVELS];
   int32_t cols_per_lane[AMG_MAX_LEVELS];  /* tuned: lanes per row = nrhs / cols_per_lane */
   double setup_ms, tune_ms;
+  int32_t cols_per_lane_corr[AMG_MAX_LEVELS];  /* tuned, for the sweep that adds the coarse correction */
+  int32_t tile_rows;                  /* tuned rows per reduction tile of the level-0 PCG kernels */
+  int32_t spmm_cols;                  /* tuned right-hand-side columns per thread of the level-0 SpMM + dots */
 } amg_batch_info_t;
 
 /* Build the hierarchies of nsys systems A[0..nsys-1] (same parameters for

@@ -61,7 +61,8 @@ class amg_batch_info_t(C.Structure):
     _fields_ = [("nsys", C.c_int32), ("levels", C.c_int32), ("n", C.c_int32 * AMG_MAX_LEVELS),
                 ("n_smoothed", C.c_int32 * AMG_MAX_LEVELS), ("nnz", C.c_int64 * AMG_MAX_LEVELS),
                 ("cols_per_lane", C.c_int32 * AMG_MAX_LEVELS), ("setup_ms", C.c_double),
-                ("tune_ms", C.c_double)]
+                ("tune_ms", C.c_double), ("cols_per_lane_corr", C.c_int32 * AMG_MAX_LEVELS),
+                ("tile_rows", C.c_int32), ("spmm_cols", C.c_int32)]
 
 
 EXPORTS = {
@@ -441,6 +442,8 @@ class Batch:
         L = inf.levels
         return dict(nsys=inf.nsys, levels=L, n=list(inf.n[:L]), n_smoothed=list(inf.n_smoothed[:L]),
                     nnz=list(inf.nnz[:L]), cols_per_lane=list(inf.cols_per_lane[:L]),
+                    cols_per_lane_corr=list(inf.cols_per_lane_corr[:L]), tile_rows=inf.tile_rows,
+                    spmm_cols=inf.spmm_cols,
                     setup_ms=inf.setup_ms, tune_ms=inf.tune_ms)
 
 

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -33,10 +34,9 @@
 namespace amg {
 namespace {
 
-#ifndef AMG_BATCH_TILE
-#define AMG_BATCH_TILE 256
-#endif
-constexpr int kBTile = AMG_BATCH_TILE;   // rows per reduction tile of the level-0 PCG kernels
+// Rows per reduction tile of the level-0 PCG kernels: tuned per batch and
+// right-hand-side count among these (the first one before tuning).
+constexpr int kBTiles[] = {256, 128, 512, 1024};
 
 struct BScalars {
   double rho, c, a, rr, nr0, thr;
@@ -53,6 +53,7 @@ struct BLevel {
   dvec<long long> term_inv;     // offset of each inverse in inv_pool
   dvec<double> inv_pool;        // column-major inverses of the coarsest matrices
   int cpl = 1;                  // tuned columns per lane (sweeps / residual)
+  int cpl_corr = 1;             // tuned columns per lane of the corrected sweep
   int tune_best = 1;
   // RHS-interleaved work vectors
   dvec<double> r, x, t;
@@ -81,10 +82,38 @@ inline dim3 grid_for(int64_t n, int block = kBlock) {
 #endif
 constexpr int kMaxGrid = AMG_BATCH_MAX_GRID;
 
-inline dim3 vgrid(int64_t threads) {
-  const int64_t nvb = std::max<int64_t>(1, (threads + kBlock - 1) / kBlock);
-  return dim3(static_cast<unsigned>(std::min<int64_t>(nvb, kMaxGrid)));
+// Grid of a virtual-block kernel: the workgroups that fit on the device at
+// once (the kernel's occupancy times the compute units, at most kMaxGrid),
+// so that the rounds of vspan are walked by resident workgroups only and the
+// rows in flight form one moving window per XCD.
+template <class K>
+int resident_workgroups(K kern) {
+  struct Entry {
+    const void *kern;
+    int dev, grid;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  const void *key = reinterpret_cast<const void *>(kern);
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  for (const Entry &e : cache)
+    if (e.kern == key && e.dev == dev) return e.grid;
+  int cus = 0, occ = 0;
+  AMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  AMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlock, 0));
+  const int g = std::max(kXcd, std::min(kMaxGrid, occ * cus));
+  cache.push_back(Entry{key, dev, g});
+  return g;
 }
+
+template <class K>
+dim3 rgrid(K kern, int64_t threads) {
+  const int64_t nvb = std::max<int64_t>(1, (threads + kBlock - 1) / kBlock);
+  return dim3(static_cast<unsigned>(std::min<int64_t>(nvb, resident_workgroups(kern))));
+}
+
 
 struct VSpan {
   int64_t b, e, step;
@@ -586,14 +615,16 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
   if (threadIdx.x < NR) part[(static_cast<int64_t>(tile) * NR + threadIdx.x) * 3] = t;
 }
 
-template <int NR>
+// PC columns per thread (tuned: fewer columns hold fewer gathered values in
+// registers and let more waves run).
+template <int NR, int PC>
 __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
     const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ sptr, const int *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
     double *__restrict__ v, double *__restrict__ part) {
   AMG_SKIP_IF_DONE();
-  constexpr int PC = pcg_cols<NR>(), LPR = NR / PC;
+  constexpr int LPR = NR / PC;
   __shared__ double red[kBlock * PC];
   const int cb = (threadIdx.x % LPR) * PC;
   const VSpan sp = vspan(static_cast<int64_t>(ntiles) * kBlock);
@@ -811,7 +842,9 @@ struct amg_batch {
   std::vector<int64_t> n0;             // level-0 rows per user system
   std::vector<int64_t> user_off, int_off;   // level-0 row offsets (user order / internal order)
   std::vector<amg::BLevel> B;
-  int ntiles = 0;
+  std::vector<int64_t> roff0;          // level-0 row offsets per internal position
+  int ntiles = 0, tile_rows = 0, max_tiles = 0;
+  int spmm_cols = 1;                   // tuned columns per thread of the level-0 SpMM + dots
   amg::dvec<int> trow0, trow1, tsys, tile_ptr;
   // per-nrhs state
   int nr = 0;
@@ -851,7 +884,7 @@ template <> const float *bpval<float>(const Level &L) { return L.pvalf.p; }
 template <class T, int NR, int CPL>
 void launch_bsweep(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), rgrid((k_bsweep<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
                      s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn);
 }
 
@@ -859,14 +892,14 @@ template <int NR, int CPL>
 void launch_bsweep_widen(const int *skip, BLevel &L, int n, const float *rhs, const float *x,
                          double *xn, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep<float, NR, CPL, double>), vgrid(static_cast<int64_t>(n) * LPR),
+  hipLaunchKernelGGL((k_bsweep<float, NR, CPL, double>), rgrid((k_bsweep<float, NR, CPL, double>), static_cast<int64_t>(n) * LPR),
                      dim3(kBlock), 0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, L.L.S.valf.p, rhs, x, xn);
 }
 
 template <class T, int NR, int CPL>
 void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), rgrid((k_bresid<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
                      s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t);
 }
 
@@ -874,7 +907,7 @@ template <class T, int NR, int CPL>
 void launch_bsweep_corr(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
                         hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), vgrid(static_cast<int64_t>(n) * LPR), dim3(kBlock),
+  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), rgrid((k_bsweep_corr<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock),
                      0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p,
                      bpval<T>(L.L), e, xn);
 }
@@ -893,7 +926,7 @@ void with_cpl(int cpl, F &&f) {
 template <class T, int NR>
 void corr_sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
                     hipStream_t s) {
-  with_cpl<NR>(L.cpl, [&](auto C) { launch_bsweep_corr<T, NR, decltype(C)::value>(skip, L, n, rhs, e, x, xn, s); });
+  with_cpl<NR>(L.cpl_corr, [&](auto C) { launch_bsweep_corr<T, NR, decltype(C)::value>(skip, L, n, rhs, e, x, xn, s); });
 }
 
 template <class T, int NR>
@@ -939,22 +972,22 @@ bool bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, 
   T *A = (swaps % 2 == 0) ? out : bv_t<T>(L);
   T *Bf = (A == out) ? bv_t<T>(L) : out;
   if (P.pre_sweeps == 0) {
-    hipLaunchKernelGGL(k_bzero<T>, vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_bzero<T>, rgrid(k_bzero<T>, static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
                        static_cast<int64_t>(nc0) * NR, A);
   } else {
     if (!first_done)
-      hipLaunchKernelGGL((k_bsweep_first<T, NR>), vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock),
+      hipLaunchKernelGGL((k_bsweep_first<T, NR>), rgrid((k_bsweep_first<T, NR>), static_cast<int64_t>(nc0) * NR), dim3(kBlock),
                          0, s, skip, nc0, bdinv<T>(L.L), rhs, A);
     for (int qq = 1; qq < P.pre_sweeps; ++qq) { sweep_any<T, NR>(skip, L, nc0, rhs, A, Bf, s); std::swap(A, Bf); }
   }
   resid_any<T, NR>(skip, L, nc0, rhs, A, Bf, s);
   BLevel &C = bt->B[k + 1];
   T *xc = bfirst<T>(bt, k + 1, bv_x<T>(C));
-  hipLaunchKernelGGL((k_bagg<T, NR>), vgrid(static_cast<int64_t>(C.n) * (NR / agg_cols<NR>())), dim3(kBlock), 0, s, skip,
+  hipLaunchKernelGGL((k_bagg<T, NR>), rgrid((k_bagg<T, NR>), static_cast<int64_t>(C.n) * (NR / agg_cols<NR>())), dim3(kBlock), 0, s, skip,
                      C.n, L.L.mptr.p, L.L.mem.p, Bf, bv_r<T>(C), bdinv<T>(C.L), xc);
   (void)bvcycle_level<T, NR>(bt, skip, k + 1, bv_r<T>(C), bv_x<T>(C), xc != nullptr);
   if (P.post_sweeps == 0) {
-    hipLaunchKernelGGL((k_bprolong<T, NR>), vgrid(static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_bprolong<T, NR>), rgrid((k_bprolong<T, NR>), static_cast<int64_t>(nc0) * NR), dim3(kBlock), 0, s,
                        skip, nc0, L.L.agg.p, bpval<T>(L.L), bv_x<T>(C), A);
     return false;
   }
@@ -983,12 +1016,12 @@ void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
   if (bt->p.precision == AMG_PREC_MIXED) {
     BLevel &L = bt->B[0];
     float *x1 = bfirst<float>(bt, 0, L.xf.p);
-    hipLaunchKernelGGL((k_bd2f_first<NR>), vgrid(m), dim3(kBlock), 0, s, m,
+    hipLaunchKernelGGL((k_bd2f_first<NR>), rgrid((k_bd2f_first<NR>), m), dim3(kBlock), 0, s, m,
                        static_cast<int64_t>(L.n_cont) * NR, r, L.L.dinvf.p, L.rf.p, x1, skip);
     const bool widened = bvcycle_level<float, NR>(bt, skip, 0, L.rf.p, L.xf.p, x1 != nullptr, z);
     // rows the last sweep did not write (all rows, or those of single-level
     // systems, which the binary64 solve below overwrites anyway)
-    if (!widened) hipLaunchKernelGGL(k_bf2d, vgrid(m), dim3(kBlock), 0, s, m, L.xf.p, z, skip);
+    if (!widened) hipLaunchKernelGGL(k_bf2d, rgrid(k_bf2d, m), dim3(kBlock), 0, s, m, L.xf.p, z, skip);
     // single-level systems: their whole cycle is the binary64 direct solve
     if (L.nterm > 0)
       hipLaunchKernelGGL((k_bcoarse<double, NR>), dim3(L.nterm), dim3(kBlock), 0, s, skip,
@@ -999,22 +1032,37 @@ void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
   AMG_LAUNCH_CHECK();
 }
 
+template <int NR, int PC>
+void launch_spmm_dots_pc(amg_batch *bt, const int *skip) {
+  const BLevel &L0 = bt->B[0];
+  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR, PC>), rgrid((k_bpcg_spmm_dots<NR, PC>), static_cast<int64_t>(bt->ntiles) * kBlock),
+                     dim3(kBlock), 0, bt->stream, skip, bt->ntiles, bt->trow0.p, bt->trow1.p, L0.L.S.sptr.p,
+                     L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p, bt->v.p, bt->partials.p);
+}
+
+template <int NR>
+void launch_spmm_dots(amg_batch *bt, const int *skip) {
+  if constexpr (NR % 4 == 0) if (bt->spmm_cols == 4) return launch_spmm_dots_pc<NR, 4>(bt, skip);
+  if constexpr (NR % 2 == 0) if (bt->spmm_cols == 2) return launch_spmm_dots_pc<NR, 2>(bt, skip);
+  launch_spmm_dots_pc<NR, 1>(bt, skip);
+}
+
+template <int NR>
+void launch_update(amg_batch *bt, const int *skip) {
+  hipLaunchKernelGGL((k_bpcg_update<NR>), rgrid((k_bpcg_update<NR>), static_cast<int64_t>(bt->ntiles) * kBlock),
+                     dim3(kBlock), 0, bt->stream, skip, bt->ntiles, bt->trow0.p, bt->trow1.p, bt->tsys.p,
+                     bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p, bt->sc.p, bt->partials.p);
+}
+
 template <int NR>
 void benqueue_iteration(amg_batch *bt, int maxit) {
   hipStream_t s = bt->stream;
-  const BLevel &L0 = bt->B[0];
   const int *skip = bt->all_done.p;
   bvcycle<NR>(bt, skip, bt->r.p, bt->w.p);
-  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR>), vgrid(static_cast<int64_t>(bt->ntiles) * kBlock), dim3(kBlock), 0,
-                     s, skip, bt->ntiles, bt->trow0.p,
-                     bt->trow1.p, L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p,
-                     bt->v.p, bt->partials.p);
+  launch_spmm_dots<NR>(bt, skip);
   hipLaunchKernelGGL((k_bpcg_dots_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, skip,
                      bt->tile_ptr.p, bt->partials.p, bt->sc.p);
-  hipLaunchKernelGGL((k_bpcg_update<NR>), vgrid(static_cast<int64_t>(bt->ntiles) * kBlock), dim3(kBlock), 0,
-                     s, skip, bt->ntiles, bt->trow0.p,
-                     bt->trow1.p, bt->tsys.p, bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p,
-                     bt->sc.p, bt->partials.p);
+  launch_update<NR>(bt, skip);
   hipLaunchKernelGGL((k_bpcg_norm_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, skip,
                      bt->tile_ptr.p, bt->partials.p, bt->sc.p, maxit, bt->active.p);
   hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p,
@@ -1023,36 +1071,105 @@ void benqueue_iteration(amg_batch *bt, int maxit) {
 }
 
 // Time the sweep variants on every level with active smoothing rows and keep
-// the fastest columns-per-lane (rows per wave = 64 / (NR / cpl)).
+// the fastest columns-per-lane (rows per wave = 64 / (NR / cpl)); the
+// corrected sweep (which also gathers P values, aggregate ids and the
+// coarse correction) is timed and chosen on its own.
+// Time of five back-to-back runs of launch() on s, after one warm run.
+struct LaunchTimer {
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  explicit LaunchTimer(hipStream_t st) : s(st) {
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+  }
+  ~LaunchTimer() {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  LaunchTimer(const LaunchTimer &) = delete;
+  LaunchTimer &operator=(const LaunchTimer &) = delete;
+  template <class F>
+  float operator()(F &&launch) {
+    launch();
+    AMG_HIP(hipEventRecord(e0, s));
+    for (int q = 0; q < 5; ++q) launch();
+    AMG_HIP(hipEventRecord(e1, s));
+    AMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  }
+};
+
 template <class T, int NR>
 void autotune(amg_batch *bt) {
   hipStream_t s = bt->stream;
-  hipEvent_t e0, e1;
-  AMG_HIP(hipEventCreate(&e0));
-  AMG_HIP(hipEventCreate(&e1));
-  for (auto &L : bt->B) {
-    L.cpl = 1;
+  LaunchTimer time5(s);
+  for (size_t k = 0; k < bt->B.size(); ++k) {
+    BLevel &L = bt->B[k];
+    L.cpl = L.cpl_corr = 1;
     if (L.n_cont == 0 || NR == 1) continue;
     const int64_t m = static_cast<int64_t>(L.n) * NR;
     T *x = bv_x<T>(L), *t = bv_t<T>(L), *r = bv_r<T>(L);
-    for (T *p : {x, t, r}) hipLaunchKernelGGL(k_bzero<T>, vgrid(m), dim3(kBlock), 0, s, m, p);
-    float best = 1e30f;
+    for (T *p : {x, t, r}) hipLaunchKernelGGL(k_bzero<T>, rgrid(k_bzero<T>, m), dim3(kBlock), 0, s, m, p);
+    T *e = nullptr;
+    if (k + 1 < bt->B.size()) {
+      const int64_t mc = static_cast<int64_t>(bt->B[k + 1].n) * NR;
+      e = bv_x<T>(bt->B[k + 1]);
+      hipLaunchKernelGGL(k_bzero<T>, rgrid(k_bzero<T>, mc), dim3(kBlock), 0, s, mc, e);
+    }
+    float best = 1e30f, best_corr = 1e30f;
+    int win_corr = 1;
     for (int cpl : {1, 2, 4, 8, 16}) {
       if (NR % cpl != 0) continue;
-      L.cpl = cpl;
-      sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s);   // warm
-      AMG_HIP(hipEventRecord(e0, s));
-      for (int q = 0; q < 5; ++q) sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s);
-      AMG_HIP(hipEventRecord(e1, s));
-      AMG_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      L.cpl = L.cpl_corr = cpl;
+      const float ms = time5([&] { sweep_any<T, NR>(nullptr, L, L.n_cont, r, x, t, s); });
       if (ms < best) { best = ms; L.tune_best = cpl; }
+      if (e) {
+        const float mc = time5([&] { corr_sweep_any<T, NR>(nullptr, L, L.n_cont, r, e, x, t, s); });
+        if (mc < best_corr) { best_corr = mc; win_corr = cpl; }
+      }
     }
     L.cpl = L.tune_best;
+    L.cpl_corr = e ? win_corr : L.cpl;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+}
+
+void set_tiles(amg_batch *bt, int tile_rows);
+
+// Time the level-0 SpMM + dots and update kernels for each reduction tile
+// size and keep the fastest.  The vectors and per-pair scalars are zeroed
+// first (every pair live, c = a = 0); a solve re-initialises all of them.
+template <int NR>
+void tune_tiles(amg_batch *bt) {
+  hipStream_t s = bt->stream;
+  const int64_t m0 = static_cast<int64_t>(bt->B[0].n) * NR;
+  for (auto *v : {&bt->u, &bt->r, &bt->w, &bt->v, &bt->d, &bt->q})
+    hipLaunchKernelGGL(k_bzero<double>, rgrid(k_bzero<double>, m0), dim3(kBlock), 0, s, m0, v->p);
+  AMG_HIP(hipMemsetAsync(bt->sc.p, 0, sizeof(BScalars) * bt->sc.n, s));
+  LaunchTimer time5(s);
+  // columns per thread of the SpMM + dots, at the first tile size
+  set_tiles(bt, kBTiles[0]);
+  float best = 1e30f;
+  int win_cols = 1;
+  for (int pc : {4, 2, 1}) {
+    if (NR % pc != 0) continue;
+    bt->spmm_cols = pc;
+    const float ms = time5([&] { launch_spmm_dots<NR>(bt, nullptr); });
+    if (ms < best) { best = ms; win_cols = pc; }
+  }
+  bt->spmm_cols = win_cols;
+  best = 1e30f;
+  int win = kBTiles[0];
+  for (int tr : kBTiles) {
+    set_tiles(bt, tr);
+    const float ms = time5([&] {
+      launch_spmm_dots<NR>(bt, nullptr);
+      launch_update<NR>(bt, nullptr);
+    });
+    if (ms < best) { best = ms; win = tr; }
+  }
+  set_tiles(bt, win);
 }
 
 }  // namespace
@@ -1062,6 +1179,45 @@ namespace amg {
 namespace {
 
 // ------------------------------------------------------------ batched setup
+int count_tiles(const std::vector<int64_t> &roff0, int tile_rows) {
+  int64_t n = 0;
+  for (size_t p = 0; p + 1 < roff0.size(); ++p) n += (roff0[p + 1] - roff0[p] + tile_rows - 1) / tile_rows;
+  return static_cast<int>(n);
+}
+
+// Level-0 reduction tiles of at most tile_rows rows, never crossing a
+// system; the device arrays are sized for the largest tile count.
+void set_tiles(amg_batch *bt, int tile_rows) {
+  hipStream_t s = bt->stream;
+  const int nsys = bt->nsys;
+  const std::vector<int64_t> &roff0 = bt->roff0;
+  std::vector<int> r0, r1, ts, tp(nsys + 1, 0);
+  for (int p = 0; p < nsys; ++p) {
+    tp[p] = static_cast<int>(r0.size());
+    for (int64_t a = roff0[p]; a < roff0[p + 1]; a += tile_rows) {
+      r0.push_back(static_cast<int>(a));
+      r1.push_back(static_cast<int>(std::min<int64_t>(a + tile_rows, roff0[p + 1])));
+      ts.push_back(p);
+    }
+  }
+  tp[nsys] = static_cast<int>(r0.size());
+  bt->ntiles = static_cast<int>(r0.size());
+  bt->tile_rows = tile_rows;
+  if (bt->trow0.n != static_cast<size_t>(bt->max_tiles)) {
+    bt->trow0.alloc(bt->max_tiles);
+    bt->trow1.alloc(bt->max_tiles);
+    bt->tsys.alloc(bt->max_tiles);
+  }
+  if (bt->tile_ptr.n != static_cast<size_t>(nsys + 1)) bt->tile_ptr.alloc(nsys + 1);
+  if (bt->ntiles > 0) {
+    AMG_HIP(hipMemcpyAsync(bt->trow0.p, r0.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(bt->trow1.p, r1.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+    AMG_HIP(hipMemcpyAsync(bt->tsys.p, ts.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
+  }
+  AMG_HIP(hipMemcpyAsync(bt->tile_ptr.p, tp.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+  AMG_HIP(hipStreamSynchronize(s));
+}
+
 void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
   hipStream_t s = bt->stream;
   const bool mixed = bt->p.precision == AMG_PREC_MIXED;
@@ -1085,7 +1241,14 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
   // small kernels and host reads, so they overlap well on the GPU).
   int dev = 0;
   AMG_HIP(hipGetDevice(&dev));
-  const int nthreads = std::max(1, std::min(nsys, kBuildThreads));
+  // AMG_BUILD_THREADS (1 .. kBuildThreads) lowers the thread count, e.g.
+  // for tools that trace every dispatch of every thread
+  int want = kBuildThreads;
+  if (const char *env = std::getenv("AMG_BUILD_THREADS")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= kBuildThreads) want = v;
+  }
+  const int nthreads = std::max(1, std::min(nsys, want));
   std::atomic<int> next{0};
   std::mutex emu;
   Error first{AMG_OK, ""};
@@ -1236,25 +1399,10 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
     AMG_HIP(hipStreamSynchronize(s));
   }
   // level-0 tiles (never crossing a system) and row offsets
-  std::vector<int> r0, r1, ts, tp(nsys + 1, 0);
-  for (int p = 0; p < nsys; ++p) {
-    tp[p] = static_cast<int>(r0.size());
-    for (int64_t a = roff0[p]; a < roff0[p + 1]; a += kBTile) {
-      r0.push_back(static_cast<int>(a));
-      r1.push_back(static_cast<int>(std::min<int64_t>(a + kBTile, roff0[p + 1])));
-      ts.push_back(p);
-    }
-  }
-  tp[nsys] = static_cast<int>(r0.size());
-  bt->ntiles = static_cast<int>(r0.size());
-  bt->trow0.alloc(bt->ntiles);
-  bt->trow1.alloc(bt->ntiles);
-  bt->tsys.alloc(bt->ntiles);
-  bt->tile_ptr.alloc(nsys + 1);
-  AMG_HIP(hipMemcpyAsync(bt->trow0.p, r0.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(bt->trow1.p, r1.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(bt->tsys.p, ts.data(), sizeof(int) * bt->ntiles, hipMemcpyHostToDevice, s));
-  AMG_HIP(hipMemcpyAsync(bt->tile_ptr.p, tp.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+  bt->roff0 = roff0;
+  bt->max_tiles = 0;
+  for (int tr : kBTiles) bt->max_tiles = std::max(bt->max_tiles, count_tiles(roff0, tr));
+  set_tiles(bt, kBTiles[0]);
   bt->user_off.assign(nsys + 1, 0);
   bt->int_off.assign(nsys, 0);
   for (int sid = 0; sid < nsys; ++sid) {
@@ -1285,7 +1433,7 @@ void batch_buffers(amg_batch *bt) {
   }
   const size_t m0 = static_cast<size_t>(bt->B[0].n) * NR;
   for (auto *v : {&bt->bint, &bt->u, &bt->r, &bt->w, &bt->v, &bt->d, &bt->q}) v->alloc(m0);
-  bt->partials.alloc(static_cast<size_t>(bt->ntiles) * NR * 3);
+  bt->partials.alloc(static_cast<size_t>(bt->max_tiles) * NR * 3);
   bt->sc.alloc(static_cast<size_t>(bt->nsys) * NR);
   bt->active.alloc(1);
   bt->all_done.alloc(1);
@@ -1299,6 +1447,7 @@ void batch_buffers(amg_batch *bt) {
     if (mixed) autotune<float, NR>(bt);
     else autotune<double, NR>(bt);
   }
+  tune_tiles<NR>(bt);
   AMG_HIP(hipStreamSynchronize(bt->stream));
   bt->tune_ms = wall_ms() - t0;
   bt->nr = NR;
@@ -1327,8 +1476,8 @@ int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int
   const BLevel &L0 = bt->B[0];
   batch_permute<NR>(bt, Bu, bt->bint.p, true);
   batch_permute<NR>(bt, Xu, bt->u.p, true);
-  hipLaunchKernelGGL(k_bzero<double>, vgrid(m0), dim3(kBlock), 0, s, m0, bt->d.p);
-  hipLaunchKernelGGL(k_bzero<double>, vgrid(m0), dim3(kBlock), 0, s, m0, bt->q.p);
+  hipLaunchKernelGGL(k_bzero<double>, rgrid(k_bzero<double>, m0), dim3(kBlock), 0, s, m0, bt->d.p);
+  hipLaunchKernelGGL(k_bzero<double>, rgrid(k_bzero<double>, m0), dim3(kBlock), 0, s, m0, bt->q.p);
   AMG_HIP(hipMemsetAsync(bt->active.p, 0, sizeof(int), s));
   hipLaunchKernelGGL((k_bpcg_init<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, bt->trow0.p, bt->trow1.p,
                      L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->bint.p, bt->u.p, bt->r.p,
@@ -1471,7 +1620,10 @@ int amg_batch_info(const amg_batch *bt, amg_batch_info_t *out) {
     out->n_smoothed[k] = bt->B[k].n_cont;
     out->nnz[k] = bt->B[k].L.A.nnz;
     out->cols_per_lane[k] = bt->B[k].cpl;
+    out->cols_per_lane_corr[k] = bt->B[k].cpl_corr;
   }
+  out->tile_rows = bt->tile_rows;
+  out->spmm_cols = bt->spmm_cols;
   out->setup_ms = bt->setup_ms;
   out->tune_ms = bt->tune_ms;
   return AMG_OK;

@@ -47,6 +47,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(amg_csr), offsetof(amg_csr, nnz), offsetof(amg_csr, val), offsetof(amg_csr, on_device));
   printf("%zu %zu %zu\n", sizeof(amg_params), offsetof(amg_params, smooth_vector), offsetof(amg_params, stream));
   printf("%zu %zu %zu %zu\n", sizeof(amg_info_t), offsetof(amg_info_t, nnz), offsetof(amg_info_t, opc), offsetof(amg_info_t, device_bytes));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(amg_batch_info_t), offsetof(amg_batch_info_t, nnz), offsetof(amg_batch_info_t, cols_per_lane_corr), offsetof(amg_batch_info_t, tile_rows), offsetof(amg_batch_info_t, spmm_cols));
   return 0;
 }
 ''')
@@ -62,6 +63,10 @@ int main(void) {
     c = list(map(int, out[2].split()))
     assert c == [C.sizeof(amd.amg_info_t), amd.amg_info_t.nnz.offset, amd.amg_info_t.opc.offset,
                  amd.amg_info_t.device_bytes.offset]
+    d = list(map(int, out[3].split()))
+    assert d == [C.sizeof(amd.amg_batch_info_t), amd.amg_batch_info_t.nnz.offset,
+                 amd.amg_batch_info_t.cols_per_lane_corr.offset, amd.amg_batch_info_t.tile_rows.offset,
+                 amd.amg_batch_info_t.spmm_cols.offset]
 
 
 def test_defaults_and_strings_without_gpu():

@@ -63,8 +63,10 @@ def test_batched_vcycle_matches_oracle(nrhs, precision):
     # the autotuner's pick is timing-dependent: any width that divides nrhs
     for k in range(inf["levels"]):
         if inf["n_smoothed"][k] > 0:
-            cpl = inf["cols_per_lane"][k]
-            assert cpl in (1, 2, 4, 8, 16) and nrhs % cpl == 0
+            for cpl in (inf["cols_per_lane"][k], inf["cols_per_lane_corr"][k]):
+                assert cpl in (1, 2, 4, 8, 16) and nrhs % cpl == 0
+    assert inf["tile_rows"] in (128, 256, 512, 1024)
+    assert inf["spmm_cols"] in (1, 2, 4) and nrhs % inf["spmm_cols"] == 0
 
 
 @pytest.mark.parametrize("precision", [0, 1])
