@@ -131,7 +131,8 @@ def batched_leg(amd, torch, W, np, dev):
                 edges_min=min(edges), edges_max=max(edges), solve_s=t, solve_s_first=times[0],
                 status=st, iters_max=int(its.max()), iters_mean=float(its.mean()),
                 relres_max=float(rel.max()), pair_solves_per_s=len(systems) * nrhs / t,
-                levels=inf["levels"], cols_per_lane=inf["cols_per_lane"],
+                levels=inf["levels"], level_rows=inf["n"], level_nnz=inf["nnz"],
+                cols_per_lane=inf["cols_per_lane"],
                 cols_per_lane_corr=inf["cols_per_lane_corr"], tile_rows=inf["tile_rows"], spmm_cols=inf["spmm_cols"],
                 setup_ms=inf["setup_ms"], tune_ms=inf["tune_ms"])
 

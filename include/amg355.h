@@ -305,7 +305,11 @@ typedef struct {
 
 /* Build the hierarchies of nsys systems A[0..nsys-1] (same parameters for
  * all; smooth_vec GIVEN is not accepted).  Errors as amg_setup, plus
- * UNSUPPORTED when a system does not end in a direct coarsest solve. */
+ * UNSUPPORTED when a system does not end in a direct coarsest solve.  The
+ * systems are set up by up to 8 host threads at once; the environment
+ * variable AMG_BUILD_THREADS (1 .. 8) lowers that number.  The first solve
+ * with a given nrhs also times the kernel variants (the tuned choices are
+ * reported by amg_batch_info). */
 int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_batch **out);
 
 /* Solve A_s X_s = B_s for every system s.  B, X: device pointers; systems are
