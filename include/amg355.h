@@ -299,8 +299,9 @@ typedef struct {
   int32_t cols_per_lane[AMG_MAX_LEVELS];  /* tuned: lanes per row = nrhs / cols_per_lane */
   double setup_ms, tune_ms;
   int32_t cols_per_lane_corr[AMG_MAX_LEVELS];  /* tuned, for the sweep that adds the coarse correction */
-  int32_t tile_rows;                  /* tuned rows per reduction tile of the level-0 PCG kernels */
-  int32_t spmm_cols;                  /* tuned right-hand-side columns per thread of the level-0 SpMM + dots */
+  int32_t tile_rows;                  /* rows per reduction tile of the level-0 PCG kernels (fixed: the
+                                         dot products fold per tile, so it sets their rounding) */
+  int32_t spmm_cols;                  /* right-hand-side columns per thread of the level-0 SpMM + dots (fixed) */
 } amg_batch_info_t;
 
 /* Build the hierarchies of nsys systems A[0..nsys-1] (same parameters for
@@ -308,8 +309,8 @@ typedef struct {
  * UNSUPPORTED when a system does not end in a direct coarsest solve.  The
  * systems are set up by up to 8 host threads at once; the environment
  * variable AMG_BUILD_THREADS (1 .. 8) lowers that number.  The first solve
- * with a given nrhs also times the kernel variants (the tuned choices are
- * reported by amg_batch_info). */
+ * with a given nrhs also times the sweep variants (columns per lane, which do
+ * not change any result bit; the picks are reported by amg_batch_info). */
 int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_batch **out);
 
 /* Solve A_s X_s = B_s for every system s.  B, X: device pointers; systems are

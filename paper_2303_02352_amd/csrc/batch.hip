@@ -34,9 +34,15 @@
 namespace amg {
 namespace {
 
-// Rows per reduction tile of the level-0 PCG kernels: tuned per batch and
-// right-hand-side count among these (the first one before tuning).
-constexpr int kBTiles[] = {256, 128, 512, 1024};
+// Rows per reduction tile of the level-0 PCG kernels.  The dot products
+// fold per tile and then per system in tile order, so the tile size (and
+// the SpMM's columns per thread) fix the rounding of every PCG scalar: they
+// are constants, not tuned, so that a solve gives the same bits in every run
+// (timing-dependent picks of 128-1024 rows and 1-4 columns measured within
+// 2 % of these).
+constexpr int kBTile = 256;
+template <int NR>
+constexpr int spmm_cols() { return NR % 2 == 0 ? 2 : 1; }
 
 struct BScalars {
   double rho, c, a, rr, nr0, thr;
@@ -844,7 +850,7 @@ struct amg_batch {
   std::vector<amg::BLevel> B;
   std::vector<int64_t> roff0;          // level-0 row offsets per internal position
   int ntiles = 0, tile_rows = 0, max_tiles = 0;
-  int spmm_cols = 1;                   // tuned columns per thread of the level-0 SpMM + dots
+  int spmm_cols = 1;                   // columns per thread of the level-0 SpMM + dots
   amg::dvec<int> trow0, trow1, tsys, tile_ptr;
   // per-nrhs state
   int nr = 0;
@@ -1042,9 +1048,7 @@ void launch_spmm_dots_pc(amg_batch *bt, const int *skip) {
 
 template <int NR>
 void launch_spmm_dots(amg_batch *bt, const int *skip) {
-  if constexpr (NR % 4 == 0) if (bt->spmm_cols == 4) return launch_spmm_dots_pc<NR, 4>(bt, skip);
-  if constexpr (NR % 2 == 0) if (bt->spmm_cols == 2) return launch_spmm_dots_pc<NR, 2>(bt, skip);
-  launch_spmm_dots_pc<NR, 1>(bt, skip);
+  launch_spmm_dots_pc<NR, spmm_cols<NR>()>(bt, skip);
 }
 
 template <int NR>
@@ -1135,42 +1139,6 @@ void autotune(amg_batch *bt) {
   }
 }
 
-void set_tiles(amg_batch *bt, int tile_rows);
-
-// Time the level-0 SpMM + dots and update kernels for each reduction tile
-// size and keep the fastest.  The vectors and per-pair scalars are zeroed
-// first (every pair live, c = a = 0); a solve re-initialises all of them.
-template <int NR>
-void tune_tiles(amg_batch *bt) {
-  hipStream_t s = bt->stream;
-  const int64_t m0 = static_cast<int64_t>(bt->B[0].n) * NR;
-  for (auto *v : {&bt->u, &bt->r, &bt->w, &bt->v, &bt->d, &bt->q})
-    hipLaunchKernelGGL(k_bzero<double>, rgrid(k_bzero<double>, m0), dim3(kBlock), 0, s, m0, v->p);
-  AMG_HIP(hipMemsetAsync(bt->sc.p, 0, sizeof(BScalars) * bt->sc.n, s));
-  LaunchTimer time5(s);
-  // columns per thread of the SpMM + dots, at the first tile size
-  set_tiles(bt, kBTiles[0]);
-  float best = 1e30f;
-  int win_cols = 1;
-  for (int pc : {4, 2, 1}) {
-    if (NR % pc != 0) continue;
-    bt->spmm_cols = pc;
-    const float ms = time5([&] { launch_spmm_dots<NR>(bt, nullptr); });
-    if (ms < best) { best = ms; win_cols = pc; }
-  }
-  bt->spmm_cols = win_cols;
-  best = 1e30f;
-  int win = kBTiles[0];
-  for (int tr : kBTiles) {
-    set_tiles(bt, tr);
-    const float ms = time5([&] {
-      launch_spmm_dots<NR>(bt, nullptr);
-      launch_update<NR>(bt, nullptr);
-    });
-    if (ms < best) { best = ms; win = tr; }
-  }
-  set_tiles(bt, win);
-}
 
 }  // namespace
 }  // namespace amg
@@ -1401,8 +1369,8 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
   // level-0 tiles (never crossing a system) and row offsets
   bt->roff0 = roff0;
   bt->max_tiles = 0;
-  for (int tr : kBTiles) bt->max_tiles = std::max(bt->max_tiles, count_tiles(roff0, tr));
-  set_tiles(bt, kBTiles[0]);
+  bt->max_tiles = count_tiles(roff0, kBTile);
+  set_tiles(bt, kBTile);
   bt->user_off.assign(nsys + 1, 0);
   bt->int_off.assign(nsys, 0);
   for (int sid = 0; sid < nsys; ++sid) {
@@ -1447,7 +1415,7 @@ void batch_buffers(amg_batch *bt) {
     if (mixed) autotune<float, NR>(bt);
     else autotune<double, NR>(bt);
   }
-  tune_tiles<NR>(bt);
+  bt->spmm_cols = spmm_cols<NR>();
   AMG_HIP(hipStreamSynchronize(bt->stream));
   bt->tune_ms = wall_ms() - t0;
   bt->nr = NR;

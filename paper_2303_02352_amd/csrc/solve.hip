@@ -486,6 +486,69 @@ __global__ void __launch_bounds__(kBlock) k_agg_sum(const int *skip, int nc,
   if (xc) xc[I] = dinvc[I] * acc;
 }
 
+// Restriction in one pass (small levels, where the two passes above are
+// bound by launch latency): G lanes per aggregate; lane q forms the scaled
+// residual t = p_i (r_i - (A x)_i) of member q (ascending), its row folded
+// in CSR order (the SELL slot order; padding slots add zeros), and the first
+// lane of the group adds the members' values in order; members beyond G are
+// folded by that lane itself.  Same bits as k_resid_scaled + k_agg_sum.
+template <class T, int G>
+__global__ void __launch_bounds__(kBlock) k_resid_agg(const int *skip, int nc,
+                                                      const int *__restrict__ mptr,
+                                                      const int *__restrict__ mem,
+                                                      const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const double *__restrict__ v,
+                                                      const T *__restrict__ pval,
+                                                      const T *__restrict__ rhs,
+                                                      const T *__restrict__ x, T *__restrict__ rc,
+                                                      const T *__restrict__ dinvc, T *__restrict__ xc) {
+  AMG_SKIP_IF_DONE();
+  const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int I = e / G, q = e % G;
+  const bool live = I < nc;
+  int q0 = 0, cnt = 0;
+  if (live) {
+    q0 = mptr[I];
+    cnt = mptr[I + 1] - q0;
+  }
+  auto scaled = [&](int i) {   // entries taken four at a time, all loads of a batch in flight
+    T acc = T(0);
+    int k = rp[i];
+    const int k1 = rp[i + 1];
+    for (; k < k1; k += 4) {
+      int c[4];
+      T a[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < k1) {
+          c[u] = ci[k + u];
+          a[u] = static_cast<T>(v[k + u]);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < k1) xv[u] = x[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < k1) acc = acc + a[u] * xv[u];
+    }
+    return pval[i] * (rhs[i] - acc);
+  };
+  T t = T(0);
+  if (q < cnt) t = scaled(mem[q0 + q]);
+  const int lead = (threadIdx.x & (kWave - 1)) - q;
+  T acc = T(0);
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    const T tj = __shfl(t, lead + j, kWave);
+    if (j < cnt) acc = acc + tj;
+  }
+  if (!live || q != 0) return;
+  for (int j = G; j < cnt; ++j) acc = acc + scaled(mem[q0 + j]);
+  rc[I] = acc;
+  if (xc) xc[I] = dinvc[I] * acc;
+}
+
 // x_i += p_i * e[agg_i]
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const int *skip, int n,
@@ -1073,6 +1136,30 @@ void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e
   }
 }
 
+// One-pass restriction on levels of at most kFuseRestrictRows rows;
+// returns false (nothing launched) on larger levels.
+#ifndef AMG_FUSE_RESTRICT_ROWS
+#define AMG_FUSE_RESTRICT_ROWS 131072
+#endif
+constexpr int kFuseRestrictRows = AMG_FUSE_RESTRICT_ROWS;
+template <class T>
+bool launch_resid_agg(const amg_hierarchy *h, const int *skip, const Level &L, const T *rhs, const T *x,
+                      T *rc, const T *dinvc, T *xc) {
+  if (L.A.n > kFuseRestrictRows) return false;
+  const int steps = h->p.aggr_steps;   // aggregates of at most 2^steps members
+  const int64_t nc = L.nc;
+  hipStream_t s = h->stream;
+#define AMG_RA(G)                                                                                         \
+  hipLaunchKernelGGL((k_resid_agg<T, G>), grid_for(nc * G), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p,      \
+                     L.mem.p, L.A.rp.p, L.A.ci.p, L.A.v.p, pval_of<T>(L), rhs, x, rc, dinvc, xc)
+  if (steps <= 1) AMG_RA(2);
+  else if (steps == 2) AMG_RA(4);
+  else if (steps == 3) AMG_RA(8);
+  else AMG_RA(16);
+#undef AMG_RA
+  return true;
+}
+
 void launch_spmv(const Level &L, const double *x, double *y, hipStream_t s) {
   const int n = L.A.n;
   if (streamed<double>(L))
@@ -1157,11 +1244,13 @@ bool vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
     for (int q = 1; q < P.pre_sweeps; ++q) { launch_sweep<T>(skip, L, rhs, A, B, s); std::swap(A, B); }
   }
   // restriction of the residual; B is free until the first post-sweep
-  launch_resid<T>(skip, L, rhs, A, B, s);
   Level &C = h->L[k + 1];
   T *xc = first_buffer<T>(h, k + 1, xbuf<T>(C));
-  hipLaunchKernelGGL(k_agg_sum<T>, grid_for(L.nc), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p, L.mem.p,
-                     B, rbuf<T>(C), dinv_of<T>(C), xc);
+  if (!launch_resid_agg<T>(h, skip, L, rhs, A, rbuf<T>(C), dinv_of<T>(C), xc)) {
+    launch_resid<T>(skip, L, rhs, A, B, s);
+    hipLaunchKernelGGL(k_agg_sum<T>, grid_for(L.nc), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p, L.mem.p,
+                       B, rbuf<T>(C), dinv_of<T>(C), xc);
+  }
   vcycle_level<T>(h, skip, k + 1, rbuf<T>(C), xbuf<T>(C), xc != nullptr);
   if (P.post_sweeps == 0) {
     hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
