@@ -59,7 +59,10 @@ extern "C" {
 #define AMG_SMOOTH_GIVEN 2        /* w supplied in amg_params.smooth_vector (e.g. a learned surrogate) */
 #define AMG_SMOOTH_LEARNED 3      /* w predicted by the message-passing network (amg_mpnn below)
                                      with amg_params.model_params; relaxation (smooth_sweeps)
-                                     when the prediction is unusable */
+                                     when the prediction is unusable.  The network's buffers
+                                     (about 224 bytes per fine row) are kept per device until
+                                     the process ends and reused by later learned setups, which
+                                     take turns on a device */
 /* precision */
 #define AMG_PREC_DOUBLE 0         /* everything in binary64 */
 #define AMG_PREC_MIXED 1          /* V-cycle below the coarsest level in binary32; PCG,

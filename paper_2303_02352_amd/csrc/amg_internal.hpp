@@ -474,6 +474,8 @@ void enqueue_vcycle(amg_hierarchy *h, const double *r, double *z);          // t
 void enqueue_vcycle_single(amg_hierarchy *h, const double *r, double *z);   // h's own V-cycle
 // the first m hierarchies' composite with binary64 cycles (bootstrap estimates)
 void enqueue_composite(amg_hierarchy *h, int m, const double *r, double *z);
+// Network prediction inside amg_setup (per-device cached network; mpnn.hip).
+int mpnn_predict_for_setup(const float *params, const amg_csr *A, double *w_out, hipStream_t s);
 void bootstrap_build(amg_hierarchy *h);   // adds hierarchies per max_hrc / bootstrap_rate
 void destroy_components(amg_hierarchy *h);
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y);

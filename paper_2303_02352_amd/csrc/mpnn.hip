@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "amg_internal.hpp"
@@ -413,6 +414,35 @@ struct amg_mpnn {
 namespace amg {
 namespace {
 
+void mpnn_alloc_params(amg_mpnn *m) {
+  m->theta.alloc(kNP); m->m1.alloc(kNP); m->m2.alloc(kNP); m->grad.alloc(kNP);
+  m->Wt1.alloc(2 * kF0 * kHid); m->Wt2.alloc(2 * kHid * kHid);
+  m->f1.alloc(19 * kHid); m->f2.alloc(67 * kHid);
+}
+
+// Parameters (NULL: zeros) to the device, packed weights, Adam moments
+// cleared; synchronises m->stream.
+void mpnn_load_params(amg_mpnn *m, const float *params) {
+  std::vector<float> init(kNP, 0.0f);
+  if (params) std::memcpy(init.data(), params, sizeof(float) * kNP);
+  for (float x : init)
+    if (!std::isfinite(x)) fail(AMG_ERR_NONFINITE, "non-finite network parameter");
+  AMG_HIP(hipMemcpyAsync(m->theta.p, init.data(), sizeof(float) * kNP, hipMemcpyHostToDevice, m->stream));
+  AMG_HIP(hipMemsetAsync(m->m1.p, 0, sizeof(float) * kNP, m->stream));
+  AMG_HIP(hipMemsetAsync(m->m2.p, 0, sizeof(float) * kNP, m->stream));
+  hipLaunchKernelGGL(k_pack_weights, grid_for(2 * kHid * kHid), dim3(kBlock), 0, m->stream, m->theta.p,
+                     m->Wt1.p, m->Wt2.p);
+  AMG_LAUNCH_CHECK();
+  AMG_HIP(hipStreamSynchronize(m->stream));
+}
+
+}  // namespace
+}  // namespace amg
+
+
+namespace amg {
+namespace {
+
 // Forward buffers (features, activations, prediction) for n rows; the
 // backward pass's buffers only when training.
 void mpnn_reserve(amg_mpnn *m, int n) {
@@ -511,6 +541,50 @@ float mpnn_train(amg_mpnn *m, const amg_csr *A, const double *wt, float lr, floa
 }  // namespace
 }  // namespace amg
 
+namespace amg {
+
+// The network inside amg_setup (AMG_SMOOTH_LEARNED): one network per device,
+// kept for the life of the process, so that a setup does not allocate and
+// free the forward buffers (about 224 bytes per row) each time; they grow
+// to the largest n seen.  Setups on one device take turns (mutex); the
+// work runs on the setup's stream s and is finished when this returns.
+int mpnn_predict_for_setup(const float *params, const amg_csr *A, double *w_out, hipStream_t s) {
+  struct Cache {
+    std::mutex mu;
+    amg_mpnn *m = nullptr;
+  };
+  static Cache cache[kMaxDevices];
+  int dev = 0;
+  AMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(AMG_ERR_DEVICE, "device index out of range");
+  Cache &c = cache[dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  NoPool no_pool;   // the buffers outlive this setup and its stream
+  return api_guarded([&] {
+    if (!c.m) {
+      amg_mpnn *m = new amg_mpnn();
+      m->stream = s;
+      try {
+        mpnn_alloc_params(m);
+      } catch (...) {
+        delete m;
+        throw;
+      }
+      c.m = m;
+    }
+    amg_mpnn *m = c.m;
+    m->stream = s;
+    mpnn_load_params(m, params);
+    check_csr(A);
+    mpnn_forward(m, A, w_out);
+    AMG_HIP(hipStreamSynchronize(s));
+    m->stream = nullptr;
+    return AMG_OK;
+  });
+}
+
+}  // namespace amg
+
 extern "C" {
 
 int amg_mpnn_create(const float *params, void *stream, amg_mpnn **out) {
@@ -528,21 +602,8 @@ int amg_mpnn_create(const float *params, void *stream, amg_mpnn **out) {
     m->own_stream = 1;
   }
   const int st = amg::api_guarded([&] {
-    using namespace amg;
-    m->theta.alloc(kNP); m->m1.alloc(kNP); m->m2.alloc(kNP); m->grad.alloc(kNP);
-    m->Wt1.alloc(2 * kF0 * kHid); m->Wt2.alloc(2 * kHid * kHid);
-    m->f1.alloc(19 * kHid); m->f2.alloc(67 * kHid);
-    std::vector<float> init(kNP, 0.0f);
-    if (params) std::memcpy(init.data(), params, sizeof(float) * kNP);
-    for (float x : init)
-      if (!std::isfinite(x)) fail(AMG_ERR_NONFINITE, "non-finite network parameter");
-    AMG_HIP(hipMemcpyAsync(m->theta.p, init.data(), sizeof(float) * kNP, hipMemcpyHostToDevice, m->stream));
-    AMG_HIP(hipMemsetAsync(m->m1.p, 0, sizeof(float) * kNP, m->stream));
-    AMG_HIP(hipMemsetAsync(m->m2.p, 0, sizeof(float) * kNP, m->stream));
-    hipLaunchKernelGGL(k_pack_weights, grid_for(2 * kHid * kHid), dim3(kBlock), 0, m->stream, m->theta.p,
-                       m->Wt1.p, m->Wt2.p);
-    AMG_LAUNCH_CHECK();
-    AMG_HIP(hipStreamSynchronize(m->stream));
+    amg::mpnn_alloc_params(m);
+    amg::mpnn_load_params(m, params);
     return AMG_OK;
   });
   if (st != AMG_OK) {

@@ -1808,13 +1808,8 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   bool relax = (P.smooth_vec == AMG_SMOOTH_RELAX);
   h->smooth_status = AMG_OK;
   if (P.smooth_vec == AMG_SMOOTH_LEARNED) {
-    amg_mpnn *m = nullptr;
-    int st = amg_mpnn_create(P.model_params, s, &m);
-    if (st == AMG_OK) {
-      const amg_csr Adev{n, L0.A.nnz, L0.A.rp.p, L0.A.ci.p, L0.A.v.p, 1};
-      st = amg_mpnn_predict(m, &Adev, L0.w.p, nullptr);
-    }
-    amg_mpnn_destroy(m);
+    const amg_csr Adev{n, L0.A.nnz, L0.A.rp.p, L0.A.ci.p, L0.A.v.p, 1};
+    int st = mpnn_predict_for_setup(P.model_params, &Adev, L0.w.p, s);
     if (st == AMG_OK) {
       dvec<int> flag(1);
       AMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
