@@ -163,8 +163,8 @@ def learned_leg(amd, torch, W, np, dev):
         return dict(status=st, iters=it, relres=rel, solve_s=t,
                     conv_factor=float(rel ** (1.0 / max(1, it))))
 
-    def form(**kw):
-        H, ts = timed(lambda: amd.Hierarchy(*csr, smooth_sweeps=20, **kw))
+    def form(sweeps=20, **kw):
+        H, ts = timed(lambda: amd.Hierarchy(*csr, smooth_sweeps=sweeps, **kw))
         inf = H.info()
         rec = dict(setup_s=ts, wgen_s=inf["setup_smooth_ms"] / 1e3, smooth_status=inf["smooth_status"],
                    **solve(H), levels=inf["n"], opc=inf["opc"], matching_rounds=inf["matching_rounds"],
@@ -184,6 +184,19 @@ def learned_leg(amd, torch, W, np, dev):
     res["speedup_setup_plus_solve"] = (p["setup_s"] + p["solve_s"]) / (l["setup_s"] + l["solve_s"])
     res["model"] = dict(final_loss=meta.get("final_loss"), steps=meta.get("steps"),
                         training_fields=len(meta.get("fields", [])))
+    # A costlier generator, RELAX(640), against the network trained on its
+    # vectors (same fields and recipe): the network replaces 640 sweeps by
+    # one prediction, but cannot reproduce their long-range structure.
+    p640, meta640 = surrogate.load_params(surrogate.RELAX640_MODEL)
+    for rep in range(2):
+        plain640 = form(640, smooth_vec=amd.AMG_SMOOTH_RELAX)
+        learned640 = form(640, model_params=p640)
+    res["relax640"] = dict(
+        plain=plain640, learned=learned640, model_final_loss=meta640.get("final_loss"),
+        speedup_setup_plus_solve=(plain640["setup_s"] + plain640["solve_s"]) /
+                                 (learned640["setup_s"] + learned640["solve_s"]),
+        vs_relax20_setup_plus_solve=(p["setup_s"] + p["solve_s"]) /
+                                    (learned640["setup_s"] + learned640["solve_s"]))
     return res
 
 

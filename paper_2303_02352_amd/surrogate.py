@@ -10,8 +10,10 @@ passing it to amg_setup (``Hierarchy(..., model_params=params)``,
 AMG_SMOOTH_LEARNED): the library predicts the vector, checks it and falls
 back to relaxation by itself.
 
-Command line (writes the model file used by bench.py):
+Command line (writes the model files used by bench.py):
     python -m paper_2303_02352_amd.surrogate --out paper_2303_02352_amd/models/mpnn_lognormal.json
+    python -m paper_2303_02352_amd.surrogate --relax-sweeps 640 \
+        --out paper_2303_02352_amd/models/mpnn_lognormal_relax640.json
 """
 from __future__ import annotations
 
@@ -26,6 +28,8 @@ import paper_2303_02352_amd as amd
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(HERE, "models", "mpnn_lognormal.json")
+# trained on RELAX(640) targets (--relax-sweeps 640), same fields and steps
+RELAX640_MODEL = os.path.join(HERE, "models", "mpnn_lognormal_relax640.json")
 RELAX_SWEEPS = 20
 
 
