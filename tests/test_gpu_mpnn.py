@@ -160,6 +160,25 @@ def test_learned_mode_through_the_c_abi():
     _levels_equal(Hl, Hg)
 
 
+def test_learned_setups_reuse_the_network_across_sizes_and_parameters():
+    """The setup keeps one network per device: learned setups of growing and
+    shrinking sizes, with two parameter sets, each equal to the GIVEN path
+    with a fresh network's prediction."""
+    import paper_2303_02352_amd as amd
+    from paper_2303_02352_amd import surrogate
+    p1, _ = surrogate.load_params()
+    p2 = M.init_params(11).astype(np.float32)
+    for N, params in ((12, p1), (30, p2), (9, p1), (30, p1)):
+        A = W.lognormal7(N, 40 + N, ell=4.0)
+        rp, ci, va = dev(A.row_ptr), dev(A.col), dev(A.val)
+        w = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        amd.SmoothVectorNet(params).predict(rp, ci, va, w_out=w)
+        say("learned setup n=%d" % A.n)
+        Hl = amd.Hierarchy(rp, ci, va, model_params=params)
+        assert Hl.info()["smooth_status"] == amd.AMG_OK
+        _levels_equal(Hl, amd.Hierarchy(rp, ci, va, smooth_vector=w))
+
+
 @pytest.mark.parametrize("bias", [1e30, -1e30])
 def test_learned_mode_falls_back_to_relaxation(bias):
     """A parameter set whose prediction overflows (w = inf) or underflows
