@@ -48,6 +48,28 @@ __device__ __forceinline__ bf16 f2bf(float f) {
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
 
 // ------------------------------------------------------------- features
+// A row's CSR entries, eight at a time with every load of a batch issued
+// before the first use; f(k, col, val) in CSR order.
+template <class F>
+__device__ __forceinline__ void csr_row_batched(int kb, int ke, const int *__restrict__ ci,
+                                                const double *__restrict__ v, F f) {
+  for (int k0 = kb; k0 < ke; k0 += 8) {
+    int c[8];
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < ke) {
+        c[u] = ci[k0 + u];
+        a[u] = v[k0 + u];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < ke) f(k0 + u, c[u], a[u]);
+  }
+}
+
+// Features 0-3 and 5-7 of row i (feature 4, the second sweep, is k_feat2's),
+// stored as one 16-byte row with a zero in place of feature 4.
 __global__ void k_feat1(int n, const int *__restrict__ rp, const int *__restrict__ ci,
                         const double *__restrict__ v, bf16 *__restrict__ X, float *__restrict__ s_out,
                         double *__restrict__ w1) {
@@ -55,27 +77,33 @@ __global__ void k_feat1(int n, const int *__restrict__ rp, const int *__restrict
   if (i >= n) return;
   double d = 0.0, s = 0.0, l1 = 0.0, ax = 0.0, mx = 0.0, mn = INFINITY;
   int noff = 0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    const double a = v[k];
+  csr_row_batched(rp[i], rp[i + 1], ci, v, [&](int, int c, double a) {
     l1 = l1 + fabs(a);
     ax = ax + a;
-    if (ci[k] == i) { d = a; continue; }
+    if (c == i) {
+      d = a;
+      return;
+    }
     s = s + fabs(a);
     mx = fmax(mx, fabs(a));
     mn = fmin(mn, fabs(a));
     ++noff;
-  }
+  });
   const double w = 1.0 - (1.0 / l1) * ax;
   w1[i] = w;
   s_out[i] = static_cast<float>(s);
-  bf16 *x = X + static_cast<int64_t>(i) * kF0;
+  bf16 x[kF0];
   x[0] = f2bf(1.0f);
   x[1] = f2bf(static_cast<float>(log(d) / 4.0));
   x[2] = f2bf(static_cast<float>(s / d));
   x[3] = f2bf(static_cast<float>(w));
+  x[4] = 0;
   x[5] = f2bf(noff > 0 ? static_cast<float>(log(mx / mn) / 4.0) : 0.0f);
   x[6] = f2bf(static_cast<float>(noff / 6.0));
   x[7] = f2bf(0.0f);
+  uint4 o;
+  __builtin_memcpy(&o, x, sizeof(o));
+  *reinterpret_cast<uint4 *>(X + static_cast<int64_t>(i) * kF0) = o;
 }
 
 __global__ void k_feat2(int n, const int *__restrict__ rp, const int *__restrict__ ci,
@@ -84,9 +112,25 @@ __global__ void k_feat2(int n, const int *__restrict__ rp, const int *__restrict
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double l1 = 0.0, ax = 0.0;
-  for (int k = rp[i]; k < rp[i + 1]; ++k) {
-    l1 = l1 + fabs(v[k]);
-    ax = ax + v[k] * w1[ci[k]];
+  const int kb = rp[i], ke = rp[i + 1];
+  for (int k0 = kb; k0 < ke; k0 += 8) {
+    int c[8];
+    double a[8], wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < ke) {
+        c[u] = ci[k0 + u];
+        a[u] = v[k0 + u];
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < ke) wv[u] = w1[c[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k0 + u < ke) {
+        l1 = l1 + fabs(a[u]);
+        ax = ax + a[u] * wv[u];
+      }
   }
   X[static_cast<int64_t>(i) * kF0 + 4] = f2bf(static_cast<float>(w1[i] - (1.0 / l1) * ax));
 }
@@ -173,6 +217,8 @@ __global__ void __launch_bounds__(kBlock) k_agg_t_add(int n, const int *__restri
 // Wt is W transposed (32 x K, bfloat16).  MFMA 16x16x16 (bf16 in, f32 acc):
 // lane l supplies A[row l%16][k 4(l/16)..+3], B[k 4(l/16)..+3][col l%16] and
 // receives D[row 4(l/16)+i][col l%16], i = 0..3.
+constexpr int kDenseTiles = 4;   // 16-row tiles per wavefront (their loads in flight together)
+
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_dense(int n, const bf16 *__restrict__ Ua,
                                                   const bf16 *__restrict__ Ub,
@@ -180,34 +226,55 @@ __global__ void __launch_bounds__(kBlock) k_dense(int n, const bf16 *__restrict_
                                                   const float *__restrict__ b,
                                                   bf16 *__restrict__ H) {
   constexpr int FH = K / 2;
+  // the wavefront's output tiles (16 x 32 each), written out as whole 64-byte rows
+  __shared__ __attribute__((aligned(16))) bf16 tile[kBlock / kWave][kDenseTiles * 16 * kHid];
   const int lane = threadIdx.x & (kWave - 1);
-  const int r0 = (blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * 16;
+  const int wv = threadIdx.x / kWave;
+  const int r0 = (blockIdx.x * (kBlock / kWave) + wv) * (16 * kDenseTiles);
   if (r0 >= n) return;
-  const int arow = r0 + (lane & 15);
   const int kq = 4 * (lane >> 4);
+  short4v a[kDenseTiles][K / 16];
 #pragma unroll
-  for (int ct = 0; ct < kHid / 16; ++ct) {
-    float4v acc = {0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < kDenseTiles; ++t) {
+    const int arow = r0 + 16 * t + (lane & 15);
 #pragma unroll
     for (int kc = 0; kc < K / 16; ++kc) {
       const int k = kc * 16 + kq;
-      short4v a = {0, 0, 0, 0};
+      a[t][kc] = short4v{0, 0, 0, 0};
       if (arow < n) {
         const bf16 *src = (k < FH) ? Ua + static_cast<int64_t>(arow) * FH + k
                                    : Ub + static_cast<int64_t>(arow) * FH + (k - FH);
-        a = *reinterpret_cast<const short4v *>(src);
+        a[t][kc] = *reinterpret_cast<const short4v *>(src);
       }
-      const short4v bb =
-          *reinterpret_cast<const short4v *>(Wt + static_cast<int64_t>(ct * 16 + (lane & 15)) * K + k);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc, 0, 0, 0);
     }
+  }
+  bf16 *T = tile[wv];
+#pragma unroll
+  for (int ct = 0; ct < kHid / 16; ++ct) {
+    short4v bb[K / 16];
+#pragma unroll
+    for (int kc = 0; kc < K / 16; ++kc)
+      bb[kc] = *reinterpret_cast<const short4v *>(Wt + static_cast<int64_t>(ct * 16 + (lane & 15)) * K +
+                                                  kc * 16 + kq);
     const int col = ct * 16 + (lane & 15);
     const float bias = b[col];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = r0 + kq + q;
-      if (row < n) H[static_cast<int64_t>(row) * kHid + col] = f2bf(fmaxf(acc[q] + bias, 0.0f));
+    for (int t = 0; t < kDenseTiles; ++t) {
+      float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < K / 16; ++kc)
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t][kc], bb[kc], acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) T[(16 * t + kq + q) * kHid + col] = f2bf(fmaxf(acc[q] + bias, 0.0f));
     }
+  }
+  __builtin_amdgcn_wave_barrier();   // a wavefront's LDS accesses complete in issue order
+#pragma unroll
+  for (int t = 0; t < kDenseTiles; ++t) {
+    const int lr = 16 * t + (lane >> 2);
+    if (r0 + lr < n)
+      *reinterpret_cast<uint4 *>(H + static_cast<int64_t>(r0 + lr) * kHid + 8 * (lane & 3)) =
+          *reinterpret_cast<const uint4 *>(T + lr * kHid + 8 * (lane & 3));
   }
 }
 
@@ -479,7 +546,7 @@ void mpnn_forward(amg_mpnn *m, const amg_csr *A, double *w_out) {
   hipLaunchKernelGGL(k_feat2, grid_for(n), dim3(kBlock), 0, s, n, rp, ci, v, m->w1.p, m->X0.p);
   hipLaunchKernelGGL(k_agg<kF0>, grid_for(static_cast<int64_t>(n) * (kF0 / 8)), dim3(kBlock), 0, s, n, rp, ci,
                      v, m->s.p, m->X0.p, m->N0.p);
-  const dim3 gd = grid_for(ceil_div(n, 16), kBlock / kWave);
+  const dim3 gd = grid_for(ceil_div(n, 16 * kDenseTiles), kBlock / kWave);
   hipLaunchKernelGGL(k_dense<2 * kF0>, gd, dim3(kBlock), 0, s, n, m->X0.p, m->N0.p, m->Wt1.p,
                      m->theta.p + ob1, m->h1.p);
   hipLaunchKernelGGL(k_agg<kHid>, grid_for(static_cast<int64_t>(n) * (kHid / 8)), dim3(kBlock), 0, s, n, rp,
