@@ -112,7 +112,7 @@ typedef struct {
  *   value_coding AUTO, n_parts 1, cycle_type V, relax_type and coarse_relax
  *   L1_JACOBI, max_hrc 1, bootstrap_type MULT, bootstrap_its 15,
  *   bootstrap_seed 1, bootstrap_rate 0.8, smooth_vector NULL, model_params
- *   NULL, stream NULL.
+ *   NULL, model_path NULL, stream NULL.
  * The paper's own runs (Sec. 5, Appendix A) use aggr_steps 3, coarse_max
  * 40*nd, coarse_solver JACOBI with 20 sweeps. */
 typedef struct {
@@ -144,6 +144,10 @@ typedef struct {
   double bootstrap_rate;   /* (0, 1]: desired convergence rate of the composite */
   const double *smooth_vector; /* n values, same memory space as the CSR, for AMG_SMOOTH_GIVEN */
   const float *model_params;   /* AMG_SMOOTH_LEARNED: AMG_MPNN_NPARAMS floats in host memory */
+  const char *model_path;      /* AMG_SMOOTH_LEARNED without model_params: a file of the
+                                  parameters, read by amg_mpnn_read_params; a file that
+                                  cannot be read is an unusable model (relaxation is used and
+                                  smooth_status reports AMG_ERR_MODEL) */
   void *stream;            /* hipStream_t on which the solve-phase work is ordered; NULL =
                               a blocking stream the library keeps for this hierarchy alone
                               (reused after amg_destroy).  A caller's stream must stay
@@ -356,6 +360,13 @@ typedef struct amg_mpnn amg_mpnn;
 /* params: host array of AMG_MPNN_NPARAMS floats (NULL = all zero).
  * stream: hipStream_t (NULL = a library-owned stream). */
 int amg_mpnn_create(const float *params, void *stream, amg_mpnn **out);
+/* Read AMG_MPNN_NPARAMS parameters from a text file into the host array
+ * params: the numbers of the first [...] list after a "params" key (the JSON
+ * model files the Python module writes), or, in a file without that key,
+ * its first AMG_MPNN_NPARAMS numbers (separated by white space or commas).
+ * Host only (no device needed).  Errors: INVALID (NULL argument), MODEL
+ * (file unreadable, too few numbers, or text that is not a number). */
+int amg_mpnn_read_params(const char *path, float *params);
 /* Copy the current parameters to a host array of AMG_MPNN_NPARAMS floats. */
 int amg_mpnn_get_params(const amg_mpnn *m, float *params);
 /* Node features as the network stores them (bfloat16 values widened to

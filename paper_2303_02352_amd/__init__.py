@@ -43,7 +43,7 @@ class amg_params(C.Structure):
         "value_coding", "n_parts", "cycle_type", "relax_type", "coarse_relax", "max_hrc",
         "bootstrap_type", "bootstrap_its", "bootstrap_seed")] + [
         ("bootstrap_rate", C.c_double), ("smooth_vector", C.c_void_p),
-        ("model_params", C.c_void_p), ("stream", C.c_void_p)]
+        ("model_params", C.c_void_p), ("model_path", C.c_char_p), ("stream", C.c_void_p)]
 
 
 class amg_info_t(C.Structure):
@@ -92,6 +92,7 @@ EXPORTS = {
     "amg_batch_info": (C.c_int, [C.c_void_p, C.POINTER(amg_batch_info_t)]),
     "amg_batch_destroy": (None, [C.c_void_p]),
     "amg_mpnn_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "amg_mpnn_read_params": (C.c_int, [C.c_char_p, C.c_void_p]),
     "amg_mpnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "amg_mpnn_features": (C.c_int, [C.c_void_p, C.POINTER(amg_csr), C.c_void_p]),
     "amg_mpnn_predict": (C.c_int, [C.c_void_p, C.POINTER(amg_csr), C.c_void_p, C.c_void_p]),
@@ -232,7 +233,8 @@ class Hierarchy:
     ``smooth_vector`` is an array of n doubles in the CSR's memory space.
     """
 
-    def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, model_params=None, **params):
+    def __init__(self, row_ptr, col, val, stream=None, smooth_vector=None, model_params=None,
+                 model_path=None, **params):
         L = load()
         A, self.n, self.nnz = _csr_args(row_ptr, col, val)
         p = default_params(**params)
@@ -246,12 +248,18 @@ class Hierarchy:
                 raise ValueError("model_params: shape %s, expected (%d,)" % (theta.shape, AMG_MPNN_NPARAMS))
             p.smooth_vec = AMG_SMOOTH_LEARNED
             p.model_params = theta.ctypes.data
+        path = None
+        if model_path is not None:
+            path = os.fsencode(model_path)
+            p.smooth_vec = AMG_SMOOTH_LEARNED
+            p.model_path = path
         p.stream = stream if stream is not None else (current_stream() if A.on_device else None)
         self.params = p
         h = C.c_void_p()
         st = L.amg_setup(C.byref(A), C.byref(p), C.byref(h))
         p.smooth_vector = None   # read during amg_setup only
         p.model_params = None
+        p.model_path = None
         if st != AMG_OK:
             raise AMGError(st, "amg_setup")
         self.h = h
@@ -445,6 +453,16 @@ class Batch:
                     cols_per_lane_corr=list(inf.cols_per_lane_corr[:L]), tile_rows=inf.tile_rows,
                     spmm_cols=inf.spmm_cols,
                     setup_ms=inf.setup_ms, tune_ms=inf.tune_ms)
+
+
+def read_model_params(path) -> np.ndarray:
+    """The network parameters of a model file, read by the library
+    (amg_mpnn_read_params; host only)."""
+    out = np.empty(AMG_MPNN_NPARAMS, dtype=np.float32)
+    st = load().amg_mpnn_read_params(os.fsencode(path), out.ctypes.data)
+    if st != AMG_OK:
+        raise AMGError(st, "amg_mpnn_read_params")
+    return out
 
 
 class SmoothVectorNet:

@@ -476,6 +476,9 @@ void enqueue_vcycle_single(amg_hierarchy *h, const double *r, double *z);   // h
 void enqueue_composite(amg_hierarchy *h, int m, const double *r, double *z);
 // Network prediction inside amg_setup (per-device cached network; mpnn.hip).
 int mpnn_predict_for_setup(const float *params, const amg_csr *A, double *w_out, hipStream_t s);
+// AMG_MPNN_NPARAMS parameters from a model file into out; false when the file
+// cannot be read or does not hold them (host only; mpnn.hip).
+bool mpnn_read_params_file(const char *path, float *out);
 void bootstrap_build(amg_hierarchy *h);   // adds hierarchies per max_hrc / bootstrap_rate
 void destroy_components(amg_hierarchy *h);
 void enqueue_spmv(amg_hierarchy *h, int k, const double *x, double *y);

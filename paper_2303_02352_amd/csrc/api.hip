@@ -46,8 +46,8 @@ int check_params(const amg_params *p) {
     return set_error(AMG_ERR_INVALID, "unknown smooth_vec");
   if (p->smooth_vec == AMG_SMOOTH_GIVEN && !p->smooth_vector)
     return set_error(AMG_ERR_INVALID, "smooth_vec = GIVEN needs smooth_vector");
-  if (p->smooth_vec == AMG_SMOOTH_LEARNED && !p->model_params)
-    return set_error(AMG_ERR_INVALID, "smooth_vec = LEARNED needs model_params");
+  if (p->smooth_vec == AMG_SMOOTH_LEARNED && !p->model_params && !p->model_path)
+    return set_error(AMG_ERR_INVALID, "smooth_vec = LEARNED needs model_params or model_path");
   if (p->precision != AMG_PREC_DOUBLE && p->precision != AMG_PREC_MIXED)
     return set_error(AMG_ERR_INVALID, "unknown precision");
   if (p->value_coding != AMG_VALUES_PLAIN && p->value_coding != AMG_VALUES_AUTO)
@@ -172,6 +172,7 @@ int amg_params_default(amg_params *p) {
   p->bootstrap_rate = 0.8;
   p->smooth_vector = nullptr;
   p->model_params = nullptr;
+  p->model_path = nullptr;
   p->stream = nullptr;
   return AMG_OK;
 }
@@ -214,6 +215,7 @@ int amg_setup(const amg_csr *A, const amg_params *p, amg_hierarchy **h_out) {
   for (amg_hierarchy *c : h->comp) c->stream = h->stream;
   h->p.smooth_vector = nullptr;
   h->p.model_params = nullptr;
+  h->p.model_path = nullptr;
   if (st != AMG_OK) {
     std::string msg = g_last_error;
     amg_destroy(h);

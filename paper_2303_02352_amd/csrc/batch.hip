@@ -1261,6 +1261,7 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
   }
   if (first.code != AMG_OK) fail(first.code, first.msg);
   bt->p.model_params = nullptr;
+  bt->p.model_path = nullptr;
   // deepest systems first (stable): active systems on any level form a prefix
   std::vector<int> order(nsys);
   std::iota(order.begin(), order.end(), 0);
@@ -1519,7 +1520,7 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   amg_batch *bt = new (std::nothrow) amg_batch();
   if (!bt) return amg::api_set_error(AMG_ERR_NOMEM, "host allocation failed");
   bt->p = *p;
-  bt->p.smooth_vector = nullptr;   // (model_params stays valid while amg_batch_setup runs)
+  bt->p.smooth_vector = nullptr;   // (model_params / model_path stay valid while amg_batch_setup runs)
   if (p->stream) {
     bt->stream = static_cast<hipStream_t>(p->stream);
   } else {

@@ -17,6 +17,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <cstdlib>
+#include <cstdio>
 #include <mutex>
 #include <vector>
 
@@ -610,6 +613,39 @@ float mpnn_train(amg_mpnn *m, const amg_csr *A, const double *wt, float lr, floa
 
 namespace amg {
 
+// Model file: the numbers of the first [...] after a "params" key, or the
+// file's first numbers when it has no such key; white space and commas
+// separate them.  Exactly AMG_MPNN_NPARAMS are taken; fewer, or text that is
+// not a number before they are complete, is a failure.
+bool mpnn_read_params_file(const char *path, float *out) {
+  if (!path || !out) return false;
+  std::FILE *f = std::fopen(path, "rb");
+  if (!f) return false;
+  std::string text;
+  char buf[1 << 16];
+  for (size_t got; (got = std::fread(buf, 1, sizeof(buf), f)) > 0;) text.append(buf, got);
+  const bool read_ok = !std::ferror(f);
+  std::fclose(f);
+  if (!read_ok) return false;
+  size_t pos = 0;
+  const size_t key = text.find("\"params\"");
+  if (key != std::string::npos) {
+    pos = text.find('[', key);
+    if (pos == std::string::npos) return false;
+    ++pos;
+  }
+  const char *p = text.c_str() + pos;
+  for (int i = 0; i < AMG_MPNN_NPARAMS; ++i) {
+    while (*p == ' ' || *p == ',' || *p == '\n' || *p == '\r' || *p == '\t') ++p;
+    char *end = nullptr;
+    const double v = std::strtod(p, &end);
+    if (end == p) return false;
+    out[i] = static_cast<float>(v);
+    p = end;
+  }
+  return true;
+}
+
 // The network inside amg_setup (AMG_SMOOTH_LEARNED): one network per device,
 // kept for the life of the process, so that a setup does not allocate and
 // free the forward buffers (about 224 bytes per row) each time; they grow
@@ -653,6 +689,13 @@ int mpnn_predict_for_setup(const float *params, const amg_csr *A, double *w_out,
 }  // namespace amg
 
 extern "C" {
+
+int amg_mpnn_read_params(const char *path, float *params) {
+  if (!path || !params) return amg::api_set_error(AMG_ERR_INVALID, "NULL argument");
+  if (!amg::mpnn_read_params_file(path, params))
+    return amg::api_set_error(AMG_ERR_MODEL, std::string("cannot read network parameters from ") + path);
+  return AMG_OK;
+}
 
 int amg_mpnn_create(const float *params, void *stream, amg_mpnn **out) {
   if (out) *out = nullptr;

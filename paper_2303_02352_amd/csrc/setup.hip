@@ -1809,7 +1809,15 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
   h->smooth_status = AMG_OK;
   if (P.smooth_vec == AMG_SMOOTH_LEARNED) {
     const amg_csr Adev{n, L0.A.nnz, L0.A.rp.p, L0.A.ci.p, L0.A.v.p, 1};
-    int st = mpnn_predict_for_setup(P.model_params, &Adev, L0.w.p, s);
+    std::vector<float> from_file;
+    const float *theta = P.model_params;
+    int st = AMG_OK;
+    if (!theta) {   // the parameters from model_path
+      from_file.resize(AMG_MPNN_NPARAMS);
+      st = mpnn_read_params_file(P.model_path, from_file.data()) ? AMG_OK : AMG_ERR_MODEL;
+      theta = from_file.data();
+    }
+    if (st == AMG_OK) st = mpnn_predict_for_setup(theta, &Adev, L0.w.p, s);
     if (st == AMG_OK) {
       dvec<int> flag(1);
       AMG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));

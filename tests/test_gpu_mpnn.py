@@ -179,6 +179,24 @@ def test_learned_setups_reuse_the_network_across_sizes_and_parameters():
         _levels_equal(Hl, amd.Hierarchy(rp, ci, va, smooth_vector=w))
 
 
+def test_learned_mode_from_a_model_file(tmp_path):
+    """model_path instead of model_params: the same hierarchy; a file that
+    cannot be read falls back to relaxation with smooth_status MODEL."""
+    import paper_2303_02352_amd as amd
+    from paper_2303_02352_amd import surrogate
+    A = W.lognormal7(20, 9, ell=4.0)
+    rp, ci, va = dev(A.row_ptr), dev(A.col), dev(A.val)
+    params, meta = surrogate.load_params()
+    Hp = amd.Hierarchy(rp, ci, va, model_params=params)
+    Hf = amd.Hierarchy(rp, ci, va, model_path=surrogate.DEFAULT_MODEL)
+    assert Hf.info()["smooth_status"] == amd.AMG_OK
+    _levels_equal(Hf, Hp)
+    Hm = amd.Hierarchy(rp, ci, va, model_path=tmp_path / "missing.json", smooth_sweeps=20)
+    Hr = amd.Hierarchy(rp, ci, va, smooth_vec=amd.AMG_SMOOTH_RELAX, smooth_sweeps=20)
+    assert Hm.info()["smooth_status"] == amd.AMG_ERR_MODEL
+    _levels_equal(Hm, Hr)
+
+
 @pytest.mark.parametrize("bias", [1e30, -1e30])
 def test_learned_mode_falls_back_to_relaxation(bias):
     """A parameter set whose prediction overflows (w = inf) or underflows
