@@ -332,6 +332,14 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
 int amg_batch_solve(amg_batch *bt, int32_t nrhs, const double *B, double *X, double rtol,
                     int32_t maxit, int32_t *iters, double *relres, int32_t *status);
 
+/* amg_batch_solve with one pair of vectors per system: B[s], X[s] (host arrays
+ * of nsys device pointers, s in the order given to amg_batch_setup), each an
+ * n_s x nrhs row-major block (entry (i, c) at i * nrhs + c).  Same outputs,
+ * errors and results as amg_batch_solve; INVALID when a pointer is NULL. */
+int amg_batch_solve_systems(amg_batch *bt, int32_t nrhs, const double *const *B, double *const *X,
+                            double rtol, int32_t maxit, int32_t *iters, double *relres,
+                            int32_t *status);
+
 /* Z = B_s R for every system and right-hand side (one batched V-cycle), same
  * layout as amg_batch_solve.  Synchronises. */
 int amg_batch_vcycle(amg_batch *bt, int32_t nrhs, const double *R, double *Z);

@@ -88,6 +88,8 @@ EXPORTS = {
                                   C.POINTER(C.c_void_p)]),
     "amg_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                   C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "amg_batch_solve_systems": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "amg_batch_vcycle": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "amg_batch_info": (C.c_int, [C.c_void_p, C.POINTER(amg_batch_info_t)]),
     "amg_batch_destroy": (None, [C.c_void_p]),
@@ -435,6 +437,27 @@ class Batch:
                                     _ptr(it), _ptr(rel), _ptr(pst))
         if check and st < 0:
             raise AMGError(st, "amg_batch_solve")
+        return st, it.reshape(ns, nrhs), rel.reshape(ns, nrhs), pst.reshape(ns, nrhs)
+
+    def solve_systems(self, Bs, Xs, nrhs, rtol=1e-6, maxit=1000, check=True):
+        """One (n_s * nrhs) vector per system for B and X (amg_batch_solve_systems);
+        returns as solve()."""
+        ns = len(self.sizes)
+        if int(nrhs) < 1:
+            raise ValueError("nrhs must be positive")
+        if len(Bs) != ns or len(Xs) != ns:
+            raise ValueError("one B and one X per system expected (%d systems)" % ns)
+        pb = (C.c_void_p * ns)(*[_arr(b, "B[%d]" % k, "float64", self.sizes[k] * int(nrhs),
+                                      ("cuda", self.device)) for k, b in enumerate(Bs)])
+        px = (C.c_void_p * ns)(*[_arr(x, "X[%d]" % k, "float64", self.sizes[k] * int(nrhs),
+                                      ("cuda", self.device)) for k, x in enumerate(Xs)])
+        it = np.zeros(ns * nrhs, np.int32)
+        rel = np.zeros(ns * nrhs)
+        pst = np.zeros(ns * nrhs, np.int32)
+        st = load().amg_batch_solve_systems(self.h, int(nrhs), pb, px, float(rtol), int(maxit),
+                                            _ptr(it), _ptr(rel), _ptr(pst))
+        if check and st < 0:
+            raise AMGError(st, "amg_batch_solve_systems")
         return st, it.reshape(ns, nrhs), rel.reshape(ns, nrhs), pst.reshape(ns, nrhs)
 
     def vcycle(self, R, Z, nrhs):

@@ -1422,22 +1422,33 @@ void batch_buffers(amg_batch *bt) {
   bt->nr = NR;
 }
 
+// The caller's vectors: one block with the systems one after another
+// (base), or one pointer per system (each, in the order of amg_batch_setup).
+struct UserVecs {
+  const double *base = nullptr;
+  const double *const *each = nullptr;
+  double *at(const amg_batch *bt, int sid, int nr) const {
+    return const_cast<double *>(each ? each[sid] : base + bt->user_off[sid] * nr);
+  }
+};
+
 // user layout (systems in user order) <-> internal layout (depth order)
 template <int NR>
-void batch_permute(amg_batch *bt, const double *src, double *dst, bool to_internal) {
+void batch_permute(amg_batch *bt, const UserVecs &user, double *internal, bool to_internal) {
   for (int sid = 0; sid < bt->nsys; ++sid) {
-    const int64_t ui = bt->user_off[sid] * NR, ii = bt->int_off[sid] * NR, m = bt->n0[sid] * NR;
+    const int64_t ii = bt->int_off[sid] * NR, m = bt->n0[sid] * NR;
+    double *u = user.at(bt, sid, NR);
     if (to_internal)
-      AMG_HIP(hipMemcpyAsync(dst + ii, src + ui, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
+      AMG_HIP(hipMemcpyAsync(internal + ii, u, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
     else
-      AMG_HIP(hipMemcpyAsync(dst + ui, src + ii, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
+      AMG_HIP(hipMemcpyAsync(u, internal + ii, sizeof(double) * m, hipMemcpyDeviceToDevice, bt->stream));
   }
 }
 
 constexpr int kGraphIters = 32;   // iterations per graph launch
 
 template <int NR>
-int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int maxit,
+int batch_solve_nr(amg_batch *bt, const UserVecs &Bu, const UserVecs &Xu, double rtol, int maxit,
                    int32_t *iters, double *relres, int32_t *status) {
   hipStream_t s = bt->stream;
   batch_buffers<NR>(bt);
@@ -1470,7 +1481,7 @@ int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int
     AMG_HIP(hipGraphLaunch(bt->graph_exec, s));
     AMG_HIP(hipStreamSynchronize(s));
   }
-  batch_permute<NR>(bt, bt->u.p, Xu, false);
+  batch_permute<NR>(bt, Xu, bt->u.p, false);
   std::vector<BScalars> S(static_cast<size_t>(bt->nsys) * NR);
   AMG_HIP(hipMemcpyAsync(S.data(), bt->sc.p, sizeof(BScalars) * S.size(), hipMemcpyDeviceToHost, s));
   AMG_HIP(hipStreamSynchronize(s));
@@ -1492,12 +1503,32 @@ int batch_solve_nr(amg_batch *bt, const double *Bu, double *Xu, double rtol, int
 }
 
 template <int NR>
-void batch_vcycle_nr(amg_batch *bt, const double *Ru, double *Zu) {
+void batch_vcycle_nr(amg_batch *bt, const UserVecs &Ru, const UserVecs &Zu) {
   batch_buffers<NR>(bt);
   batch_permute<NR>(bt, Ru, bt->r.p, true);
   bvcycle<NR>(bt, nullptr, bt->r.p, bt->w.p);
-  batch_permute<NR>(bt, bt->w.p, Zu, false);
+  batch_permute<NR>(bt, Zu, bt->w.p, false);
   AMG_HIP(hipStreamSynchronize(bt->stream));
+}
+
+}  // namespace
+}  // namespace amg
+
+namespace amg {
+namespace {
+
+int batch_solve_any(amg_batch *bt, int32_t nrhs, const UserVecs &B, const UserVecs &X, double rtol,
+                    int32_t maxit, int32_t *iters, double *relres, int32_t *status) {
+  return api_guarded([&] {
+    switch (nrhs) {
+      case 1: return amg::batch_solve_nr<1>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 2: return amg::batch_solve_nr<2>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 4: return amg::batch_solve_nr<4>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 8: return amg::batch_solve_nr<8>(bt, B, X, rtol, maxit, iters, relres, status);
+      case 16: return amg::batch_solve_nr<16>(bt, B, X, rtol, maxit, iters, relres, status);
+      default: return amg::api_set_error(AMG_ERR_UNSUPPORTED, "nrhs must be 1, 2, 4, 8 or 16");
+    }
+  });
 }
 
 }  // namespace
@@ -1548,31 +1579,42 @@ int amg_batch_setup(int32_t nsys, const amg_csr *A, const amg_params *p, amg_bat
   return AMG_OK;
 }
 
+
 int amg_batch_solve(amg_batch *bt, int32_t nrhs, const double *B, double *X, double rtol,
                     int32_t maxit, int32_t *iters, double *relres, int32_t *status) {
   if (!bt || !B || !X || !iters || !relres || !status || !(rtol > 0.0) || maxit < 1)
     return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
-  return amg::api_guarded([&] {
-    switch (nrhs) {
-      case 1: return amg::batch_solve_nr<1>(bt, B, X, rtol, maxit, iters, relres, status);
-      case 2: return amg::batch_solve_nr<2>(bt, B, X, rtol, maxit, iters, relres, status);
-      case 4: return amg::batch_solve_nr<4>(bt, B, X, rtol, maxit, iters, relres, status);
-      case 8: return amg::batch_solve_nr<8>(bt, B, X, rtol, maxit, iters, relres, status);
-      case 16: return amg::batch_solve_nr<16>(bt, B, X, rtol, maxit, iters, relres, status);
-      default: return amg::api_set_error(AMG_ERR_UNSUPPORTED, "nrhs must be 1, 2, 4, 8 or 16");
-    }
-  });
+  amg::UserVecs b, x;
+  b.base = B;
+  x.base = X;
+  return amg::batch_solve_any(bt, nrhs, b, x, rtol, maxit, iters, relres, status);
+}
+
+int amg_batch_solve_systems(amg_batch *bt, int32_t nrhs, const double *const *B, double *const *X,
+                            double rtol, int32_t maxit, int32_t *iters, double *relres,
+                            int32_t *status) {
+  if (!bt || !B || !X || !iters || !relres || !status || !(rtol > 0.0) || maxit < 1)
+    return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
+  for (int sid = 0; sid < bt->nsys; ++sid)
+    if (!B[sid] || !X[sid]) return amg::api_set_error(AMG_ERR_INVALID, "NULL system vector");
+  amg::UserVecs b, x;
+  b.each = B;
+  x.each = X;
+  return amg::batch_solve_any(bt, nrhs, b, x, rtol, maxit, iters, relres, status);
 }
 
 int amg_batch_vcycle(amg_batch *bt, int32_t nrhs, const double *R, double *Z) {
   if (!bt || !R || !Z || R == Z) return amg::api_set_error(AMG_ERR_INVALID, "bad argument");
+  amg::UserVecs r, z;
+  r.base = R;
+  z.base = Z;
   return amg::api_guarded([&] {
     switch (nrhs) {
-      case 1: amg::batch_vcycle_nr<1>(bt, R, Z); break;
-      case 2: amg::batch_vcycle_nr<2>(bt, R, Z); break;
-      case 4: amg::batch_vcycle_nr<4>(bt, R, Z); break;
-      case 8: amg::batch_vcycle_nr<8>(bt, R, Z); break;
-      case 16: amg::batch_vcycle_nr<16>(bt, R, Z); break;
+      case 1: amg::batch_vcycle_nr<1>(bt, r, z); break;
+      case 2: amg::batch_vcycle_nr<2>(bt, r, z); break;
+      case 4: amg::batch_vcycle_nr<4>(bt, r, z); break;
+      case 8: amg::batch_vcycle_nr<8>(bt, r, z); break;
+      case 16: amg::batch_vcycle_nr<16>(bt, r, z); break;
       default: return amg::api_set_error(AMG_ERR_UNSUPPORTED, "nrhs must be 1, 2, 4, 8 or 16");
     }
     return AMG_OK;

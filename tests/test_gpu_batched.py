@@ -115,6 +115,24 @@ def test_batched_masks_keep_converged_pairs_frozen():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+def test_batched_solve_with_one_vector_per_system():
+    """amg_batch_solve_systems (B[s], X[s] apart) gives the bits of amg_batch_solve
+    on the stacked block, with initial guesses taken from X[s]."""
+    systems = [W.poisson7(N) for N in (9, 6, 5)]
+    bt = _batch(systems, precision=1)
+    nrhs = 8
+    bs = [np.ascontiguousarray(A.scipy() @ W.batched_rhs(s, A.n, nrhs).T) for s, A in enumerate(systems)]
+    x0 = [0.1 * W.uniform_pm1(30 + s, A.n * nrhs) for s, A in enumerate(systems)]
+    X = dev(_stack(x0))
+    st, its, rel, pst = bt.solve(dev(_stack(bs)), X, nrhs)
+    Xs = [dev(x) for x in x0]
+    st2, its2, rel2, pst2 = bt.solve_systems([dev(b) for b in bs], Xs, nrhs)
+    say("  stacked %s, per system %s" % (its.max(), its2.max()))
+    assert st == st2 == 0
+    assert np.array_equal(its, its2) and np.array_equal(rel, rel2) and np.array_equal(pst, pst2)
+    assert np.array_equal(bits(host(X)), bits(np.concatenate([host(x) for x in Xs])))
+
+
 def test_batched_errors():
     import paper_2303_02352_amd as amd
     systems = [W.poisson7(N) for N in (6, 5)]
