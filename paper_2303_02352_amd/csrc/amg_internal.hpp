@@ -438,6 +438,7 @@ struct amg_hierarchy {
   // levels [tail_start, levels) run inside one workgroup (coarse-tail kernel)
   int tail_start = 0;
   int tail_w = 0;              // widest SELL slice (slots) among the tail levels
+  bool tail_general = false;   // the tail runs the general cycle (k_cycle_tail_g, 5 vectors per level)
   amg::dvec<unsigned char> tail_desc_d, tail_desc_f;   // TailDesc<double> / <float> arrays
   // PCG vectors
   amg::dvec<double> u, r, w, v, d, q;

@@ -667,12 +667,43 @@ __device__ __forceinline__ T tail_dot(const TailRow<T, W> &R, const T *X) {
   return acc;
 }
 
+// The direct coarsest solve of the tail kernels, X = A^-1 rhs with the
+// explicit inverse (binary64): X_i = sum over c ascending of Ainv[c n + i]
+// rhs_c.  The workgroup forms the products of K columns at a time (one
+// coalesced load per thread) into LDS, then thread i adds its row's
+// products in column order: the same products and the same order of sums
+// as a row-by-row loop, with one memory round trip per K columns instead of
+// a chain of them.  n <= the workgroup size; called by the whole workgroup.
+constexpr int kTailGemv = 4096;   // LDS doubles for the staged products
+static_assert(kDenseMax <= kTailThreads, "one thread per row of the dense coarsest level");
+
+template <class T>
+__device__ __forceinline__ void tail_dense_solve(int n, const double *__restrict__ Ainv, const T *rhs, T *X,
+                                                 double *P) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int K = max(1, min(n, kTailGemv / n));
+  double acc = 0.0;
+  for (int c0 = 0; c0 < n; c0 += K) {
+    const int kc = min(K, n - c0);
+    for (int e = t; e < kc * n; e += nt) {
+      const int cc = e / n, i = e - cc * n;
+      P[e] = Ainv[static_cast<int64_t>(c0 + cc) * n + i] * static_cast<double>(rhs[c0 + cc]);
+    }
+    __syncthreads();
+    if (t < n)
+      for (int cc = 0; cc < kc; ++cc) acc = acc + P[cc * n + t];
+    __syncthreads();
+  }
+  if (t < n) X[t] = static_cast<T>(acc);
+}
+
 template <class T, int W>
 __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(
     const int *skip, int m, const TailDesc<T> *__restrict__ D, const double *__restrict__ Ainv,
     int dense, int pre, int post, int csw, const T *__restrict__ top_rhs, T *__restrict__ top_out) {
   AMG_SKIP_IF_DONE();
   __shared__ T lds[kTailLds];
+  __shared__ double gemv[kTailGemv];
   const int t = threadIdx.x, nt = blockDim.x;
   // level j: R = lds + off, X0 = R + n, X1 = R + 2n, Tt = R + 3n; bit j of
   // `sel` says which iterate holds the level's current x (uniform)
@@ -732,21 +763,7 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(
     const T *rhs = lds + L.lds;
     T *X = lds + L.lds + n, *Y = lds + L.lds + 2 * n;
     if (dense) {
-      for (int i = t; i < n; i += nt) {
-        double acc = 0.0;
-        const double *col = Ainv + i;
-        int c = 0;
-        for (; c + 4 <= n; c += 4) {
-          const double a0 = col[static_cast<int64_t>(c) * n], a1 = col[static_cast<int64_t>(c + 1) * n];
-          const double a2 = col[static_cast<int64_t>(c + 2) * n], a3 = col[static_cast<int64_t>(c + 3) * n];
-          acc = acc + a0 * static_cast<double>(rhs[c]);
-          acc = acc + a1 * static_cast<double>(rhs[c + 1]);
-          acc = acc + a2 * static_cast<double>(rhs[c + 2]);
-          acc = acc + a3 * static_cast<double>(rhs[c + 3]);
-        }
-        for (; c < n; ++c) acc = acc + col[static_cast<int64_t>(c) * n] * static_cast<double>(rhs[c]);
-        X[i] = static_cast<T>(acc);
-      }
+      tail_dense_solve<T>(n, Ainv, rhs, X, gemv);
     } else {
       TailRow<T, W> R;
       if (t < n) {
@@ -789,6 +806,170 @@ __global__ void __launch_bounds__(kTailThreads) k_vcycle_tail(
   {
     const TailDesc<T> L = D[0];
     const T *X = lds + L.lds + ((sel & 1) ? 2 * L.n : L.n);
+    for (int i = t; i < L.n; i += nt) top_out[i] = X[i];
+  }
+}
+
+// Coarse tail of the general cycle (binary64, l1-Jacobi smoothing on every
+// level, direct or l1-Jacobi coarsest solve) for V-, H- and W-cycles: the
+// levels from the tail's first on, in one workgroup.  Level j of the tail
+// (level k0 + j of the hierarchy) makes g_j coarse-grid corrections per
+// visit: e = C(r_c), then e += C(r_c - A_c e) (W: g = 2; H: g = 2 on odd
+// levels; V: g = 1).  The recursion runs as a loop over (level, direction)
+// with the per-level state in bit masks (uniform over the workgroup).  Five
+// LDS vectors per level: right-hand side, two iterates, scaled residual, and
+// E, the sum of the corrections this level's cycles return to the level
+// above.  Same operations and fold orders as the kernel-by-kernel cycle.
+template <int W>
+__global__ void __launch_bounds__(kTailThreads) k_cycle_tail_g(
+    const int *skip, int m, int k0, int cycle, const TailDesc<double> *__restrict__ D,
+    const double *__restrict__ Ainv, int dense, int pre, int post, int csw,
+    const double *__restrict__ top_rhs, double *__restrict__ top_out) {
+  AMG_SKIP_IF_DONE();
+  __shared__ double lds[kTailLds];
+  __shared__ double gemv[kTailGemv];
+  const int t = threadIdx.x, nt = blockDim.x;
+  auto corrections = [&](int j) {
+    const int k = k0 + j;
+    return cycle == AMG_CYCLE_W ? 2 : (cycle == AMG_CYCLE_H && k % 2 == 1 ? 2 : 1);
+  };
+  unsigned long long sel = 0;     // bit j: level j's current iterate is its second one
+  unsigned long long more = 0;    // bit j: level j still owes a second correction
+  unsigned long long first = 0;   // bit j: level j has not received a correction yet
+  auto iterate = [&](const TailDesc<double> &L, int j) {
+    return lds + L.lds + (((sel >> j) & 1) ? 2 : 1) * L.n;
+  };
+  {
+    const TailDesc<double> L = D[0];
+    for (int i = t; i < L.n; i += nt) lds[L.lds + i] = top_rhs[i];
+  }
+  __syncthreads();
+  int j = 0;
+  bool down = true;
+  for (;;) {
+    const TailDesc<double> L = D[j];
+    const int n = L.n;
+    double *rhs = lds + L.lds;
+    if (down && j == m - 1) {
+      // ---- coarsest level, from zero
+      double *X = rhs + n, *Y = rhs + 2 * n;
+      if (dense) {
+        tail_dense_solve<double>(n, Ainv, rhs, X, gemv);
+      } else {
+        TailRow<double, W> R;
+        if (t < n) {
+          tail_load<double, W>(L, t, R);
+          X[t] = R.dinv * rhs[t];
+        }
+        __syncthreads();
+        for (int q = 1; q < csw; ++q) {
+          if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<double, W>(R, X));
+          __syncthreads();
+          double *tmp = X; X = Y; Y = tmp;
+        }
+      }
+      if (X != rhs + n) sel |= 1ull << j;
+      else sel &= ~(1ull << j);
+      __syncthreads();
+      if (j == 0) break;
+      --j;
+      down = false;
+      continue;
+    }
+    if (down) {
+      // ---- pre-smoothing from zero, scaled residual, restriction
+      const TailDesc<double> C = D[j + 1];
+      double *X = rhs + n, *Y = rhs + 2 * n, *Tt = rhs + 3 * n;
+      TailRow<double, W> R;
+      double pv = 0.0;
+      int mb = 0, mc = 0, mm[8];
+      if (t < L.nc) {
+        mb = L.mptr[t];
+        mc = L.mptr[t + 1] - mb;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < mc) mm[k] = L.mem[mb + k];
+      }
+      if (t < n) {
+        tail_load<double, W>(L, t, R);
+        pv = L.pval[t];
+        X[t] = (pre > 0) ? R.dinv * rhs[t] : 0.0;
+      }
+      __syncthreads();
+      for (int q = 1; q < pre; ++q) {
+        if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<double, W>(R, X));
+        __syncthreads();
+        double *tmp = X; X = Y; Y = tmp;
+      }
+      if (t < n) Tt[t] = pv * (rhs[t] - tail_dot<double, W>(R, X));
+      if (X != rhs + n) sel |= 1ull << j;
+      else sel &= ~(1ull << j);
+      __syncthreads();
+      if (t < L.nc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k < mc) acc = acc + Tt[mm[k]];
+        for (int k = 8; k < mc; ++k) acc = acc + Tt[L.mem[mb + k]];
+        lds[C.lds + t] = acc;
+      }
+      __syncthreads();
+      first |= 1ull << j;
+      if (corrections(j) > 1) more |= 1ull << j;
+      else more &= ~(1ull << j);
+      ++j;
+      continue;
+    }
+    // ---- up: level j receives the result of a cycle on level j + 1
+    const TailDesc<double> C = D[j + 1];
+    const double *e_in = iterate(C, j + 1);
+    double *Ebuf = lds + C.lds + 4 * C.n;
+    const bool is_first = (first >> j) & 1, owes = (more >> j) & 1;
+    const double *E = e_in;
+    if (!is_first || owes) {
+      for (int i = t; i < C.n; i += nt) Ebuf[i] = is_first ? e_in[i] : Ebuf[i] + e_in[i];
+      __syncthreads();
+      E = Ebuf;
+    }
+    first &= ~(1ull << j);
+    if (owes) {
+      // r_c <- r_c - A_c e (each row reads and writes only its own entry of r_c)
+      more &= ~(1ull << j);
+      double *rc = lds + C.lds;
+      if (t < C.n) {
+        TailRow<double, W> Rc;
+        tail_load<double, W>(C, t, Rc);
+        rc[t] = rc[t] - tail_dot<double, W>(Rc, E);
+      }
+      __syncthreads();
+      ++j;
+      down = true;
+      continue;
+    }
+    // ---- x += P e, then the post-smoothing sweeps
+    {
+      double *X = iterate(L, j);
+      double *Y = (X == rhs + n) ? rhs + 2 * n : rhs + n;
+      TailRow<double, W> R;
+      if (t < n) {
+        X[t] = X[t] + L.pval[t] * E[L.agg[t]];
+        if (post > 0) tail_load<double, W>(L, t, R);
+      }
+      __syncthreads();
+      for (int q = 0; q < post; ++q) {
+        if (t < n) Y[t] = X[t] + R.dinv * (rhs[t] - tail_dot<double, W>(R, X));
+        __syncthreads();
+        double *tmp = X; X = Y; Y = tmp;
+      }
+      if (X != rhs + n) sel |= 1ull << j;
+      else sel &= ~(1ull << j);
+    }
+    if (j == 0) break;
+    --j;
+  }
+  {
+    const TailDesc<double> L = D[0];
+    const double *X = iterate(L, 0);
     for (int i = t; i < L.n; i += nt) top_out[i] = X[i];
   }
 }
@@ -1454,8 +1635,11 @@ void smooth_more_g(amg_hierarchy *h, const int *skip, int k, int type, int pass,
     const double *d = (type == AMG_RELAX_L1_JACOBI) ? L.dinv.p : L.djac.p;
     double *a = x, *b = L.t.p;
     for (int q = 0; q < nsw; ++q) {
-      hipLaunchKernelGGL(k_csr_sweep, grid_for(n), dim3(kBlock), 0, s, skip, n, L.A.rp.p, L.A.ci.p, L.A.v.p,
-                         d, r, a, b);
+      if (type == AMG_RELAX_L1_JACOBI)   // the V-cycle's sweep kernels: the same fold and 1 / l1 bits
+        launch_sweep<double>(skip, L, r, a, b, s);
+      else
+        hipLaunchKernelGGL(k_csr_sweep, grid_for(n), dim3(kBlock), 0, s, skip, n, L.A.rp.p, L.A.ci.p,
+                           L.A.v.p, d, r, a, b);
       std::swap(a, b);
     }
     if (a != x) hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kBlock), 0, s, skip, n, a, x);
@@ -1492,6 +1676,14 @@ void cycle_general(amg_hierarchy *h, const int *skip, int k, const double *rhs, 
   const int n = L.A.n;
   const int nl = static_cast<int>(h->L.size());
   const amg_params &P = h->p;
+  if (h->tail_general && k >= h->tail_start) {   // this level and all below in one workgroup
+    auto kern = (h->tail_w <= 8) ? k_cycle_tail_g<8> : k_cycle_tail_g<16>;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kTailThreads), 0, s, skip, nl - k, k, P.cycle_type,
+                       tail_desc<double>(h) + (k - h->tail_start), h->Ainv.p, h->coarse_dense,
+                       P.pre_sweeps, P.post_sweeps, P.coarse_sweeps, rhs, out);
+    AMG_LAUNCH_CHECK();
+    return;
+  }
   if (k == nl - 1) {
     if (h->coarse_dense) {   // the coarse-tail kernel holding only this level: z = A^-1 r
       auto kern = (h->tail_w <= 8) ? k_vcycle_tail<double, 8> : k_vcycle_tail<double, 16>;
@@ -1703,8 +1895,10 @@ void enqueue_iteration(amg_hierarchy *h, PcgState ps) {
   AMG_LAUNCH_CHECK();
 }
 
+// vectors: LDS vectors per row and level (4 for the V-cycle tail, 5 for the
+// general cycle's)
 template <class T>
-void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32) {
+void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32, int vectors) {
   std::vector<TailDesc<T>> D;
   int lds = 0;
   for (size_t k = h->tail_start; k < h->L.size(); ++k) {
@@ -1713,7 +1907,7 @@ void upload_tail(amg_hierarchy *h, dvec<unsigned char> &dst, bool fp32) {
     t.n = L.A.n;
     t.nc = L.nc;
     t.lds = lds;
-    lds += 4 * L.A.n;
+    lds += vectors * L.A.n;
     t.sptr = L.S.sptr.p;
     t.col = L.S.col.p;
     t.val = val_ref<T>(L.S).val;   // the tail reads plain values
@@ -1761,14 +1955,23 @@ void alloc_solve_buffers(amg_hierarchy *h) {
   // binary64 sweeps, which the tail kernel does not provide; the general
   // cycle uses it for the direct coarsest solve only)
   const bool general = general_cycle(h);
-  const bool tail_ok = !(mixed && h->p.precond && !h->coarse_dense && nl > 1) && !general;
+  // the general cycle's own tail: l1-Jacobi smoothing everywhere, a direct
+  // or l1-Jacobi coarsest solve (V/H/W); other smoothers run level by level
+  h->tail_general = general && h->p.relax_type == AMG_RELAX_L1_JACOBI &&
+                    (h->coarse_dense || h->p.coarse_relax == AMG_RELAX_L1_JACOBI);
+  const int vectors = h->tail_general ? 5 : 4;
+  const bool tail_ok = !(mixed && h->p.precond && !h->coarse_dense && nl > 1) && (!general || h->tail_general);
+  // (a W-cycle visits the j-th tail level 2^j times: at most 12 levels, so
+  // that one tail launch stays short whatever the hierarchy's depth)
+  constexpr int kTailGeneralLevels = 12;
   for (int k = nl - 1; tail_ok && k >= 0; --k) {
     const int nk = h->L[k].A.n;
-    if (nk > kTailRows || used + 4 * nk > kTailLds) break;
-    used += 4 * nk;
+    if (nk > kTailRows || used + vectors * nk > kTailLds) break;
+    if (h->tail_general && nl - k > kTailGeneralLevels) break;
+    used += vectors * nk;
     h->tail_start = k;
   }
-  if (general && h->coarse_dense) {
+  if (general && !h->tail_general && h->coarse_dense) {
     h->tail_start = nl - 1;
     used = 4 * h->L[nl - 1].A.n;
   }
@@ -1783,8 +1986,8 @@ void alloc_solve_buffers(amg_hierarchy *h) {
     AMG_HIP(hipStreamSynchronize(h->stream));
     for (int q = 0; q < S.nslices; ++q) h->tail_w = std::max(h->tail_w, (sp[q + 1] - sp[q]) / kSlice);
   }
-  upload_tail<double>(h, h->tail_desc_d, false);
-  if (mixed) upload_tail<float>(h, h->tail_desc_f, true);
+  upload_tail<double>(h, h->tail_desc_d, false, vectors);
+  if (mixed) upload_tail<float>(h, h->tail_desc_f, true, vectors);
   if (general) prepare_general(h);
   h->sc.alloc(1);
   AMG_HIP(hipMemsetAsync(h->sc.p, 0, sizeof(Scalars), h->stream));
