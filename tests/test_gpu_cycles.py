@@ -58,6 +58,19 @@ def test_coarsest_sweeps(crelax):
     _check(A, params)
 
 
+@pytest.mark.parametrize("cycle", [1, 2])
+@pytest.mark.parametrize("coarse_solver", [0, 1])
+def test_l1_cycles_in_the_coarse_tail(cycle, coarse_solver):
+    """H/W-cycles with l1-Jacobi everywhere run their levels below 1024 rows
+    in one workgroup (the general cycle's tail), with a direct or an
+    l1-Jacobi coarsest solve."""
+    A = W.poisson7(26)
+    params = dict(cycle_type=cycle, relax_type=4, coarse_solver=coarse_solver, coarse_relax=4,
+                  coarse_sweeps=6, coarse_max=300, pre_sweeps=3, post_sweeps=2)
+    say("tail cycle", cycle, "coarse solver", coarse_solver)
+    _check(A, params)
+
+
 @pytest.mark.parametrize("relax", [1, 3])
 def test_gauss_seidel_multi_launch_levels(relax):
     """48^3 = 110592 rows on the fine level: one launch per schedule level."""
