@@ -466,7 +466,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *A);
 void coarse_factor(amg_hierarchy *h);
 void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s);  // out: n+1 entries
 int device_read_int(const int *p, hipStream_t s);
-void finalize_level(Level &Lv, hipStream_t s, bool want_float);  // l1 diagonal + SELL from Lv.A
+void finalize_level(Level &Lv, hipStream_t s, bool want_float, bool want_codes);  // l1 diagonal + SELL from Lv.A
 double wall_ms();
 
 // -------------------------------------------------------- solve interface

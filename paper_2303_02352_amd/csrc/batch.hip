@@ -60,6 +60,7 @@ struct BLevel {
   dvec<double> inv_pool;        // column-major inverses of the coarsest matrices
   int cpl = 1;                  // tuned columns per lane (sweeps / residual)
   int cpl_corr = 1;             // tuned columns per lane of the corrected sweep
+  int cpl_wide = 1;             // tuned columns per lane of the widening last sweep (level 0, binary32)
   int tune_best = 1;
   // RHS-interleaved work vectors
   dvec<double> r, x, t;
@@ -290,6 +291,100 @@ __device__ __forceinline__ void brow(const int *__restrict__ sptr, const int *__
   l1 = m;
 }
 
+// Compact columns and value codes of a stacked level (the single-system SELL
+// forms: 16-bit offsets from a per-slot-group base and one byte per slot
+// naming an entry of the level's value table, both stored by quads of four
+// slots per lane).  code == nullptr: the level has more than kDictMax
+// distinct values and is read from col / val.
+template <class T>
+struct BCodes {
+  const int *cbase, *qptr;
+  const unsigned short *cdel;
+  const unsigned char *code;
+  const T *dict;
+  int ndict;
+};
+
+// The value table in LDS (one copy per workgroup); called by every thread.
+template <class T>
+__device__ __forceinline__ void stage_bdict(const BCodes<T> &K, T *sd) {
+  if (!K.code) return;   // uniform
+  for (int i = threadIdx.x; i < K.ndict; i += blockDim.x) sd[i] = K.dict[i];
+  __syncthreads();
+}
+
+// brow through the compact columns and codes: the same slots, values and
+// fold order (slot order, padding slots included), so the same bits.
+template <class T, int NR, int CPL, bool kCorr, int KB>
+__device__ __forceinline__ void brow_coded(const BCodes<T> &K, const T *sd, int s, int b, int width,
+                                           const T *__restrict__ x, int lane, int cb, T (&acc)[CPL],
+                                           T &l1, const int *__restrict__ agg,
+                                           const T *__restrict__ pval, const T *__restrict__ e) {
+  const int64_t q = static_cast<int64_t>(K.qptr[s]) * 64 + lane;
+  const unsigned long long *dq = reinterpret_cast<const unsigned long long *>(K.cdel) + q;
+  const unsigned *cq = reinterpret_cast<const unsigned *>(K.code) + q;
+  const int *bp = K.cbase + (b >> 6);
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) acc[j] = T(0);
+  T m = T(0);
+  for (int k0 = 0; k0 < width; k0 += 4) {
+    const int t = k0 >> 2;
+    const unsigned long long d = dq[static_cast<int64_t>(t) * 64];
+    const unsigned w = cq[static_cast<int64_t>(t) * 64];
+    int c[4];
+    T a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      c[j] = bp[k0 + j] + static_cast<int>((d >> (16 * j)) & 0xffffu);   // in range: cbase is padded
+      a[j] = sd[(w >> (8 * j)) & 0xffu];
+    }
+    const int nv = width - k0 < 4 ? width - k0 : 4;
+#pragma unroll
+    for (int u0 = 0; u0 < 4; u0 += KB) {
+      if (u0 >= nv) break;
+      int cc[KB];
+      T xv[KB][CPL];
+      const int nb = nv - u0 < KB ? nv - u0 : KB;
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        cc[u] = c[u0 + u];
+        if (u < nb) ldcols<T, CPL>(x + static_cast<int64_t>(cc[u]) * NR + cb, xv[u]);
+      }
+      if constexpr (kCorr) correct<T, NR, CPL, KB>(cc, nb, agg, pval, e, cb, xv);
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
+        if (u < nb) {
+          m = m + fabs(a[u0 + u]);
+#pragma unroll
+          for (int jj = 0; jj < CPL; ++jj) acc[jj] = acc[jj] + a[u0 + u] * xv[u][jj];
+        }
+    }
+  }
+  l1 = m;
+}
+
+// Row `row` from the codes where its slice is compact and the level coded,
+// else from col / val.
+template <class T, int NR, int CPL, bool kCorr = false>
+__device__ __forceinline__ void brow_k(const BCodes<T> &K, const T *sd, const int *__restrict__ sptr,
+                                       const int *__restrict__ col, const T *__restrict__ val,
+                                       const T *__restrict__ x, int row, int cb, T (&acc)[CPL], T &l1,
+                                       const int *__restrict__ agg = nullptr,
+                                       const T *__restrict__ pval = nullptr,
+                                       const T *__restrict__ e = nullptr) {
+  if (K.code) {
+    const int s = row >> 6;
+    const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
+    if (width > 0 && K.cbase[b >> 6] >= 0) {
+      constexpr int kBytes = CPL * static_cast<int>(sizeof(T)) * (kCorr ? 2 : 1);
+      constexpr int KB = kBytes <= 64 ? 4 : (kBytes <= 128 ? 2 : 1);
+      brow_coded<T, NR, CPL, kCorr, KB>(K, sd, s, b, width, x, row & 63, cb, acc, l1, agg, pval, e);
+      return;
+    }
+  }
+  brow<T, NR, CPL, kCorr>(sptr, col, val, x, row, cb, acc, l1, agg, pval, e);
+}
+
 // xn = x + dinv (rhs - A x) on rows [0, n).  TO = double with T = float
 // writes the binary32 result widened (exactly) to binary64: the last sweep
 // of a binary32 cycle then delivers the binary64 output itself.
@@ -299,8 +394,11 @@ __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
                                                    const int *__restrict__ col,
                                                    const T *__restrict__ val,
                                                    const T *__restrict__ rhs,
-                                                   const T *__restrict__ x, TO *__restrict__ xn) {
+                                                   const T *__restrict__ x, TO *__restrict__ xn,
+                                                   BCodes<T> K) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sd[kDictMax];
+  stage_bdict(K, sd);
   constexpr int LPR = NR / CPL;
   const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
   for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
@@ -308,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], l1;
-  brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
+  brow_k<T, NR, CPL>(K, sd, sptr, col, val, x, row, cb, acc, l1);
   const T di = T(1) / l1;
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
   T xo[CPL], bo[CPL];
@@ -334,8 +432,11 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
                                                         const T *__restrict__ x,
                                                         const int *__restrict__ agg,
                                                         const T *__restrict__ pval,
-                                                        const T *__restrict__ e, T *__restrict__ xn) {
+                                                        const T *__restrict__ e, T *__restrict__ xn,
+                                                        BCodes<T> K) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sd[kDictMax];
+  stage_bdict(K, sd);
   constexpr int LPR = NR / CPL;
   const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
   for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
@@ -343,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], m;
-  brow<T, NR, CPL, true>(sptr, col, val, x, row, cb, acc, m, agg, pval, e);
+  brow_k<T, NR, CPL, true>(K, sd, sptr, col, val, x, row, cb, acc, m, agg, pval, e);
   const T di = T(1) / m;
   const T pr = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
@@ -368,8 +469,11 @@ __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
                                                    const T *__restrict__ val,
                                                    const T *__restrict__ pval,
                                                    const T *__restrict__ rhs,
-                                                   const T *__restrict__ x, T *__restrict__ t) {
+                                                   const T *__restrict__ x, T *__restrict__ t,
+                                                   BCodes<T> K) {
   AMG_SKIP_IF_DONE();
+  __shared__ T sd[kDictMax];
+  stage_bdict(K, sd);
   constexpr int LPR = NR / CPL;
   const VSpan sp = vspan(static_cast<int64_t>(n) * LPR);
   for (int64_t vb = sp.b; vb < sp.e; vb += sp.step) {
@@ -377,7 +481,7 @@ __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], l1;
-  brow<T, NR, CPL>(sptr, col, val, x, row, cb, acc, l1);
+  brow_k<T, NR, CPL>(K, sd, sptr, col, val, x, row, cb, acc, l1);
   const T p = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
   T bo[CPL], out[CPL];
@@ -597,9 +701,12 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
                                                       const double *__restrict__ b,
                                                       const double *__restrict__ u,
                                                       double *__restrict__ r,
-                                                      double *__restrict__ part) {
+                                                      double *__restrict__ part,
+                                                      BCodes<double> K) {
   constexpr int PC = pcg_cols<NR>(), LPR = NR / PC;
   __shared__ double red[kBlock * PC];
+  __shared__ double sd[kDictMax];
+  stage_bdict(K, sd);
   const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int cb = (threadIdx.x % LPR) * PC;
   double rr[PC];
@@ -607,7 +714,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
   for (int j = 0; j < PC; ++j) rr[j] = 0.0;
   for (int row = trow0[tile] + threadIdx.x / LPR; row < trow1[tile]; row += kBlock / LPR) {
     double acc[PC], l1, bo[PC], ro[PC];
-    brow<double, NR, PC>(sptr, col, val, u, row, cb, acc, l1);
+    brow_k<double, NR, PC>(K, sd, sptr, col, val, u, row, cb, acc, l1);
     const int64_t o = static_cast<int64_t>(row) * NR + cb;
     ldcols<double, PC>(b + o, bo);
 #pragma unroll
@@ -628,8 +735,10 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
     const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ sptr, const int *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ w, const double *__restrict__ r, const double *__restrict__ q,
-    double *__restrict__ v, double *__restrict__ part) {
+    double *__restrict__ v, double *__restrict__ part, BCodes<double> K) {
   AMG_SKIP_IF_DONE();
+  __shared__ double sd[kDictMax];
+  stage_bdict(K, sd);
   constexpr int LPR = NR / PC;
   __shared__ double red[kBlock * PC];
   const int cb = (threadIdx.x % LPR) * PC;
@@ -641,7 +750,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
   for (int j = 0; j < PC; ++j) al[j] = be[j] = ga[j] = 0.0;
   for (int row = trow0[tile] + threadIdx.x / LPR; row < trow1[tile]; row += kBlock / LPR) {
     double acc[PC], l1, wo[PC], ro[PC], qo[PC];
-    brow<double, NR, PC>(sptr, col, val, w, row, cb, acc, l1);
+    brow_k<double, NR, PC>(K, sd, sptr, col, val, w, row, cb, acc, l1);
     const int64_t o = static_cast<int64_t>(row) * NR + cb;
     stcols<double, PC>(v + o, acc);
     ldcols<double, PC>(w + o, wo);
@@ -886,12 +995,21 @@ template <> const float *bdinv<float>(const Level &L) { return L.dinvf.p; }
 template <class T> const T *bpval(const Level &L);
 template <> const double *bpval<double>(const Level &L) { return L.pval.p; }
 template <> const float *bpval<float>(const Level &L) { return L.pvalf.p; }
+template <class T> const T *bdict(const Sell &S);
+template <> const double *bdict<double>(const Sell &S) { return S.dict.p; }
+template <> const float *bdict<float>(const Sell &S) { return S.dictf.p; }
+template <class T>
+BCodes<T> bcodes(const Level &L) {
+  const Sell &S = L.S;
+  const bool coded = S.ndict > 0 && S.cdel.p && S.code.p;
+  return BCodes<T>{S.cbase.p, S.qptr.p, S.cdel.p, coded ? S.code.p : nullptr, bdict<T>(S), S.ndict};
+}
 
 template <class T, int NR, int CPL>
 void launch_bsweep(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
   constexpr int LPR = NR / CPL;
   hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), rgrid((k_bsweep<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
-                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn);
+                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn, bcodes<T>(L.L));
 }
 
 template <int NR, int CPL>
@@ -899,14 +1017,16 @@ void launch_bsweep_widen(const int *skip, BLevel &L, int n, const float *rhs, co
                          double *xn, hipStream_t s) {
   constexpr int LPR = NR / CPL;
   hipLaunchKernelGGL((k_bsweep<float, NR, CPL, double>), rgrid((k_bsweep<float, NR, CPL, double>), static_cast<int64_t>(n) * LPR),
-                     dim3(kBlock), 0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, L.L.S.valf.p, rhs, x, xn);
+                     dim3(kBlock), 0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, L.L.S.valf.p, rhs, x, xn,
+                     bcodes<float>(L.L));
 }
 
 template <class T, int NR, int CPL>
 void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
   constexpr int LPR = NR / CPL;
   hipLaunchKernelGGL((k_bresid<T, NR, CPL>), rgrid((k_bresid<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
-                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t);
+                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t,
+                     bcodes<T>(L.L));
 }
 
 template <class T, int NR, int CPL>
@@ -915,7 +1035,7 @@ void launch_bsweep_corr(const int *skip, BLevel &L, int n, const T *rhs, const T
   constexpr int LPR = NR / CPL;
   hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), rgrid((k_bsweep_corr<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock),
                      0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p,
-                     bpval<T>(L.L), e, xn);
+                     bpval<T>(L.L), e, xn, bcodes<T>(L.L));
 }
 
 // Calls f(std::integral_constant<int, C>) with C = cpl when cpl divides NR
@@ -943,7 +1063,7 @@ void sweep_any(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *x
 template <int NR>
 void sweep_widen_any(const int *skip, BLevel &L, int n, const float *rhs, const float *x, double *xn,
                      hipStream_t s) {
-  with_cpl<NR>(L.cpl, [&](auto C) { launch_bsweep_widen<NR, decltype(C)::value>(skip, L, n, rhs, x, xn, s); });
+  with_cpl<NR>(L.cpl_wide, [&](auto C) { launch_bsweep_widen<NR, decltype(C)::value>(skip, L, n, rhs, x, xn, s); });
 }
 
 template <class T, int NR>
@@ -1043,7 +1163,8 @@ void launch_spmm_dots_pc(amg_batch *bt, const int *skip) {
   const BLevel &L0 = bt->B[0];
   hipLaunchKernelGGL((k_bpcg_spmm_dots<NR, PC>), rgrid((k_bpcg_spmm_dots<NR, PC>), static_cast<int64_t>(bt->ntiles) * kBlock),
                      dim3(kBlock), 0, bt->stream, skip, bt->ntiles, bt->trow0.p, bt->trow1.p, L0.L.S.sptr.p,
-                     L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p, bt->v.p, bt->partials.p);
+                     L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p, bt->v.p, bt->partials.p,
+                     bcodes<double>(L0.L));
 }
 
 template <int NR>
@@ -1123,7 +1244,7 @@ void autotune(amg_batch *bt) {
       hipLaunchKernelGGL(k_bzero<T>, rgrid(k_bzero<T>, mc), dim3(kBlock), 0, s, mc, e);
     }
     float best = 1e30f, best_corr = 1e30f;
-    int win_corr = 1;
+    int win_corr = 1, win_wide = 1;
     for (int cpl : {1, 2, 4, 8, 16}) {
       if (NR % cpl != 0) continue;
       L.cpl = L.cpl_corr = cpl;
@@ -1136,6 +1257,19 @@ void autotune(amg_batch *bt) {
     }
     L.cpl = L.tune_best;
     L.cpl_corr = e ? win_corr : L.cpl;
+    L.cpl_wide = L.cpl;
+    if constexpr (std::is_same<T, float>::value) {
+      if (k == 0) {   // the last post-sweep of a binary32 cycle writes binary64 (into w here)
+        float best_wide = 1e30f;
+        for (int cpl : {1, 2, 4, 8, 16}) {
+          if (NR % cpl != 0) continue;
+          L.cpl_wide = cpl;
+          const float mw = time5([&] { sweep_widen_any<NR>(nullptr, L, L.n_cont, r, x, bt->w.p, s); });
+          if (mw < best_wide) { best_wide = mw; win_wide = cpl; }
+        }
+        L.cpl_wide = win_wide;
+      }
+    }
   }
 }
 
@@ -1308,7 +1442,7 @@ void batch_build(amg_batch *bt, int nsys, const amg_csr *A) {
     }
     hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, s, C.rp.p + C.n, static_cast<int>(C.nnz));
     AMG_LAUNCH_CHECK();
-    finalize_level(BL.L, s, mixed);
+    finalize_level(BL.L, s, mixed, true);
     if (ncnt > 0 && k + 1 < max_nl) {
       std::vector<int64_t> coff(ncnt + 1, 0);
       for (int p = 0; p < ncnt; ++p) coff[p + 1] = coff[p] + H[order[p]]->L[k + 1].A.n;
@@ -1461,7 +1595,7 @@ int batch_solve_nr(amg_batch *bt, const UserVecs &Bu, const UserVecs &Xu, double
   AMG_HIP(hipMemsetAsync(bt->active.p, 0, sizeof(int), s));
   hipLaunchKernelGGL((k_bpcg_init<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, bt->trow0.p, bt->trow1.p,
                      L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->bint.p, bt->u.p, bt->r.p,
-                     bt->partials.p);
+                     bt->partials.p, bcodes<double>(L0.L));
   hipLaunchKernelGGL((k_bpcg_init_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, bt->tile_ptr.p,
                      bt->partials.p, bt->sc.p, rtol, bt->active.p);
   hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p, bt->host_flag_dev);

@@ -1614,7 +1614,9 @@ void keep_pool_memory() {
 // Entry points for the other translation units (batched hierarchy).
 void device_exclusive_scan(const int *in, int *out, int n, hipStream_t s) { exclusive_scan(in, out, n, s); }
 int device_read_int(const int *p, hipStream_t s) { return read_int(p, s); }
-void finalize_level(Level &Lv, hipStream_t s, bool want_float) { finish_level(Lv, s, want_float, false); }
+void finalize_level(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
+  finish_level(Lv, s, want_float, want_codes);
+}
 double wall_ms() { return now_ms(); }
 
 // ================================================= bootstrap composite
