@@ -365,30 +365,36 @@ __device__ __forceinline__ void brow_coded(const BCodes<T> &K, const T *sd, int 
 
 // Row `row` from the codes where its slice is compact and the level coded,
 // else from col / val.
-template <class T, int NR, int CPL, bool kCorr = false>
+template <class T, int NR, int CPL, bool kCorr = false, bool kCO = false>
 __device__ __forceinline__ void brow_k(const BCodes<T> &K, const T *sd, const int *__restrict__ sptr,
                                        const int *__restrict__ col, const T *__restrict__ val,
                                        const T *__restrict__ x, int row, int cb, T (&acc)[CPL], T &l1,
                                        const int *__restrict__ agg = nullptr,
                                        const T *__restrict__ pval = nullptr,
                                        const T *__restrict__ e = nullptr) {
-  if (K.code) {
+  constexpr int kBytes = CPL * static_cast<int>(sizeof(T)) * (kCorr ? 2 : 1);
+  constexpr int KB = kBytes <= 64 ? 4 : (kBytes <= 128 ? 2 : 1);
+  if constexpr (kCO) {   // the level is coded and every slice compact: no plain path compiled
     const int s = row >> 6;
     const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
-    if (width > 0 && K.cbase[b >> 6] >= 0) {
-      constexpr int kBytes = CPL * static_cast<int>(sizeof(T)) * (kCorr ? 2 : 1);
-      constexpr int KB = kBytes <= 64 ? 4 : (kBytes <= 128 ? 2 : 1);
-      brow_coded<T, NR, CPL, kCorr, KB>(K, sd, s, b, width, x, row & 63, cb, acc, l1, agg, pval, e);
-      return;
+    brow_coded<T, NR, CPL, kCorr, KB>(K, sd, s, b, width, x, row & 63, cb, acc, l1, agg, pval, e);
+  } else {
+    if (K.code) {
+      const int s = row >> 6;
+      const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
+      if (width > 0 && K.cbase[b >> 6] >= 0) {
+        brow_coded<T, NR, CPL, kCorr, KB>(K, sd, s, b, width, x, row & 63, cb, acc, l1, agg, pval, e);
+        return;
+      }
     }
+    brow<T, NR, CPL, kCorr>(sptr, col, val, x, row, cb, acc, l1, agg, pval, e);
   }
-  brow<T, NR, CPL, kCorr>(sptr, col, val, x, row, cb, acc, l1, agg, pval, e);
 }
 
 // xn = x + dinv (rhs - A x) on rows [0, n).  TO = double with T = float
 // writes the binary32 result widened (exactly) to binary64: the last sweep
 // of a binary32 cycle then delivers the binary64 output itself.
-template <class T, int NR, int CPL, class TO = T>
+template <class T, int NR, int CPL, class TO = T, bool kCO = false>
 __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
                                                    const int *__restrict__ sptr,
                                                    const int *__restrict__ col,
@@ -406,7 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], l1;
-  brow_k<T, NR, CPL>(K, sd, sptr, col, val, x, row, cb, acc, l1);
+  brow_k<T, NR, CPL, false, kCO>(K, sd, sptr, col, val, x, row, cb, acc, l1);
   const T di = T(1) / l1;
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
   T xo[CPL], bo[CPL];
@@ -423,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep(const int *skip, int n,
 // iterate read at column c is y_c = x_c + p_c e[agg_c] (the value k_bprolong
 // stores), xn = y + dinv (rhs - A y); y is never written.  Rows [0, n) all
 // continue to the coarser level.
-template <class T, int NR, int CPL>
+template <class T, int NR, int CPL, bool kCO = false>
 __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
                                                         const int *__restrict__ sptr,
                                                         const int *__restrict__ col,
@@ -444,7 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], m;
-  brow_k<T, NR, CPL, true>(K, sd, sptr, col, val, x, row, cb, acc, m, agg, pval, e);
+  brow_k<T, NR, CPL, true, kCO>(K, sd, sptr, col, val, x, row, cb, acc, m, agg, pval, e);
   const T di = T(1) / m;
   const T pr = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
@@ -462,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_bsweep_corr(const int *skip, int n,
 }
 
 // t = p (rhs - A x) on rows [0, n)
-template <class T, int NR, int CPL>
+template <class T, int NR, int CPL, bool kCO = false>
 __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
                                                    const int *__restrict__ sptr,
                                                    const int *__restrict__ col,
@@ -481,7 +487,7 @@ __global__ void __launch_bounds__(kBlock) k_bresid(const int *skip, int n,
   const int row = static_cast<int>(gid / LPR), cb = static_cast<int>(gid % LPR) * CPL;
   if (row >= n) continue;
   T acc[CPL], l1;
-  brow_k<T, NR, CPL>(K, sd, sptr, col, val, x, row, cb, acc, l1);
+  brow_k<T, NR, CPL, false, kCO>(K, sd, sptr, col, val, x, row, cb, acc, l1);
   const T p = pval[row];
   const int64_t o = static_cast<int64_t>(row) * NR + cb;
   T bo[CPL], out[CPL];
@@ -730,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
 
 // PC columns per thread (tuned: fewer columns hold fewer gathered values in
 // registers and let more waves run).
-template <int NR, int PC>
+template <int NR, int PC, bool kCO = false>
 __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
     const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ sptr, const int *__restrict__ col, const double *__restrict__ val,
@@ -750,7 +756,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_spmm_dots(
   for (int j = 0; j < PC; ++j) al[j] = be[j] = ga[j] = 0.0;
   for (int row = trow0[tile] + threadIdx.x / LPR; row < trow1[tile]; row += kBlock / LPR) {
     double acc[PC], l1, wo[PC], ro[PC], qo[PC];
-    brow_k<double, NR, PC>(K, sd, sptr, col, val, w, row, cb, acc, l1);
+    brow_k<double, NR, PC, false, kCO>(K, sd, sptr, col, val, w, row, cb, acc, l1);
     const int64_t o = static_cast<int64_t>(row) * NR + cb;
     stcols<double, PC>(v + o, acc);
     ldcols<double, PC>(w + o, wo);
@@ -1005,37 +1011,61 @@ BCodes<T> bcodes(const Level &L) {
   return BCodes<T>{S.cbase.p, S.qptr.p, S.cdel.p, coded ? S.code.p : nullptr, bdict<T>(S), S.ndict};
 }
 
+// Every slice compact and the values coded: the kernels without the plain path.
+inline bool coded_only(const Level &L) {
+  return L.S.ndict > 0 && L.S.nslots > 0 && L.S.groups_compact * kSlice == L.S.nslots;
+}
+
+template <class T, int NR, int CPL, class TO, bool kCO>
+void launch_bsweep_as(const int *skip, BLevel &L, int n, const T *rhs, const T *x, TO *xn, hipStream_t s) {
+  constexpr int LPR = NR / CPL;
+  auto kern = k_bsweep<T, NR, CPL, TO, kCO>;
+  hipLaunchKernelGGL(kern, rgrid(kern, static_cast<int64_t>(n) * LPR), dim3(kBlock), 0, s, skip, n,
+                     L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn, bcodes<T>(L.L));
+}
+
 template <class T, int NR, int CPL>
 void launch_bsweep(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *xn, hipStream_t s) {
-  constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep<T, NR, CPL>), rgrid((k_bsweep<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
-                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, xn, bcodes<T>(L.L));
+  if (coded_only(L.L)) launch_bsweep_as<T, NR, CPL, T, true>(skip, L, n, rhs, x, xn, s);
+  else launch_bsweep_as<T, NR, CPL, T, false>(skip, L, n, rhs, x, xn, s);
 }
 
 template <int NR, int CPL>
 void launch_bsweep_widen(const int *skip, BLevel &L, int n, const float *rhs, const float *x,
                          double *xn, hipStream_t s) {
+  if (coded_only(L.L)) launch_bsweep_as<float, NR, CPL, double, true>(skip, L, n, rhs, x, xn, s);
+  else launch_bsweep_as<float, NR, CPL, double, false>(skip, L, n, rhs, x, xn, s);
+}
+
+template <class T, int NR, int CPL, bool kCO>
+void launch_bresid_as(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep<float, NR, CPL, double>), rgrid((k_bsweep<float, NR, CPL, double>), static_cast<int64_t>(n) * LPR),
-                     dim3(kBlock), 0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, L.L.S.valf.p, rhs, x, xn,
-                     bcodes<float>(L.L));
+  auto kern = k_bresid<T, NR, CPL, kCO>;
+  hipLaunchKernelGGL(kern, rgrid(kern, static_cast<int64_t>(n) * LPR), dim3(kBlock), 0, s, skip, n,
+                     L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t, bcodes<T>(L.L));
 }
 
 template <class T, int NR, int CPL>
 void launch_bresid(const int *skip, BLevel &L, int n, const T *rhs, const T *x, T *t, hipStream_t s) {
+  if (coded_only(L.L)) launch_bresid_as<T, NR, CPL, true>(skip, L, n, rhs, x, t, s);
+  else launch_bresid_as<T, NR, CPL, false>(skip, L, n, rhs, x, t, s);
+}
+
+template <class T, int NR, int CPL, bool kCO>
+void launch_bsweep_corr_as(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
+                           hipStream_t s) {
   constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bresid<T, NR, CPL>), rgrid((k_bresid<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock), 0,
-                     s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), bpval<T>(L.L), rhs, x, t,
+  auto kern = k_bsweep_corr<T, NR, CPL, kCO>;
+  hipLaunchKernelGGL(kern, rgrid(kern, static_cast<int64_t>(n) * LPR), dim3(kBlock), 0, s, skip, n,
+                     L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p, bpval<T>(L.L), e, xn,
                      bcodes<T>(L.L));
 }
 
 template <class T, int NR, int CPL>
 void launch_bsweep_corr(const int *skip, BLevel &L, int n, const T *rhs, const T *e, const T *x, T *xn,
                         hipStream_t s) {
-  constexpr int LPR = NR / CPL;
-  hipLaunchKernelGGL((k_bsweep_corr<T, NR, CPL>), rgrid((k_bsweep_corr<T, NR, CPL>), static_cast<int64_t>(n) * LPR), dim3(kBlock),
-                     0, s, skip, n, L.L.S.sptr.p, L.L.S.col.p, bvals<T>(L.L), rhs, x, L.L.agg.p,
-                     bpval<T>(L.L), e, xn, bcodes<T>(L.L));
+  if (coded_only(L.L)) launch_bsweep_corr_as<T, NR, CPL, true>(skip, L, n, rhs, e, x, xn, s);
+  else launch_bsweep_corr_as<T, NR, CPL, false>(skip, L, n, rhs, e, x, xn, s);
 }
 
 // Calls f(std::integral_constant<int, C>) with C = cpl when cpl divides NR
@@ -1161,7 +1191,8 @@ void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
 template <int NR, int PC>
 void launch_spmm_dots_pc(amg_batch *bt, const int *skip) {
   const BLevel &L0 = bt->B[0];
-  hipLaunchKernelGGL((k_bpcg_spmm_dots<NR, PC>), rgrid((k_bpcg_spmm_dots<NR, PC>), static_cast<int64_t>(bt->ntiles) * kBlock),
+  auto kern = coded_only(L0.L) ? k_bpcg_spmm_dots<NR, PC, true> : k_bpcg_spmm_dots<NR, PC, false>;
+  hipLaunchKernelGGL(kern, rgrid(kern, static_cast<int64_t>(bt->ntiles) * kBlock),
                      dim3(kBlock), 0, bt->stream, skip, bt->ntiles, bt->trow0.p, bt->trow1.p, L0.L.S.sptr.p,
                      L0.L.S.col.p, L0.L.S.val.p, bt->w.p, bt->r.p, bt->q.p, bt->v.p, bt->partials.p,
                      bcodes<double>(L0.L));
