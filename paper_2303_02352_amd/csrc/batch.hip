@@ -327,20 +327,26 @@ __device__ __forceinline__ void brow_coded(const BCodes<T> &K, const T *sd, int 
 #pragma unroll
   for (int j = 0; j < CPL; ++j) acc[j] = T(0);
   T m = T(0);
-  for (int k0 = 0; k0 < width; k0 += 4) {
-    const int t = k0 >> 2;
-    const unsigned long long d = dq[static_cast<int64_t>(t) * 64];
-    const unsigned w = cq[static_cast<int64_t>(t) * 64];
-    int c[4];
-    T a[4];
+  constexpr int QN = KB > 4 ? 2 : 1;   // quads per step: their loads, then all their gathers
+  constexpr int SL = 4 * QN;
+  for (int k0 = 0; k0 < width; k0 += SL) {
+    int c[SL];
+    T a[SL];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      c[j] = bp[k0 + j] + static_cast<int>((d >> (16 * j)) & 0xffffu);   // in range: cbase is padded
-      a[j] = sd[(w >> (8 * j)) & 0xffu];
+    for (int qn = 0; qn < QN; ++qn) {
+      if (k0 + 4 * qn >= width) break;   // the slice's last quad
+      const int64_t t = (k0 >> 2) + qn;
+      const unsigned long long d = dq[t * 64];
+      const unsigned w = cq[t * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[4 * qn + j] = bp[k0 + 4 * qn + j] + static_cast<int>((d >> (16 * j)) & 0xffffu);   // cbase is padded
+        a[4 * qn + j] = sd[(w >> (8 * j)) & 0xffu];
+      }
     }
-    const int nv = width - k0 < 4 ? width - k0 : 4;
+    const int nv = width - k0 < SL ? width - k0 : SL;
 #pragma unroll
-    for (int u0 = 0; u0 < 4; u0 += KB) {
+    for (int u0 = 0; u0 < SL; u0 += KB) {
       if (u0 >= nv) break;
       int cc[KB];
       T xv[KB][CPL];
@@ -373,7 +379,10 @@ __device__ __forceinline__ void brow_k(const BCodes<T> &K, const T *sd, const in
                                        const T *__restrict__ pval = nullptr,
                                        const T *__restrict__ e = nullptr) {
   constexpr int kBytes = CPL * static_cast<int>(sizeof(T)) * (kCorr ? 2 : 1);
-  constexpr int KB = kBytes <= 64 ? 4 : (kBytes <= 128 ? 2 : 1);
+  // eight slots in flight for binary32 pieces of up to 32 bytes (two quads
+  // per step); binary64 keeps four (the SpMM + dots measured slower with
+  // eight: 1.79 vs 1.73 ms, its registers cost a wavefront)
+  constexpr int KB = (kBytes <= 32 && sizeof(T) == 4) ? 8 : (kBytes <= 64 ? 4 : (kBytes <= 128 ? 2 : 1));
   if constexpr (kCO) {   // the level is coded and every slice compact: no plain path compiled
     const int s = row >> 6;
     const int b = sptr[s], width = (sptr[s + 1] - b) >> 6;
