@@ -707,6 +707,22 @@ __device__ __forceinline__ double tile_column_sum_v(const double (&v)[PC], doubl
   return s;
 }
 
+// The binary32 cycle's entry, written by the kernels that produce r (the
+// PCG init and update) instead of a pass of its own: rf = (float) r and, on
+// the first m1 entries (rows that smooth), the first iterate xf = dinvf rf.
+// rf == nullptr: not wanted (binary64 cycle, or no preconditioner).
+struct BFirst {
+  const float *dinvf;
+  float *rf, *xf;
+  int64_t m1;
+  __device__ __forceinline__ void put(int64_t o, int row, double r) const {
+    if (!rf) return;
+    const float b = static_cast<float>(r);
+    rf[o] = b;
+    if (xf && o < m1) xf[o] = dinvf[row] * b;
+  }
+};
+
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ trow0,
                                                       const int *__restrict__ trow1,
@@ -717,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
                                                       const double *__restrict__ u,
                                                       double *__restrict__ r,
                                                       double *__restrict__ part,
-                                                      BCodes<double> K) {
+                                                      BCodes<double> K, BFirst F) {
   constexpr int PC = pcg_cols<NR>(), LPR = NR / PC;
   __shared__ double red[kBlock * PC];
   __shared__ double sd[kDictMax];
@@ -736,6 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_init(const int *__restrict__ tr
     for (int j = 0; j < PC; ++j) {
       ro[j] = bo[j] - acc[j];
       rr[j] = rr[j] + ro[j] * ro[j];
+      F.put(o + j, row, ro[j]);
     }
     stcols<double, PC>(r + o, ro);
   }
@@ -891,7 +908,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_update(
     const int *skip, int ntiles, const int *__restrict__ trow0, const int *__restrict__ trow1,
     const int *__restrict__ tsys, const double *__restrict__ w, const double *__restrict__ v,
     double *__restrict__ d, double *__restrict__ u, double *__restrict__ q, double *__restrict__ r,
-    const BScalars *__restrict__ sc, double *__restrict__ part) {
+    const BScalars *__restrict__ sc, double *__restrict__ part, BFirst F) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kBlock];
   const int c = threadIdx.x % NR;
@@ -915,6 +932,7 @@ __global__ void __launch_bounds__(kBlock) k_bpcg_update(
       const double ri = r[o] - a * qi;
       r[o] = ri;
       rr = rr + ri * ri;
+      F.put(o, row, ri);   // frozen pairs keep their last entry values: their columns are unused
     }
   }
   rr = tile_column_sum<NR>(rr, red);
@@ -1120,6 +1138,14 @@ T *bfirst(amg_batch *bt, int k, T *out) {
   return (swaps % 2 == 0) ? out : bv_t<T>(L);
 }
 
+// What the PCG kernels write for the binary32 cycle's entry (none otherwise).
+template <int NR>
+BFirst bfirst_out(amg_batch *bt) {
+  if (!bt->p.precond || bt->p.precision != AMG_PREC_MIXED) return BFirst{nullptr, nullptr, nullptr, 0};
+  BLevel &L = bt->B[0];
+  return BFirst{L.L.dinvf.p, L.rf.p, bfirst<float>(bt, 0, L.xf.p), static_cast<int64_t>(L.n_cont) * NR};
+}
+
 // z64 (binary32 cycle, level 0 only): the last post-sweep writes its rows
 // there, widened, instead of into `out`; returns whether it did.
 template <class T, int NR>
@@ -1171,7 +1197,7 @@ bool bvcycle_level(amg_batch *bt, const int *skip, int k, const T *rhs, T *out, 
 }
 
 template <int NR>
-void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
+void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z, bool entry_done = false) {
   hipStream_t s = bt->stream;
   const int64_t m = static_cast<int64_t>(bt->B[0].n) * NR;
   if (!bt->p.precond) {
@@ -1181,8 +1207,9 @@ void bvcycle(amg_batch *bt, const int *skip, const double *r, double *z) {
   if (bt->p.precision == AMG_PREC_MIXED) {
     BLevel &L = bt->B[0];
     float *x1 = bfirst<float>(bt, 0, L.xf.p);
-    hipLaunchKernelGGL((k_bd2f_first<NR>), rgrid((k_bd2f_first<NR>), m), dim3(kBlock), 0, s, m,
-                       static_cast<int64_t>(L.n_cont) * NR, r, L.L.dinvf.p, L.rf.p, x1, skip);
+    if (!entry_done)   // else the kernel that produced r wrote rf and x1 (bfirst_out)
+      hipLaunchKernelGGL((k_bd2f_first<NR>), rgrid((k_bd2f_first<NR>), m), dim3(kBlock), 0, s, m,
+                         static_cast<int64_t>(L.n_cont) * NR, r, L.L.dinvf.p, L.rf.p, x1, skip);
     const bool widened = bvcycle_level<float, NR>(bt, skip, 0, L.rf.p, L.xf.p, x1 != nullptr, z);
     // rows the last sweep did not write (all rows, or those of single-level
     // systems, which the binary64 solve below overwrites anyway)
@@ -1216,14 +1243,15 @@ template <int NR>
 void launch_update(amg_batch *bt, const int *skip) {
   hipLaunchKernelGGL((k_bpcg_update<NR>), rgrid((k_bpcg_update<NR>), static_cast<int64_t>(bt->ntiles) * kBlock),
                      dim3(kBlock), 0, bt->stream, skip, bt->ntiles, bt->trow0.p, bt->trow1.p, bt->tsys.p,
-                     bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p, bt->sc.p, bt->partials.p);
+                     bt->w.p, bt->v.p, bt->d.p, bt->u.p, bt->q.p, bt->r.p, bt->sc.p, bt->partials.p,
+                     bfirst_out<NR>(bt));
 }
 
 template <int NR>
 void benqueue_iteration(amg_batch *bt, int maxit) {
   hipStream_t s = bt->stream;
   const int *skip = bt->all_done.p;
-  bvcycle<NR>(bt, skip, bt->r.p, bt->w.p);
+  bvcycle<NR>(bt, skip, bt->r.p, bt->w.p, true);   // r came from the init or the last update
   launch_spmm_dots<NR>(bt, skip);
   hipLaunchKernelGGL((k_bpcg_dots_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, skip,
                      bt->tile_ptr.p, bt->partials.p, bt->sc.p);
@@ -1635,7 +1663,7 @@ int batch_solve_nr(amg_batch *bt, const UserVecs &Bu, const UserVecs &Xu, double
   AMG_HIP(hipMemsetAsync(bt->active.p, 0, sizeof(int), s));
   hipLaunchKernelGGL((k_bpcg_init<NR>), dim3(bt->ntiles), dim3(kBlock), 0, s, bt->trow0.p, bt->trow1.p,
                      L0.L.S.sptr.p, L0.L.S.col.p, L0.L.S.val.p, bt->bint.p, bt->u.p, bt->r.p,
-                     bt->partials.p, bcodes<double>(L0.L));
+                     bt->partials.p, bcodes<double>(L0.L), bfirst_out<NR>(bt));
   hipLaunchKernelGGL((k_bpcg_init_finish<NR>), dim3(bt->nsys), dim3(kBFinish), 0, s, bt->tile_ptr.p,
                      bt->partials.p, bt->sc.p, rtol, bt->active.p);
   hipLaunchKernelGGL(k_ball_done, dim3(1), dim3(1), 0, s, bt->active.p, bt->all_done.p, bt->host_flag_dev);
