@@ -319,6 +319,7 @@ struct Sell {
   int n = 0;
   int nslices = 0;
   int64_t nslots = 0;
+  int wmin = 0, wmax = 0;   // narrowest and widest slice (slots per lane)
   dvec<int> sptr;     // nslices + 1 slot offsets (multiples of 64)
   dvec<int> col;
   dvec<double> val;

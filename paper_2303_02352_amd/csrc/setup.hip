@@ -933,18 +933,31 @@ __global__ void k_sort_members(int nc, const int *mptr, int *mem) {
 // Slots of each slice (64 x its widest row), and their total in 64 bits:
 // the slot offsets are int32, so the host refuses a level whose total does
 // not fit before any slot is indexed.
+// Slots per slice (64 x the widest row), their total in total[0], and the
+// widest and narrowest slice as total[1] = max width, total[2] = max of
+// (2^31 - 1 - width).
 __global__ void k_sell_width(int n, int nslices, const int *rp, int *slots, unsigned long long *total) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = 0;
+  unsigned long long v = 0, wmax = 0, wneg = 0;
   if (s < nslices) {
     int w = 0;
     const int r0 = s * kSlice, r1 = min(n, r0 + kSlice);
     for (int r = r0; r < r1; ++r) w = max(w, rp[r + 1] - rp[r]);
     v = static_cast<unsigned long long>(w) * kSlice;
     slots[s] = static_cast<int>(v);   // used only when the total fits
+    wmax = static_cast<unsigned long long>(w);
+    wneg = static_cast<unsigned long long>(0x7fffffff - w);
   }
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);   // every lane of the wavefront
-  if ((threadIdx.x & 63) == 0 && v) atomicAdd(total, v);
+  for (int o = 32; o > 0; o >>= 1) {   // every lane of the wavefront
+    v += __shfl_xor(v, o, 64);
+    wmax = max(wmax, static_cast<unsigned long long>(__shfl_xor(wmax, o, 64)));
+    wneg = max(wneg, static_cast<unsigned long long>(__shfl_xor(wneg, o, 64)));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (v) atomicAdd(total, v);
+    if (wmax) atomicMax(total + 1, wmax);
+    if (wneg) atomicMax(total + 2, wneg);
+  }
 }
 
 __global__ void k_sell_fill(int n, int nslices, const int *rp, const int *ci, const double *v,
@@ -1377,14 +1390,17 @@ void build_sell(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   S.n = n;
   S.nslices = ceil_div(n, kSlice);
   tvec<int> slots(S.nslices, s);
-  tvec<unsigned long long> total(1, s);
+  tvec<unsigned long long> total(3, s);
   S.sptr.alloc(S.nslices + 1);
-  AMG_HIP(hipMemsetAsync(total.p, 0, sizeof(unsigned long long), s));
+  AMG_HIP(hipMemsetAsync(total.p, 0, 3 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_sell_width, grid_for(S.nslices), dim3(kBlock), 0, s, n, S.nslices,
                      Lv.A.rp.p, slots.p, total.p);
   AMG_LAUNCH_CHECK();
-  unsigned long long nslots = 0;
-  read_small(&nslots, total.p, sizeof(nslots), s);
+  unsigned long long tw[3] = {0, 0, 0};
+  read_small(tw, total.p, sizeof(tw), s);
+  const unsigned long long nslots = tw[0];
+  S.wmax = static_cast<int>(tw[1]);
+  S.wmin = 0x7fffffff - static_cast<int>(tw[2]);
   if (nslots >= (1ull << 31))
     fail(AMG_ERR_UNSUPPORTED, "a level's SELL form needs 2^31 or more slots (rows of very different "
                               "lengths share slices); slot offsets are int32");

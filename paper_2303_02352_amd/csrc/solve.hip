@@ -249,30 +249,17 @@ __device__ __forceinline__ void sell_row(const SellRef &S, const ValDev<T> &V,
   sell_row_g<T, kStream>(S, V, Plain<T>{x}, r, sum, l1);
 }
 
-// Two rows of one lane, in slices sa and sb (wavefront-uniform), folded
-// together when both slices are compact and coded with at most 8 slots:
-// every load of both rows is issued before the first use, which doubles the
-// loads in flight per wavefront on these short rows.  Slots past a row's
-// width are read at clamped, in-range places and left out of the fold, so
-// the fold is the one of row_fold.  Returns false (nothing done) otherwise.
+// The fold of two rows of one lane, in slices sa and sb (wavefront-uniform),
+// both compact and coded with 1 to 8 slots, from their group bases: column
+// offsets and codes of both rows, then the iterate at every slot, all in
+// flight before the first use (twice the loads per wavefront of one row).
+// Slots past a row's width are read at clamped, in-range places and left
+// out of the fold, so the fold is the one of row_fold.
 template <class T, bool kStream, class G>
-__device__ __forceinline__ bool fold2_short(const SellRef &S, const ValDev<T> &V, G x, int sa, int sb,
-                                            int lane, T &sum0, T &l10, T &sum1, T &l11) {
-  if (!V.code || !S.cdel) return false;
-  // every scalar read first (slice bounds, quad offsets, then the 8 group
-  // bases of each slice, in range through the padding), the tests after
-  const int ba = S.sptr[sa], ea = S.sptr[sa + 1], bb = S.sptr[sb], eb = S.sptr[sb + 1];
-  const int qsa = S.qptr[sa], qsb = S.qptr[sb];
-  const int wa = (ea - ba) >> 6, wb = (eb - bb) >> 6;
-  const int ga = ba >> 6, gb = bb >> 6;
-  int basea[8], baseb[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    basea[j] = S.cbase[ga + j];
-    baseb[j] = S.cbase[gb + j];
-  }
-  if (wa < 1 || wb < 1 || wa > 8 || wb > 8) return false;
-  if (basea[0] < 0 || baseb[0] < 0) return false;
+__device__ __forceinline__ void fold2_bases(const ValDev<T> &V, const SellRef &S, G x, int sa, int sb,
+                                            int lane, int wa, int wb, int qsa, int qsb,
+                                            const int (&basea)[8], const int (&baseb)[8], T &sum0,
+                                            T &l10, T &sum1, T &l11) {
   const unsigned long long *cd = reinterpret_cast<const unsigned long long *>(S.cdel);
   const unsigned *cc = reinterpret_cast<const unsigned *>(V.code);
   const int64_t qa = static_cast<int64_t>(qsa) * 64 + lane;
@@ -320,6 +307,29 @@ __device__ __forceinline__ bool fold2_short(const SellRef &S, const ValDev<T> &V
   l10 = m0;
   sum1 = acc1;
   l11 = m1;
+}
+
+// fold2_bases where it applies (both slices compact and coded, 1 to 8
+// slots); returns false (nothing done) otherwise.
+template <class T, bool kStream, class G>
+__device__ __forceinline__ bool fold2_short(const SellRef &S, const ValDev<T> &V, G x, int sa, int sb,
+                                            int lane, T &sum0, T &l10, T &sum1, T &l11) {
+  if (!V.code || !S.cdel) return false;
+  // every scalar read first (slice bounds, quad offsets, then the 8 group
+  // bases of each slice, in range through the padding), the tests after
+  const int ba = S.sptr[sa], ea = S.sptr[sa + 1], bb = S.sptr[sb], eb = S.sptr[sb + 1];
+  const int qsa = S.qptr[sa], qsb = S.qptr[sb];
+  const int wa = (ea - ba) >> 6, wb = (eb - bb) >> 6;
+  const int ga = ba >> 6, gb = bb >> 6;
+  int basea[8], baseb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    basea[j] = S.cbase[ga + j];
+    baseb[j] = S.cbase[gb + j];
+  }
+  if (wa < 1 || wb < 1 || wa > 8 || wb > 8) return false;
+  if (basea[0] < 0 || baseb[0] < 0) return false;
+  fold2_bases<T, kStream>(V, S, x, sa, sb, lane, wa, wb, qsa, qsb, basea, baseb, sum0, l10, sum1, l11);
   return true;
 }
 
@@ -418,6 +428,77 @@ __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_resid_scaled2(const 
   rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T) { t[r] = pval[r] * (rhs[r] - sum); });
 }
 
+// Read in place of a null `skip`.
+__device__ const int kNeverDone = 0;
+
+// Sweep (kResid false: out = x + dinv (rhs - A x), or widened into xw) or
+// scaled residual (kResid true: out = pval (rhs - A x)) on a level whose
+// slices are all compact and coded with 1 to 8 slots (short_coded), two
+// slices per wavefront like k_sweep2.  On the small levels a pass costs its
+// memory round trips, so the loads go out in three rounds with nothing in
+// between: the done flag, slice bounds, quad offsets, table entry and the
+// rows' own operands; then group bases, column offsets and codes; then the
+// iterate at the columns.  Same slots and fold as k_sweep2: same bits.
+template <class T, bool kStream, bool kResid>
+__global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_short2(const int *skip, int n, SellRef S,
+                                                   ValRef<T> vref,
+                                                   const T *__restrict__ pval,
+                                                   const T *__restrict__ rhs,
+                                                   const T *__restrict__ x, T *__restrict__ out,
+                                                   double *__restrict__ xw) {
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  // The kernel arguments, all read before anything else.  (The empty asm
+  // statements take values as operands so that the compiler has them ready
+  // at that point: loads it would otherwise issue one by one, each after the
+  // previous one has returned, go out together.)
+  const int *sptr = S.sptr, *qptr = S.qptr, *cbase = S.cbase;
+  const T *own = kResid ? pval : x;
+  const int *sk = skip ? skip : &kNeverDone;
+  const int nb = static_cast<int>(gridDim.x);
+  asm volatile("" ::"s"(n), "s"(nb), "s"(sptr), "s"(qptr), "s"(cbase), "s"(S.cdel), "s"(vref.code),
+               "s"(vref.dict), "s"(vref.ndict), "s"(own), "s"(rhs), "s"(x), "s"(out), "s"(xw), "s"(sk));
+  const int r0 = xcd_block(blockIdx.x, nb) * (2 * kBlock) + threadIdx.x;
+  const int r1 = r0 + kBlock;
+  const int nsl = (n + 63) >> 6;
+  const int sa = __builtin_amdgcn_readfirstlane(r0 >> 6);
+  if (sa >= nsl) return;   // whole wavefront
+  const bool two = sa + kBlock / 64 < nsl;
+  const int sb = two ? sa + kBlock / 64 : sa;
+  // round 1
+  const int done = *sk;
+  const ValDev<T> val = stage_dict(vref, sdict);
+  const int ba = sptr[sa], ea = sptr[sa + 1], bb = sptr[sb], eb = sptr[sb + 1];
+  const int qsa = qptr[sa], qsb = qptr[sb];
+  const int ra = r0 < n ? r0 : n - 1, rb = (two && r1 < n) ? r1 : ra;
+  const T oa = own[ra], ob = own[rb], ha = rhs[ra], hb = rhs[rb];
+  asm volatile("" ::"s"(done), "s"(ba), "s"(ea), "s"(bb), "s"(eb), "s"(qsa), "s"(qsb));
+  if (done) return;
+  // round 2: the group bases (in range through the padding), then the rest
+  const int wa = (ea - ba) >> 6, wb = (eb - bb) >> 6;
+  const int ga = ba >> 6, gb = bb >> 6;
+  int basea[8], baseb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    basea[j] = S.cbase[ga + j];
+    baseb[j] = S.cbase[gb + j];
+  }
+  T s0, m0, s1, m1;
+  fold2_bases<T, kStream>(val, S, Plain<T>{x}, sa, sb, r0 & 63, wa, wb, qsa, qsb, basea, baseb, s0, m0,
+                          s1, m1);
+  auto put = [&](int r, T sum, T l1, T o, T h) {
+    if constexpr (kResid) {
+      out[r] = o * (h - sum);
+    } else {
+      const T di = T(1) / l1;
+      const T v = o + di * (h - sum);
+      if (xw) xw[r] = static_cast<double>(v);
+      else out[r] = v;
+    }
+  };
+  if (r0 < n) put(r0, s0, m0, oa, ha);
+  if (two && r1 < n) put(r1, s1, m1, ob, hb);
+}
+
 // First post-smoothing sweep with the coarse-grid correction folded in:
 // y = x + P e is formed where it is read (the value k_prolong would store)
 // and xn = y + dinv (rhs - A y); y itself is never written.
@@ -440,6 +521,84 @@ __global__ void __launch_bounds__(kBlock) k_sweep_corr(const int *skip, int n, S
   sell_row_g<T, kStream>(S, val, y, r, s, m);
   const T di = T(1) / m;
   xn[r] = y(r) + di * (rhs[r] - s);
+}
+
+// k_sweep_corr on a short_coded level, one row per lane, in four rounds of
+// loads: the done flag, slice bounds, quad offset, table entry and the
+// row's own x, p, aggregate and rhs; then group bases, column offsets,
+// codes and the row's e; then x, p and aggregate at the columns; then e at
+// their aggregates.  Same values and fold as k_sweep_corr: same bits.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_short_corr(const int *skip, int n, SellRef S, ValRef<T> vref,
+                                                       const T *__restrict__ rhs,
+                                                       const T *__restrict__ x,
+                                                       const int *__restrict__ agg,
+                                                       const T *__restrict__ pval,
+                                                       const T *__restrict__ e, T *__restrict__ xn) {
+  __shared__ T sdict[kDictMax * (kBlock / kWave)];
+  const int *sptr = S.sptr, *qptr = S.qptr, *cbase = S.cbase;
+  const int *sk = skip ? skip : &kNeverDone;
+  const int nb = static_cast<int>(gridDim.x);
+  asm volatile("" ::"s"(n), "s"(nb), "s"(sptr), "s"(qptr), "s"(cbase), "s"(S.cdel), "s"(vref.code),
+               "s"(vref.dict), "s"(vref.ndict), "s"(rhs), "s"(x), "s"(agg), "s"(pval), "s"(e), "s"(xn),
+               "s"(sk));
+  const int r = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
+  const int sl = __builtin_amdgcn_readfirstlane(r >> 6);
+  if (sl >= ((n + 63) >> 6)) return;   // whole wavefront
+  // round 1
+  const int done = *sk;
+  const ValDev<T> val = stage_dict(vref, sdict);
+  const int b = sptr[sl], en = sptr[sl + 1], qs = qptr[sl];
+  const int rr = r < n ? r : n - 1;
+  const T xr = x[rr], pr = pval[rr], hr = rhs[rr];
+  const int ar = agg[rr];
+  asm volatile("" ::"s"(done), "s"(b), "s"(en), "s"(qs));
+  if (done) return;
+  // round 2
+  const int w = (en - b) >> 6, g = b >> 6, lane = r & 63;
+  int base[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) base[j] = cbase[g + j];   // in range through the padding
+  const T er = e[ar];
+  const unsigned long long *cd = reinterpret_cast<const unsigned long long *>(S.cdel);
+  const unsigned *cc = reinterpret_cast<const unsigned *>(val.code);
+  const int64_t qa = static_cast<int64_t>(qs) * 64 + lane;
+  const int t2 = w > 4 ? 64 : 0;
+  const unsigned long long d0 = cd[qa], d1 = cd[qa + t2];
+  const unsigned k0 = cc[qa], k1 = cc[qa + t2];
+  // round 3
+  int c[8], ac[8];
+  T xc[8], pc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned long long d = j < 4 ? d0 : d1;
+    c[j] = j < w ? base[j] + static_cast<int>((d >> (16 * (j & 3))) & 0xffffu) : sl * 64;
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xc[j] = x[c[j]];
+    pc[j] = pval[c[j]];
+    ac[j] = agg[c[j]];
+  }
+  // round 4
+  T ec[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ec[j] = e[ac[j]];
+  val.publish();
+  T acc = T(0), m = T(0);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned kk = j < 4 ? k0 : k1;
+    const T a = val.mine[(kk >> (8 * (j & 3))) & 0xffu];
+    if (j < w) {
+      acc = acc + a * (xc[j] + pc[j] * ec[j]);
+      m = m + fabs(a);
+    }
+  }
+  if (r < n) {
+    const T di = T(1) / m;
+    xn[r] = (xr + pr * er) + di * (hr - acc);
+  }
 }
 
 // First sweep from x = 0: x = dinv * r.
@@ -497,7 +656,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_sum(const int *skip, int nc,
 // in CSR order (the SELL slot order; padding slots add zeros), and the first
 // lane of the group adds the members' values in order; members beyond G are
 // folded by that lane itself.  Same bits as k_resid_scaled + k_agg_sum.
-template <class T, int G>
+template <class T, int G, bool kShort = false>
 __global__ void __launch_bounds__(kBlock) k_resid_agg(const int *skip, int nc,
                                                       const int *__restrict__ mptr,
                                                       const int *__restrict__ mem,
@@ -508,36 +667,55 @@ __global__ void __launch_bounds__(kBlock) k_resid_agg(const int *skip, int nc,
                                                       const T *__restrict__ rhs,
                                                       const T *__restrict__ x, T *__restrict__ rc,
                                                       const T *__restrict__ dinvc, T *__restrict__ xc) {
-  AMG_SKIP_IF_DONE();
-  const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  // kShort (rows of at most 8 entries): the kernel arguments, the done
+  // flag, the aggregate's bounds and its diagonal go out together, and a
+  // row's entries in one batch (see k_short2 for the empty asm statements)
+  const int *sk = skip ? skip : &kNeverDone;
+  const int nb = static_cast<int>(gridDim.x);
+  if constexpr (kShort) {
+    asm volatile("" ::"s"(nc), "s"(nb), "s"(mptr), "s"(mem), "s"(rp), "s"(ci), "s"(v), "s"(pval), "s"(rhs),
+                 "s"(x), "s"(rc), "s"(dinvc), "s"(xc), "s"(sk));
+  } else {
+    AMG_SKIP_IF_DONE();
+  }
+  const int e = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
   const int I = e / G, q = e % G;
   const bool live = I < nc;
   int q0 = 0, cnt = 0;
+  T dI = T(0);
   if (live) {
     q0 = mptr[I];
     cnt = mptr[I + 1] - q0;
+    if (kShort && xc) dI = dinvc[I];
   }
-  auto scaled = [&](int i) {   // entries taken four at a time, all loads of a batch in flight
+  if constexpr (kShort) {
+    const int done = *sk;
+    asm volatile("" ::"s"(done), "v"(q0), "v"(cnt));
+    if (done) return;
+  }
+  constexpr int KB = kShort ? 8 : 4;
+  auto scaled = [&](int i) {   // entries taken KB at a time, all loads of a batch in flight
+    const T pi = pval[i], hi = rhs[i];
     T acc = T(0);
     int k = rp[i];
     const int k1 = rp[i + 1];
-    for (; k < k1; k += 4) {
-      int c[4];
-      T a[4], xv[4];
+    for (; k < k1; k += KB) {
+      int c[KB];
+      T a[KB], xv[KB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < KB; ++u)
         if (k + u < k1) {
           c[u] = ci[k + u];
           a[u] = static_cast<T>(v[k + u]);
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < KB; ++u)
         if (k + u < k1) xv[u] = x[c[u]];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < KB; ++u)
         if (k + u < k1) acc = acc + a[u] * xv[u];
     }
-    return pval[i] * (rhs[i] - acc);
+    return pi * (hi - acc);
   };
   T t = T(0);
   if (q < cnt) t = scaled(mem[q0 + q]);
@@ -551,7 +729,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_agg(const int *skip, int nc,
   if (!live || q != 0) return;
   for (int j = G; j < cnt; ++j) acc = acc + scaled(mem[q0 + j]);
   rc[I] = acc;
-  if (xc) xc[I] = dinvc[I] * acc;
+  if (xc) xc[I] = (kShort ? dI : dinvc[I]) * acc;
 }
 
 // x_i += p_i * e[agg_i]
@@ -1254,11 +1432,38 @@ bool streamed(const Level &L) {
   return bytes >= AMG_STREAM_MIN_MB * 1048576.0;
 }
 
+// Levels read by k_short2 / k_short_corr: every slice compact and coded,
+// 1 to 8 slots per lane, and in the binary64 cycle at most 2^18 rows (the
+// larger binary64 levels are bandwidth-bound and measured faster with
+// k_sweep2, 160^3 solve 9.05 ms with this cap, 9.09 ms with 2^17 and 9.44 ms
+// with none; the binary32 cycle is fastest with every level here, 7.27 ms
+// against 7.44 ms with a 2^20 cap).
+#ifndef AMG_SHORT_MAX_ROWS_F64
+#define AMG_SHORT_MAX_ROWS_F64 262144
+#endif
+#ifndef AMG_SHORT_MAX_ROWS_F32
+#define AMG_SHORT_MAX_ROWS_F32 0x7fffffff
+#endif
+template <class T>
+bool short_coded(const Sell &S) {
+  const int cap = sizeof(T) == 8 ? AMG_SHORT_MAX_ROWS_F64 : AMG_SHORT_MAX_ROWS_F32;
+  return S.ndict > 0 && S.n <= cap && S.groups_compact * kSlice == S.nslots && S.wmin >= 1 && S.wmax <= 8;
+}
+
 // xw: store the new iterate widened to binary64 there instead of in xn.
 template <class T>
 void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *xn, hipStream_t s,
                   double *xw = nullptr) {
   const int n = L.A.n;
+  if (short_coded<T>(L.S)) {
+    if (streamed<T>(L))
+      hipLaunchKernelGGL((k_short2<T, true, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), nullptr, rhs, x, xn, xw);
+    else
+      hipLaunchKernelGGL((k_short2<T, false, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), nullptr, rhs, x, xn, xw);
+    return;
+  }
   if (L.S.ndict) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_sweep2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
@@ -1279,6 +1484,15 @@ void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *
 template <class T>
 void launch_resid(const int *skip, const Level &L, const T *rhs, const T *x, T *t, hipStream_t s) {
   const int n = L.A.n;
+  if (short_coded<T>(L.S)) {
+    if (streamed<T>(L))
+      hipLaunchKernelGGL((k_short2<T, true, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t, nullptr);
+    else
+      hipLaunchKernelGGL((k_short2<T, false, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
+                         sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t, nullptr);
+    return;
+  }
   if (L.S.ndict) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_resid_scaled2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip,
@@ -1313,6 +1527,9 @@ void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e
     hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
                        e, x);
     launch_sweep<T>(skip, L, rhs, x, xn, s);
+  } else if (short_coded<T>(L.S)) {
+    hipLaunchKernelGGL(k_short_corr<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, sell_ref(L.S),
+                       val_ref<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
   } else if (streamed<T>(L)) {
     hipLaunchKernelGGL((k_sweep_corr<T, true>), grid_for(n), dim3(kBlock), 0, s, skip, n,
                        sell_ref(L.S), val_ref<T>(L.S), rhs, x, L.agg.p, pval_of<T>(L), e, xn);
@@ -1322,6 +1539,9 @@ void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e
   }
 }
 
+#ifndef AMG_SHORT_RESTRICT
+#define AMG_SHORT_RESTRICT 1
+#endif
 // One-pass restriction on levels of at most kFuseRestrictRows rows;
 // returns false (nothing launched) on larger levels.
 #ifndef AMG_FUSE_RESTRICT_ROWS
@@ -1335,13 +1555,18 @@ bool launch_resid_agg(const amg_hierarchy *h, const int *skip, const Level &L, c
   const int steps = h->p.aggr_steps;   // aggregates of at most 2^steps members
   const int64_t nc = L.nc;
   hipStream_t s = h->stream;
-#define AMG_RA(G)                                                                                         \
-  hipLaunchKernelGGL((k_resid_agg<T, G>), grid_for(nc * G), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p,      \
+  const bool shortr = AMG_SHORT_RESTRICT && L.S.wmax <= 8;   // every row at most 8 entries
+#define AMG_RA(G, S)                                                                                      \
+  hipLaunchKernelGGL((k_resid_agg<T, G, S>), grid_for(nc * G), dim3(kBlock), 0, s, skip, L.nc, L.mptr.p,   \
                      L.mem.p, L.A.rp.p, L.A.ci.p, L.A.v.p, pval_of<T>(L), rhs, x, rc, dinvc, xc)
-  if (steps <= 1) AMG_RA(2);
-  else if (steps == 2) AMG_RA(4);
-  else if (steps == 3) AMG_RA(8);
-  else AMG_RA(16);
+#define AMG_RA2(G)        \
+  if (shortr) AMG_RA(G, true); \
+  else AMG_RA(G, false)
+  if (steps <= 1) { AMG_RA2(2); }
+  else if (steps == 2) { AMG_RA2(4); }
+  else if (steps == 3) { AMG_RA2(8); }
+  else { AMG_RA2(16); }
+#undef AMG_RA2
 #undef AMG_RA
   return true;
 }
