@@ -1171,8 +1171,9 @@ __device__ __forceinline__ double group_sum(double v, double *red) {
 }
 
 // Fold part[q*3 + o], q = 0..np-1, for o < NQ: each thread folds its
-// indices q = tid, tid + 1024, ... in order (loads issued four at a time),
-// then the workgroup sum combines the threads in a fixed order.
+// indices q = tid, tid + 1024, ... in order (up to 8192 partials: all loads
+// of a thread in flight at once; beyond, four at a time), then the
+// workgroup sum combines the threads in a fixed order.
 template <int NQ>
 __device__ __forceinline__ void fold_parts(const double *__restrict__ part, int np, double *red,
                                            double *out) {
@@ -1180,6 +1181,20 @@ __device__ __forceinline__ void fold_parts(const double *__restrict__ part, int 
 #pragma unroll
   for (int o = 0; o < NQ; ++o) acc[o] = 0.0;
   int q = threadIdx.x;
+  if (np <= 8 * kFinish) {
+    double v[8][NQ];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int o = 0; o < NQ; ++o)
+        if (q + u * kFinish < np) v[u][o] = part[(q + u * kFinish) * 3 + o];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q + u * kFinish < np)
+#pragma unroll
+        for (int o = 0; o < NQ; ++o) acc[o] = acc[o] + v[u][o];
+    q = np;
+  }
   for (; q + 3 * kFinish < np; q += 4 * kFinish) {
     double v[4][NQ];
 #pragma unroll
@@ -1305,11 +1320,11 @@ __global__ void __launch_bounds__(kFinish) k_pcg_dots_finish(const int *skip, in
                                                              const double *part, Scalars *sc) {
   AMG_SKIP_IF_DONE();
   __shared__ double red[kFinish / kWave];
+  const double rho_prev = sc->rho;   // read with the partials
   double t[3];
   fold_parts<3>(part, nb, red, t);
   if (threadIdx.x == 0) {
     const double A = t[0], B = t[1], G = t[2];
-    const double rho_prev = sc->rho;
     const double rho = B - (G * G) / rho_prev;
     sc->alpha = A;
     sc->beta = B;
@@ -1373,19 +1388,21 @@ __global__ void __launch_bounds__(kFinish) k_pcg_norm_finish(const int *skip, in
                                                              Scalars *host) {
   __shared__ double red[kFinish / kWave];
   const bool live = !(*skip);
+  const double thr = sc->thr;   // read with the partials
+  const int it = sc->it, maxit = sc->maxit;
   double tot = 0.0;
   if (live) fold_parts<1>(part, nb, red, &tot);
   if (threadIdx.x == 0) {
     if (live) {
       const double nr = sqrt(tot);
       sc->rr = tot;
-      if (nr <= sc->thr) {
+      if (nr <= thr) {
         sc->conv = 1;
         sc->done = 1;
       } else if (!isfinite(nr)) {
         sc->status = AMG_ERR_NONFINITE;
         sc->done = 1;
-      } else if (sc->it >= sc->maxit) {
+      } else if (it >= maxit) {
         sc->done = 1;
       }
     }
