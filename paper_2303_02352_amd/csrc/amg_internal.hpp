@@ -389,6 +389,11 @@ struct Level {
   dvec<int> agg;          // n: coarse row of fine row i
   dvec<double> pval;      // n: value of P(i, agg[i])
   dvec<float> pvalf;
+  // P values as codes (coded hierarchies, at most kDictMax distinct values):
+  // pval[i] = pdict[pcode[i]] bit for bit; npdict = 0: read pval
+  dvec<unsigned char> pcode;
+  dvec<double> pdict;
+  int npdict = 0;
   dvec<int> mptr, mem;    // CSR of P^T: members of each aggregate, ascending
   // V-cycle work vectors
   dvec<double> r, x, t;
@@ -408,6 +413,17 @@ struct Scalars {        // PCG state living in device memory
   int conv;     // 1 if ||r|| <= rtol ||r_0|| was reached
   int maxit;
   int pad;
+};
+
+// P values as a kernel reads them: pval[i], or pdict[pcode[i]] when coded.
+template <class T>
+struct PVals {
+  const T *pval;
+  const unsigned char *pcode;   // null: read pval
+  const T *pdict;
+#ifdef __HIPCC__
+  __device__ __forceinline__ T operator()(int i) const { return pcode ? pdict[pcode[i]] : pval[i]; }
+#endif
 };
 
 // Device-side description of one level for the coarse-tail kernel.

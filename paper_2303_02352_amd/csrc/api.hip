@@ -89,6 +89,7 @@ int64_t device_bytes(const amg_hierarchy *h) {
     b += L.S.code.bytes() + L.S.dict.bytes() + L.S.dictf.bytes();
     b += L.dinv.bytes() + L.w.bytes() + L.dinvf.bytes() + L.agg.bytes() + L.pval.bytes();
     b += L.pvalf.bytes() + L.mptr.bytes() + L.mem.bytes();
+    b += L.pcode.bytes() + L.pdict.bytes();
     b += L.r.bytes() + L.x.bytes() + L.t.bytes() + L.rf.bytes() + L.xf.bytes() + L.tf.bytes();
     b += L.djac.bytes() + L.ge.bytes() + L.gw.bytes() + L.gz.bytes() + L.gs_rows.bytes() + L.gs_ptr_d.bytes();
   }

@@ -1384,6 +1384,42 @@ void build_codes(Sell &S, hipStream_t s, bool want_float) {
   S.ndict = nd;
 }
 
+// code[i] = rank of v[i] in the table (every value was inserted)
+__global__ void k_dict_encode_flat(int n, const double *__restrict__ v, const unsigned long long *__restrict__ tab,
+                                   const int *__restrict__ rank, unsigned char *__restrict__ code) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int h = dict_find(tab, static_cast<unsigned long long>(__double_as_longlong(v[i])));
+  code[i] = static_cast<unsigned char>(h >= 0 ? rank[h] : 0);
+}
+
+// P values of a level as codes into a table of their distinct bit patterns,
+// when there are at most kDictMax of them (the binary64 prolongation and
+// restriction then read one byte per row instead of eight).
+void build_pcodes(Level &Lv, hipStream_t s) {
+  Lv.npdict = 0;
+  const int n = Lv.A.n;
+  if (n <= 0 || !Lv.pval.p) return;
+  tvec<unsigned long long> tab(kDictSlots, s);
+  tvec<int> cnt(1, s), rank(kDictSlots, s);
+  hipLaunchKernelGGL(k_fill_u64, dim3(kDictSlots / kBlock), dim3(kBlock), 0, s, kDictSlots, tab.p,
+                     kDictEmpty);
+  AMG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int), s));
+  const unsigned gi = static_cast<unsigned>(std::min<int64_t>(4096, ceil_div(n, kBlock)));
+  hipLaunchKernelGGL(k_dict_insert, dim3(gi), dim3(kBlock), 0, s, static_cast<int64_t>(n), Lv.pval.p, tab.p,
+                     cnt.p);
+  AMG_LAUNCH_CHECK();
+  const int nd = read_int(cnt.p, s);
+  if (nd < 1 || nd > kDictMax) return;
+  Lv.pdict.alloc(nd);
+  Lv.pcode.alloc(n);
+  hipLaunchKernelGGL(k_dict_rank, dim3(1), dim3(kBlock), 0, s, tab.p, rank.p, Lv.pdict.p, nullptr);
+  hipLaunchKernelGGL(k_dict_encode_flat, grid_for(n), dim3(kBlock), 0, s, n, Lv.pval.p, tab.p, rank.p,
+                     Lv.pcode.p);
+  AMG_LAUNCH_CHECK();
+  Lv.npdict = nd;
+}
+
 void build_sell(Level &Lv, hipStream_t s, bool want_float, bool want_codes) {
   Sell &S = Lv.S;
   const int n = Lv.A.n;
@@ -1932,6 +1968,7 @@ void build_hierarchy(amg_hierarchy *h, const amg_csr *Ain) {
                          Lk.pval.p, Lk.pvalf.p);
       AMG_LAUNCH_CHECK();
     }
+    if (want_codes) build_pcodes(Lk, s);
     if (nparts > 1) off_level = std::move(cur.offc);
     Level next;
     next.A = std::move(cur.Ac);

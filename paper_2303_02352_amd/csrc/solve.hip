@@ -416,8 +416,7 @@ __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_sweep2(const int *sk
 
 template <class T, bool kStream>
 __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_resid_scaled2(const int *skip, int n, SellRef S,
-                                                          ValRef<T> vref,
-                                                          const T *__restrict__ pval,
+                                                          ValRef<T> vref, PVals<T> pval,
                                                           const T *__restrict__ rhs,
                                                           const T *__restrict__ x,
                                                           T *__restrict__ t) {
@@ -425,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_resid_scaled2(const 
   __shared__ T sdict[kDictMax * (kBlock / kWave)];
   const ValDev<T> val = stage_dict(vref, sdict);
   const int r0 = xcd_block(blockIdx.x, gridDim.x) * (2 * kBlock) + threadIdx.x;
-  rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T) { t[r] = pval[r] * (rhs[r] - sum); });
+  rows2<T, kStream>(S, val, Plain<T>{x}, n, r0, [&](int r, T sum, T) { t[r] = pval(r) * (rhs[r] - sum); });
 }
 
 // Read in place of a null `skip`.
@@ -441,8 +440,7 @@ __device__ const int kNeverDone = 0;
 // iterate at the columns.  Same slots and fold as k_sweep2: same bits.
 template <class T, bool kStream, bool kResid>
 __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_short2(const int *skip, int n, SellRef S,
-                                                   ValRef<T> vref,
-                                                   const T *__restrict__ pval,
+                                                   ValRef<T> vref, PVals<T> pval,
                                                    const T *__restrict__ rhs,
                                                    const T *__restrict__ x, T *__restrict__ out,
                                                    double *__restrict__ xw) {
@@ -452,11 +450,11 @@ __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_short2(const int *sk
   // at that point: loads it would otherwise issue one by one, each after the
   // previous one has returned, go out together.)
   const int *sptr = S.sptr, *qptr = S.qptr, *cbase = S.cbase;
-  const T *own = kResid ? pval : x;
   const int *sk = skip ? skip : &kNeverDone;
   const int nb = static_cast<int>(gridDim.x);
   asm volatile("" ::"s"(n), "s"(nb), "s"(sptr), "s"(qptr), "s"(cbase), "s"(S.cdel), "s"(vref.code),
-               "s"(vref.dict), "s"(vref.ndict), "s"(own), "s"(rhs), "s"(x), "s"(out), "s"(xw), "s"(sk));
+               "s"(vref.dict), "s"(vref.ndict), "s"(pval.pval), "s"(pval.pcode), "s"(pval.pdict), "s"(rhs),
+               "s"(x), "s"(out), "s"(xw), "s"(sk));
   const int r0 = xcd_block(blockIdx.x, nb) * (2 * kBlock) + threadIdx.x;
   const int r1 = r0 + kBlock;
   const int nsl = (n + 63) >> 6;
@@ -470,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) AMG_EIGHT_WAVES k_short2(const int *sk
   const int ba = sptr[sa], ea = sptr[sa + 1], bb = sptr[sb], eb = sptr[sb + 1];
   const int qsa = qptr[sa], qsb = qptr[sb];
   const int ra = r0 < n ? r0 : n - 1, rb = (two && r1 < n) ? r1 : ra;
-  const T oa = own[ra], ob = own[rb], ha = rhs[ra], hb = rhs[rb];
+  const T oa = kResid ? pval(ra) : x[ra], ob = kResid ? pval(rb) : x[rb], ha = rhs[ra], hb = rhs[rb];
   asm volatile("" ::"s"(done), "s"(ba), "s"(ea), "s"(bb), "s"(eb), "s"(qsa), "s"(qsb));
   if (done) return;
   // round 2: the group bases (in range through the padding), then the rest
@@ -735,12 +733,11 @@ __global__ void __launch_bounds__(kBlock) k_resid_agg(const int *skip, int nc,
 // x_i += p_i * e[agg_i]
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_prolong(const int *skip, int n,
-                                                    const int *__restrict__ agg,
-                                                    const T *__restrict__ pval,
+                                                    const int *__restrict__ agg, PVals<T> pval,
                                                     const T *__restrict__ e, T *__restrict__ x) {
   AMG_SKIP_IF_DONE();
   const int r = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (r < n) x[r] = x[r] + pval[r] * e[agg[r]];
+  if (r < n) x[r] = x[r] + pval(r) * e[agg[r]];
 }
 
 template <class T>
@@ -1417,6 +1414,16 @@ template <> const float *dinv_of<float>(const Level &L) { return L.dinvf.p; }
 template <class T> const T *pval_of(const Level &L);
 template <> const double *pval_of<double>(const Level &L) { return L.pval.p; }
 template <> const float *pval_of<float>(const Level &L) { return L.pvalf.p; }
+// P values for the kernels that read them coded when the level has codes
+// (binary64 cycle: 1 byte instead of 8 per row, 160^3 solve 9.05 -> 8.95 ms;
+// the binary32 cycle reads pvalf, 7.26 ms against 7.33 ms with codes, where
+// the table lookup's extra round trip outweighs 3 bytes per row)
+template <class T> PVals<T> pvals_of(const Level &L);
+template <> PVals<double> pvals_of<double>(const Level &L) {
+  return PVals<double>{L.pval.p, L.npdict ? L.pcode.p : nullptr, L.pdict.p};
+}
+template <> PVals<float> pvals_of<float>(const Level &L) { return PVals<float>{L.pvalf.p, nullptr, nullptr}; }
+template <class T> PVals<T> plain_pvals(const T *p) { return PVals<T>{p, nullptr, nullptr}; }
 template <class T> T *rbuf(Level &L);
 template <> double *rbuf<double>(Level &L) { return L.r.p; }
 template <> float *rbuf<float>(Level &L) { return L.rf.p; }
@@ -1475,10 +1482,10 @@ void launch_sweep(const int *skip, const Level &L, const T *rhs, const T *x, T *
   if (short_coded<T>(L.S)) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_short2<T, true, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), nullptr, rhs, x, xn, xw);
+                         sell_ref(L.S), val_ref<T>(L.S), plain_pvals<T>(nullptr), rhs, x, xn, xw);
     else
       hipLaunchKernelGGL((k_short2<T, false, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), nullptr, rhs, x, xn, xw);
+                         sell_ref(L.S), val_ref<T>(L.S), plain_pvals<T>(nullptr), rhs, x, xn, xw);
     return;
   }
   if (L.S.ndict) {
@@ -1504,19 +1511,19 @@ void launch_resid(const int *skip, const Level &L, const T *rhs, const T *x, T *
   if (short_coded<T>(L.S)) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_short2<T, true, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t, nullptr);
+                         sell_ref(L.S), val_ref<T>(L.S), pvals_of<T>(L), rhs, x, t, nullptr);
     else
       hipLaunchKernelGGL((k_short2<T, false, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip, n,
-                         sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t, nullptr);
+                         sell_ref(L.S), val_ref<T>(L.S), pvals_of<T>(L), rhs, x, t, nullptr);
     return;
   }
   if (L.S.ndict) {
     if (streamed<T>(L))
       hipLaunchKernelGGL((k_resid_scaled2<T, true>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip,
-                         n, sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
+                         n, sell_ref(L.S), val_ref<T>(L.S), pvals_of<T>(L), rhs, x, t);
     else
       hipLaunchKernelGGL((k_resid_scaled2<T, false>), grid_for(n, 2 * kBlock), dim3(kBlock), 0, s, skip,
-                         n, sell_ref(L.S), val_ref<T>(L.S), pval_of<T>(L), rhs, x, t);
+                         n, sell_ref(L.S), val_ref<T>(L.S), pvals_of<T>(L), rhs, x, t);
     return;
   }
   if (streamed<T>(L))
@@ -1541,7 +1548,7 @@ void launch_corr_sweep(const int *skip, const Level &L, const T *rhs, const T *e
                        hipStream_t s) {
   const int n = L.A.n;
   if (AMG_FUSE_PROLONG == 0 || (AMG_FUSE_PROLONG == 1 && n > kFuseMaxRows)) {
-    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pvals_of<T>(L),
                        e, x);
     launch_sweep<T>(skip, L, rhs, x, xn, s);
   } else if (short_coded<T>(L.S)) {
@@ -1681,7 +1688,7 @@ bool vcycle_level(amg_hierarchy *h, const int *skip, int k, const T *rhs, T *out
   }
   vcycle_level<T>(h, skip, k + 1, rbuf<T>(C), xbuf<T>(C), xc != nullptr);
   if (P.post_sweeps == 0) {
-    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pval_of<T>(L),
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pvals_of<T>(L),
                        xbuf<T>(C), A);
     return false;
   }
@@ -1950,7 +1957,7 @@ void cycle_general(amg_hierarchy *h, const int *skip, int k, const double *rhs, 
     cycle_general(h, skip, k + 1, C.gw.p, C.gz.p);
     hipLaunchKernelGGL(k_add_to, grid_for(nc), dim3(kBlock), 0, s, skip, nc, C.ge.p, C.gz.p);
   }
-  hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, L.pval.p, C.ge.p,
+  hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, skip, n, L.agg.p, pvals_of<double>(L), C.ge.p,
                      L.x.p);
   smooth_more_g(h, skip, k, P.relax_type, -1, rhs, P.post_sweeps, L.x.p);
   hipLaunchKernelGGL(k_copy, grid_for(n), dim3(kBlock), 0, s, skip, n, L.x.p, out);
@@ -2449,7 +2456,7 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
         break;
       case 3:
         hipLaunchKernelGGL(k_prolong<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, L.agg.p,
-                           L.pval.p, h->L[k + 1].x.p, L.t.p);
+                           pvals_of<double>(L), h->L[k + 1].x.p, L.t.p);
         break;
       case 5:
         launch_corr_sweep<double>(nullptr, L, L.r.p, h->L[k + 1].x.p, L.x.p, L.t.p, s);
