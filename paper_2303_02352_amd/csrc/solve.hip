@@ -2501,11 +2501,12 @@ void time_kernel(amg_hierarchy *h, int kernel, int k, int reps, double *avg_ms, 
                               : 4.0 * nnz;
   const double vbytes = S.ndict ? 1.0 * nnz + bv * S.ndict : bv * nnz;
   const double mat = vbytes + idx + 4.0 * (S.nslices + 1);
+  const double pv = L.npdict ? 1.0 * nd + bv * L.npdict : bv * nd;   // P values, coded or not
   switch (kernel) {
     case 0: *bytes = mat + 2 * bv * nd + (k == 0 ? 2 * bv * nd : 0.0); break;
     case 1: *bytes = mat + 3 * bv * nd; break;
-    case 2: *bytes = mat + 5 * bv * nd + 4 * nd + 4 * (ncd + 1) + 3 * bv * ncd; break;
-    case 3: *bytes = 3 * bv * nd + 4 * nd + bv * ncd; break;
+    case 2: *bytes = mat + 4 * bv * nd + pv + 4 * nd + 4 * (ncd + 1) + 3 * bv * ncd; break;
+    case 3: *bytes = 2 * bv * nd + pv + 4 * nd + bv * ncd; break;
     case 5: *bytes = mat + 4 * bv * nd + 4 * nd + bv * ncd; break;
     case 4: {
       const FirstOut fo = first_out_for(h, h->w.p);
