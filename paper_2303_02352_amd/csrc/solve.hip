@@ -2281,7 +2281,8 @@ constexpr int kAhead = AMG_QUEUE_AHEAD;
 // Alg. 1.  One iteration = one graph launch [V-cycle, v = A w + dots,
 // scalars, vector updates + ||r||^2, convergence test, copy of the scalars
 // to pinned host memory].  The host keeps one further iteration queued and
-// waits on the older one; a queued iteration after convergence does nothing.
+// waits on the older one; a queued iteration after convergence does nothing
+// (and is not queued when the residual trend says the older one ends it).
 //
 // alloc_free: the iteration's kernels are launched one by one (no graph is
 // instantiated) and the host waits by polling the scalars the last kernel of
@@ -2349,11 +2350,22 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
       AMG_HIP(hipEventRecord(ev[launched % (kAhead + 1)], s));
     };
     for (int k = 0; k < kAhead && launched < maxit; ++k) push();
+    // ||r||^2 after the last two finished iterations (rr_old: -1 when unknown)
+    double rr_new = st.rr, rr_old = -1.0;
+    const double thr2 = st.thr * st.thr;
     for (int j = 1;; ++j) {
-      if (launched < maxit) push();
+      // iteration j is queued; the next one is queued behind it unless j is
+      // expected to end the solve (the residual norm extrapolated from the
+      // last two within 3 rtol ||r_0||): an iteration queued after
+      // convergence still dispatches every kernel of the graph
+      const bool last = rr_old > 0.0 && rr_new * (rr_new / rr_old) <= 9.0 * thr2;
+      if (launched < maxit && launched < j + kAhead && !last) push();
       AMG_HIP(hipEventSynchronize(ev[j % (kAhead + 1)]));
-      const volatile int *done = &h->sc_host->done;
-      if (*done || j >= maxit) break;
+      const volatile Scalars *m = h->sc_host;
+      if (m->done || j >= maxit) break;
+      rr_old = rr_new;
+      rr_new = m->rr;
+      if (launched == j && launched < maxit) push();   // the one held back
     }
     AMG_HIP(hipStreamSynchronize(s));
     for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
