@@ -291,10 +291,11 @@ int amg_time_kernel(amg_hierarchy *h, int32_t kernel, int32_t k, int32_t reps, d
  * (every (system, right-hand side) pair is its own flexible CG, Alg. 1, with
  * its own stopping test).  The hierarchies are built per system with the
  * single-system setup and stacked level by level; vectors are RHS-
- * interleaved.  The iterations run as one hipGraph launch per 32 iterations
- * (a whole solve of up to 32 iterations is one launch); converged pairs stay
- * frozen, so per-pair iteration counts are exact.  Every system must end in a
- * direct coarsest solve (coarse_solver CHOLESKY, coarsest n <= 1024). */
+ * interleaved.  The iterations run as hipGraph launches of two iterations
+ * each, the host checking between launches whether every pair has converged;
+ * converged pairs stay frozen, so per-pair iteration counts are exact.  Every
+ * system must end in a direct coarsest solve (coarse_solver CHOLESKY,
+ * coarsest n <= 1024). */
 typedef struct amg_batch amg_batch;   /* opaque, owned by the library */
 
 typedef struct {

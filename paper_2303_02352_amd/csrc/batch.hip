@@ -11,9 +11,9 @@
 //
 // Each (system, right-hand side) pair is its own flexible CG (Alg. 1) with
 // its own scalars and stopping test; a pair that has converged keeps its
-// vectors frozen, so iteration counts are exact per pair.  The whole solve
-// is captured as one hipGraph (iterations unrolled, masked) and launched
-// once.  Rows-per-wave of the smoothing and residual kernels (lanes per row
+// vectors frozen, so iteration counts are exact per pair.  Iterations are
+// captured as one hipGraph (unrolled, masked) launched until every pair has
+// converged.  Rows-per-wave of the smoothing and residual kernels (lanes per row
 // = NR / columns-per-lane) are chosen per level by timing the candidates.
 #include <hip/hip_runtime.h>
 
@@ -1647,7 +1647,14 @@ void batch_permute(amg_batch *bt, const UserVecs &user, double *internal, bool t
   }
 }
 
-constexpr int kGraphIters = 32;   // iterations per graph launch
+// Iterations per graph launch.  Iterations launched after every pair has
+// converged still dispatch all their kernels (about 73 at 64 x 16, 0.2-0.3 ms
+// an iteration), so launches are short: 64 x 16 solve 0.1719 s with 32
+// (20 such iterations), 0.1698 s with 1, 2 or 4.
+#ifndef AMG_BATCH_GRAPH_ITERS
+#define AMG_BATCH_GRAPH_ITERS 2
+#endif
+constexpr int kGraphIters = AMG_BATCH_GRAPH_ITERS;
 
 template <int NR>
 int batch_solve_nr(amg_batch *bt, const UserVecs &Bu, const UserVecs &Xu, double rtol, int maxit,
