@@ -2304,10 +2304,13 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
                        b, h->u.p, h->r.p, ps.part, first_out_for(h, h->w.p));
   hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, ps.part, ps.sc, rtol, maxit);
   AMG_LAUNCH_CHECK();
-  AMG_HIP(hipMemcpyAsync(h->sc_host, ps.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-  AMG_HIP(hipStreamSynchronize(s));
-  Scalars st = *h->sc_host;
-  if (!st.done && alloc_free) {
+  Scalars st{};
+  if (alloc_free) {   // the mirror starts from the initial state (polled below)
+    AMG_HIP(hipMemcpyAsync(h->sc_host, ps.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    AMG_HIP(hipStreamSynchronize(s));
+    st = *h->sc_host;
+  }
+  if (alloc_free && !st.done) {
     const volatile Scalars *mirror = h->sc_host;
     // true once iteration j has ended (or the solve has), read from the mirror
     auto ended = [&](int j) { return mirror->done != 0 || mirror->it >= j; };
@@ -2328,9 +2331,10 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
         ++launched;
       }
     }
-    AMG_HIP(hipStreamSynchronize(s));
-    st = *h->sc_host;
-  } else if (!st.done) {
+  } else if (!alloc_free) {
+    // the first iterations are queued right behind the initial residual,
+    // with no host round trip in between (they do nothing if it already
+    // ended the solve: zero or non-finite right-hand side)
     if (h->use_graph && !h->graph_exec) {
       capture_graph(h->stream, &h->graph, [&] { enqueue_iteration(h, ps); });
       AMG_HIP(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
@@ -2350,9 +2354,8 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
       AMG_HIP(hipEventRecord(ev[launched % (kAhead + 1)], s));
     };
     for (int k = 0; k < kAhead && launched < maxit; ++k) push();
-    // ||r||^2 after the last two finished iterations (rr_old: -1 when unknown)
-    double rr_new = st.rr, rr_old = -1.0;
-    const double thr2 = st.thr * st.thr;
+    // ||r||^2 after the last two finished iterations (-1 while unknown)
+    double rr_new = -1.0, rr_old = -1.0, thr2 = 0.0;
     for (int j = 1;; ++j) {
       // iteration j is queued; the next one is queued behind it unless j is
       // expected to end the solve (the residual norm extrapolated from the
@@ -2363,16 +2366,25 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
       AMG_HIP(hipEventSynchronize(ev[j % (kAhead + 1)]));
       const volatile Scalars *m = h->sc_host;
       if (m->done || j >= maxit) break;
+      if (j == 1) {
+        rr_new = m->nr0 * m->nr0;
+        thr2 = m->thr * m->thr;
+      }
       rr_old = rr_new;
       rr_new = m->rr;
       if (launched == j && launched < maxit) push();   // the one held back
     }
+    // the solution copy goes behind whatever is still queued; the events
+    // are destroyed once the stream has drained
+    AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     AMG_HIP(hipStreamSynchronize(s));
     for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
-    st = *h->sc_host;
   }
-  AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  AMG_HIP(hipStreamSynchronize(s));
+  if (alloc_free) {
+    AMG_HIP(hipMemcpyAsync(x, h->u.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AMG_HIP(hipStreamSynchronize(s));
+  }
+  st = *h->sc_host;   // the scalars after the last iteration that ran
   *iters = st.it;
   *relres = (st.nr0 == 0.0) ? 0.0 : sqrt(st.rr) / st.nr0;
   if (st.status != 0) return st.status;
