@@ -1232,11 +1232,14 @@ __device__ __forceinline__ void first_out(const FirstOut &fo, int i, double ri) 
 
 // r = b - A u, partial ||r||^2 per workgroup (kRowsDot rows per thread).
 template <bool kStream>
+// r = b - A x0 with x0 the caller's initial guess; the iterate u = x0 and
+// the recurrences' d = q = 0 are written here too (no separate passes).
 __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, SellRef S,
                                                      ValRef<double> vref,
                                                      const double *__restrict__ b,
-                                                     const double *__restrict__ u,
-                                                     double *__restrict__ r,
+                                                     const double *__restrict__ x0,
+                                                     double *__restrict__ u, double *__restrict__ d,
+                                                     double *__restrict__ q, double *__restrict__ r,
                                                      double *__restrict__ part, FirstOut fo) {
   __shared__ double red[kBlock / kWave];
   __shared__ double sdict[kDictMax * (kBlock / kWave)];
@@ -1249,9 +1252,12 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init(int n, SellRef S,
     const int row = (lb * kRowsDot + h) * kBlock + threadIdx.x;
     if (row < n) {
       double s, m;
-      sell_row<double, kStream>(S, val, u, row, s, m);
+      sell_row<double, kStream>(S, val, x0, row, s, m);
       const double ri = b[row] - s;
       r[row] = ri;
+      u[row] = x0[row];
+      d[row] = 0.0;
+      q[row] = 0.0;
       first_out(fo, row, ri);
       rr = rr + ri * ri;
     }
@@ -2293,15 +2299,12 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
   hipStream_t s = h->stream;
   const Level &L0 = h->L[0];
   const int n = L0.A.n, nb = nb_dot(n);
-  AMG_HIP(hipMemcpyAsync(h->u.p, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->d.p);
-  hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, s, nullptr, n, h->q.p);
   if (streamed<double>(L0))
     hipLaunchKernelGGL(k_pcg_init<true>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
-                       b, h->u.p, h->r.p, ps.part, first_out_for(h, h->w.p));
+                       b, x, h->u.p, h->d.p, h->q.p, h->r.p, ps.part, first_out_for(h, h->w.p));
   else
     hipLaunchKernelGGL(k_pcg_init<false>, dim3(nb), dim3(kBlock), 0, s, n, sell_ref(L0.S), val_ref<double>(L0.S),
-                       b, h->u.p, h->r.p, ps.part, first_out_for(h, h->w.p));
+                       b, x, h->u.p, h->d.p, h->q.p, h->r.p, ps.part, first_out_for(h, h->w.p));
   hipLaunchKernelGGL(k_pcg_init_finish, dim3(1), dim3(kFinish), 0, s, nb, ps.part, ps.sc, rtol, maxit);
   AMG_LAUNCH_CHECK();
   Scalars st{};
