@@ -2322,6 +2322,11 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
       enqueue_iteration(h, ps);
       ++launched;
     }
+    // as below for the graph path: no iteration queued behind one that the
+    // residual trend says ends the solve (||r||^2 of the last two: rr_old,
+    // rr_new)
+    double rr_old = -1.0, rr_new = mirror->rr;
+    const double thr2 = mirror->thr * mirror->thr;
     for (int j = 1;; ++j) {
       while (!ended(j)) {
         const hipError_t q = hipStreamQuery(s);
@@ -2329,7 +2334,12 @@ int pcg_run(amg_hierarchy *h, PcgState ps, bool alloc_free, const double *b, dou
         if (q != hipErrorNotReady) AMG_HIP(q);
       }
       if (mirror->done || j >= maxit) break;
-      if (launched < maxit) {
+      rr_old = rr_new;
+      rr_new = mirror->rr;
+      // iteration j + 1 must be queued; the one after it only if j + 1 is
+      // not expected to end the solve
+      const bool last = rr_old > 0.0 && rr_new * (rr_new / rr_old) <= 9.0 * thr2;
+      if (launched < maxit && (launched <= j || !last)) {
         enqueue_iteration(h, ps);
         ++launched;
       }
